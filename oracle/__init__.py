@@ -1,0 +1,133 @@
+"""Python access to the plain FP64 CPU oracle (liboracle_tsqbx.so).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg call this; the product library never does.  This module only
+marshals arrays; every number comes from tsqbx_oracle.c.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tsqbx_oracle.c")
+LIB = os.path.join(HERE, "liboracle_tsqbx.so")
+
+SLP, DLP = 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: plain FP64, no fast-math, no FMA contraction."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+               "-shared", "-std=c11", "-Wall", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_sources", ctypes.c_int64),
+        ("sources", ctypes.c_void_p),
+        ("weights", ctypes.c_void_p),
+        ("normals", ctypes.c_void_p),
+        ("n_centers", ctypes.c_int64),
+        ("centers", ctypes.c_void_p),
+        ("list_offsets", ctypes.c_void_p),
+        ("list_sources", ctypes.c_void_p),
+        ("n_targets", ctypes.c_int64),
+        ("targets", ctypes.c_void_p),
+        ("target_center", ctypes.c_void_p),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        lib = ctypes.CDLL(LIB)
+        lib.tsqbx_oracle_pair.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_void_p]
+        lib.tsqbx_oracle_pair.restype = None
+        lib.tsqbx_oracle_eval.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_uint,
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int]
+        lib.tsqbx_oracle_eval.restype = ctypes.c_int
+        lib.tsqbx_oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def max_threads() -> int:
+    return int(_load().tsqbx_oracle_max_threads())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def pair(t, c, s, nu, p: int):
+    """(G^(p), nu . grad_s G^(p), sum |terms| of each) for one pair."""
+    t, c, s = _f64(t, 3), _f64(c, 3), _f64(s, 3)
+    nu = None if nu is None else _f64(nu, 3)
+    out = np.zeros(4)
+    _load().tsqbx_oracle_pair(_ptr(t), _ptr(c), _ptr(s), _ptr(nu), int(p), _ptr(out))
+    return out
+
+
+def evaluate(sources, weights, normals, centers, list_offsets, list_sources, targets,
+             target_center, sigma, p: int, layers: int, select=None, n_threads: int = 0):
+    """Potentials at all targets (or the `select`ed ones).
+
+    Returns dict with keys 'slp', 'dlp', 'abs_slp', 'abs_dlp' (None for a
+    layer not requested).
+    """
+    lib = _load()
+    src = _f64(sources)
+    w = _f64(weights)
+    nrm = None if normals is None else _f64(normals)
+    ctr = _f64(centers)
+    off = np.ascontiguousarray(list_offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(list_sources, dtype=np.int32)
+    tgt = _f64(targets)
+    tc = None if target_center is None else np.ascontiguousarray(target_center, dtype=np.int32)
+    sig = _f64(sigma)
+    prob = _Problem(len(src), _ptr(src), _ptr(w), _ptr(nrm), len(ctr), _ptr(ctr), _ptr(off),
+                    _ptr(idx), len(tgt), _ptr(tgt), _ptr(tc))
+    sel = None if select is None else np.ascontiguousarray(select, dtype=np.int64)
+    n_out = len(tgt) if sel is None else len(sel)
+    want_s, want_d = bool(layers & SLP), bool(layers & DLP)
+    out = {k: None for k in ("slp", "dlp", "abs_slp", "abs_dlp")}
+    if want_s:
+        out["slp"], out["abs_slp"] = np.zeros(n_out), np.zeros(n_out)
+    if want_d:
+        out["dlp"], out["abs_dlp"] = np.zeros(n_out), np.zeros(n_out)
+    rc = lib.tsqbx_oracle_eval(ctypes.byref(prob), int(p), int(layers), _ptr(sig),
+                               n_out, _ptr(sel), _ptr(out["slp"]), _ptr(out["dlp"]),
+                               _ptr(out["abs_slp"]), _ptr(out["abs_dlp"]), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return out
+
+
+def evaluate_geometry(g, p=None, layers=None, sigma=None, select=None, n_threads: int = 0):
+    """evaluate() on any object with the workload Geometry attributes."""
+    return evaluate(g.sources, g.weights, g.normals, g.centers, g.list_offsets, g.list_sources,
+                    g.targets, g.target_center, g.sigma if sigma is None else sigma,
+                    g.p if p is None else p, g.layers if layers is None else layers,
+                    select=select, n_threads=n_threads)
