@@ -1,0 +1,315 @@
+"""Benchmark: TSQBX pair-terms/s in FP64 on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-serve]
+                    [--with-d] [--requests R]
+
+The headline `value` is the plain single- plus double-layer evaluation at
+p = 16 on the perturbed-sphere workload (262144 sources, 65536 targets,
+ball lists of radius 0.15 about centers 0.02 inside the surface), inputs
+resident in device memory, K timed steps.  One step = staging of q = w sigma
+plus the evaluation kernel.  Extra objects report the batched workload (64
+geometries, mixed p, one persistent launch vs plain per-geometry launches)
+and the served Poisson stream (p50/p99 latency).  The oracle timed on the
+host cores is reported as `cpu_baseline`.  Progress goes to stderr; one JSON
+line goes to stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TSQBX pair-terms/s FP64 at p=16 (batched vs plain) + p50/p99 request latency"
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_per_pair(p: int, layers: int) -> int:
+    """FP64 operations per (target, source) pair executed by the evaluation
+    kernel (add/mul = 1, fma = 2, the reciprocal-square-root estimate = 1)."""
+    if p == 0:
+        return {1: 31, 2: 49, 3: 52}[layers]
+    return {1: 6 * p + 26, 2: 8 * p + 42, 3: 10 * p + 44}[layers]
+
+
+def timed_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1e3
+
+
+def cpu_baseline(g, p, layers):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.evaluate_geometry(g, p=p, layers=layers)
+    t1 = time.perf_counter() - t0
+    reps = int(max(1, min(math.ceil(10.0 / max(t1, 1e-3)), 30.0 / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.evaluate_geometry(g, p=p, layers=layers)
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": g.pair_terms(p, layers) / dt, "unit": "pair-terms/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"the whole timed workload (all {g.n_targets} targets, p={p}, "
+                      f"layers={layers}) evaluated {reps}x by the FP64 C oracle, OpenMP over targets",
+            "seconds_per_pass": dt}
+
+
+def bench_batched(ctx, api, torch, W, steps, warmup):
+    log("generating 64 batched geometries (mixed p, single layer)")
+    geoms = W.config_c()
+    items = []
+    for g in geoms:
+        geom = ctx.geometry(g)
+        items.append(dict(geom=geom, p=g.p, layers=g.layers,
+                          sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64),
+                          out_slp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)))
+    pair_terms = sum(it["geom"].pair_terms(it["p"], it["layers"]) for it in items)
+    plain_out = [torch.zeros_like(it["out_slp"]) for it in items]
+
+    def plain():
+        for it, o in zip(items, plain_out):
+            ctx.eval_async(it["geom"], it["sigma"], it["p"], it["layers"], o)
+            torch.cuda.synchronize()
+
+    log("timing plain per-geometry launches")
+    wall_plain, _ = timed_steps(plain, max(steps // 4, 3), 2, torch)
+    plan = ctx.plan(items)
+    log("timing the batched plan (graph replay)")
+    wall_plan, ev_plan = timed_steps(lambda: plan.execute(), steps, warmup, torch)
+    n_plain = max(steps // 4, 3)
+    diff = max(float((a["out_slp"] - b).abs().max()) for a, b in zip(items, plain_out))
+    res = {
+        "workload": "64 geometries (ellipsoids / perturbed spheres), N log-uniform 2048..65536, "
+                    "T=N/4, p in {4,8,12,16}, single layer, ball lists r=8h",
+        "pair_terms": pair_terms,
+        "plain_pair_terms_per_s": pair_terms * n_plain / wall_plain,
+        "batched_pair_terms_per_s": pair_terms * steps / wall_plan,
+        "plain_ms": wall_plain / n_plain * 1e3,
+        "batched_ms": wall_plan / steps * 1e3,
+        "max_abs_diff_batched_vs_plain": diff,
+        "plan": plan.info(),
+    }
+    res["speedup"] = res["batched_pair_terms_per_s"] / res["plain_pair_terms_per_s"]
+    plan.close()
+    for it in items:
+        it["geom"].close()
+    return res
+
+
+def bench_d(ctx, api, torch, W, steps, warmup):
+    log("generating 16 high-order geometries (k-NN lists 100..8000, p=24, double layer)")
+    geoms = W.config_d()
+    items = []
+    for g in geoms:
+        geom = ctx.geometry(g)
+        items.append(dict(geom=geom, p=24, layers=2,
+                          sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64),
+                          out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)))
+    pair_terms = sum(it["geom"].pair_terms(24, 2) for it in items)
+    pairs = sum(it["geom"].pairs for it in items)
+
+    def plain():
+        for it in items:
+            ctx.eval_async(it["geom"], it["sigma"], 24, 2, None, it["out_dlp"])
+            torch.cuda.synchronize()
+
+    wall_plain, _ = timed_steps(plain, 3, 1, torch)
+    plan = ctx.plan(items)
+    wall_plan, _ = timed_steps(lambda: plan.execute(), max(steps // 2, 3), 1, torch)
+    res = {
+        "workload": "16 perturbed spheres, N=131072, T=32768, p=24, double layer, k-NN lists "
+                    "log-uniform 100..8000",
+        "pair_terms": pair_terms,
+        "plain_pair_terms_per_s": pair_terms * 3 / wall_plain,
+        "batched_pair_terms_per_s": pair_terms * max(steps // 2, 3) / wall_plan,
+        "batched_tflops": pairs * flops_per_pair(24, 2) * max(steps // 2, 3) / wall_plan / 1e12,
+    }
+    res["speedup"] = res["batched_pair_terms_per_s"] / res["plain_pair_terms_per_s"]
+    plan.close()
+    for it in items:
+        it["geom"].close()
+    return res
+
+
+def bench_serve(ctx, api, torch, W, n_requests):
+    log("generating 32 resident geometries for serving")
+    geoms = W.config_e_geometries()
+    gs = [ctx.geometry(g) for g in geoms]
+    reqs = W.config_e_requests(n_requests, rate_hz=1.0)
+    sigmas = [W.request_sigma(r, geoms[r.geometry].n_sources) for r in reqs]
+    per_req = [gs[r.geometry].pair_terms(r.p, r.layers) for r in reqs]
+    budget = 2 << 30
+    # closed loop, one plain launch per request in arrival order (the baseline)
+    log("serving baseline: one plain synchronous evaluation per request")
+    k0 = min(len(reqs), 300)
+    t0 = time.perf_counter()
+    for r, s in zip(reqs[:k0], sigmas[:k0]):
+        ctx.eval(gs[r.geometry], s, r.p, r.layers)
+    plain_rate = sum(per_req[:k0]) / (time.perf_counter() - t0)
+    plain_rps = k0 / (time.perf_counter() - t0)
+    # saturation: everything submitted at once
+    srv = ctx.server(budget, 64)
+    log("serving: saturation run")
+    t0 = time.perf_counter()
+    for r, s in zip(reqs, sigmas):
+        srv.submit(gs[r.geometry], s, r.p, r.layers)
+    srv.drain(600)
+    sat_s = time.perf_counter() - t0
+    sat_rps = len(reqs) / sat_s
+    srv.close()
+    # open loop at 0.7 x saturation
+    rate = 0.7 * sat_rps
+    arrivals = np.array([r.arrival_s for r in reqs]) / rate  # unit-rate schedule scaled
+    srv = ctx.server(budget, 64)
+    log(f"serving: Poisson stream at {rate:.0f} requests/s")
+    t0 = time.perf_counter()
+    for r, s, ta in zip(reqs, sigmas, arrivals):
+        while time.perf_counter() - t0 < ta:
+            pass
+        srv.submit(gs[r.geometry], s, r.p, r.layers)
+    srv.drain(600)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    for g in gs:
+        g.close()
+    return {
+        "workload": f"{n_requests} requests, Poisson arrivals at 0.7x saturation, 32 resident "
+                    "geometries N log-uniform 4096..262144, p in {8,16}, single or double layer",
+        "offered_rps": rate,
+        "saturation_rps": sat_rps,
+        "served_pair_terms_per_s": st["pair_terms_completed"] / wall,
+        "saturation_pair_terms_per_s": sum(per_req) / sat_s,
+        "plain_sequential_pair_terms_per_s": plain_rate,
+        "plain_sequential_rps": plain_rps,
+        "speedup_saturation_vs_plain": (sum(per_req) / sat_s) / plain_rate,
+        "latency_p50_ms": st["latency_p50_ms"],
+        "latency_p90_ms": st["latency_p90_ms"],
+        "latency_p99_ms": st["latency_p99_ms"],
+        "latency_max_ms": st["latency_max_ms"],
+        "queue_p50_ms": st["queue_p50_ms"],
+        "queue_p99_ms": st["queue_p99_ms"],
+        "steps": st["steps"],
+        "peak_bytes_in_flight": st["peak_bytes_in_flight"],
+        "budget_bytes": st["budget_bytes"],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--with-d", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--requests", type=int, default=2000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the evaluation shards by "
+              "targets across GPUs but this build measures the single-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1811_01110_amd import api
+    from paper_1811_01110_amd import workloads as W
+
+    log("generating the p=16 perturbed-sphere workload")
+    g = W.config_b()
+    p, layers = 16, 3
+    ctx = api.Context(0)
+    geom = ctx.geometry(g)
+    sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
+    os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
+    od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
+    step = lambda: ctx.eval_async(geom, sig, p, layers, os_, od_)
+    log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
+    wall, ev = timed_steps(step, args.steps, args.warmup, torch)
+    pair_terms = geom.pair_terms(p, layers)
+    ms = wall / args.steps * 1e3
+    flops = geom.pairs * flops_per_pair(p, layers)
+    achieved = flops / (ev / args.steps) / 1e12
+    tuning = ctx.get_tuning(p, layers, geom.pairs // geom.n_targets)
+
+    # spot parity on a few targets
+    import oracle
+
+    sel = np.arange(0, g.n_targets, max(g.n_targets // 64, 1))
+    ref = oracle.evaluate_geometry(g, p=p, layers=layers, select=sel)
+    s_np, d_np = os_.cpu().numpy()[sel], od_.cpu().numpy()[sel]
+    spot = {"targets": int(len(sel)),
+            "max_err_over_abs_scale": float(max(np.max(np.abs(s_np - ref["slp"]) / ref["abs_slp"]),
+                                                np.max(np.abs(d_np - ref["dlp"]) / ref["abs_dlp"])))}
+
+    out = {
+        "metric": METRIC,
+        "value": pair_terms / (ms / 1e3),
+        "unit": "pair-terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain single+double layer, p=16: perturbed sphere r=1+0.1f, 262144 "
+                        "sources, 65536 targets, centers 0.02 inside, ball lists r=0.15",
+            "p": p, "layers": "slp+dlp", "n_sources": g.n_sources, "n_targets": g.n_targets,
+            "pairs": geom.pairs, "mean_list": geom.pairs / g.n_targets,
+            "parallelism": "single GPU", "tuning": tuning,
+        },
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "kernel": "k_eval<16,3,64,2> (+ k_stage)", "event_ms_per_step": ev / args.steps * 1e3,
+            "flops_per_pair": flops_per_pair(p, layers),
+        },
+        "parity_spot": spot,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on the same workload")
+        out["cpu_baseline"] = cpu_baseline(g, p, layers)
+    geom.close()
+    del sig, os_, od_
+    if not args.no_batched:
+        out["batched"] = bench_batched(ctx, api, torch, W, args.steps, args.warmup)
+    if args.with_d:
+        out["batched_high_order"] = bench_d(ctx, api, torch, W, args.steps, args.warmup)
+    if not args.no_serve:
+        out["serving"] = bench_serve(ctx, api, torch, W, args.requests)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,253 @@
+/*
+ * tsqbx.h -- C ABI of libtsqbx.so: target-specific QBX (TSQBX) near-field
+ * evaluation of Laplace layer potentials on AMD MI355X (gfx950), in FP64.
+ *
+ * The operation (Wala & Kloeckner, "Optimization of fast algorithms for
+ * global quadrature by expansion using target-specific expansions"):
+ *
+ * For every target t with its QBX center c = c(t) (targets are associated
+ * with expansion balls, Sec. 3.2, stage 1 of Algorithm 1) and every source y
+ * of the center's near-field list L(c) (the sources of U_b, W_b close and
+ * X_b close for the box b owning c, Sec. 3.3; stages 3, 5(a) and 6(a) of
+ * Algorithm 1), with strength q_y = w_y sigma_y (eq. pt-pot):
+ *
+ *   single layer  out_slp[t] = sum_{y in L(c)} q_y G^(p)(t, y)
+ *   double layer  out_dlp[t] = sum_{y in L(c)} q_y nu_y . grad_y G^(p)(t, y)
+ *
+ *   G^(p)(t, y) = 1/(4 pi) sum_{n=0..p} |t-c|^n / |y-c|^{n+1} P_n(cos gamma)
+ *
+ * with gamma the angle between t-c and y-c (eq. tsqbx, Sec. 2.7, and the
+ * first formula of App. A) and grad_y the source gradient of App. A.  P_n is
+ * the Legendre polynomial; the expansion has p+1 terms, n = 0..p (Sec. 2.3:
+ * a p-th order expansion keeps the first p+1 terms).  The factor 1/(4 pi) is
+ * that of the Laplace Green's function (eq. laplace-green-function).  nu_y is
+ * the outward unit normal at y, so with centers inside the surface the double
+ * layer is the interior-side value.
+ *
+ * The result is the L^{qbx,near} term of Algorithm 1; TSQBX_ACCUMULATE adds
+ * it into the output so that a caller can sum it with far-field terms
+ * (stage 9).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns a tsqbx_status.  On error nothing is written to
+ *    any output and tsqbx_last_error() describes the failure (per thread).
+ *  - The caller owns every array it passes.  Handles are owned by the library
+ *    until their destroy call; destroy(NULL) is a no-op returning TSQBX_OK.
+ *  - Coordinates are [n][3] row-major float64 (numpy (n, 3) C order).
+ *  - Outputs are indexed by the caller's target order.
+ *  - Preconditions not checked: |y - c| > 0 for every listed pair, and
+ *    finite inputs.  |t - c| < |y - c| is needed for the truncated series to
+ *    approximate the kernel (App. A), not for the sum to be defined.
+ */
+#ifndef TSQBX_H
+#define TSQBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSQBX_OK = 0,
+  TSQBX_E_INVALID = -1, /* malformed argument: NULL pointer, bad layer mask, bad CSR */
+  TSQBX_E_RANGE = -2,   /* index or order outside its range (p > TSQBX_P_MAX, index >= n) */
+  TSQBX_E_NOMEM = -3,   /* host or device allocation failed */
+  TSQBX_E_DEVICE = -4,  /* a HIP runtime call failed (message names it) */
+  TSQBX_E_BUDGET = -5,  /* a request can never fit the server's device-memory budget */
+  TSQBX_E_STATE = -6,   /* call not valid in the object's current state */
+  TSQBX_E_TIMEOUT = -7  /* a wait ran out of time; the work is still pending */
+} tsqbx_status;
+
+/* Layer bitmask: which potentials to evaluate. */
+enum { TSQBX_SLP = 1u, TSQBX_DLP = 2u };
+
+/* Flags. */
+enum {
+  TSQBX_ACCUMULATE = 1u, /* eval: add into the outputs instead of overwriting */
+  TSQBX_NO_REORDER = 2u  /* geometry_create: keep the caller's source/target order on device */
+};
+
+/* Highest supported expansion order. */
+#define TSQBX_P_MAX 32
+
+typedef struct tsqbx_ctx tsqbx_ctx;
+typedef struct tsqbx_geometry tsqbx_geometry;
+typedef struct tsqbx_plan tsqbx_plan;
+typedef struct tsqbx_server tsqbx_server;
+
+/*
+ * Geometry: sources with weights (eq. pt-pot), normals for the double layer,
+ * QBX centers with their near-field source lists in CSR form, targets and the
+ * target -> center association.  All pointers are host pointers.
+ */
+typedef struct {
+  int64_t n_sources;           /* N >= 0 */
+  const double *sources;       /* [N][3] source points y */
+  const double *weights;       /* [N] quadrature x area weights w_y */
+  const double *normals;       /* [N][3] outward unit normals, or NULL (then no TSQBX_DLP) */
+  int64_t n_centers;           /* M >= 0 */
+  const double *centers;       /* [M][3] expansion centers c */
+  const int64_t *list_offsets; /* [M+1], offsets[0] = 0, nondecreasing */
+  const int32_t *list_sources; /* [offsets[M]] source indices in [0, N); repeats count twice */
+  int64_t n_targets;           /* T >= 0 */
+  const double *targets;       /* [T][3] target points t */
+  const int32_t *target_center;/* [T] center of each target in [0, M); NULL: T == M, target i uses center i */
+} tsqbx_geometry_desc;
+
+typedef struct {
+  int64_t n_sources, n_centers, n_targets;
+  int64_t nnz;          /* list entries */
+  int64_t pairs;        /* sum over targets of the length of their center's list */
+  int64_t max_list;     /* longest list */
+  size_t device_bytes;  /* device memory held by the geometry */
+  int has_normals;
+} tsqbx_geometry_info;
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tsqbx_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * stays valid until the next failing call on the same thread. */
+const char *tsqbx_last_error(void);
+
+/* Host-only check of a geometry description (touches no device): CSR shape,
+ * index ranges, target->center map.  Returns TSQBX_OK, TSQBX_E_INVALID or
+ * TSQBX_E_RANGE.  geometry_create performs the same checks. */
+int tsqbx_validate_geometry(const tsqbx_geometry_desc *desc);
+
+/* Check (p, layers) against a geometry's capabilities without a launch:
+ * p in [0, TSQBX_P_MAX], layers a nonempty subset of SLP|DLP, DLP needs
+ * normals.  geom may be NULL (then the normals check is skipped). */
+int tsqbx_check_request(const tsqbx_geometry *geom, int p, unsigned layers);
+
+/* Context on one HIP device (device ordinal as hipSetDevice takes it). */
+int tsqbx_ctx_create(int device, tsqbx_ctx **out);
+int tsqbx_ctx_destroy(tsqbx_ctx *ctx);
+
+/* Copy a geometry into device memory.  The library reorders sources and
+ * targets along a Morton curve for locality (unless TSQBX_NO_REORDER) and
+ * sorts each list ascending; outputs are still in the caller's order.  The
+ * caller may free its arrays when the call returns. */
+int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *desc, unsigned flags,
+                          tsqbx_geometry **out);
+int tsqbx_geometry_destroy(tsqbx_geometry *geom);
+int tsqbx_geometry_get_info(const tsqbx_geometry *geom, tsqbx_geometry_info *out);
+
+/* Plain evaluation, host pointers, synchronous.  sigma: [N] density in the
+ * caller's source order; out_slp / out_dlp: [T], required for each requested
+ * layer (may be NULL for a layer not requested). */
+int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
+               const double *sigma, double *out_slp, double *out_dlp, unsigned flags);
+
+/* Plain evaluation, device pointers, asynchronous on hip_stream (a
+ * hipStream_t passed as void*, NULL = the null stream).  The buffers must stay
+ * valid until the stream work completes.  Calls on one geometry use that
+ * geometry's own staging buffer, so two of them must not overlap in time on
+ * different streams (calls on the same stream are ordered and safe). */
+int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
+                     const double *d_sigma, double *d_out_slp, double *d_out_dlp,
+                     unsigned flags, void *hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Launch tuning.  The per-target summation order is fixed by the list and by
+ * group_lanes only, so results are bitwise identical across every other
+ * setting, and across the plain, batched and served paths at equal
+ * group_lanes.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int waves_per_block;   /* 1, 2, 4, 8 or 16 */
+  int group_lanes;       /* lanes that share one target: 64, 32 or 16 */
+  int unroll;            /* independent pairs in flight per lane: 1, 2 or 4 */
+  int xcd_remap;         /* 1: give each XCD a contiguous range of targets */
+} tsqbx_tuning;
+
+/* The tuning the library uses for (p, layers) and a typical list length. */
+int tsqbx_get_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
+                     tsqbx_tuning *out);
+/* Override it (all later launches on ctx for this (p, layers) bucket). */
+int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
+                     const tsqbx_tuning *tuning);
+
+/* Time every candidate tuning on geom (device-resident sigma of ones) and
+ * install the fastest for its (p, layers, list-length) bucket.  *out receives
+ * it; best_ms (nullable) the kernel time. */
+int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
+                   tsqbx_tuning *out, double *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Batched evaluation: many (geometry, p, layers) items in one persistent
+ * kernel launch, captured once into a HIP graph and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const tsqbx_geometry *geom;
+  int p;
+  unsigned layers;
+  const double *d_sigma;   /* device [N] */
+  double *d_out_slp;       /* device [T] or NULL */
+  double *d_out_dlp;       /* device [T] or NULL */
+} tsqbx_item;
+
+typedef struct {
+  int64_t n_items;
+  int64_t n_units;       /* work units the persistent kernel schedules */
+  int64_t pairs;
+  int64_t pair_terms;    /* sum over items of pairs x (p+1) x layer count */
+  int grid_blocks;
+  int waves_per_block;
+  size_t device_bytes;   /* plan-owned device memory */
+} tsqbx_plan_info;
+
+/* Build a plan.  Items' geometries and device buffers must outlive the plan;
+ * the same geometry may appear in several items (each item gets its own
+ * staging).  flags: TSQBX_ACCUMULATE applies to every item. */
+int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items,
+                      unsigned flags, tsqbx_plan **out);
+/* Run every item once on hip_stream (graph replay after the first call). */
+int tsqbx_plan_execute(tsqbx_plan *plan, void *hip_stream);
+int tsqbx_plan_get_info(const tsqbx_plan *plan, tsqbx_plan_info *out);
+int tsqbx_plan_destroy(tsqbx_plan *plan);
+
+/* ---------------------------------------------------------------------------
+ * Serving: requests against device-resident geometries, admitted under a
+ * device-memory budget and batched continuously: requests that arrive while
+ * others run are launched in the next step on another stream, so their work
+ * overlaps on the device.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint64_t submitted, admitted, completed, failed, rejected;
+  uint64_t steps;               /* batched launches */
+  size_t bytes_in_flight, peak_bytes_in_flight, budget_bytes;
+  int64_t pair_terms_completed;
+  double latency_p50_ms, latency_p90_ms, latency_p99_ms, latency_max_ms;
+  double queue_p50_ms, queue_p99_ms; /* submit -> launch */
+  double busy_s;                /* wall time with at least one step on the device */
+} tsqbx_server_stats;
+
+/* hbm_budget: bytes of per-request device memory that may be in flight
+ * (staging records, density, outputs); max_slots: requests in flight. */
+int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots,
+                        tsqbx_server **out);
+/* Bytes a request on geom with these layers reserves from the budget. */
+int tsqbx_server_request_bytes(const tsqbx_geometry *geom, unsigned layers, size_t *out);
+/* Queue a request.  sigma_host is copied before the call returns; the output
+ * buffers must stay valid until the ticket completes.  Thread-safe. */
+int tsqbx_server_submit(tsqbx_server *srv, const tsqbx_geometry *geom, int p, unsigned layers,
+                        const double *sigma_host, double *out_slp_host, double *out_dlp_host,
+                        uint64_t *ticket);
+/* *done = 1 once the outputs are written (0 while pending).  Returns the
+ * request's error status if it failed. */
+int tsqbx_server_poll(tsqbx_server *srv, uint64_t ticket, int *done);
+/* Block until the ticket completes or timeout_s passes (TSQBX_E_TIMEOUT). */
+int tsqbx_server_wait(tsqbx_server *srv, uint64_t ticket, double timeout_s);
+/* Block until every submitted request has completed. */
+int tsqbx_server_drain(tsqbx_server *srv, double timeout_s);
+int tsqbx_server_get_stats(tsqbx_server *srv, tsqbx_server_stats *out);
+/* Stop accepting requests, finish the ones in flight, free everything. */
+int tsqbx_server_destroy(tsqbx_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSQBX_H */

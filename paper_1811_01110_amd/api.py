@@ -1,0 +1,326 @@
+"""Python binding of libtsqbx.so: argument marshalling only.
+
+Every step of the evaluation runs in the library's HIP kernels.  torch
+supplies device memory and streams for the asynchronous entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+SLP, DLP, ACCUMULATE, NO_REORDER, P_MAX = L.SLP, L.DLP, L.ACCUMULATE, L.NO_REORDER, L.P_MAX
+
+
+class TsqbxError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"tsqbx error {code}: {message}")
+        self.code = code
+
+
+def _lib():
+    return L.load()
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = _lib().tsqbx_last_error()
+        raise TsqbxError(rc, msg.decode() if msg else "")
+
+
+def _f64(a, cols=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if cols is not None and a.size:
+        a = a.reshape(-1, cols)
+    return a
+
+
+def _ptr(a):
+    """Data pointer of an array (NULL only for None; empty arrays stay non-NULL)."""
+    return None if a is None else a.ctypes.data
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _tensor_ptr(t, n, name):
+    if t is None:
+        return None
+    import torch
+
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t.data_ptr() if n else None
+
+
+def make_desc(sources, weights, normals, centers, list_offsets, list_sources, targets,
+              target_center=None):
+    """A tsqbx_geometry_desc plus the arrays it points into (keep both alive)."""
+    keep = dict(
+        sources=_f64(sources, 3), weights=_f64(weights),
+        normals=None if normals is None else _f64(normals, 3),
+        centers=_f64(centers, 3),
+        list_offsets=np.ascontiguousarray(list_offsets, dtype=np.int64),
+        list_sources=np.ascontiguousarray(list_sources, dtype=np.int32),
+        targets=_f64(targets, 3),
+        target_center=None if target_center is None else np.ascontiguousarray(target_center, dtype=np.int32),
+    )
+    d = L.GeometryDesc(
+        len(keep["weights"]), _ptr(keep["sources"]), _ptr(keep["weights"]), _ptr(keep["normals"]),
+        len(keep["list_offsets"]) - 1, _ptr(keep["centers"]), keep["list_offsets"].ctypes.data,
+        _ptr(keep["list_sources"]), keep["targets"].shape[0] if keep["targets"].size else 0,
+        _ptr(keep["targets"]), _ptr(keep["target_center"]))
+    return d, keep
+
+
+def validate_geometry(**arrays) -> None:
+    """Host-only validation of a geometry description (raises TsqbxError)."""
+    d, keep = make_desc(**arrays)
+    _check(_lib().tsqbx_validate_geometry(ctypes.byref(d)))
+
+
+class Context:
+    """A library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib().tsqbx_ctx_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _check(_lib().tsqbx_ctx_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- geometry ---------------------------------------------------------
+    def geometry(self, g=None, *, flags: int = 0, **arrays) -> "Geometry":
+        """Upload a workload Geometry (or keyword arrays) to the device."""
+        if g is not None:
+            arrays = dict(sources=g.sources, weights=g.weights, normals=g.normals,
+                          centers=g.centers, list_offsets=g.list_offsets,
+                          list_sources=g.list_sources, targets=g.targets,
+                          target_center=g.target_center)
+        return Geometry(self, flags=flags, **arrays)
+
+    # -- evaluation ---------------------------------------------------------
+    def eval(self, geom: "Geometry", sigma, p: int, layers: int, out_slp=None, out_dlp=None,
+             flags: int = 0):
+        """Synchronous evaluation with host arrays; returns (slp, dlp)."""
+        sig = _f64(sigma)
+        if sig.size != geom.n_sources:
+            raise ValueError(f"sigma has {sig.size} entries, expected {geom.n_sources}")
+        T = geom.n_targets
+        if layers & SLP and out_slp is None:
+            out_slp = np.zeros(T)
+        if layers & DLP and out_dlp is None:
+            out_dlp = np.zeros(T)
+        for o in (out_slp, out_dlp):
+            if o is not None and (o.dtype != np.float64 or not o.flags.c_contiguous or o.size != T):
+                raise ValueError("outputs must be contiguous float64 arrays of n_targets entries")
+        _check(_lib().tsqbx_eval(self.handle, geom.handle, int(p), int(layers), _ptr(sig),
+                                 _ptr(out_slp) if layers & SLP else None,
+                                 _ptr(out_dlp) if layers & DLP else None, int(flags)))
+        return (out_slp if layers & SLP else None), (out_dlp if layers & DLP else None)
+
+    def eval_async(self, geom: "Geometry", sigma, p: int, layers: int, out_slp=None,
+                   out_dlp=None, flags: int = 0, stream=None):
+        """Asynchronous evaluation on device tensors (torch, float64)."""
+        s = _tensor_ptr(sigma, geom.n_sources, "sigma")
+        a = _tensor_ptr(out_slp, geom.n_targets, "out_slp") if layers & SLP else None
+        b = _tensor_ptr(out_dlp, geom.n_targets, "out_dlp") if layers & DLP else None
+        _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, a, b,
+                                       int(flags), _stream_handle(stream)))
+
+    # -- tuning -------------------------------------------------------------
+    def get_tuning(self, p: int, layers: int, mean_list: int) -> dict:
+        t = L.Tuning()
+        _check(_lib().tsqbx_get_tuning(self.handle, int(p), int(layers), int(mean_list),
+                                       ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, p: int, layers: int, mean_list: int, **tuning) -> None:
+        cur = self.get_tuning(p, layers, mean_list)
+        cur.update(tuning)
+        t = L.Tuning(**cur)
+        _check(_lib().tsqbx_set_tuning(self.handle, int(p), int(layers), int(mean_list),
+                                       ctypes.byref(t)))
+
+    def autotune(self, geom: "Geometry", p: int, layers: int):
+        t = L.Tuning()
+        ms = ctypes.c_double()
+        _check(_lib().tsqbx_autotune(self.handle, geom.handle, int(p), int(layers),
+                                     ctypes.byref(t), ctypes.byref(ms)))
+        return t.as_dict(), ms.value
+
+    # -- batched and served -------------------------------------------------
+    def plan(self, items: Sequence[dict], flags: int = 0) -> "Plan":
+        return Plan(self, items, flags)
+
+    def server(self, hbm_budget: int, max_slots: int) -> "Server":
+        return Server(self, hbm_budget, max_slots)
+
+
+class Geometry:
+    """A device-resident geometry (sources, weights, normals, centers, lists, targets)."""
+
+    def __init__(self, ctx: Context, *, flags: int = 0, **arrays):
+        d, keep = make_desc(**arrays)
+        h = ctypes.c_void_p()
+        _check(_lib().tsqbx_geometry_create(ctx.handle, ctypes.byref(d), int(flags), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        info = L.GeometryInfo()
+        _check(_lib().tsqbx_geometry_get_info(h, ctypes.byref(info)))
+        self.n_sources = info.n_sources
+        self.n_targets = info.n_targets
+        self.n_centers = info.n_centers
+        self.nnz = info.nnz
+        self.pairs = info.pairs
+        self.max_list = info.max_list
+        self.device_bytes = info.device_bytes
+        self.has_normals = bool(info.has_normals)
+
+    def close(self):
+        if self.handle:
+            _check(_lib().tsqbx_geometry_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.ctx.handle:
+                self.close()
+        except Exception:
+            pass
+
+    def pair_terms(self, p: int, layers: int) -> int:
+        return self.pairs * (p + 1) * bin(layers).count("1")
+
+
+class Plan:
+    """Many (geometry, p, layers) items in one persistent, graph-replayed launch.
+
+    items: dicts with geom, p, layers, sigma (device tensor), out_slp, out_dlp.
+    """
+
+    def __init__(self, ctx: Context, items: Sequence[dict], flags: int = 0):
+        arr = (L.Item * len(items))()
+        self._keep = list(items)
+        for i, it in enumerate(items):
+            g = it["geom"]
+            lay = int(it["layers"])
+            arr[i].geom = g.handle
+            arr[i].p = int(it["p"])
+            arr[i].layers = lay
+            arr[i].d_sigma = _tensor_ptr(it["sigma"], g.n_sources, "sigma")
+            arr[i].d_out_slp = _tensor_ptr(it.get("out_slp"), g.n_targets, "out_slp") if lay & SLP else None
+            arr[i].d_out_dlp = _tensor_ptr(it.get("out_dlp"), g.n_targets, "out_dlp") if lay & DLP else None
+        h = ctypes.c_void_p()
+        _check(_lib().tsqbx_plan_create(ctx.handle, len(items), arr, int(flags), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+
+    def execute(self, stream=None):
+        _check(_lib().tsqbx_plan_execute(self.handle, _stream_handle(stream)))
+
+    def info(self) -> dict:
+        i = L.PlanInfo()
+        _check(_lib().tsqbx_plan_get_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in i._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(_lib().tsqbx_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.ctx.handle:
+                self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over device-resident geometries."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int):
+        h = ctypes.c_void_p()
+        _check(_lib().tsqbx_server_create(ctx.handle, int(hbm_budget), int(max_slots), ctypes.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self._live = {}
+
+    @staticmethod
+    def request_bytes(geom: Geometry, layers: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib().tsqbx_server_request_bytes(geom.handle, int(layers), ctypes.byref(n)))
+        return n.value
+
+    def submit(self, geom: Geometry, sigma, p: int, layers: int):
+        """Queue a request; returns (ticket, out_slp, out_dlp) host arrays filled on completion."""
+        sig = _f64(sigma)
+        if sig.size != geom.n_sources:
+            raise ValueError("sigma has the wrong length")
+        T = geom.n_targets
+        os_ = np.zeros(T) if layers & SLP else None
+        od_ = np.zeros(T) if layers & DLP else None
+        tk = ctypes.c_uint64()
+        _check(_lib().tsqbx_server_submit(self.handle, geom.handle, int(p), int(layers), _ptr(sig),
+                                          _ptr(os_), _ptr(od_), ctypes.byref(tk)))
+        self._live[tk.value] = (os_, od_)
+        return tk.value, os_, od_
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(_lib().tsqbx_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        _check(_lib().tsqbx_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s)))
+        return self._live.pop(ticket, (None, None))
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(_lib().tsqbx_server_drain(self.handle, float(timeout_s)))
+
+    def stats(self) -> dict:
+        s = L.ServerStats()
+        _check(_lib().tsqbx_server_get_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self.handle:
+            _check(_lib().tsqbx_server_destroy(self.handle))
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            if self.ctx.handle:
+                self.close()
+        except Exception:
+            pass

@@ -1,0 +1,579 @@
+// Host runtime of libtsqbx.so: errors, contexts, device-resident geometry,
+// plain evaluation and tuning.  See include/tsqbx.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <vector>
+
+#include "tsqbx_internal.h"
+
+namespace tsqbx {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(TSQBX_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(TSQBX_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Sets the context's device for the lifetime of the guard, restoring the
+// caller's current device afterwards.
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class F>
+static void parallel_for(int64_t n, F &&f) {
+  const int64_t hw = std::max<int64_t>(1, std::min<int64_t>(16, std::thread::hardware_concurrency()));
+  const int64_t nt = std::min<int64_t>(hw, std::max<int64_t>(1, n / 256));
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  std::atomic<int64_t> next{0};
+  for (int64_t k = 0; k < nt; ++k)
+    th.emplace_back([&] {
+      for (;;) {
+        const int64_t b = next.fetch_add(64);
+        if (b >= n) break;
+        const int64_t e = std::min(n, b + 64);
+        for (int64_t i = b; i < e; ++i) f(i);
+      }
+    });
+  for (auto &t : th) t.join();
+}
+
+// 63-bit Morton keys of points in their bounding box (21 bits per axis).
+static uint64_t spread21(uint64_t v) {
+  v &= 0x1fffffULL;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+static std::vector<uint64_t> morton_keys(const double *xyz, int64_t n) {
+  std::vector<uint64_t> key(n);
+  if (n == 0) return key;
+  double lo[3] = {xyz[0], xyz[1], xyz[2]}, hi[3] = {xyz[0], xyz[1], xyz[2]};
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], xyz[3 * i + a]);
+      hi[a] = std::max(hi[a], xyz[3 * i + a]);
+    }
+  double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+  const double scale = double((1 << 21) - 1) / span;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t q[3];
+    for (int a = 0; a < 3; ++a) {
+      double v = (xyz[3 * i + a] - lo[a]) * scale;
+      v = std::min(std::max(v, 0.0), double((1 << 21) - 1));
+      q[a] = (uint64_t)v;
+    }
+    key[i] = spread21(q[0]) << 2 | spread21(q[1]) << 1 | spread21(q[2]);
+  }
+  return key;
+}
+
+static std::vector<int64_t> order_by_key(const std::vector<uint64_t> &key) {
+  std::vector<int64_t> ord(key.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+    return key[a] != key[b] ? key[a] < key[b] : a < b;
+  });
+  return ord;
+}
+
+static int validate(const tsqbx_geometry_desc *d) {
+  if (!d) return fail(TSQBX_E_INVALID, "geometry description is NULL");
+  if (d->n_sources < 0 || d->n_centers < 0 || d->n_targets < 0)
+    return fail(TSQBX_E_INVALID, "negative count (sources %lld, centers %lld, targets %lld)",
+                (long long)d->n_sources, (long long)d->n_centers, (long long)d->n_targets);
+  if (d->n_sources > INT32_MAX || d->n_targets > INT32_MAX || d->n_centers > INT32_MAX)
+    return fail(TSQBX_E_RANGE, "counts must stay below 2^31");
+  if (d->n_sources > 0 && (!d->sources || !d->weights))
+    return fail(TSQBX_E_INVALID, "sources or weights is NULL");
+  if (d->n_centers > 0 && !d->centers) return fail(TSQBX_E_INVALID, "centers is NULL");
+  if (!d->list_offsets) return fail(TSQBX_E_INVALID, "list_offsets is NULL");
+  if (d->n_targets > 0 && !d->targets) return fail(TSQBX_E_INVALID, "targets is NULL");
+  if (!d->target_center && d->n_targets != d->n_centers)
+    return fail(TSQBX_E_INVALID, "target_center is NULL but n_targets (%lld) != n_centers (%lld)",
+                (long long)d->n_targets, (long long)d->n_centers);
+  const int64_t *off = d->list_offsets;
+  if (off[0] != 0) return fail(TSQBX_E_INVALID, "list_offsets[0] = %lld, expected 0", (long long)off[0]);
+  for (int64_t i = 0; i < d->n_centers; ++i) {
+    if (off[i + 1] < off[i])
+      return fail(TSQBX_E_INVALID, "list_offsets decreases at center %lld", (long long)i);
+    if (off[i + 1] - off[i] > INT32_MAX)
+      return fail(TSQBX_E_RANGE, "list of center %lld is longer than 2^31-1", (long long)i);
+  }
+  const int64_t nnz = off[d->n_centers];
+  if (nnz > 0 && !d->list_sources) return fail(TSQBX_E_INVALID, "list_sources is NULL");
+  for (int64_t j = 0; j < nnz; ++j) {
+    const int32_t s = d->list_sources[j];
+    if (s < 0 || (int64_t)s >= d->n_sources)
+      return fail(TSQBX_E_RANGE, "list_sources[%lld] = %d is outside [0, %lld)", (long long)j, s,
+                  (long long)d->n_sources);
+  }
+  if (d->target_center)
+    for (int64_t t = 0; t < d->n_targets; ++t) {
+      const int32_t c = d->target_center[t];
+      if (c < 0 || (int64_t)c >= d->n_centers)
+        return fail(TSQBX_E_RANGE, "target_center[%lld] = %d is outside [0, %lld)", (long long)t, c,
+                    (long long)d->n_centers);
+    }
+  return TSQBX_OK;
+}
+
+static int check_request(const tsqbx_geometry *g, int p, unsigned layers) {
+  if (p < 0 || p > TSQBX_P_MAX)
+    return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
+  if (layers == 0 || (layers & ~3u))
+    return fail(TSQBX_E_INVALID, "layers = %u is not a nonempty subset of SLP|DLP", layers);
+  if (g && (layers & TSQBX_DLP) && !g->has_normals)
+    return fail(TSQBX_E_INVALID, "double layer requested but the geometry has no normals");
+  return TSQBX_OK;
+}
+
+uint64_t tuning_key(int p, unsigned layers, int64_t mean_list) {
+  int bucket = 0;
+  while (bucket < 40 && (int64_t(1) << (bucket + 1)) <= mean_list) ++bucket;
+  return (uint64_t)p << 16 | (uint64_t)layers << 8 | (uint64_t)bucket;
+}
+
+Tuning default_tuning(int p, unsigned layers, int64_t mean_list) {
+  (void)p;
+  (void)layers;
+  Tuning t;
+  t.waves_per_block = 4;
+  t.xcd_remap = 1;
+  if (mean_list < 48) {
+    t.group_lanes = 16;
+    t.unroll = 2;
+  } else if (mean_list < 160) {
+    t.group_lanes = 32;
+    t.unroll = 2;
+  } else {
+    t.group_lanes = 64;
+    t.unroll = 2;
+  }
+  return t;
+}
+
+Tuning lookup_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list) {
+  std::lock_guard<std::mutex> lk(ctx->tuning_mu);
+  auto it = ctx->tuning.find(tuning_key(p, layers, mean_list));
+  if (it != ctx->tuning.end()) return it->second;
+  return default_tuning(p, layers, mean_list);
+}
+
+static int64_t mean_list_of(const tsqbx_geometry *g) {
+  return g->n_targets > 0 ? (g->pairs + g->n_targets - 1) / g->n_targets : 0;
+}
+
+static void free_geometry(tsqbx_geometry *g) {
+  if (!g) return;
+  void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->tgt, g->idx, g->stage.posq, g->stage.qn};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  delete g;
+}
+
+template <class T>
+static hipError_t dev_upload(T **dst, const T *src, size_t n, size_t *bytes) {
+  *dst = nullptr;
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void **)dst, n * sizeof(T));
+  if (e != hipSuccess) return e;
+  *bytes += n * sizeof(T);
+  if (src) return hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+  return hipSuccess;
+}
+
+}  // namespace tsqbx
+
+using namespace tsqbx;
+
+extern "C" {
+
+int tsqbx_version(void) { return 10000; }
+
+const char *tsqbx_last_error(void) { return g_err.c_str(); }
+
+int tsqbx_validate_geometry(const tsqbx_geometry_desc *desc) { return validate(desc); }
+
+int tsqbx_check_request(const tsqbx_geometry *geom, int p, unsigned layers) {
+  return check_request(geom, p, layers);
+}
+
+int tsqbx_ctx_create(int device, tsqbx_ctx **out) {
+  if (!out) return fail(TSQBX_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n)
+    return fail(TSQBX_E_RANGE, "device %d is outside [0, %d)", device, n);
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  auto *c = new tsqbx_ctx;
+  c->device = device;
+  e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete c;
+    return fail_hip(e, "context setup");
+  }
+  *out = c;
+  return TSQBX_OK;
+}
+
+int tsqbx_ctx_destroy(tsqbx_ctx *ctx) {
+  if (!ctx) return TSQBX_OK;
+  DeviceGuard dg(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
+  if (ctx->d_out) (void)hipFree(ctx->d_out);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return TSQBX_OK;
+}
+
+int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned flags,
+                          tsqbx_geometry **out) {
+  if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc != TSQBX_OK) return rc;
+  const int64_t N = d->n_sources, M = d->n_centers, T = d->n_targets;
+  const bool reorder = !(flags & TSQBX_NO_REORDER);
+
+  // device order of sources (Morton) and its inverse
+  std::vector<int64_t> src_ord(N);
+  std::iota(src_ord.begin(), src_ord.end(), 0);
+  if (reorder && N > 1) src_ord = order_by_key(morton_keys(d->sources, N));
+  std::vector<int32_t> src_rank(N);
+  for (int64_t i = 0; i < N; ++i) src_rank[src_ord[i]] = (int32_t)i;
+
+  // device order of targets: by Morton key of their center, then center, then index
+  std::vector<int32_t> tc(T);
+  for (int64_t t = 0; t < T; ++t) tc[t] = d->target_center ? d->target_center[t] : (int32_t)t;
+  std::vector<int64_t> tgt_ord(T);
+  std::iota(tgt_ord.begin(), tgt_ord.end(), 0);
+  if (reorder && T > 1) {
+    std::vector<uint64_t> ckey = morton_keys(d->centers, M);
+    std::sort(tgt_ord.begin(), tgt_ord.end(), [&](int64_t a, int64_t b) {
+      const uint64_t ka = ckey[tc[a]], kb = ckey[tc[b]];
+      if (ka != kb) return ka < kb;
+      if (tc[a] != tc[b]) return tc[a] < tc[b];
+      return a < b;
+    });
+  }
+
+  // one device row per distinct center, in order of first use
+  std::vector<int64_t> row_of_center(M, -1);
+  std::vector<int64_t> row_center;
+  for (int64_t k = 0; k < T; ++k) {
+    const int32_t c = tc[tgt_ord[k]];
+    if (row_of_center[c] < 0) {
+      row_of_center[c] = (int64_t)row_center.size();
+      row_center.push_back(c);
+    }
+  }
+  const int64_t R = (int64_t)row_center.size();
+  std::vector<int64_t> row_off(R + 1, 0);
+  for (int64_t r = 0; r < R; ++r) {
+    const int32_t c = (int32_t)row_center[r];
+    row_off[r + 1] = row_off[r] + (d->list_offsets[c + 1] - d->list_offsets[c]);
+  }
+  const int64_t nnz_dev = row_off[R];
+  std::vector<int32_t> idx(nnz_dev);
+  parallel_for(R, [&](int64_t r) {
+    const int32_t c = (int32_t)row_center[r];
+    const int64_t b = d->list_offsets[c], e = d->list_offsets[c + 1];
+    int32_t *dst = idx.data() + row_off[r];
+    for (int64_t j = b; j < e; ++j) dst[j - b] = src_rank[d->list_sources[j]];
+    std::sort(dst, dst + (e - b));
+  });
+
+  std::vector<TargetRec> recs(T);
+  int64_t pairs = 0, max_list = 0;
+  std::vector<int64_t> host_row_len(T);
+  for (int64_t k = 0; k < T; ++k) {
+    const int64_t t = tgt_ord[k];
+    const int32_t c = tc[t];
+    const int64_t r = row_of_center[c];
+    TargetRec &x = recs[k];
+    for (int a = 0; a < 3; ++a) {
+      x.c[a] = d->centers[3 * c + a];
+      x.d[a] = d->targets[3 * t + a] - d->centers[3 * c + a];
+    }
+    x.row_begin = row_off[r];
+    x.row_len = (int32_t)(row_off[r + 1] - row_off[r]);
+    x.out_index = (int32_t)t;
+    pairs += x.row_len;
+    max_list = std::max<int64_t>(max_list, x.row_len);
+    host_row_len[k] = x.row_len;
+  }
+
+  std::vector<double4> pos(N), nrm(d->normals ? N : 0);
+  std::vector<int64_t> perm(reorder ? N : 0);
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t s = src_ord[i];
+    pos[i] = make_double4(d->sources[3 * s], d->sources[3 * s + 1], d->sources[3 * s + 2],
+                          d->weights[s]);
+    if (d->normals)
+      nrm[i] = make_double4(d->normals[3 * s], d->normals[3 * s + 1], d->normals[3 * s + 2], 0.0);
+    if (reorder) perm[i] = s;
+  }
+
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  auto *g = new tsqbx_geometry;
+  g->ctx = ctx;
+  g->device = ctx->device;
+  g->n_sources = N;
+  g->n_centers = M;
+  g->n_targets = T;
+  g->nnz = nnz_dev;
+  g->pairs = pairs;
+  g->max_list = max_list;
+  g->has_normals = d->normals != nullptr;
+  g->host_row_len = std::move(host_row_len);
+  size_t bytes = 0;
+  hipError_t e = dev_upload(&g->src_pos, pos.data(), N, &bytes);
+  if (e == hipSuccess && d->normals) e = dev_upload(&g->src_nrm, nrm.data(), N, &bytes);
+  if (e == hipSuccess && reorder) e = dev_upload(&g->src_perm, perm.data(), N, &bytes);
+  if (e == hipSuccess) e = dev_upload(&g->tgt, recs.data(), T, &bytes);
+  if (e == hipSuccess) e = dev_upload(&g->idx, idx.data(), nnz_dev, &bytes);
+  if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N, &bytes);
+  if (e == hipSuccess && d->normals) e = dev_upload<double4>(&g->stage.qn, nullptr, N, &bytes);
+  if (e != hipSuccess) {
+    free_geometry(g);
+    return fail_hip(e, "geometry upload");
+  }
+  g->device_bytes = bytes;
+  *out = g;
+  return TSQBX_OK;
+}
+
+int tsqbx_geometry_destroy(tsqbx_geometry *g) {
+  if (!g) return TSQBX_OK;
+  DeviceGuard dg(g->device);
+  (void)hipDeviceSynchronize();
+  free_geometry(g);
+  return TSQBX_OK;
+}
+
+int tsqbx_geometry_get_info(const tsqbx_geometry *g, tsqbx_geometry_info *out) {
+  if (!g || !out) return fail(TSQBX_E_INVALID, "geometry or out is NULL");
+  out->n_sources = g->n_sources;
+  out->n_centers = g->n_centers;
+  out->n_targets = g->n_targets;
+  out->nnz = g->nnz;
+  out->pairs = g->pairs;
+  out->max_list = g->max_list;
+  out->device_bytes = g->device_bytes;
+  out->has_normals = g->has_normals ? 1 : 0;
+  return TSQBX_OK;
+}
+
+int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
+                     const double *d_sigma, double *d_out_slp, double *d_out_dlp, unsigned flags,
+                     void *hip_stream) {
+  if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
+  if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
+  int rc = check_request(g, p, layers);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  if (g->n_targets > 0 && (((layers & TSQBX_SLP) && !d_out_slp) || ((layers & TSQBX_DLP) && !d_out_dlp)))
+    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
+  TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, s));
+  TSQBX_HIP(launch_eval(g, p, layers, g->stage, d_out_slp, d_out_dlp,
+                        (flags & TSQBX_ACCUMULATE) != 0, tn, s));
+  return TSQBX_OK;
+}
+
+int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
+               const double *sigma, double *out_slp, double *out_dlp, unsigned flags) {
+  if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
+  if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
+  int rc = check_request(g, p, layers);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_sources > 0 && !sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  if (g->n_targets > 0 && (((layers & TSQBX_SLP) && !out_slp) || ((layers & TSQBX_DLP) && !out_dlp)))
+    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
+  if (ctx->d_sigma_cap < N) {
+    if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
+    ctx->d_sigma = nullptr;
+    ctx->d_sigma_cap = 0;
+    TSQBX_HIP(hipMalloc((void **)&ctx->d_sigma, N * sizeof(double)));
+    ctx->d_sigma_cap = N;
+  }
+  if (ctx->d_out_cap < 2 * T) {
+    if (ctx->d_out) (void)hipFree(ctx->d_out);
+    ctx->d_out = nullptr;
+    ctx->d_out_cap = 0;
+    TSQBX_HIP(hipMalloc((void **)&ctx->d_out, 2 * T * sizeof(double)));
+    ctx->d_out_cap = 2 * T;
+  }
+  hipStream_t s = ctx->stream;
+  if (N) TSQBX_HIP(hipMemcpyAsync(ctx->d_sigma, sigma, N * sizeof(double), hipMemcpyHostToDevice, s));
+  double *ds = ctx->d_out, *dd = ctx->d_out + T;
+  const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
+  TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, s));
+  TSQBX_HIP(launch_eval(g, p, layers, g->stage, ds, dd, false, tn, s));
+  std::vector<double> hs((layers & TSQBX_SLP) ? T : 0), hd((layers & TSQBX_DLP) ? T : 0);
+  if (T && (layers & TSQBX_SLP))
+    TSQBX_HIP(hipMemcpyAsync(hs.data(), ds, T * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (T && (layers & TSQBX_DLP))
+    TSQBX_HIP(hipMemcpyAsync(hd.data(), dd, T * sizeof(double), hipMemcpyDeviceToHost, s));
+  TSQBX_HIP(hipStreamSynchronize(s));
+  const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
+  for (size_t i = 0; i < hs.size(); ++i) out_slp[i] = acc ? out_slp[i] + hs[i] : hs[i];
+  for (size_t i = 0; i < hd.size(); ++i) out_dlp[i] = acc ? out_dlp[i] + hd[i] : hd[i];
+  return TSQBX_OK;
+}
+
+int tsqbx_get_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
+                     tsqbx_tuning *out) {
+  if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
+  int rc = check_request(nullptr, p, layers);
+  if (rc != TSQBX_OK) return rc;
+  const Tuning t = lookup_tuning(ctx, p, layers, mean_list);
+  out->waves_per_block = t.waves_per_block;
+  out->group_lanes = t.group_lanes;
+  out->unroll = t.unroll;
+  out->xcd_remap = t.xcd_remap;
+  return TSQBX_OK;
+}
+
+int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
+                     const tsqbx_tuning *tuning) {
+  if (!ctx || !tuning) return fail(TSQBX_E_INVALID, "ctx or tuning is NULL");
+  int rc = check_request(nullptr, p, layers);
+  if (rc != TSQBX_OK) return rc;
+  Tuning t;
+  t.waves_per_block = tuning->waves_per_block;
+  t.group_lanes = tuning->group_lanes;
+  t.unroll = tuning->unroll;
+  t.xcd_remap = tuning->xcd_remap;
+  if (!tuning_supported(t))
+    return fail(TSQBX_E_INVALID, "unsupported tuning (waves %d, group %d, unroll %d, remap %d)",
+                t.waves_per_block, t.group_lanes, t.unroll, t.xcd_remap);
+  std::lock_guard<std::mutex> lk(ctx->tuning_mu);
+  ctx->tuning[tuning_key(p, layers, mean_list)] = t;
+  return TSQBX_OK;
+}
+
+int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
+                   tsqbx_tuning *out, double *best_ms) {
+  if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
+  int rc = check_request(g, p, layers);
+  if (rc != TSQBX_OK) return rc;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  const size_t N = std::max<int64_t>(g->n_sources, 1), T = std::max<int64_t>(g->n_targets, 1);
+  double *sig = nullptr, *o = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<double> ones(N, 1.0);
+  auto cleanup = [&] {
+    if (sig) (void)hipFree(sig);
+    if (o) (void)hipFree(o);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  hipError_t e = hipMalloc((void **)&sig, N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&o, 2 * T * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(sig, ones.data(), N * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  hipStream_t s = ctx->stream;
+  if (e == hipSuccess) e = launch_stage(g, sig, layers, g->stage, s);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail_hip(e, "autotune setup");
+  }
+  Tuning best;
+  double best_t = 1e300;
+  const int GU[][2] = {{64, 1}, {64, 2}, {64, 4}, {32, 2}, {16, 2}};
+  const int W[] = {2, 4, 8, 16};
+  for (auto &gu : GU)
+    for (int w : W)
+      for (int remap = 0; remap <= 1; ++remap) {
+        Tuning t;
+        t.group_lanes = gu[0];
+        t.unroll = gu[1];
+        t.waves_per_block = w;
+        t.xcd_remap = remap;
+        e = launch_eval(g, p, layers, g->stage, o, o + T, false, t, s);  // warm-up
+        float best_rep = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess) e = launch_eval(g, p, layers, g->stage, o, o + T, false, t, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          best_rep = std::min(best_rep, ms);
+        }
+        if (e != hipSuccess) {
+          cleanup();
+          return fail_hip(e, "autotune launch");
+        }
+        if (best_rep < best_t) {
+          best_t = best_rep;
+          best = t;
+        }
+      }
+  cleanup();
+  {
+    std::lock_guard<std::mutex> lk(ctx->tuning_mu);
+    ctx->tuning[tuning_key(p, layers, mean_list_of(g))] = best;
+  }
+  if (out) {
+    out->waves_per_block = best.waves_per_block;
+    out->group_lanes = best.group_lanes;
+    out->unroll = best.unroll;
+    out->xcd_remap = best.xcd_remap;
+  }
+  if (best_ms) *best_ms = best_t;
+  return TSQBX_OK;
+}
+
+}  // extern "C"

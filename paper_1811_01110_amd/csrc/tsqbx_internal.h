@@ -1,0 +1,128 @@
+// Internal declarations shared by the host runtime and the kernels of
+// libtsqbx.so.  Not part of the public ABI (include/tsqbx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tsqbx.h"
+
+namespace tsqbx {
+
+// One target in device order: its center, the offset t - c, and the CSR row
+// of its center (64 bytes, read once per target with one scalar load).
+struct alignas(64) TargetRec {
+  double c[3];
+  double d[3];
+  int64_t row_begin;
+  int32_t row_len;
+  int32_t out_index;  // caller's target index
+};
+static_assert(sizeof(TargetRec) == 64, "TargetRec layout");
+
+// Per-source staging built for each evaluation: position and strength
+// q = w sigma, and q times the normal (double layer).
+struct SourceStage {
+  double4 *posq = nullptr;  // [N] (x, y, z, q)
+  double4 *qn = nullptr;    // [N] (q nx, q ny, q nz, 0)
+};
+
+struct Tuning {
+  int waves_per_block = 4;
+  int group_lanes = 64;
+  int unroll = 2;
+  int xcd_remap = 1;
+};
+
+}  // namespace tsqbx
+
+struct tsqbx_ctx {
+  int device = 0;
+  int num_cus = 0;
+  hipStream_t stream = nullptr;  // stream of the synchronous tsqbx_eval
+  std::mutex mu;
+  // host-pointer eval staging (grown on demand)
+  double *d_sigma = nullptr;
+  size_t d_sigma_cap = 0;
+  double *d_out = nullptr;
+  size_t d_out_cap = 0;
+  // tuning table: key = (p, layers, list bucket)
+  std::map<uint64_t, tsqbx::Tuning> tuning;
+  std::mutex tuning_mu;
+};
+
+struct tsqbx_geometry {
+  tsqbx_ctx *ctx = nullptr;
+  int device = 0;
+  int64_t n_sources = 0, n_centers = 0, n_targets = 0, nnz = 0, pairs = 0, max_list = 0;
+  bool has_normals = false;
+  double4 *src_pos = nullptr;    // [N] (x, y, z, w) in device order
+  double4 *src_nrm = nullptr;    // [N] (nx, ny, nz, 0) or null
+  int64_t *src_perm = nullptr;   // [N] device order -> caller index, null if identity
+  tsqbx::TargetRec *tgt = nullptr;  // [T] in device order
+  int32_t *idx = nullptr;        // [nnz'] lists in device numbering, one row per target group
+  tsqbx::SourceStage stage;      // staging used by the plain path
+  size_t device_bytes = 0;
+  std::vector<int64_t> host_row_len;  // per device-order target, for planning
+};
+
+namespace tsqbx {
+
+// error reporting (thread-local message)
+int fail(int code, const char *fmt, ...);
+int fail_hip(hipError_t e, const char *what);
+#define TSQBX_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e__ = (call);                              \
+    if (e__ != hipSuccess) return ::tsqbx::fail_hip(e__, #call); \
+  } while (0)
+
+// kernel launchers (tsqbx_kernels.hip)
+hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
+                        const SourceStage &st, hipStream_t s);
+hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
+                       double *out_s, double *out_d, bool accumulate, const Tuning &tn,
+                       hipStream_t s);
+bool tuning_supported(const Tuning &tn);
+
+// Persistent batched kernel.
+struct WorkItem {           // one (geometry, p, layers) item of a plan, 128 bytes
+  const TargetRec *tgt;
+  const int32_t *idx;
+  const double4 *posq;
+  const double4 *qn;
+  double *out_s;
+  double *out_d;
+  int32_t p;
+  int32_t layers;
+  int32_t accumulate;
+  int32_t pad0;
+  int64_t pad1[2];
+};
+struct WorkUnit {           // a run of consecutive targets of one item, 16 bytes
+  int32_t item;
+  int32_t first;            // first device-order target
+  int32_t count;
+  int32_t pad;
+};
+struct PersistentArgs {
+  const WorkItem *items;
+  const WorkUnit *units;
+  int64_t n_units;
+  unsigned int *ticket;     // zeroed by launch_reset before each run
+};
+hipError_t launch_reset(unsigned int *ticket, hipStream_t s);
+hipError_t launch_persistent(const PersistentArgs &a, int grid, const Tuning &tn, hipStream_t s);
+int persistent_max_grid(int num_cus, const Tuning &tn);
+
+Tuning default_tuning(int p, unsigned layers, int64_t mean_list);
+Tuning lookup_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list);
+uint64_t tuning_key(int p, unsigned layers, int64_t mean_list);
+
+}  // namespace tsqbx

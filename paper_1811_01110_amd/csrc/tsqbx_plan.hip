@@ -1,0 +1,266 @@
+// Batched evaluation: many (geometry, p, layers) items in one persistent
+// kernel launch, captured once into a HIP graph and replayed.
+//
+// Work is cut into units (runs of consecutive device-order targets of one
+// item, sized so that every unit costs about the same number of pair-terms);
+// the persistent kernel's waves take units from an atomic ticket counter.
+// Items are ordered largest first and units keep their spatial (Morton) order
+// inside an item, so concurrently running waves share source records in L2.
+// Each target is summed by the same device routine as the plain path, so a
+// plan's results equal plain evaluations with the same group width bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "tsqbx_internal.h"
+
+using namespace tsqbx;
+
+struct tsqbx_plan {
+  tsqbx_ctx *ctx = nullptr;
+  int device = 0;
+  std::vector<tsqbx_item> items;
+  std::vector<SourceStage> stages;
+  WorkItem *d_items = nullptr;
+  WorkUnit *d_units = nullptr;
+  unsigned int *d_ticket = nullptr;
+  int64_t n_units = 0;
+  int64_t pairs = 0, pair_terms = 0;
+  int grid = 0;
+  Tuning tn;
+  size_t device_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+struct Guard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit Guard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~Guard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+void free_plan(tsqbx_plan *pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  for (auto &s : pl->stages) {
+    if (s.posq) (void)hipFree(s.posq);
+    if (s.qn) (void)hipFree(s.qn);
+  }
+  if (pl->d_items) (void)hipFree(pl->d_items);
+  if (pl->d_units) (void)hipFree(pl->d_units);
+  if (pl->d_ticket) (void)hipFree(pl->d_ticket);
+  delete pl;
+}
+
+int layer_count(unsigned l) { return ((l & 1u) ? 1 : 0) + ((l & 2u) ? 1 : 0); }
+
+// Relative cost of one pair: per-order work plus the per-pair setup.
+double pair_cost(int p, unsigned layers) {
+  const double per_order = (layers == 3) ? 7.0 : (layers == 2 ? 6.0 : 4.0);
+  const double setup = (layers & 2u) ? 40.0 : 22.0;
+  return per_order * std::max(p - 1, 0) + setup;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, unsigned flags,
+                      tsqbx_plan **out) {
+  if (!ctx || !out || n_items < 0 || (n_items > 0 && !items))
+    return fail(TSQBX_E_INVALID, "plan_create: ctx, out or items is NULL, or n_items < 0");
+  *out = nullptr;
+  if (n_items > INT32_MAX) return fail(TSQBX_E_RANGE, "too many items");
+  for (int64_t i = 0; i < n_items; ++i) {
+    const tsqbx_item &it = items[i];
+    if (!it.geom) return fail(TSQBX_E_INVALID, "item %lld: geometry is NULL", (long long)i);
+    if (it.geom->ctx != ctx)
+      return fail(TSQBX_E_INVALID, "item %lld: geometry belongs to another context", (long long)i);
+    int rc = tsqbx_check_request(it.geom, it.p, it.layers);
+    if (rc != TSQBX_OK) return rc;
+    if (it.geom->n_sources > 0 && !it.d_sigma)
+      return fail(TSQBX_E_INVALID, "item %lld: sigma is NULL", (long long)i);
+    if (it.geom->n_targets > 0 &&
+        (((it.layers & TSQBX_SLP) && !it.d_out_slp) || ((it.layers & TSQBX_DLP) && !it.d_out_dlp)))
+      return fail(TSQBX_E_INVALID, "item %lld: output for a requested layer is NULL", (long long)i);
+  }
+  Guard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+
+  auto *pl = new tsqbx_plan;
+  pl->ctx = ctx;
+  pl->device = ctx->device;
+  pl->items.assign(items, items + n_items);
+
+  // one launch shape for the whole plan, from the pair-weighted mean list length
+  int64_t tot_pairs = 0, tot_targets = 0;
+  int pmax = 0;
+  unsigned lay_all = 0;
+  for (auto &it : pl->items) {
+    tot_pairs += it.geom->pairs;
+    tot_targets += it.geom->n_targets;
+    pmax = std::max(pmax, it.p);
+    lay_all |= it.layers;
+    pl->pairs += it.geom->pairs;
+    pl->pair_terms += it.geom->pairs * (int64_t)(it.p + 1) * layer_count(it.layers);
+  }
+  const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
+  pl->tn = lookup_tuning(ctx, pmax, lay_all ? lay_all : 1u, mean_list);
+  if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent body holds every (p, layers) path
+  if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, 3u, mean_list);
+  const int TPW = 64 / pl->tn.group_lanes;
+
+  // item order: largest first
+  std::vector<int64_t> ord(n_items);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::vector<double> icost(n_items);
+  double total = 0;
+  for (int64_t i = 0; i < n_items; ++i) {
+    icost[i] = (double)pl->items[i].geom->pairs * pair_cost(pl->items[i].p, pl->items[i].layers);
+    total += icost[i];
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return icost[a] > icost[b]; });
+
+  // units of roughly equal cost: aim at ~16 units per resident wave
+  const int grid_max = persistent_max_grid(ctx->num_cus > 0 ? ctx->num_cus : 256, pl->tn);
+  const double waves = (double)grid_max * pl->tn.waves_per_block;
+  const double target_cost = std::max(total / (waves * 16.0), 1.0);
+  std::vector<WorkUnit> units;
+  for (int64_t oi : ord) {
+    const tsqbx_geometry *g = pl->items[oi].geom;
+    const double pc = pair_cost(pl->items[oi].p, pl->items[oi].layers);
+    int64_t k = 0;
+    while (k < g->n_targets) {
+      double c = 0;
+      int64_t e = k;
+      // whole groups of TPW targets, at most 4096 targets per unit
+      while (e < g->n_targets && (e == k || c < target_cost) && e - k < 4096) {
+        const int64_t ge = std::min<int64_t>(g->n_targets, e + TPW);
+        for (int64_t x = e; x < ge; ++x) c += (double)(g->host_row_len[x] + 1) * pc;
+        e = ge;
+      }
+      units.push_back(WorkUnit{(int32_t)oi, (int32_t)k, (int32_t)(e - k), 0});
+      k = e;
+    }
+  }
+  pl->n_units = (int64_t)units.size();
+  if (pl->n_units > INT32_MAX) {
+    free_plan(pl);
+    return fail(TSQBX_E_RANGE, "too many work units");
+  }
+  pl->grid = (int)std::max<int64_t>(
+      1, std::min<int64_t>(grid_max, (pl->n_units + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block));
+
+  // per-item staging and the device copies of items and units
+  std::vector<WorkItem> witems(n_items);
+  hipError_t e = hipSuccess;
+  pl->stages.resize(n_items);
+  for (int64_t i = 0; i < n_items && e == hipSuccess; ++i) {
+    const tsqbx_item &it = pl->items[i];
+    const size_t N = (size_t)it.geom->n_sources;
+    if (N) {
+      e = hipMalloc((void **)&pl->stages[i].posq, N * sizeof(double4));
+      pl->device_bytes += N * sizeof(double4);
+      if (e == hipSuccess && (it.layers & TSQBX_DLP)) {
+        e = hipMalloc((void **)&pl->stages[i].qn, N * sizeof(double4));
+        pl->device_bytes += N * sizeof(double4);
+      }
+    }
+    WorkItem &w = witems[i];
+    w = WorkItem{};
+    w.tgt = it.geom->tgt;
+    w.idx = it.geom->idx;
+    w.posq = pl->stages[i].posq;
+    w.qn = pl->stages[i].qn;
+    w.out_s = it.d_out_slp;
+    w.out_d = it.d_out_dlp;
+    w.p = it.p;
+    w.layers = (int32_t)it.layers;
+    w.accumulate = (flags & TSQBX_ACCUMULATE) ? 1 : 0;
+  }
+  if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_items, n_items * sizeof(WorkItem));
+  if (e == hipSuccess && n_items)
+    e = hipMemcpy(pl->d_items, witems.data(), n_items * sizeof(WorkItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && pl->n_units)
+    e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
+  if (e == hipSuccess && pl->n_units)
+    e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void **)&pl->d_ticket, sizeof(unsigned int));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+  pl->device_bytes += n_items * sizeof(WorkItem) + units.size() * sizeof(WorkUnit) + sizeof(unsigned);
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return fail_hip(e, "plan setup");
+  }
+  *out = pl;
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
+  if (!pl) return fail(TSQBX_E_INVALID, "plan is NULL");
+  Guard dg(pl->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  if (!pl->exec) {
+    // capture: staging for every item, ticket reset (a kernel, not a memset
+    // node), then the persistent kernel
+    hipStream_t cs = pl->cap_stream;
+    TSQBX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < pl->items.size() && e == hipSuccess; ++i)
+      e = launch_stage(pl->items[i].geom, pl->items[i].d_sigma, pl->items[i].layers, pl->stages[i], cs);
+    if (e == hipSuccess && pl->n_units > 0) e = launch_reset(pl->d_ticket, cs);
+    if (e == hipSuccess && pl->n_units > 0) {
+      PersistentArgs a{pl->d_items, pl->d_units, pl->n_units, pl->d_ticket};
+      e = launch_persistent(a, pl->grid, pl->tn, cs);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail_hip(e != hipSuccess ? e : e2, "plan capture");
+    }
+    pl->graph = g;
+    e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      pl->exec = nullptr;
+      return fail_hip(e, "hipGraphInstantiate");
+    }
+  }
+  TSQBX_HIP(hipGraphLaunch(pl->exec, (hipStream_t)hip_stream));
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_get_info(const tsqbx_plan *pl, tsqbx_plan_info *out) {
+  if (!pl || !out) return fail(TSQBX_E_INVALID, "plan or out is NULL");
+  out->n_items = (int64_t)pl->items.size();
+  out->n_units = pl->n_units;
+  out->pairs = pl->pairs;
+  out->pair_terms = pl->pair_terms;
+  out->grid_blocks = pl->grid;
+  out->waves_per_block = pl->tn.waves_per_block;
+  out->device_bytes = pl->device_bytes;
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_destroy(tsqbx_plan *pl) {
+  if (!pl) return TSQBX_OK;
+  Guard dg(pl->device);
+  (void)hipDeviceSynchronize();
+  free_plan(pl);
+  return TSQBX_OK;
+}
+
+}  // extern "C"

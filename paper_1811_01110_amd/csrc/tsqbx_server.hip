@@ -1,0 +1,633 @@
+// Serving: evaluation requests against device-resident geometries, admitted
+// under a device-memory budget and batched continuously.
+//
+// A scheduler thread admits queued requests in FIFO order while their buffers
+// fit in the budget (one device arena of exactly that size) and a request
+// slot is free, and launches everything it admitted as one step: density
+// uploads, staging kernels and one persistent kernel over the step's work
+// units, then output downloads.  Up to kStreams steps are in flight on
+// separate streams, so requests that arrive while a step runs are launched in
+// the next step and overlap with it on the device.  A completion thread polls
+// the steps' events, copies outputs to the callers' buffers, releases the
+// memory and wakes the scheduler.  Every request is summed by the same device
+// routine with the same group width whatever it is batched with, so its
+// result does not depend on the mix.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <thread>
+#include <vector>
+
+#include "tsqbx_internal.h"
+
+using namespace tsqbx;
+
+namespace {
+
+constexpr int kStreams = 4;
+constexpr size_t kAlign = 256;
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing on free.
+class Arena {
+ public:
+  void init(size_t size) { free_.assign(1, {0, size}); }
+  bool alloc(size_t n, size_t *off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= n) {
+        *off = it->first;
+        it->first += n;
+        it->second -= n;
+        if (it->second == 0) free_.erase(it);
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    auto it = free_.begin();
+    while (it != free_.end() && it->first < off) ++it;
+    it = free_.insert(it, {off, n});
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+        it = pv;
+      }
+    }
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+  }
+
+ private:
+  std::list<std::pair<size_t, size_t>> free_;  // (offset, length), sorted by offset
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  const tsqbx_geometry *geom = nullptr;
+  int p = 0;
+  unsigned layers = 0;
+  std::vector<double> sigma;
+  double *out_s = nullptr, *out_d = nullptr;
+  size_t bytes = 0, arena_off = 0;
+  double t_submit = 0, t_launch = 0, t_done = 0;
+  int status = TSQBX_OK;
+  bool done = false;
+};
+
+struct Step {
+  int stream = -1;
+  std::vector<Request *> reqs;
+  hipEvent_t done_ev = nullptr;
+  double t_launch = 0;
+};
+
+struct StreamSlot {
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;
+  bool busy = false;
+  // step metadata (grown on demand)
+  WorkItem *d_items = nullptr;
+  WorkUnit *d_units = nullptr;
+  unsigned int *d_ticket = nullptr;
+  size_t cap_items = 0, cap_units = 0;
+  // pinned staging for densities (in) and outputs (out)
+  double *h_buf = nullptr;
+  size_t cap_h = 0;
+  WorkItem *h_items = nullptr;
+  WorkUnit *h_units = nullptr;
+};
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = q * (v.size() - 1);
+  const size_t i = (size_t)pos;
+  const double f = pos - i;
+  return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+struct tsqbx_server {
+  tsqbx_ctx *ctx = nullptr;
+  int device = 0;
+  size_t budget = 0;
+  int max_slots = 0;
+  Tuning tn;
+  char *arena_base = nullptr;
+  Arena arena;
+  StreamSlot streams[kStreams];
+
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done, cv_comp;
+  std::deque<Request *> queue;
+  std::map<uint64_t, Request *> all;
+  std::vector<Step> inflight;
+  uint64_t next_ticket = 1;
+  bool stopping = false;
+  size_t bytes_in_flight = 0, peak_bytes = 0;
+  int reqs_in_flight = 0;
+  tsqbx_server_stats st{};
+  std::vector<double> lat_ms, queue_ms;
+  double busy_since = -1, busy_acc = 0;
+  std::thread sched, comp;
+
+  int launch_step(Step &step, std::string &err);
+  void scheduler();
+  void completer();
+};
+
+static size_t request_bytes(const tsqbx_geometry *g, unsigned layers) {
+  const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
+  size_t b = align_up(N * sizeof(double)) + align_up(N * sizeof(double4));
+  if (layers & TSQBX_DLP) b += align_up(N * sizeof(double4));
+  if (layers & TSQBX_SLP) b += align_up(T * sizeof(double));
+  if (layers & TSQBX_DLP) b += align_up(T * sizeof(double));
+  return std::max<size_t>(b, kAlign);
+}
+
+// Launch one step (called by the scheduler with the lock released).
+int tsqbx_server::launch_step(Step &step, std::string &err) {
+  StreamSlot &ss = streams[step.stream];
+  hipStream_t s = ss.s;
+  // host staging layout: [sigma of each request][outputs of each request]
+  size_t h_need = 0;
+  for (Request *r : step.reqs) {
+    h_need += (size_t)r->geom->n_sources;
+    if (r->layers & TSQBX_SLP) h_need += (size_t)r->geom->n_targets;
+    if (r->layers & TSQBX_DLP) h_need += (size_t)r->geom->n_targets;
+  }
+  hipError_t e = hipSuccess;
+  auto fail_e = [&](hipError_t x, const char *what) {
+    err = std::string(what) + ": " + hipGetErrorString(x);
+    return TSQBX_E_DEVICE;
+  };
+  if (ss.cap_h < h_need) {
+    if (ss.h_buf) (void)hipHostFree(ss.h_buf);
+    ss.h_buf = nullptr;
+    ss.cap_h = 0;
+    e = hipHostMalloc((void **)&ss.h_buf, std::max<size_t>(h_need, 1) * sizeof(double), 0);
+    if (e != hipSuccess) return fail_e(e, "hipHostMalloc");
+    ss.cap_h = h_need;
+  }
+  // work items and units, tuned once per server (results do not depend on the mix)
+  const int TPW = 64 / tn.group_lanes;
+  std::vector<WorkItem> items(step.reqs.size());
+  std::vector<WorkUnit> units;
+  size_t hpos = 0;
+  std::vector<std::pair<double *, double *>> host_out(step.reqs.size());
+  for (size_t i = 0; i < step.reqs.size(); ++i) {
+    Request *r = step.reqs[i];
+    const tsqbx_geometry *g = r->geom;
+    const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
+    char *base = arena_base + r->arena_off;
+    double *d_sigma = (double *)base;
+    size_t off = align_up(N * sizeof(double));
+    SourceStage stg;
+    stg.posq = (double4 *)(base + off);
+    off += align_up(N * sizeof(double4));
+    if (r->layers & TSQBX_DLP) {
+      stg.qn = (double4 *)(base + off);
+      off += align_up(N * sizeof(double4));
+    }
+    double *d_out_s = nullptr, *d_out_d = nullptr;
+    if (r->layers & TSQBX_SLP) {
+      d_out_s = (double *)(base + off);
+      off += align_up(T * sizeof(double));
+    }
+    if (r->layers & TSQBX_DLP) d_out_d = (double *)(base + off);
+    double *hs = ss.h_buf + hpos;
+    if (N) std::memcpy(hs, r->sigma.data(), N * sizeof(double));
+    hpos += N;
+    if (N && e == hipSuccess)
+      e = hipMemcpyAsync(d_sigma, hs, N * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_stage(g, d_sigma, r->layers, stg, s);
+    WorkItem &w = items[i];
+    w = WorkItem{};
+    w.tgt = g->tgt;
+    w.idx = g->idx;
+    w.posq = stg.posq;
+    w.qn = stg.qn;
+    w.out_s = d_out_s;
+    w.out_d = d_out_d;
+    w.p = r->p;
+    w.layers = (int32_t)r->layers;
+    for (int64_t k = 0; k < g->n_targets; k += 8 * TPW)
+      units.push_back(WorkUnit{(int32_t)i, (int32_t)k,
+                               (int32_t)std::min<int64_t>(8 * TPW, g->n_targets - k), 0});
+    host_out[i] = {d_out_s, d_out_d};
+  }
+  if (e != hipSuccess) return fail_e(e, "step upload");
+  if (!units.empty()) {
+    if (ss.cap_items < items.size()) {
+      if (ss.d_items) (void)hipFree(ss.d_items);
+      if (ss.h_items) (void)hipHostFree(ss.h_items);
+      ss.d_items = nullptr;
+      ss.h_items = nullptr;
+      ss.cap_items = 0;
+      const size_t cap = std::max<size_t>(64, items.size() * 2);
+      e = hipMalloc((void **)&ss.d_items, cap * sizeof(WorkItem));
+      if (e == hipSuccess) e = hipHostMalloc((void **)&ss.h_items, cap * sizeof(WorkItem), 0);
+      if (e != hipSuccess) return fail_e(e, "step item buffers");
+      ss.cap_items = cap;
+    }
+    if (ss.cap_units < units.size()) {
+      if (ss.d_units) (void)hipFree(ss.d_units);
+      if (ss.h_units) (void)hipHostFree(ss.h_units);
+      ss.d_units = nullptr;
+      ss.h_units = nullptr;
+      ss.cap_units = 0;
+      const size_t cap = std::max<size_t>(4096, units.size() * 2);
+      e = hipMalloc((void **)&ss.d_units, cap * sizeof(WorkUnit));
+      if (e == hipSuccess) e = hipHostMalloc((void **)&ss.h_units, cap * sizeof(WorkUnit), 0);
+      if (e != hipSuccess) return fail_e(e, "step unit buffers");
+      ss.cap_units = cap;
+    }
+    std::memcpy(ss.h_items, items.data(), items.size() * sizeof(WorkItem));
+    std::memcpy(ss.h_units, units.data(), units.size() * sizeof(WorkUnit));
+    e = hipMemcpyAsync(ss.d_items, ss.h_items, items.size() * sizeof(WorkItem),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ss.d_units, ss.h_units, units.size() * sizeof(WorkUnit),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_reset(ss.d_ticket, s);
+    if (e == hipSuccess) {
+      PersistentArgs a{ss.d_items, ss.d_units, (int64_t)units.size(), ss.d_ticket};
+      const int gmax = persistent_max_grid(ctx->num_cus > 0 ? ctx->num_cus : 256, tn);
+      const int grid = (int)std::max<int64_t>(
+          1, std::min<int64_t>(gmax, ((int64_t)units.size() + tn.waves_per_block - 1) / tn.waves_per_block));
+      e = launch_persistent(a, grid, tn, s);
+    }
+    if (e != hipSuccess) return fail_e(e, "step launch");
+  }
+  // outputs back to pinned staging
+  for (size_t i = 0; i < step.reqs.size() && e == hipSuccess; ++i) {
+    Request *r = step.reqs[i];
+    const size_t T = (size_t)r->geom->n_targets;
+    if (!T) continue;
+    if (r->layers & TSQBX_SLP) {
+      e = hipMemcpyAsync(ss.h_buf + hpos, host_out[i].first, T * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+      hpos += T;
+    }
+    if (e == hipSuccess && (r->layers & TSQBX_DLP)) {
+      e = hipMemcpyAsync(ss.h_buf + hpos, host_out[i].second, T * sizeof(double),
+                         hipMemcpyDeviceToHost, s);
+      hpos += T;
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(ss.ev, s);
+  if (e != hipSuccess) return fail_e(e, "step download");
+  step.done_ev = ss.ev;
+  return TSQBX_OK;
+}
+
+void tsqbx_server::scheduler() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_sched.wait(lk, [&] {
+      if (stopping && queue.empty()) return true;
+      if (queue.empty()) return false;
+      bool free_stream = false;
+      for (auto &ss : streams) free_stream |= !ss.busy;
+      return free_stream && reqs_in_flight < max_slots &&
+             bytes_in_flight + queue.front()->bytes <= budget;
+    });
+    if (stopping && queue.empty()) break;
+    // admit in FIFO order while memory and slots allow
+    Step step;
+    for (int k = 0; k < kStreams; ++k)
+      if (!streams[k].busy) {
+        step.stream = k;
+        break;
+      }
+    while (!queue.empty() && reqs_in_flight < max_slots) {
+      Request *r = queue.front();
+      size_t off = 0;
+      if (bytes_in_flight + r->bytes > budget || !arena.alloc(r->bytes, &off)) break;
+      queue.pop_front();
+      r->arena_off = off;
+      bytes_in_flight += r->bytes;
+      peak_bytes = std::max(peak_bytes, bytes_in_flight);
+      ++reqs_in_flight;
+      ++st.admitted;
+      step.reqs.push_back(r);
+    }
+    if (step.reqs.empty()) {
+      // the head fits the budget but not the fragmented arena: wait for a release
+      cv_sched.wait_for(lk, std::chrono::milliseconds(1));
+      continue;
+    }
+    streams[step.stream].busy = true;
+    const double t0 = now_s();
+    for (Request *r : step.reqs) r->t_launch = t0;
+    step.t_launch = t0;
+    if (busy_since < 0) busy_since = t0;
+    lk.unlock();
+    std::string err;
+    int rc = launch_step(step, err);
+    lk.lock();
+    if (rc != TSQBX_OK) {
+      // the stream may hold partial work: wait for it, then fail the step's requests
+      lk.unlock();
+      (void)hipStreamSynchronize(streams[step.stream].s);
+      lk.lock();
+      for (Request *r : step.reqs) {
+        r->status = rc;
+        r->done = true;
+        r->t_done = now_s();
+        arena.release(r->arena_off, r->bytes);
+        bytes_in_flight -= r->bytes;
+        --reqs_in_flight;
+        ++st.failed;
+      }
+      streams[step.stream].busy = false;
+      fprintf(stderr, "tsqbx server: step failed: %s\n", err.c_str());
+      if (inflight.empty() && busy_since >= 0) {
+        busy_acc += now_s() - busy_since;
+        busy_since = -1;
+      }
+      cv_done.notify_all();
+      continue;
+    }
+    ++st.steps;
+    inflight.push_back(std::move(step));
+    cv_comp.notify_all();
+  }
+}
+
+void tsqbx_server::completer() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_comp.wait(lk, [&] { return !inflight.empty() || (stopping && queue.empty() && reqs_in_flight == 0); });
+    if (inflight.empty()) break;
+    // find a finished step (poll without the lock)
+    std::vector<hipEvent_t> evs;
+    for (auto &s : inflight) evs.push_back(s.done_ev);
+    lk.unlock();
+    int found = -1;
+    hipError_t qerr = hipSuccess;
+    for (int spin = 0; found < 0; ++spin) {
+      for (size_t i = 0; i < evs.size(); ++i) {
+        hipError_t q = hipEventQuery(evs[i]);
+        if (q == hipSuccess) {
+          found = (int)i;
+          break;
+        }
+        if (q != hipErrorNotReady) {
+          found = (int)i;
+          qerr = q;
+          break;
+        }
+      }
+      if (found < 0) {
+        if (spin < 200)
+          std::this_thread::yield();
+        else
+          std::this_thread::sleep_for(std::chrono::microseconds(20));
+      }
+      if (spin > 0 && spin % 64 == 0) {
+        // new steps may have been launched meanwhile
+        std::lock_guard<std::mutex> g(mu);
+        if (inflight.size() != evs.size()) break;
+      }
+    }
+    lk.lock();
+    if (found < 0) continue;
+    Step step = std::move(inflight[found]);
+    inflight.erase(inflight.begin() + found);
+    StreamSlot &ss = streams[step.stream];
+    // outputs: pinned staging -> callers' buffers (layout mirrors launch_step)
+    size_t hpos = 0;
+    for (Request *r : step.reqs) hpos += (size_t)r->geom->n_sources;
+    const double t1 = now_s();
+    for (Request *r : step.reqs) {
+      const size_t T = (size_t)r->geom->n_targets;
+      if (qerr == hipSuccess) {
+        if (r->layers & TSQBX_SLP) {
+          if (T) std::memcpy(r->out_s, ss.h_buf + hpos, T * sizeof(double));
+          hpos += T;
+        }
+        if (r->layers & TSQBX_DLP) {
+          if (T) std::memcpy(r->out_d, ss.h_buf + hpos, T * sizeof(double));
+          hpos += T;
+        }
+        ++st.completed;
+        st.pair_terms_completed +=
+            r->geom->pairs * (int64_t)(r->p + 1) * (((r->layers & 1) ? 1 : 0) + ((r->layers & 2) ? 1 : 0));
+      } else {
+        r->status = TSQBX_E_DEVICE;
+        ++st.failed;
+      }
+      r->t_done = t1;
+      r->done = true;
+      lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
+      queue_ms.push_back((r->t_launch - r->t_submit) * 1e3);
+      arena.release(r->arena_off, r->bytes);
+      bytes_in_flight -= r->bytes;
+      --reqs_in_flight;
+      r->sigma.clear();
+      r->sigma.shrink_to_fit();
+    }
+    ss.busy = false;
+    if (inflight.empty() && busy_since >= 0) {
+      busy_acc += t1 - busy_since;
+      busy_since = -1;
+    }
+    cv_done.notify_all();
+    cv_sched.notify_all();
+  }
+}
+
+extern "C" {
+
+int tsqbx_server_request_bytes(const tsqbx_geometry *geom, unsigned layers, size_t *out) {
+  if (!geom || !out) return fail(TSQBX_E_INVALID, "geometry or out is NULL");
+  if (layers == 0 || (layers & ~3u)) return fail(TSQBX_E_INVALID, "bad layer mask %u", layers);
+  *out = request_bytes(geom, layers);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_server **out) {
+  if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
+  *out = nullptr;
+  if (hbm_budget < kAlign || max_slots <= 0)
+    return fail(TSQBX_E_INVALID, "budget must be at least %zu bytes and max_slots positive", kAlign);
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  TSQBX_HIP(hipSetDevice(ctx->device));
+  auto *sv = new tsqbx_server;
+  sv->ctx = ctx;
+  sv->device = ctx->device;
+  sv->budget = hbm_budget / kAlign * kAlign;
+  sv->max_slots = max_slots;
+  sv->tn = default_tuning(16, 3u, 1024);
+  sv->tn.group_lanes = 64;
+  sv->tn.unroll = 2;
+  sv->st.budget_bytes = sv->budget;
+  hipError_t e = hipMalloc((void **)&sv->arena_base, sv->budget);
+  for (int k = 0; k < kStreams && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&sv->streams[k].s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->streams[k].ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void **)&sv->streams[k].d_ticket, sizeof(unsigned int));
+  }
+  if (e != hipSuccess) {
+    for (auto &ss : sv->streams) {
+      if (ss.d_ticket) (void)hipFree(ss.d_ticket);
+      if (ss.ev) (void)hipEventDestroy(ss.ev);
+      if (ss.s) (void)hipStreamDestroy(ss.s);
+    }
+    if (sv->arena_base) (void)hipFree(sv->arena_base);
+    delete sv;
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return fail_hip(e, "server setup");
+  }
+  sv->arena.init(sv->budget);
+  sv->sched = std::thread([sv] { sv->scheduler(); });
+  sv->comp = std::thread([sv] { sv->completer(); });
+  if (prev >= 0) (void)hipSetDevice(prev);
+  *out = sv;
+  return TSQBX_OK;
+}
+
+int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
+                        const double *sigma_host, double *out_slp_host, double *out_dlp_host,
+                        uint64_t *ticket) {
+  if (!sv || !geom || !ticket) return fail(TSQBX_E_INVALID, "server, geometry or ticket is NULL");
+  if (geom->ctx != sv->ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
+  int rc = tsqbx_check_request(geom, p, layers);
+  if (rc != TSQBX_OK) return rc;
+  if (geom->n_sources > 0 && !sigma_host) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  if (geom->n_targets > 0 && (((layers & TSQBX_SLP) && !out_slp_host) || ((layers & TSQBX_DLP) && !out_dlp_host)))
+    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  const size_t bytes = request_bytes(geom, layers);
+  auto *r = new Request;
+  r->geom = geom;
+  r->p = p;
+  r->layers = layers;
+  r->sigma.assign(sigma_host, sigma_host + geom->n_sources);
+  r->out_s = out_slp_host;
+  r->out_d = out_dlp_host;
+  r->bytes = bytes;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  ++sv->st.submitted;
+  if (sv->stopping) {
+    delete r;
+    return fail(TSQBX_E_STATE, "server is shutting down");
+  }
+  if (bytes > sv->budget) {
+    ++sv->st.rejected;
+    delete r;
+    return fail(TSQBX_E_BUDGET, "request needs %zu bytes but the budget is %zu", bytes, sv->budget);
+  }
+  r->ticket = sv->next_ticket++;
+  r->t_submit = now_s();
+  sv->all[r->ticket] = r;
+  sv->queue.push_back(r);
+  *ticket = r->ticket;
+  sv->cv_sched.notify_all();
+  return TSQBX_OK;
+}
+
+int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {
+  if (!sv || !done) return fail(TSQBX_E_INVALID, "server or done is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return fail(TSQBX_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  *done = it->second->done ? 1 : 0;
+  if (it->second->done && it->second->status != TSQBX_OK)
+    return fail(it->second->status, "request %llu failed", (unsigned long long)ticket);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_wait(tsqbx_server *sv, uint64_t ticket, double timeout_s) {
+  if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return fail(TSQBX_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  Request *r = it->second;
+  if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; }))
+    return fail(TSQBX_E_TIMEOUT, "request %llu not done after %.3f s", (unsigned long long)ticket, timeout_s);
+  if (r->status != TSQBX_OK) return fail(r->status, "request %llu failed", (unsigned long long)ticket);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_drain(tsqbx_server *sv, double timeout_s) {
+  if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                            [&] { return sv->queue.empty() && sv->reqs_in_flight == 0; }))
+    return fail(TSQBX_E_TIMEOUT, "requests still pending after %.3f s", timeout_s);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_get_stats(tsqbx_server *sv, tsqbx_server_stats *out) {
+  if (!sv || !out) return fail(TSQBX_E_INVALID, "server or out is NULL");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  *out = sv->st;
+  out->bytes_in_flight = sv->bytes_in_flight;
+  out->peak_bytes_in_flight = sv->peak_bytes;
+  out->latency_p50_ms = percentile(sv->lat_ms, 0.50);
+  out->latency_p90_ms = percentile(sv->lat_ms, 0.90);
+  out->latency_p99_ms = percentile(sv->lat_ms, 0.99);
+  out->latency_max_ms = sv->lat_ms.empty() ? 0.0 : *std::max_element(sv->lat_ms.begin(), sv->lat_ms.end());
+  out->queue_p50_ms = percentile(sv->queue_ms, 0.50);
+  out->queue_p99_ms = percentile(sv->queue_ms, 0.99);
+  out->busy_s = sv->busy_acc + (sv->busy_since >= 0 ? now_s() - sv->busy_since : 0.0);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_destroy(tsqbx_server *sv) {
+  if (!sv) return TSQBX_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stopping = true;
+  }
+  sv->cv_sched.notify_all();
+  sv->cv_comp.notify_all();
+  if (sv->sched.joinable()) sv->sched.join();
+  {
+    // wake the completer once the last step is done
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->reqs_in_flight == 0; });
+  }
+  sv->cv_comp.notify_all();
+  if (sv->comp.joinable()) sv->comp.join();
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(sv->device);
+  for (auto &ss : sv->streams) {
+    if (ss.s) (void)hipStreamSynchronize(ss.s);
+    if (ss.d_items) (void)hipFree(ss.d_items);
+    if (ss.d_units) (void)hipFree(ss.d_units);
+    if (ss.d_ticket) (void)hipFree(ss.d_ticket);
+    if (ss.h_buf) (void)hipHostFree(ss.h_buf);
+    if (ss.h_items) (void)hipHostFree(ss.h_items);
+    if (ss.h_units) (void)hipHostFree(ss.h_units);
+    if (ss.ev) (void)hipEventDestroy(ss.ev);
+    if (ss.s) (void)hipStreamDestroy(ss.s);
+  }
+  if (sv->arena_base) (void)hipFree(sv->arena_base);
+  for (auto &kv : sv->all) delete kv.second;
+  if (prev >= 0) (void)hipSetDevice(prev);
+  delete sv;
+  return TSQBX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""The C ABI on the CPU: the library loads, exports every declared entry
+point, and rejects malformed input before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1811_01110_amd import _lib as L
+from paper_1811_01110_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_names():
+    txt = open(os.path.join(ROOT, "include", "tsqbx.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsqbx_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _header_names()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(L.exported_names())
+
+
+def test_version_and_null_destroys():
+    lib = L.load()
+    assert lib.tsqbx_version() >= 10000
+    for fn in ("tsqbx_ctx_destroy", "tsqbx_geometry_destroy", "tsqbx_plan_destroy",
+               "tsqbx_server_destroy"):
+        assert getattr(lib, fn)(None) == 0
+
+
+def _arrays(n=10, m=4, lens=(2, 0, 3, 1)):
+    rng = np.random.default_rng(0)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return dict(sources=rng.standard_normal((n, 3)), weights=np.ones(n),
+                normals=np.tile([0, 0, 1.0], (n, 1)), centers=np.zeros((m, 3)),
+                list_offsets=off, list_sources=rng.integers(0, n, off[-1]).astype(np.int32),
+                targets=np.zeros((m, 3)), target_center=None)
+
+
+def test_validate_accepts_good_geometry():
+    api.validate_geometry(**_arrays())
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda a: a.update(list_offsets=np.array([1, 2, 2, 5, 6])), L.E_INVALID),
+    (lambda a: a.update(list_offsets=np.array([0, 3, 2, 5, 6])), L.E_INVALID),
+    (lambda a: a["list_sources"].__setitem__(0, 10), L.E_RANGE),
+    (lambda a: a["list_sources"].__setitem__(1, -1), L.E_RANGE),
+    (lambda a: a.update(target_center=np.array([0, 1, 4], dtype=np.int32),
+                        targets=np.zeros((3, 3))), L.E_RANGE),
+    (lambda a: a.update(targets=np.zeros((3, 3))), L.E_INVALID),
+])
+def test_validate_rejects(mutate, code):
+    a = _arrays()
+    mutate(a)
+    with pytest.raises(api.TsqbxError) as ei:
+        api.validate_geometry(**a)
+    assert ei.value.code == code
+    assert L.load().tsqbx_last_error()
+
+
+def test_check_request_ranges():
+    lib = L.load()
+    assert lib.tsqbx_check_request(None, 0, 1) == 0
+    assert lib.tsqbx_check_request(None, 32, 3) == 0
+    assert lib.tsqbx_check_request(None, 33, 1) == L.E_RANGE
+    assert lib.tsqbx_check_request(None, -1, 1) == L.E_RANGE
+    assert lib.tsqbx_check_request(None, 4, 0) == L.E_INVALID
+    assert lib.tsqbx_check_request(None, 4, 4) == L.E_INVALID
+    assert b"layers" in lib.tsqbx_last_error()
+
+
+def test_context_without_device_fails_cleanly():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(api.TsqbxError) as ei:
+        api.Context(0)
+    assert ei.value.code in (L.E_DEVICE, L.E_RANGE)

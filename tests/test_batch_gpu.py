@@ -1,0 +1,146 @@
+"""Batched plans and the request server against plain evaluations and the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import assert_parity
+from paper_1811_01110_amd import api
+from paper_1811_01110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _items(ctx, geoms, torch):
+    out = []
+    for g in geoms:
+        geom = ctx.geometry(g)
+        out.append(dict(
+            geom=geom, p=g.p, layers=g.layers, g=g,
+            sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64),
+            out_slp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64) if g.layers & 1 else None,
+            out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64) if g.layers & 2 else None))
+    return out
+
+
+def test_plan_matches_plain_and_oracle(ctx):
+    import torch
+
+    geoms = W.config_c(n_geometries=10, scale=16)
+    geoms += [W.fuzz_geometry(200 + i, n=400, m=80, max_list=200, p=p, layers=lay)
+              for i, (p, lay) in enumerate([(0, 3), (5, 2), (24, 3), (32, 1)])]
+    items = _items(ctx, geoms, torch)
+    plan = ctx.plan(items)
+    info = plan.info()
+    assert info["n_items"] == len(items) and info["n_units"] > 0
+    plan.execute()
+    torch.cuda.synchronize()
+    mean = max(sum(i["geom"].pairs for i in items) // max(sum(i["geom"].n_targets for i in items), 1), 1)
+    G = ctx.get_tuning(max(g.p for g in geoms), 3, mean)["group_lanes"]
+    for it in items:
+        g = it["g"]
+        ref = oracle.evaluate_geometry(g)
+        for k, lay in (("out_slp", 1), ("out_dlp", 2)):
+            if not g.layers & lay:
+                continue
+            got = it[k].cpu().numpy()
+            name = "slp" if lay == 1 else "dlp"
+            assert_parity(got, ref[name], ref["abs_" + name], what=f"plan {g.name} {name}")
+        # plain evaluation with the same group width gives the same bits
+        mean_i = max(it["geom"].pairs // max(it["geom"].n_targets, 1), 1)
+        ctx.set_tuning(g.p, g.layers, mean_i, group_lanes=G, unroll=2)
+        s, d = ctx.eval(it["geom"], g.sigma, g.p, g.layers)
+        if g.layers & 1:
+            assert np.array_equal(s, it["out_slp"].cpu().numpy()), g.name
+        if g.layers & 2:
+            assert np.array_equal(d, it["out_dlp"].cpu().numpy()), g.name
+    plan.close()
+
+
+def test_plan_graph_replays_follow_inputs(ctx):
+    """Each replay of the captured graph reads the current densities."""
+    import torch
+
+    geoms = [W.fuzz_geometry(300 + i, n=500, m=120, max_list=250, p=8 + 4 * i, layers=3)
+             for i in range(3)]
+    items = _items(ctx, geoms, torch)
+    plan = ctx.plan(items)
+    rng = np.random.default_rng(9)
+    for rep in range(4):
+        sigmas = [rng.standard_normal(g.n_sources) for g in geoms]
+        for it, s in zip(items, sigmas):
+            it["sigma"].copy_(torch.tensor(s, dtype=torch.float64))
+        torch.cuda.synchronize()
+        plan.execute()
+        torch.cuda.synchronize()
+        for it, s in zip(items, sigmas):
+            a, b = ctx.eval(it["geom"], s, it["p"], 3)
+            ref = oracle.evaluate_geometry(it["g"], sigma=s)
+            assert_parity(it["out_slp"].cpu().numpy(), ref["slp"], ref["abs_slp"], what=f"replay {rep}")
+            assert_parity(it["out_dlp"].cpu().numpy(), ref["dlp"], ref["abs_dlp"], what=f"replay {rep}")
+            assert_parity(it["out_slp"].cpu().numpy(), a, ref["abs_slp"])
+    plan.close()
+
+
+def test_server_alone_equals_mix(ctx):
+    geoms = W.config_e_geometries(n_geometries=4, scale=32)
+    gs = [ctx.geometry(g) for g in geoms]
+    rng = np.random.default_rng(10)
+    reqs = []
+    for i in range(24):
+        k = int(rng.integers(0, len(geoms)))
+        reqs.append((k, int(rng.choice([8, 16])), int(rng.choice([1, 2, 3])),
+                     rng.standard_normal(geoms[k].n_sources)))
+    budget = 4 * max(api.Server.request_bytes(g, 3) for g in gs)
+    srv = ctx.server(budget, 8)
+    alone = []
+    for k, p, lay, sig in reqs:
+        t, a, b = srv.submit(gs[k], sig, p, lay)
+        srv.wait(t, 60)
+        alone.append((a, b))
+    tickets = [srv.submit(gs[k], sig, p, lay) for k, p, lay, sig in reqs]
+    srv.drain(120)
+    st = srv.stats()
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    assert st["peak_bytes_in_flight"] <= budget
+    for (k, p, lay, sig), (t, a, b), (a0, b0) in zip(reqs, tickets, alone):
+        assert srv.poll(t)
+        if lay & 1:
+            assert np.array_equal(a, a0)
+        if lay & 2:
+            assert np.array_equal(b, b0)
+    # and against the oracle
+    for (k, p, lay, sig), (a0, b0) in list(zip(reqs, alone))[:6]:
+        ref = oracle.evaluate_geometry(geoms[k], p=p, layers=lay, sigma=sig)
+        if lay & 1:
+            assert_parity(a0, ref["slp"], ref["abs_slp"], what="served slp")
+        if lay & 2:
+            assert_parity(b0, ref["dlp"], ref["abs_dlp"], what="served dlp")
+    srv.close()
+
+
+def test_server_rejects_oversized_and_respects_budget(ctx):
+    g = W.fuzz_geometry(400, n=3000, m=500, max_list=100, p=8, layers=3)
+    geom = ctx.geometry(g)
+    need = api.Server.request_bytes(geom, 3)
+    srv = ctx.server(need // 2, 4)
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.submit(geom, g.sigma, 8, 3)
+    assert ei.value.code == -5
+    srv.close()
+    srv = ctx.server(need + need // 2, 4)  # room for one request at a time
+    ts = [srv.submit(geom, g.sigma, 8, 3) for _ in range(6)]
+    srv.drain(60)
+    st = srv.stats()
+    assert st["completed"] == 6 and st["peak_bytes_in_flight"] <= need + need // 2
+    for _, a, _b in ts:
+        assert np.array_equal(a, ts[0][1])
+    srv.close()

@@ -1,0 +1,166 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Bar: max|gpu - oracle| / max|oracle| <= 1e-12 and, per target,
+|gpu - oracle| <= 1e-12 * (the oracle's sum of absolute term values).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import assert_parity, cached_workload
+from paper_1811_01110_amd import api
+from paper_1811_01110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _check(ctx, g, p=None, layers=None, select=None, flags=0, what=""):
+    p = g.p if p is None else p
+    layers = g.layers if layers is None else layers
+    geom = ctx.geometry(g, flags=flags)
+    s, d = ctx.eval(geom, g.sigma, p, layers)
+    ref = oracle.evaluate_geometry(g, p=p, layers=layers, select=select)
+    sel = slice(None) if select is None else select
+    if layers & api.SLP:
+        assert_parity(s[sel], ref["slp"], ref["abs_slp"], what=f"{what} slp")
+    if layers & api.DLP:
+        assert_parity(d[sel], ref["dlp"], ref["abs_dlp"], what=f"{what} dlp")
+    geom.close()
+    return s, d
+
+
+def test_config_a_dense_lists(ctx):
+    g = cached_workload("config_a")
+    print("config A", g.n_sources, g.n_targets, flush=True)
+    _check(ctx, g, what="A")
+
+
+def test_config_b_scaled(ctx):
+    g = cached_workload("config_b", 64)
+    print("config B/64", g.n_sources, g.n_targets, g.nnz, flush=True)
+    _check(ctx, g, what="B/64")
+
+
+def test_config_b_full_size_sampled(ctx):
+    g = cached_workload("config_b", 1)
+    rng = np.random.default_rng(5)
+    sel = np.sort(rng.choice(g.n_targets, 512, replace=False))
+    print("config B full", g.n_sources, g.n_targets, g.nnz, flush=True)
+    _check(ctx, g, select=sel, what="B")
+
+
+@pytest.mark.parametrize("p", list(range(0, 33)))
+def test_every_order_ragged_lists(ctx, p):
+    g = W.fuzz_geometry(p, n=300, m=70, max_list=140, p=p, layers=3, targets_per_center=2)
+    _check(ctx, g, what=f"fuzz p={p}")
+
+
+@pytest.mark.parametrize("layers", [1, 2, 3])
+def test_layers_separately(ctx, layers):
+    g = W.fuzz_geometry(100 + layers, n=500, m=90, max_list=300, p=16, layers=layers)
+    _check(ctx, g, layers=layers, what=f"layers={layers}")
+
+
+def test_edge_cases(ctx):
+    # no targets at all
+    g = W.fuzz_geometry(7, n=20, m=5, max_list=5, p=4, layers=3)
+    g0 = W.Geometry(g.sources, g.weights, g.normals, g.centers, g.list_offsets, g.list_sources,
+                    np.zeros((0, 3)), np.zeros(0, dtype=np.int32), g.sigma, 4, 3)
+    geom = ctx.geometry(g0)
+    s, d = ctx.eval(geom, g.sigma, 4, 3)
+    assert s.size == 0 and d.size == 0
+    # every list empty
+    off = np.zeros(g.n_centers + 1, dtype=np.int64)
+    ge = W.Geometry(g.sources, g.weights, g.normals, g.centers, off, np.zeros(0, dtype=np.int32),
+                    g.targets, g.target_center, g.sigma, 4, 3)
+    geom = ctx.geometry(ge)
+    s, d = ctx.eval(geom, g.sigma, 4, 3)
+    assert np.all(s == 0) and np.all(d == 0)
+    # one source, list of length one, target at its center (rho = 0)
+    one = W.Geometry(np.array([[1.0, 2.0, 0.5]]), np.array([0.7]), np.array([[0.0, 0.6, 0.8]]),
+                     np.zeros((1, 3)), np.array([0, 1]), np.array([0], dtype=np.int32),
+                     np.zeros((1, 3)), None, np.array([1.3]), 9, 3)
+    _check(ctx, one, what="rho=0")
+
+
+def test_tuning_variants(ctx):
+    g = W.fuzz_geometry(11, n=2000, m=300, max_list=700, p=16, layers=3)
+    geom = ctx.geometry(g)
+    ref = oracle.evaluate_geometry(g)
+    mean = max(geom.pairs // max(geom.n_targets, 1), 1)
+    base = None
+    for G, U in ((64, 1), (64, 2), (64, 4), (32, 2), (16, 2)):
+        for w in (1, 4, 16):
+            for remap in (0, 1):
+                ctx.set_tuning(16, 3, mean, waves_per_block=w, group_lanes=G, unroll=U,
+                               xcd_remap=remap)
+                s, d = ctx.eval(geom, g.sigma, 16, 3)
+                assert_parity(s, ref["slp"], ref["abs_slp"], what=f"G{G}U{U}w{w}")
+                assert_parity(d, ref["dlp"], ref["abs_dlp"], what=f"G{G}U{U}w{w}")
+                if G == 64:
+                    if base is None:
+                        base = (s.copy(), d.copy())
+                    # the summation order depends only on the group width
+                    assert np.array_equal(s, base[0]) and np.array_equal(d, base[1])
+    geom.close()
+
+
+def test_async_device_path_and_accumulate(ctx):
+    import torch
+
+    g = W.fuzz_geometry(12, n=800, m=200, max_list=400, p=12, layers=3)
+    geom = ctx.geometry(g)
+    s_host, d_host = ctx.eval(geom, g.sigma, 12, 3)
+    sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
+    os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
+    od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
+    ctx.eval_async(geom, sig, 12, 3, os_, od_)
+    torch.cuda.synchronize()
+    assert np.array_equal(os_.cpu().numpy(), s_host)
+    assert np.array_equal(od_.cpu().numpy(), d_host)
+    ctx.eval_async(geom, sig, 12, 3, os_, od_, flags=api.ACCUMULATE)
+    torch.cuda.synchronize()
+    assert np.array_equal(os_.cpu().numpy(), s_host + s_host)
+    assert np.array_equal(od_.cpu().numpy(), d_host + d_host)
+    base_s = np.full(g.n_targets, 0.25)
+    out_s = base_s.copy()
+    ctx.eval(geom, g.sigma, 12, api.SLP, out_slp=out_s, flags=api.ACCUMULATE)
+    assert np.array_equal(out_s, base_s + s_host)
+    geom.close()
+
+
+def test_no_reorder_same_result(ctx):
+    g = W.fuzz_geometry(13, n=600, m=100, max_list=300, p=8, layers=3, targets_per_center=3)
+    a = _check(ctx, g, what="reorder")
+    b = _check(ctx, g, flags=api.NO_REORDER, what="no reorder")
+    ref = oracle.evaluate_geometry(g)
+    assert_parity(a[0], b[0], ref["abs_slp"])
+    assert_parity(a[1], b[1], ref["abs_dlp"])
+
+
+def test_rejects_bad_requests(ctx):
+    g = W.fuzz_geometry(14, n=50, m=10, max_list=20, p=4, layers=1)
+    g.normals = None
+    geom = ctx.geometry(g)
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval(geom, g.sigma, 4, api.DLP)
+    assert ei.value.code == -1
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval(geom, g.sigma, 33, api.SLP)
+    assert ei.value.code == -2
+    geom.close()
+
+
+def test_config_d_geometry_sampled(ctx):
+    g = cached_workload("config_d", 1)[0]
+    rng = np.random.default_rng(6)
+    sel = np.sort(rng.choice(g.n_targets, 256, replace=False))
+    print("config D[0]", g.n_sources, g.n_targets, g.nnz, flush=True)
+    _check(ctx, g, select=sel, what="D0")
