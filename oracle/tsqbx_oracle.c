@@ -32,10 +32,14 @@ void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
   }
   double shat[3] = {ds[0] / R, ds[1] / R, ds[2] / R};
   double x = dot3(that, shat);
-  double nu_s = 0.0, nu_t = 0.0;
+  double nu_s = 0.0, nu_t = 0.0, nu_len = 0.0, perp = 0.0;
   if (nu) {
     nu_s = dot3(nu, shat);
     nu_t = dot3(nu, that);
+    nu_len = sqrt(dot3(nu, nu));
+    /* |t_hat - s_hat x|: length of the P_n' direction of the gradient */
+    double w[3] = {that[0] - shat[0] * x, that[1] - shat[1] * x, that[2] - shat[2] * x};
+    perp = sqrt(dot3(w, w));
   }
   double Rinv = 1.0 / R;
 
@@ -55,7 +59,9 @@ void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
       double a = -(double)(n + 1) * nu_s * P;
       double b = (nu_t - nu_s * x) * dP;
       kd += radial_d * (a + b);
-      kd_abs += radial_d * (fabs(a) + fabs(b));
+      /* yardstick: |nu| times the size of the gradient term, which bounds
+       * the rounding of its projection on nu */
+      kd_abs += radial_d * nu_len * ((double)(n + 1) * fabs(P) + fabs(dP) * perp);
     }
     /* Bonnet: (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1};  P_{n+1}' = x P_n' + (n+1) P_n */
     double P_next = ((double)(2 * n + 1) * x * P - (double)n * P_prev) / (double)(n + 1);

@@ -35,8 +35,11 @@
  * a repeated index is summed as often as it is listed.  |s - c| = 0 is not a
  * valid input.
  *
- * abs_* receive 1/(4 pi) sum_y |w_y sigma_y| sum_n |term_n| (each product in
- * the brackets counted separately), a yardstick for rounding error.
+ * abs_* receive rounding-error yardsticks: for the single layer
+ * 1/(4 pi) sum_y |w_y sigma_y| sum_n |term_n|; for the double layer the same
+ * sum with each term replaced by |nu| times the length of the gradient term
+ * |t-c|^n/|s-c|^{n+2} [ (n+1) |P_n| + |P_n'| |t_hat - s_hat x| ], since the
+ * rounding of a projection nu . g scales with |nu| |g| and not with |nu . g|.
  */
 #ifndef TSQBX_ORACLE_H
 #define TSQBX_ORACLE_H
