@@ -37,10 +37,11 @@ def log(msg):
 
 def flops_per_pair(p: int, layers: int) -> int:
     """FP64 operations per (target, source) pair executed by the evaluation
-    kernel (add/mul = 1, fma = 2, the reciprocal-square-root estimate = 1)."""
-    if p == 0:
-        return {1: 31, 2: 49, 3: 52}[layers]
-    return {1: 6 * p + 26, 2: 8 * p + 42, 3: 10 * p + 44}[layers]
+    kernel (add/mul = 1, fma = 2, the reciprocal-square-root estimate = 1):
+    25 for the pair setup, 6 per recurrence order, and the closing sums."""
+    if layers == 1:
+        return 28 if p == 0 else 6 * p + 23
+    return 6 * max(p, 1) + (37 if layers == 2 else 48)
 
 
 def timed_steps(fn, steps, warmup, torch):
@@ -291,7 +292,7 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-            "kernel": "k_eval<16,3,64,2> (+ k_stage)", "event_ms_per_step": ev / args.steps * 1e3,
+            "kernel": "k_eval<16, 3, G, U> (+ k_stage)", "event_ms_per_step": ev / args.steps * 1e3,
             "flops_per_pair": flops_per_pair(p, layers),
         },
         "parity_spot": spot,

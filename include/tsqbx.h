@@ -72,6 +72,10 @@ enum {
 /* Highest supported expansion order. */
 #define TSQBX_P_MAX 32
 
+/* A geometry holds fewer than this many sources (2^27: device byte offsets of
+ * per-source records stay within 32 bits). */
+#define TSQBX_MAX_SOURCES 134217728LL
+
 typedef struct tsqbx_ctx tsqbx_ctx;
 typedef struct tsqbx_geometry tsqbx_geometry;
 typedef struct tsqbx_plan tsqbx_plan;
@@ -151,13 +155,14 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned
                      unsigned flags, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
- * Launch tuning.  The per-target summation order is fixed by the list and by
- * group_lanes only, so results are bitwise identical across every other
- * setting, and across the plain, batched and served paths at equal
- * group_lanes.
+ * Launch tuning.  A target's result depends only on its list, the layer mask
+ * of the call (the single layer alone runs its own recurrence; with the double
+ * layer both come from one derivative recurrence) and group_lanes: it is
+ * bitwise identical across every other setting, and across the plain, batched
+ * and served paths at equal group_lanes and layer mask.
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int waves_per_block;   /* 1, 2, 4, 8 or 16 */
+  int waves_per_block;   /* 1, 2 or 4 */
   int group_lanes;       /* lanes that share one target: 64, 32 or 16 */
   int unroll;            /* independent pairs in flight per lane: 1, 2 or 4 */
   int xcd_remap;         /* 1: give each XCD a contiguous range of targets */

@@ -116,7 +116,10 @@ static int validate(const tsqbx_geometry_desc *d) {
   if (d->n_sources < 0 || d->n_centers < 0 || d->n_targets < 0)
     return fail(TSQBX_E_INVALID, "negative count (sources %lld, centers %lld, targets %lld)",
                 (long long)d->n_sources, (long long)d->n_centers, (long long)d->n_targets);
-  if (d->n_sources > INT32_MAX || d->n_targets > INT32_MAX || d->n_centers > INT32_MAX)
+  if (d->n_sources >= TSQBX_MAX_SOURCES)
+    return fail(TSQBX_E_RANGE, "n_sources = %lld; a geometry holds fewer than %lld sources",
+                (long long)d->n_sources, (long long)TSQBX_MAX_SOURCES);
+  if (d->n_targets > INT32_MAX || d->n_centers > INT32_MAX)
     return fail(TSQBX_E_RANGE, "counts must stay below 2^31");
   if (d->n_sources > 0 && (!d->sources || !d->weights))
     return fail(TSQBX_E_INVALID, "sources or weights is NULL");
@@ -131,8 +134,9 @@ static int validate(const tsqbx_geometry_desc *d) {
   for (int64_t i = 0; i < d->n_centers; ++i) {
     if (off[i + 1] < off[i])
       return fail(TSQBX_E_INVALID, "list_offsets decreases at center %lld", (long long)i);
-    if (off[i + 1] - off[i] > INT32_MAX)
-      return fail(TSQBX_E_RANGE, "list of center %lld is longer than 2^31-1", (long long)i);
+    if (off[i + 1] - off[i] > (int64_t(1) << 30) - kRowPad)
+      return fail(TSQBX_E_RANGE, "list of center %lld is longer than 2^30 - %d entries",
+                  (long long)i, kRowPad);
   }
   const int64_t nnz = off[d->n_centers];
   if (nnz > 0 && !d->list_sources) return fail(TSQBX_E_INVALID, "list_sources is NULL");
@@ -309,9 +313,11 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   }
   const int64_t R = (int64_t)row_center.size();
   std::vector<int64_t> row_off(R + 1, 0);
+  // rows padded to a multiple of kRowPad with the zero-strength record N
   for (int64_t r = 0; r < R; ++r) {
     const int32_t c = (int32_t)row_center[r];
-    row_off[r + 1] = row_off[r] + (d->list_offsets[c + 1] - d->list_offsets[c]);
+    const int64_t len = d->list_offsets[c + 1] - d->list_offsets[c];
+    row_off[r + 1] = row_off[r] + (len + kRowPad - 1) / kRowPad * kRowPad;
   }
   const int64_t nnz_dev = row_off[R];
   std::vector<int32_t> idx(nnz_dev);
@@ -321,6 +327,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
     int32_t *dst = idx.data() + row_off[r];
     for (int64_t j = b; j < e; ++j) dst[j - b] = src_rank[d->list_sources[j]];
     std::sort(dst, dst + (e - b));
+    for (int64_t j = e - b; j < row_off[r + 1] - row_off[r]; ++j) dst[j] = (int32_t)N;
   });
 
   std::vector<TargetRec> recs(T);
@@ -335,12 +342,13 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
       x.c[a] = d->centers[3 * c + a];
       x.d[a] = d->targets[3 * t + a] - d->centers[3 * c + a];
     }
+    const int64_t len = d->list_offsets[c + 1] - d->list_offsets[c];
     x.row_begin = row_off[r];
     x.row_len = (int32_t)(row_off[r + 1] - row_off[r]);
     x.out_index = (int32_t)t;
-    pairs += x.row_len;
-    max_list = std::max<int64_t>(max_list, x.row_len);
-    host_row_len[k] = x.row_len;
+    pairs += len;
+    max_list = std::max<int64_t>(max_list, len);
+    host_row_len[k] = len;
   }
 
   std::vector<double4> pos(N), nrm(d->normals ? N : 0);
@@ -373,8 +381,8 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   if (e == hipSuccess && reorder) e = dev_upload(&g->src_perm, perm.data(), N, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->tgt, recs.data(), T, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->idx, idx.data(), nnz_dev, &bytes);
-  if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N, &bytes);
-  if (e == hipSuccess && d->normals) e = dev_upload<double4>(&g->stage.qn, nullptr, N, &bytes);
+  if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N + 1, &bytes);
+  if (e == hipSuccess && d->normals) e = dev_upload<double4>(&g->stage.qn, nullptr, N + 1, &bytes);
   if (e != hipSuccess) {
     free_geometry(g);
     return fail_hip(e, "geometry upload");
@@ -532,7 +540,7 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
   Tuning best;
   double best_t = 1e300;
   const int GU[][2] = {{64, 1}, {64, 2}, {64, 4}, {32, 2}, {16, 2}};
-  const int W[] = {2, 4, 8, 16};
+  const int W[] = {1, 2, 4};
   for (auto &gu : GU)
     for (int w : W)
       for (int remap = 0; remap <= 1; ++remap) {

@@ -26,11 +26,15 @@ struct alignas(64) TargetRec {
 };
 static_assert(sizeof(TargetRec) == 64, "TargetRec layout");
 
+// Device rows are padded to a multiple of this many entries with index N,
+// which names a zero-strength staging record.
+constexpr int kRowPad = 16;
+
 // Per-source staging built for each evaluation: position and strength
 // q = w sigma, and q times the normal (double layer).
 struct SourceStage {
-  double4 *posq = nullptr;  // [N] (x, y, z, q)
-  double4 *qn = nullptr;    // [N] (q nx, q ny, q nz, 0)
+  double4 *posq = nullptr;  // [N + 1] (x, y, z, q); entry N: far away, q = 0
+  double4 *qn = nullptr;    // [N + 1] (q nx, q ny, q nz, 0); entry N: 0
 };
 
 struct Tuning {
@@ -118,7 +122,26 @@ struct PersistentArgs {
   unsigned int *ticket;     // zeroed by launch_reset before each run
 };
 hipError_t launch_reset(unsigned int *ticket, hipStream_t s);
-hipError_t launch_persistent(const PersistentArgs &a, int grid, const Tuning &tn, hipStream_t s);
+
+// Staging of many items in one launch (batched and served paths).
+struct StageItem {         // 64 bytes
+  const double4 *pos_w;
+  const double4 *nrm;
+  const int64_t *perm;
+  const double *sigma;
+  double4 *posq;
+  double4 *qn;
+  int64_t n;
+  int32_t want_dlp;
+  int32_t pad;
+};
+StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
+                          const SourceStage &st);
+hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
+// layer_class: 1 or 2 if every item has that layer mask, else 3; p_all: the
+// order shared by every item, or -1.
+hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all, int grid,
+                             const Tuning &tn, hipStream_t s);
 int persistent_max_grid(int num_cus, const Tuning &tn);
 
 Tuning default_tuning(int p, unsigned layers, int64_t mean_list);

@@ -4,30 +4,30 @@
 // Per pair (target t, center c, listed source y) the kernels evaluate the
 // p-th order target-specific expansion of App. A,
 //   G^(p)(t, y) = 1/(4 pi) sum_{n=0..p} |t-c|^n / |y-c|^{n+1} P_n(cos gamma),
-// and the double-layer kernel nu . grad_y G^(p), through a scaled form of
-// Bonnet's recurrence that needs no division and no angle:
+// and the double-layer kernel nu . grad_y G^(p) (App. A, source gradient),
+// through scaled recurrences that need neither the angle nor a division:
 //
-//   d = y - c, delta = t - c, R^2 = d.d, beta = delta.d / R^2, g2 = |delta|^2 / R^2
-//   b_n = (|delta|/R)^n P_n(cos gamma):  b_0 = 1, b_1 = beta,
-//   (n+1) b_{n+1} = (2n+1) beta b_n - n g2 b_{n-1}
+//   d = y - c, delta = t - c, beta = delta.d / |d|^2, g2 = |delta|^2 / |d|^2,
+//   b_n = (|delta|/|d|)^n P_n(cos gamma),  E_n = (|delta|/|d|)^(n-1) P_n'(cos gamma)
+//   G^(p) = (1/(4 pi |d|)) sum_n b_n
+//   nu . grad_y G^(p) = (1/(4 pi |d|^3)) [ -(nu.d) sum_n (n+1) b_n
+//                                          + (nu.delta - beta nu.d) sum_n E_n ]
 //
-// (Bonnet's (n+1)P_{n+1} = (2n+1)xP_n - nP_{n-1} times (|delta|/R)^{n+1}),
-// so that G^(p) = (1/(4 pi R)) sum_n b_n.  Writing b_n = lam_n e_n with
-// lam_{n+1} = lam_n (2n+1)/(n+1) leaves
-//   e_{n+1} = beta e_n - kap_n g2 e_{n-1},  kap_n = (n/(n+1)) lam_{n-1}/lam_{n+1},
-// two multiplies and one FMA per order, plus one FMA for the sum.
+// (the second line is App. A's gradient with P_n' written through E_n).
+// Bonnet's recurrence times (|delta|/|d|)^(n+1) gives
+//   (n+1) b_{n+1} = (2n+1) beta b_n - n g2 b_{n-1},
+// and the derivative recurrence n P_{n+1}' = (2n+1) x P_n' - (n+1) P_{n-1}'
+//   n E_{n+1} = (2n+1) beta E_n - (n+1) g2 E_{n-1}.
+// Both are rescaled by per-order constants so that one order costs two
+// multiplies and one FMA, plus one FMA for the running sum.  When the double
+// layer is requested only the E_n are generated; the sums of b_n and
+// (n+1) b_n then follow in closed form (see pair_terms), so the single and
+// double layer together cost one recurrence.
 //
-// Double layer (App. A, gradient with respect to the source): with
-// E_n = R |delta|^{n-1} P_n'(x) / R^n, the derivative recurrence
-// P_{n+1}' = x P_n' + (n+1) P_n becomes E_{n+1} = beta E_n + (n+1) b_n, and
-//   nu . grad_y G^(p) = (1/(4 pi R^3)) [ -(nu.d) S1 + (nu.delta - beta nu.d) S2 ],
-//   S1 = sum_{n<=p} (n+1) b_n = (1 - beta) S2 + E_{p+1},  S2 = sum_{n<=p} E_n.
-// (The identity for S1 follows from summing the E recurrence.)
-//
-// 1/R comes from v_rsq_f64 refined by two Newton-Raphson steps on x^{-1/2}.
-// Sums within a target run in a fixed order (lane-strided over the list,
-// then a fixed xor-butterfly across the lanes of the group), so a target's
-// result depends only on its list and the group width.
+// 1/|d| comes from v_rsq_f64 and a second-order correction.  Sums within a
+// target run in a fixed order (lane-strided over the list, then a fixed
+// xor-butterfly across the lanes of the group), so a target's result depends
+// only on its list and the group width.
 #include "tsqbx_internal.h"
 
 namespace tsqbx {
@@ -37,113 +37,245 @@ constexpr double kInv4Pi = 1.0 / (4.0 * 3.14159265358979323846);
 
 // ---- recurrence constants (compile-time; a __constant__ copy serves the
 // runtime-order kernels, with identical values) ------------------------------
+// single layer: b_n = lam_n e_n, lam_{n+1} = lam_n (2n+1)/(n+1),
+//   e_{n+1} = beta e_n - kap_n g2 e_{n-1},  kap_n = (n/(n+1)) lam_{n-1}/lam_{n+1}
 constexpr double lam_c(int n) {
   double l = 1.0;
   for (int k = 1; k <= n; ++k) l = l * double(2 * k - 1) / double(k);
   return l;
 }
 constexpr double kap_c(int n) { return (double(n) / double(n + 1)) * lam_c(n - 1) / lam_c(n + 1); }
-constexpr double cn_c(int n) { return double(n + 1) * lam_c(n); }
+// double layer: E_n = mu_n F_n, mu_1 = 1, mu_{n+1} = mu_n (2n+1)/n,
+//   F_{n+1} = beta F_n - kapd_n g2 F_{n-1},  kapd_n = ((n+1)/n) mu_{n-1}/mu_{n+1}
+constexpr double mu_c(int n) {
+  double m = 1.0;
+  for (int k = 1; k < n; ++k) m = m * double(2 * k + 1) / double(k);
+  return m;
+}
+constexpr double kapd_c(int n) { return (double(n + 1) / double(n)) * mu_c(n - 1) / mu_c(n + 1); }
 
 struct CoefTable {
-  double lam[TSQBX_P_MAX + 2];
-  double kap[TSQBX_P_MAX + 2];
-  double cn[TSQBX_P_MAX + 2];
+  double lam[TSQBX_P_MAX + 3];
+  double kap[TSQBX_P_MAX + 3];
+  double mu[TSQBX_P_MAX + 3];
+  double kapd[TSQBX_P_MAX + 3];
 };
 constexpr CoefTable make_coef_table() {
   CoefTable t{};
-  for (int n = 0; n < TSQBX_P_MAX + 2; ++n) {
+  for (int n = 0; n < TSQBX_P_MAX + 3; ++n) {
     t.lam[n] = lam_c(n);
     t.kap[n] = n >= 1 ? kap_c(n) : 0.0;
-    t.cn[n] = cn_c(n);
+    t.mu[n] = mu_c(n);
+    t.kapd[n] = n >= 2 ? kapd_c(n) : 0.0;
   }
   return t;
 }
 __constant__ CoefTable d_coef = make_coef_table();
 
-// 1/sqrt(x) for normal x > 0: hardware estimate, then two Newton-Raphson
-// steps y <- y (3 - x y^2)/2; the second in residual form for ~1 ulp.
+// 1/sqrt(x) for normal x > 0: the hardware estimate y0 (relative error about
+// 2^-24) corrected by the second-order series of (1 - h)^(-1/2),
+// h = 1 - x y0^2: y = y0 (1 + h/2 + 3h^2/8); the dropped term is ~h^3.
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double hx = 0.5 * x;
-  y = y * fma(-hx, y * y, 1.5);
-  double e = x * y;
-  double h = fma(-e, y, 1.0);
-  return fma(0.5 * y, h, y);
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double h = fma(-(x * y0), y0, 1.0);
+  return fma(y0 * h, fma(h, 0.375, 0.5), y0);
 }
 
-// Orders 1..P-1 of the scaled recurrence, fully unrolled.
-template <int P, int L, int N>
-__device__ __forceinline__ void legendre_steps(double beta, double g2, double em1, double e,
-                                               double &S0, double &E, double &S2) {
+// State of U independent pairs advanced in lockstep, so that the U
+// dependency chains interleave in the instruction stream.
+template <int U>
+struct PairState {
+  double beta[U], g2[U];  // per-pair recurrence coefficients
+  double fm1[U], f[U];    // two consecutive scaled terms
+  double S[U];            // running sum
+};
+
+// Single layer only: e_{n+1} for n = N..P-1 and S += lam_{n+1} e_{n+1}.
+template <int P, int U, int N>
+__device__ __forceinline__ void slp_steps(PairState<U> &st) {
   if constexpr (N < P) {
     constexpr double kap = kap_c(N);
     constexpr double lam1 = lam_c(N + 1);
-    constexpr double c1 = cn_c(N + 1);
-    double en1 = fma(-kap, g2 * em1, beta * e);
-    if constexpr (L & 1) S0 = fma(lam1, en1, S0);
-    if constexpr (L & 2) {
-      S2 = S2 + E;
-      E = fma(beta, E, c1 * en1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double en1 = fma(-kap, st.g2[u] * st.fm1[u], st.beta[u] * st.f[u]);
+      st.S[u] = fma(lam1, en1, st.S[u]);
+      st.fm1[u] = st.f[u];
+      st.f[u] = en1;
     }
-    legendre_steps<P, L, N + 1>(beta, g2, e, en1, S0, E, S2);
+    slp_steps<P, U, N + 1>(st);
   }
 }
 
-// The same orders for a run-time p (constants from the table).
-template <int L>
-__device__ __forceinline__ void legendre_steps_rt(int p, double beta, double g2, double em1,
-                                                  double e, double &S0, double &E, double &S2) {
+// Derivative terms: F_{n+1} for n = N..P and S += mu_{n+1} F_{n+1} while
+// n + 1 <= P; leaves (fm1, f) = (F_P, F_{P+1}).
+template <int P, int U, int N>
+__device__ __forceinline__ void dlp_steps(PairState<U> &st) {
+  if constexpr (N <= P) {
+    constexpr double kap = kapd_c(N);
+    constexpr double mu1 = mu_c(N + 1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double fn1 = fma(-kap, st.g2[u] * st.fm1[u], st.beta[u] * st.f[u]);
+      if constexpr (N + 1 <= P) st.S[u] = fma(mu1, fn1, st.S[u]);
+      st.fm1[u] = st.f[u];
+      st.f[u] = fn1;
+    }
+    dlp_steps<P, U, N + 1>(st);
+  }
+}
+
+// The same steps for a run-time order p (constants from the table).
+template <int U>
+__device__ __forceinline__ void slp_steps_rt(int p, PairState<U> &st) {
   for (int n = 1; n < p; ++n) {
-    double en1 = fma(-d_coef.kap[n], g2 * em1, beta * e);
-    if constexpr (L & 1) S0 = fma(d_coef.lam[n + 1], en1, S0);
-    if constexpr (L & 2) {
-      S2 = S2 + E;
-      E = fma(beta, E, d_coef.cn[n + 1] * en1);
+    const double kap = d_coef.kap[n], lam1 = d_coef.lam[n + 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double en1 = fma(-kap, st.g2[u] * st.fm1[u], st.beta[u] * st.f[u]);
+      st.S[u] = fma(lam1, en1, st.S[u]);
+      st.fm1[u] = st.f[u];
+      st.f[u] = en1;
     }
-    em1 = e;
-    e = en1;
   }
 }
 
-// One pair.  (dx, dy, dz) = y - c; (tx, ty, tz) = t - c; rho2 = |t - c|^2;
-// q = w sigma; (nx, ny, nz) = q nu.  cs, cd: contributions without 1/(4 pi).
-template <int P, int L>
-__device__ __forceinline__ void pair_terms(int p_rt, double dx, double dy, double dz, double tx,
-                                           double ty, double tz, double rho2, double q, double nx,
-                                           double ny, double nz, double &cs, double &cd) {
-  double R2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  double dd = fma(tz, dz, fma(ty, dy, tx * dx));
-  double rinv = rsqrt_nr(R2);
-  double inv = rinv * rinv;
-  double beta = dd * inv;
-  double g2 = rho2 * inv;
-  const int p = P >= 0 ? P : p_rt;
-  double S0 = 1.0;  // sum_n lam_n e_n
-  double S2 = 0.0;  // sum_{n<=order} E_n
-  double E = 1.0;   // E_{order+1}
-  if (p >= 1) {
-    S0 = 1.0 + beta;
-    S2 = 1.0;
-    E = 3.0 * beta;
-    if constexpr (P >= 0)
-      legendre_steps<P, L, 1>(beta, g2, 1.0, beta, S0, E, S2);
-    else
-      legendre_steps_rt<L>(p, beta, g2, 1.0, beta, S0, E, S2);
+template <int U>
+__device__ __forceinline__ void dlp_steps_rt(int p, PairState<U> &st) {
+  for (int n = 2; n <= p; ++n) {
+    const double kap = d_coef.kapd[n], mu1 = d_coef.mu[n + 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double fn1 = fma(-kap, st.g2[u] * st.fm1[u], st.beta[u] * st.f[u]);
+      if (n + 1 <= p) st.S[u] = fma(mu1, fn1, st.S[u]);
+      st.fm1[u] = st.f[u];
+      st.f[u] = fn1;
+    }
   }
-  if constexpr (L & 1) cs = (q * rinv) * S0;
+}
+
+// Loads through global-address-space pointers: pointers that reach a kernel
+// through a device-side table would otherwise be treated as generic (flat).
+#define TSQBX_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ uint32_t load_idx(const int32_t *__restrict__ row, uint32_t j) {
+  const TSQBX_GLOBAL char *base = (const TSQBX_GLOBAL char *)row;
+  return *(const TSQBX_GLOBAL uint32_t *)(base + (size_t)(j * 4u));
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double4 load4(const double4 *__restrict__ base, uint32_t i) {
+  const TSQBX_GLOBAL char *b = (const TSQBX_GLOBAL char *)base;
+  const f64x4 v = *(const TSQBX_GLOBAL f64x4 *)(b + (size_t)(i * 32u));
+  return make_double4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ TargetRec load_target(const TSQBX_GLOBAL TargetRec *p) {
+  TargetRec t;
+  for (int a = 0; a < 3; ++a) {
+    t.c[a] = p->c[a];
+    t.d[a] = p->d[a];
+  }
+  t.row_begin = p->row_begin;
+  t.row_len = p->row_len;
+  t.out_index = p->out_index;
+  return t;
+}
+
+// U pairs of one target, added to acc_s / acc_d in the order u = 0..U-1.
+// Source records come from posq / qn at indices s[u] (q = w sigma and q nu);
+// (cx, cy, cz) = c; (tx, ty, tz) = t - c; rho2 = |t - c|^2.  The sums leave
+// out the factor 1/(4 pi).
+//
+// Single layer alone: S = sum_n b_n from the Legendre recurrence.
+// With the double layer, only the derivative terms E_n = (|delta|/R)^{n-1}
+// P_n'(x) are generated, by the three-term recurrence
+//   n P_{n+1}' = (2n+1) x P_n' - (n+1) P_{n-1}',
+// giving S2 = sum_{n<=p} E_n, E_p and E_{p+1}.  Summing
+// P_{n+1}' = x P_n' + (n+1) P_n and P_{n+1}' - P_{n-1}' = (2n+1) P_n over
+// n = 0..p yields, without division,
+//   sum_n (n+1) b_n = (1 - beta) S2 + E_{p+1}
+//   sum_n b_n       = (1 - 2 beta + g2) S2 + E_{p+1} - g2 E_p,
+// and the double layer bracket becomes (nu.delta) S2 - (nu.d)(S2 + E_{p+1}).
+template <int P, int L, int U>
+__device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
+                                           const double4 *__restrict__ posq,
+                                           const double4 *__restrict__ qn, double cx, double cy,
+                                           double cz, double tx, double ty, double tz, double rho2,
+                                           double &acc_s, double &acc_d) {
+  double4 a[U], b[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) a[u] = load4(posq, s[u]);
   if constexpr (L & 2) {
-    double S1 = fma(1.0 - beta, S2, E);
-    double nd = fma(nz, dz, fma(ny, dy, nx * dx));
-    double nt = fma(nz, tz, fma(ny, ty, nx * tx));
-    double br = fma(-nd, beta, nt);
-    double val = fma(br, S2, -nd * S1);
-    cd = val * (rinv * inv);
+#pragma unroll
+    for (int u = 0; u < U; ++u) b[u] = load4(qn, s[u]);
+  }
+  const int p = P >= 0 ? P : p_rt;
+  PairState<U> st;
+  double dx[U], dy[U], dz[U], rinv[U], inv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    dx[u] = a[u].x - cx;
+    dy[u] = a[u].y - cy;
+    dz[u] = a[u].z - cz;
+    const double R2 = fma(dz[u], dz[u], fma(dy[u], dy[u], dx[u] * dx[u]));
+    const double dd = fma(tz, dz[u], fma(ty, dy[u], tx * dx[u]));
+    rinv[u] = rsqrt_nr(R2);
+    inv[u] = rinv[u] * rinv[u];
+    st.beta[u] = dd * inv[u];
+    st.g2[u] = rho2 * inv[u];
+  }
+  if constexpr (L == 1) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      st.fm1[u] = 1.0;
+      st.f[u] = st.beta[u];
+      st.S[u] = p >= 1 ? 1.0 + st.beta[u] : 1.0;
+    }
+    if constexpr (P >= 0)
+      slp_steps<P, U, 1>(st);
+    else
+      slp_steps_rt<U>(p, st);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc_s = fma(a[u].w * rinv[u], st.S[u], acc_s);
+  } else {
+    // (fm1, f) = (F_0, F_1) for p = 0, else (F_1, F_2) = (1, beta)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      st.fm1[u] = p >= 1 ? 1.0 : 0.0;
+      st.f[u] = p >= 1 ? st.beta[u] : 1.0;
+      st.S[u] = p >= 2 ? fma(3.0, st.beta[u], 1.0) : (p == 1 ? 1.0 : 0.0);
+    }
+    if constexpr (P >= 0)
+      dlp_steps<P, U, 2>(st);
+    else
+      dlp_steps_rt<U>(p, st);
+    const double mu_p1 = P >= 0 ? mu_c(P + 1) : d_coef.mu[p + 1];
+    const double mu_p = P >= 0 ? (P >= 1 ? mu_c(P) : 0.0) : (p >= 1 ? d_coef.mu[p] : 0.0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double S2 = st.S[u];
+      const double Ep1 = mu_p1 * st.f[u];
+      if constexpr (L & 1) {
+        const double Ep = mu_p * st.fm1[u];
+        const double w = fma(-2.0, st.beta[u], 1.0 + st.g2[u]);
+        const double S0 = fma(w, S2, fma(-st.g2[u], Ep, Ep1));
+        acc_s = fma(a[u].w * rinv[u], S0, acc_s);
+      }
+      const double nd = fma(b[u].z, dz[u], fma(b[u].y, dy[u], b[u].x * dx[u]));
+      const double nt = fma(b[u].z, tz, fma(b[u].y, ty, b[u].x * tx));
+      const double val = fma(nt, S2, -nd * (S2 + Ep1));
+      acc_d = fma(val, rinv[u] * inv[u], acc_d);
+    }
   }
 }
 
-// Sum over one target's list by the G lanes of its group (lane gl of G),
-// U independent pairs in flight per lane, accumulated in list order.
+// Sum over one target's list by the G lanes of its group (lane gl of G).
+// Lane gl takes the entries gl, gl + G, gl + 2G, ... in list order and adds
+// them in that order: U at a time over the full chunks of G*U entries, then
+// one at a time over the rest.  The chunk loop's bounds are the same for the
+// whole group, so only the tail runs with idle lanes.
 template <int P, int L, int G, int U>
 __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr,
                                            const int32_t *__restrict__ idx,
@@ -153,27 +285,33 @@ __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr
   const double cx = tr.c[0], cy = tr.c[1], cz = tr.c[2];
   const double tx = tr.d[0], ty = tr.d[1], tz = tr.d[2];
   const double rho2 = fma(tz, tz, fma(ty, ty, tx * tx));
-  const int32_t *row = idx + tr.row_begin;
+  const int32_t *__restrict__ row = idx + tr.row_begin;
   const int len = tr.row_len;
   double acc_s = 0.0, acc_d = 0.0;
-  for (int j0 = gl; j0 < len; j0 += G * U) {
-    double cs[U], cd[U];
-    bool ok[U];
+  int c0 = 0;
+  if constexpr (U > 1) {
+    const int full = len - len % (G * U);
+    uint32_t s[U];
+    if (full > 0) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      int j = j0 + u * G;
-      ok[u] = j < len;
-      int s = row[ok[u] ? j : j0];
-      double4 a = posq[s];
-      double4 b = make_double4(0.0, 0.0, 0.0, 0.0);
-      if constexpr (L & 2) b = qn[s];
-      pair_terms<P, L>(p_rt, a.x - cx, a.y - cy, a.z - cz, tx, ty, tz, rho2, a.w, b.x, b.y, b.z,
-                       cs[u], cd[u]);
+      for (int u = 0; u < U; ++u) s[u] = load_idx(row, (uint32_t)(gl + u * G));
     }
+    for (; c0 < full; c0 += G * U) {
+      // indices of the next chunk (clamped into the row; unused past its end)
+      uint32_t sn[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if constexpr (L & 1) acc_s += ok[u] ? cs[u] : 0.0;
-      if constexpr (L & 2) acc_d += ok[u] ? cd[u] : 0.0;
+      for (int u = 0; u < U; ++u)
+        sn[u] = load_idx(row, (uint32_t)min(c0 + G * U + gl + u * G, len - 1));
+      pair_terms<P, L, U>(p_rt, s, posq, qn, cx, cy, cz, tx, ty, tz, rho2, acc_s, acc_d);
+#pragma unroll
+      for (int u = 0; u < U; ++u) s[u] = sn[u];
+    }
+  }
+  for (; c0 < len; c0 += G) {
+    const int j = c0 + gl;
+    if (j < len) {
+      const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
+      pair_terms<P, L, 1>(p_rt, s1, posq, qn, cx, cy, cz, tx, ty, tz, rho2, acc_s, acc_d);
     }
   }
 #pragma unroll
@@ -185,10 +323,9 @@ __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr
   out_d = acc_d * kInv4Pi;
 }
 
-template <int L>
-__device__ __forceinline__ void store_out(const TargetRec &tr, double vs, double vd,
-                                          double *__restrict__ out_s, double *__restrict__ out_d,
-                                          int accumulate) {
+template <int L, class Ptr>
+__device__ __forceinline__ void store_out(const TargetRec &tr, double vs, double vd, Ptr out_s,
+                                          Ptr out_d, int accumulate) {
   const int o = tr.out_index;
   if constexpr (L & 1) out_s[o] = accumulate ? out_s[o] + vs : vs;
   if constexpr (L & 2) out_d[o] = accumulate ? out_d[o] + vd : vd;
@@ -205,7 +342,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 template <int P, int L, int G, int U>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(256)
 k_eval(const TargetRec *__restrict__ tgt, int64_t n_targets, const int32_t *__restrict__ idx,
        const double4 *__restrict__ posq, const double4 *__restrict__ qn,
        double *__restrict__ out_s, double *__restrict__ out_d, int accumulate, int p_rt,
@@ -225,18 +362,64 @@ k_eval(const TargetRec *__restrict__ tgt, int64_t n_targets, const int32_t *__re
 }
 
 // Staging: q = w sigma in device source order, and q nu for the double layer.
+// Entry n is the padding record: finite and far from every center, q = 0, so
+// a padded list entry contributes exactly zero.
 __global__ void __launch_bounds__(256)
 k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict__ nrm,
         const int64_t *__restrict__ perm, const double *__restrict__ sigma,
         double4 *__restrict__ posq, double4 *__restrict__ qn, int want_dlp) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
        i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == n) {
+      posq[n] = make_double4(1e100, 1e100, 1e100, 0.0);
+      if (want_dlp) qn[n] = make_double4(0.0, 0.0, 0.0, 0.0);
+      continue;
+    }
     const double4 a = pos_w[i];
     const double q = a.w * sigma[perm ? perm[i] : i];
     posq[i] = make_double4(a.x, a.y, a.z, q);
     if (want_dlp) {
       const double4 v = nrm[i];
       qn[i] = make_double4(q * v.x, q * v.y, q * v.z, 0.0);
+    }
+  }
+}
+
+// The same staging for many items: blockIdx.y selects the item.
+__global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict__ items) {
+  const TSQBX_GLOBAL StageItem *gi = (const TSQBX_GLOBAL StageItem *)items + blockIdx.y;
+  const int64_t n = gi->n;
+  const int want_dlp = gi->want_dlp;
+  const TSQBX_GLOBAL double *pw = (const TSQBX_GLOBAL double *)gi->pos_w;  // (x, y, z, w)
+  const TSQBX_GLOBAL double *nv = (const TSQBX_GLOBAL double *)gi->nrm;    // (nx, ny, nz, 0)
+  const TSQBX_GLOBAL int64_t *perm = (const TSQBX_GLOBAL int64_t *)gi->perm;
+  const TSQBX_GLOBAL double *sigma = (const TSQBX_GLOBAL double *)gi->sigma;
+  TSQBX_GLOBAL double *posq = (TSQBX_GLOBAL double *)gi->posq;
+  TSQBX_GLOBAL double *qn = (TSQBX_GLOBAL double *)gi->qn;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // entry n: the padding record
+    double x = 1e100, y = 1e100, z = 1e100, q = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
+    if (i < n) {
+      x = pw[4 * i];
+      y = pw[4 * i + 1];
+      z = pw[4 * i + 2];
+      q = pw[4 * i + 3] * sigma[perm ? perm[i] : i];
+      if (want_dlp) {
+        nx = q * nv[4 * i];
+        ny = q * nv[4 * i + 1];
+        nz = q * nv[4 * i + 2];
+      }
+    }
+    posq[4 * i] = x;
+    posq[4 * i + 1] = y;
+    posq[4 * i + 2] = z;
+    posq[4 * i + 3] = q;
+    if (want_dlp) {
+      qn[4 * i] = nx;
+      qn[4 * i + 1] = ny;
+      qn[4 * i + 2] = nz;
+      qn[4 * i + 3] = 0.0;
     }
   }
 }
@@ -248,31 +431,43 @@ k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict_
 template <int P, int L, int G, int U>
 __device__ __forceinline__ void unit_body(const WorkItem &it, int first, int count, int lane) {
   constexpr int TPW = 64 / G;
+  const TSQBX_GLOBAL TargetRec *tgt = (const TSQBX_GLOBAL TargetRec *)it.tgt;
   for (int k = 0; k < count; k += TPW) {
-    const int slot = k + lane / G;
+    int slot = k + lane / G;
+    if constexpr (G == 64) slot = __builtin_amdgcn_readfirstlane(slot);
     if (slot >= count) break;  // whole groups leave together
-    const TargetRec tr = it.tgt[first + slot];
+    const TargetRec tr = load_target(tgt + first + slot);
     double vs = 0.0, vd = 0.0;
     target_sum<P, L, G, U>(it.p, lane % G, tr, it.idx, it.posq, it.qn, vs, vd);
-    if (lane % G == 0) store_out<L>(tr, vs, vd, it.out_s, it.out_d, it.accumulate);
+    if (lane % G == 0)
+      store_out<L>(tr, vs, vd, (TSQBX_GLOBAL double *)it.out_s, (TSQBX_GLOBAL double *)it.out_d,
+                   it.accumulate);
   }
 }
 
-template <int L, int G, int U>
+// PF >= 0: every item has order PF.  PF < 0: switch over the compiled
+// orders, with the remaining orders on the run-time loop (one pair in flight,
+// which keeps the kernel's register budget that of the compiled orders).
+template <int L, int PF, int G, int U>
 __device__ __forceinline__ void unit_dispatch_p(const WorkItem &it, int first, int count,
                                                 int lane) {
-  switch (it.p) {
-    case 4: unit_body<4, L, G, U>(it, first, count, lane); break;
-    case 8: unit_body<8, L, G, U>(it, first, count, lane); break;
-    case 12: unit_body<12, L, G, U>(it, first, count, lane); break;
-    case 16: unit_body<16, L, G, U>(it, first, count, lane); break;
-    case 24: unit_body<24, L, G, U>(it, first, count, lane); break;
-    default: unit_body<-1, L, G, U>(it, first, count, lane); break;
+  if constexpr (PF >= 0) {
+    unit_body<PF, L, G, U>(it, first, count, lane);
+  } else {
+    switch (it.p) {
+      case 4: unit_body<4, L, G, U>(it, first, count, lane); break;
+      case 8: unit_body<8, L, G, U>(it, first, count, lane); break;
+      case 12: unit_body<12, L, G, U>(it, first, count, lane); break;
+      case 16: unit_body<16, L, G, U>(it, first, count, lane); break;
+      case 24: unit_body<24, L, G, U>(it, first, count, lane); break;
+      default: unit_body<-1, L, G, 1>(it, first, count, lane); break;
+    }
   }
 }
 
-template <int G, int U>
-__global__ void __launch_bounds__(1024) k_persistent(PersistentArgs a) {
+// LC = layer class: 1 or 2 (every item has that mask) or 3 (any mask).
+template <int LC, int PF, int G, int U>
+__global__ void __launch_bounds__(256) k_persistent(PersistentArgs a) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned int u = 0;
@@ -281,10 +476,14 @@ __global__ void __launch_bounds__(1024) k_persistent(PersistentArgs a) {
     if ((int64_t)u >= a.n_units) break;
     const WorkUnit wu = a.units[u];
     const WorkItem it = a.items[wu.item];
-    switch (it.layers) {
-      case 1: unit_dispatch_p<1, G, U>(it, wu.first, wu.count, lane); break;
-      case 2: unit_dispatch_p<2, G, U>(it, wu.first, wu.count, lane); break;
-      default: unit_dispatch_p<3, G, U>(it, wu.first, wu.count, lane); break;
+    if constexpr (LC == 3) {
+      switch (it.layers) {
+        case 1: unit_dispatch_p<1, PF, G, U>(it, wu.first, wu.count, lane); break;
+        case 2: unit_dispatch_p<2, PF, G, U>(it, wu.first, wu.count, lane); break;
+        default: unit_dispatch_p<3, PF, G, U>(it, wu.first, wu.count, lane); break;
+      }
+    } else {
+      unit_dispatch_p<LC, PF, G, U>(it, wu.first, wu.count, lane);
     }
   }
 }
@@ -336,7 +535,7 @@ hipError_t launch_l(const tsqbx_geometry *g, int p, unsigned layers, const Sourc
 
 bool tuning_supported(const Tuning &tn) {
   const int w = tn.waves_per_block;
-  if (!(w == 1 || w == 2 || w == 4 || w == 8 || w == 16)) return false;
+  if (!(w == 1 || w == 2 || w == 4)) return false;
   if (!(tn.xcd_remap == 0 || tn.xcd_remap == 1)) return false;
   const int G = tn.group_lanes, U = tn.unroll;
   return (G == 64 && (U == 1 || U == 2 || U == 4)) || (G == 32 && U == 2) || (G == 16 && U == 2);
@@ -357,10 +556,34 @@ hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const So
 hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
                         const SourceStage &st, hipStream_t s) {
   const int64_t n = g->n_sources;
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  if (n < 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 1 + 255) / 256, 65536);
   hipLaunchKernelGGL(k_stage, dim3((unsigned)blocks), dim3(256), 0, s, n, g->src_pos, g->src_nrm,
                      g->src_perm, d_sigma, st.posq, st.qn, (layers & TSQBX_DLP) ? 1 : 0);
+  return hipGetLastError();
+}
+
+StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
+                          const SourceStage &st) {
+  StageItem it{};
+  it.pos_w = g->src_pos;
+  it.nrm = g->src_nrm;
+  it.perm = g->src_perm;
+  it.sigma = d_sigma;
+  it.posq = st.posq;
+  it.qn = st.qn;
+  it.n = g->n_sources;
+  it.want_dlp = (layers & TSQBX_DLP) ? 1 : 0;
+  return it;
+}
+
+hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n,
+                              hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (n_items > 65535) return hipErrorInvalidValue;
+  const int64_t bx = std::min<int64_t>((max_n + 1 + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_stage_multi, dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)n_items),
+                     dim3(256), 0, s, d_items);
   return hipGetLastError();
 }
 
@@ -375,21 +598,45 @@ int persistent_max_grid(int num_cus, const Tuning &tn) {
   return std::max(1, waves / tn.waves_per_block);
 }
 
-hipError_t launch_persistent(const PersistentArgs &a, int grid, const Tuning &tn, hipStream_t s) {
-  if (!tuning_supported(tn) || grid <= 0) return hipErrorInvalidValue;
+namespace {
+template <int LC, int PF>
+hipError_t launch_persistent_lp(const PersistentArgs &a, int grid, const Tuning &tn,
+                                hipStream_t s) {
   const dim3 block(64 * tn.waves_per_block);
   const int G = tn.group_lanes, U = tn.unroll;
   if (G == 64 && U == 1)
-    hipLaunchKernelGGL((k_persistent<64, 1>), dim3(grid), block, 0, s, a);
-  else if (G == 64 && U == 2)
-    hipLaunchKernelGGL((k_persistent<64, 2>), dim3(grid), block, 0, s, a);
-  else if (G == 64 && U == 4)
-    hipLaunchKernelGGL((k_persistent<64, 4>), dim3(grid), block, 0, s, a);
-  else if (G == 32 && U == 2)
-    hipLaunchKernelGGL((k_persistent<32, 2>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((k_persistent<LC, PF, 64, 1>), dim3(grid), block, 0, s, a);
+  else if (G == 64)
+    hipLaunchKernelGGL((k_persistent<LC, PF, 64, 2>), dim3(grid), block, 0, s, a);
+  else if (G == 32)
+    hipLaunchKernelGGL((k_persistent<LC, PF, 32, 2>), dim3(grid), block, 0, s, a);
   else
-    hipLaunchKernelGGL((k_persistent<16, 2>), dim3(grid), block, 0, s, a);
+    hipLaunchKernelGGL((k_persistent<LC, PF, 16, 2>), dim3(grid), block, 0, s, a);
   return hipGetLastError();
+}
+
+template <int LC>
+hipError_t launch_persistent_l(const PersistentArgs &a, int p_all, int grid, const Tuning &tn,
+                               hipStream_t s) {
+  switch (p_all) {
+    case 4: return launch_persistent_lp<LC, 4>(a, grid, tn, s);
+    case 8: return launch_persistent_lp<LC, 8>(a, grid, tn, s);
+    case 12: return launch_persistent_lp<LC, 12>(a, grid, tn, s);
+    case 16: return launch_persistent_lp<LC, 16>(a, grid, tn, s);
+    case 24: return launch_persistent_lp<LC, 24>(a, grid, tn, s);
+    default: return launch_persistent_lp<LC, -1>(a, grid, tn, s);
+  }
+}
+}  // namespace
+
+hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all, int grid,
+                             const Tuning &tn, hipStream_t s) {
+  if (!tuning_supported(tn) || grid <= 0 || tn.waves_per_block > 4) return hipErrorInvalidValue;
+  switch (layer_class) {
+    case 1: return launch_persistent_l<1>(a, p_all, grid, tn, s);
+    case 2: return launch_persistent_l<2>(a, p_all, grid, tn, s);
+    default: return launch_persistent_l<3>(a, p_all, grid, tn, s);
+  }
 }
 
 }  // namespace tsqbx

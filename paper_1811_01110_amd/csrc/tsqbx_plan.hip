@@ -24,10 +24,14 @@ struct tsqbx_plan {
   std::vector<SourceStage> stages;
   WorkItem *d_items = nullptr;
   WorkUnit *d_units = nullptr;
+  StageItem *d_stage = nullptr;  // staging of every item, one launch
+  int64_t max_sources = 0;
   unsigned int *d_ticket = nullptr;
   int64_t n_units = 0;
   int64_t pairs = 0, pair_terms = 0;
   int grid = 0;
+  unsigned layer_class = 3;  // 1 or 2 when every item has that mask
+  int p_all = -1;            // the order shared by every item, or -1
   Tuning tn;
   size_t device_bytes = 0;
   hipStream_t cap_stream = nullptr;
@@ -60,6 +64,7 @@ void free_plan(tsqbx_plan *pl) {
     if (s.qn) (void)hipFree(s.qn);
   }
   if (pl->d_items) (void)hipFree(pl->d_items);
+  if (pl->d_stage) (void)hipFree(pl->d_stage);
   if (pl->d_units) (void)hipFree(pl->d_units);
   if (pl->d_ticket) (void)hipFree(pl->d_ticket);
   delete pl;
@@ -83,7 +88,7 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (!ctx || !out || n_items < 0 || (n_items > 0 && !items))
     return fail(TSQBX_E_INVALID, "plan_create: ctx, out or items is NULL, or n_items < 0");
   *out = nullptr;
-  if (n_items > INT32_MAX) return fail(TSQBX_E_RANGE, "too many items");
+  if (n_items > 65535) return fail(TSQBX_E_RANGE, "a plan holds at most 65535 items");
   for (int64_t i = 0; i < n_items; ++i) {
     const tsqbx_item &it = items[i];
     if (!it.geom) return fail(TSQBX_E_INVALID, "item %lld: geometry is NULL", (long long)i);
@@ -109,7 +114,13 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   int64_t tot_pairs = 0, tot_targets = 0;
   int pmax = 0;
   unsigned lay_all = 0;
+  if (!pl->items.empty()) {
+    pl->layer_class = pl->items[0].layers;
+    pl->p_all = pl->items[0].p;
+  }
   for (auto &it : pl->items) {
+    if (it.layers != pl->layer_class) pl->layer_class = 3;
+    if (it.p != pl->p_all) pl->p_all = -1;
     tot_pairs += it.geom->pairs;
     tot_targets += it.geom->n_targets;
     pmax = std::max(pmax, it.p);
@@ -119,7 +130,8 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   }
   const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
   pl->tn = lookup_tuning(ctx, pmax, lay_all ? lay_all : 1u, mean_list);
-  if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent body holds every (p, layers) path
+  if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent kernels keep two pairs in flight
+  if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
   if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, 3u, mean_list);
   const int TPW = 64 / pl->tn.group_lanes;
 
@@ -166,19 +178,20 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
 
   // per-item staging and the device copies of items and units
   std::vector<WorkItem> witems(n_items);
+  std::vector<StageItem> sitems(n_items);
   hipError_t e = hipSuccess;
   pl->stages.resize(n_items);
   for (int64_t i = 0; i < n_items && e == hipSuccess; ++i) {
     const tsqbx_item &it = pl->items[i];
-    const size_t N = (size_t)it.geom->n_sources;
-    if (N) {
-      e = hipMalloc((void **)&pl->stages[i].posq, N * sizeof(double4));
-      pl->device_bytes += N * sizeof(double4);
-      if (e == hipSuccess && (it.layers & TSQBX_DLP)) {
-        e = hipMalloc((void **)&pl->stages[i].qn, N * sizeof(double4));
-        pl->device_bytes += N * sizeof(double4);
-      }
+    const size_t N1 = (size_t)it.geom->n_sources + 1;  // + the padding record
+    e = hipMalloc((void **)&pl->stages[i].posq, N1 * sizeof(double4));
+    pl->device_bytes += N1 * sizeof(double4);
+    if (e == hipSuccess && (it.layers & TSQBX_DLP)) {
+      e = hipMalloc((void **)&pl->stages[i].qn, N1 * sizeof(double4));
+      pl->device_bytes += N1 * sizeof(double4);
     }
+    sitems[i] = make_stage_item(it.geom, it.d_sigma, it.layers, pl->stages[i]);
+    pl->max_sources = std::max<int64_t>(pl->max_sources, it.geom->n_sources);
     WorkItem &w = witems[i];
     w = WorkItem{};
     w.tgt = it.geom->tgt;
@@ -194,13 +207,17 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_items, n_items * sizeof(WorkItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_items, witems.data(), n_items * sizeof(WorkItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_stage, n_items * sizeof(StageItem));
+  if (e == hipSuccess && n_items)
+    e = hipMemcpy(pl->d_stage, sitems.data(), n_items * sizeof(StageItem), hipMemcpyHostToDevice);
   if (e == hipSuccess && pl->n_units)
     e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
   if (e == hipSuccess && pl->n_units)
     e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void **)&pl->d_ticket, sizeof(unsigned int));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
-  pl->device_bytes += n_items * sizeof(WorkItem) + units.size() * sizeof(WorkUnit) + sizeof(unsigned);
+  pl->device_bytes += n_items * (sizeof(WorkItem) + sizeof(StageItem)) +
+                      units.size() * sizeof(WorkUnit) + sizeof(unsigned);
   if (e != hipSuccess) {
     free_plan(pl);
     return fail_hip(e, "plan setup");
@@ -214,17 +231,15 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
   Guard dg(pl->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   if (!pl->exec) {
-    // capture: staging for every item, ticket reset (a kernel, not a memset
-    // node), then the persistent kernel
+    // capture: staging of every item (one kernel), ticket reset (a kernel,
+    // not a memset node), then the persistent kernel
     hipStream_t cs = pl->cap_stream;
     TSQBX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (size_t i = 0; i < pl->items.size() && e == hipSuccess; ++i)
-      e = launch_stage(pl->items[i].geom, pl->items[i].d_sigma, pl->items[i].layers, pl->stages[i], cs);
+    hipError_t e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, cs);
     if (e == hipSuccess && pl->n_units > 0) e = launch_reset(pl->d_ticket, cs);
     if (e == hipSuccess && pl->n_units > 0) {
       PersistentArgs a{pl->d_items, pl->d_units, pl->n_units, pl->d_ticket};
-      e = launch_persistent(a, pl->grid, pl->tn, cs);
+      e = launch_persistent(a, pl->layer_class, pl->p_all, pl->grid, pl->tn, cs);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);

@@ -1,11 +1,12 @@
 // Serving: evaluation requests against device-resident geometries, admitted
 // under a device-memory budget and batched continuously.
 //
-// A scheduler thread admits queued requests in FIFO order while their buffers
-// fit in the budget (one device arena of exactly that size) and a request
-// slot is free, and launches everything it admitted as one step: density
-// uploads, staging kernels and one persistent kernel over the step's work
-// units, then output downloads.  Up to kStreams steps are in flight on
+// submit() copies the density into a pinned host arena (pageable memory if
+// that arena is full).  A scheduler thread admits queued requests in FIFO
+// order while their buffers fit in the budget (one device arena of exactly
+// that size) and a request slot is free, and launches everything it admitted
+// as one step: density uploads, one staging kernel and one persistent kernel
+// over the step's work units, then output downloads into pinned memory.  Up to kStreams steps are in flight on
 // separate streams, so requests that arrive while a step runs are launched in
 // the next step and overlap with it on the device.  A completion thread polls
 // the steps' events, copies outputs to the callers' buffers, releases the
@@ -80,7 +81,11 @@ struct Request {
   const tsqbx_geometry *geom = nullptr;
   int p = 0;
   unsigned layers = 0;
-  std::vector<double> sigma;
+  // host staging: [sigma (N) | out_slp (T) | out_dlp (T)], pinned when it fits
+  double *h_stage = nullptr;
+  bool pinned = false;
+  size_t pin_off = 0, pin_bytes = 0;
+  std::vector<double> pageable;  // fallback staging
   double *out_s = nullptr, *out_d = nullptr;
   size_t bytes = 0, arena_off = 0;
   double t_submit = 0, t_launch = 0, t_done = 0;
@@ -99,16 +104,12 @@ struct StreamSlot {
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   bool busy = false;
-  // step metadata (grown on demand)
-  WorkItem *d_items = nullptr;
-  WorkUnit *d_units = nullptr;
+  // step metadata, pinned host copy and device copy (grown on demand)
+  WorkItem *d_items = nullptr, *h_items = nullptr;
+  StageItem *d_stage = nullptr, *h_stage = nullptr;
+  WorkUnit *d_units = nullptr, *h_units = nullptr;
   unsigned int *d_ticket = nullptr;
-  size_t cap_items = 0, cap_units = 0;
-  // pinned staging for densities (in) and outputs (out)
-  double *h_buf = nullptr;
-  size_t cap_h = 0;
-  WorkItem *h_items = nullptr;
-  WorkUnit *h_units = nullptr;
+  size_t cap_items = 0, cap_stage = 0, cap_units = 0;
 };
 
 double percentile(std::vector<double> v, double q) {
@@ -130,6 +131,10 @@ struct tsqbx_server {
   Tuning tn;
   char *arena_base = nullptr;
   Arena arena;
+  char *pinned_base = nullptr;  // pinned host arena for densities and outputs
+  size_t pinned_cap = 0;
+  Arena pinned;
+  std::mutex pinned_mu;
   StreamSlot streams[kStreams];
 
   std::mutex mu;
@@ -147,50 +152,62 @@ struct tsqbx_server {
   std::thread sched, comp;
 
   int launch_step(Step &step, std::string &err);
+  void release_host_stage(Request *r) {
+    if (r->pinned) {
+      std::lock_guard<std::mutex> g(pinned_mu);
+      pinned.release(r->pin_off, r->pin_bytes);
+    }
+    r->pinned = false;
+    r->h_stage = nullptr;
+    std::vector<double>().swap(r->pageable);
+  }
   void scheduler();
   void completer();
 };
 
 static size_t request_bytes(const tsqbx_geometry *g, unsigned layers) {
   const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
-  size_t b = align_up(N * sizeof(double)) + align_up(N * sizeof(double4));
-  if (layers & TSQBX_DLP) b += align_up(N * sizeof(double4));
+  size_t b = align_up(N * sizeof(double)) + align_up((N + 1) * sizeof(double4));
+  if (layers & TSQBX_DLP) b += align_up((N + 1) * sizeof(double4));
   if (layers & TSQBX_SLP) b += align_up(T * sizeof(double));
   if (layers & TSQBX_DLP) b += align_up(T * sizeof(double));
   return std::max<size_t>(b, kAlign);
+}
+
+template <class T>
+static hipError_t grow_pair(T **d, T **h, size_t *cap, size_t need) {
+  if (*cap >= need) return hipSuccess;
+  if (*d) (void)hipFree(*d);
+  if (*h) (void)hipHostFree(*h);
+  *d = nullptr;
+  *h = nullptr;
+  *cap = 0;
+  const size_t n = std::max<size_t>(need * 2, 64);
+  hipError_t e = hipMalloc((void **)d, n * sizeof(T));
+  if (e == hipSuccess) e = hipHostMalloc((void **)h, n * sizeof(T), 0);
+  if (e == hipSuccess) *cap = n;
+  return e;
 }
 
 // Launch one step (called by the scheduler with the lock released).
 int tsqbx_server::launch_step(Step &step, std::string &err) {
   StreamSlot &ss = streams[step.stream];
   hipStream_t s = ss.s;
-  // host staging layout: [sigma of each request][outputs of each request]
-  size_t h_need = 0;
-  for (Request *r : step.reqs) {
-    h_need += (size_t)r->geom->n_sources;
-    if (r->layers & TSQBX_SLP) h_need += (size_t)r->geom->n_targets;
-    if (r->layers & TSQBX_DLP) h_need += (size_t)r->geom->n_targets;
-  }
   hipError_t e = hipSuccess;
   auto fail_e = [&](hipError_t x, const char *what) {
     err = std::string(what) + ": " + hipGetErrorString(x);
     return TSQBX_E_DEVICE;
   };
-  if (ss.cap_h < h_need) {
-    if (ss.h_buf) (void)hipHostFree(ss.h_buf);
-    ss.h_buf = nullptr;
-    ss.cap_h = 0;
-    e = hipHostMalloc((void **)&ss.h_buf, std::max<size_t>(h_need, 1) * sizeof(double), 0);
-    if (e != hipSuccess) return fail_e(e, "hipHostMalloc");
-    ss.cap_h = h_need;
-  }
+  const size_t K = step.reqs.size();
   // work items and units, tuned once per server (results do not depend on the mix)
   const int TPW = 64 / tn.group_lanes;
-  std::vector<WorkItem> items(step.reqs.size());
   std::vector<WorkUnit> units;
-  size_t hpos = 0;
-  std::vector<std::pair<double *, double *>> host_out(step.reqs.size());
-  for (size_t i = 0; i < step.reqs.size(); ++i) {
+  std::vector<std::pair<double *, double *>> dev_out(K);
+  int64_t max_n = 0;
+  e = grow_pair(&ss.d_items, &ss.h_items, &ss.cap_items, K);
+  if (e == hipSuccess) e = grow_pair(&ss.d_stage, &ss.h_stage, &ss.cap_stage, K);
+  if (e != hipSuccess) return fail_e(e, "step item buffers");
+  for (size_t i = 0; i < K; ++i) {
     Request *r = step.reqs[i];
     const tsqbx_geometry *g = r->geom;
     const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
@@ -199,10 +216,10 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     size_t off = align_up(N * sizeof(double));
     SourceStage stg;
     stg.posq = (double4 *)(base + off);
-    off += align_up(N * sizeof(double4));
+    off += align_up((N + 1) * sizeof(double4));
     if (r->layers & TSQBX_DLP) {
       stg.qn = (double4 *)(base + off);
-      off += align_up(N * sizeof(double4));
+      off += align_up((N + 1) * sizeof(double4));
     }
     double *d_out_s = nullptr, *d_out_d = nullptr;
     if (r->layers & TSQBX_SLP) {
@@ -210,13 +227,11 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
       off += align_up(T * sizeof(double));
     }
     if (r->layers & TSQBX_DLP) d_out_d = (double *)(base + off);
-    double *hs = ss.h_buf + hpos;
-    if (N) std::memcpy(hs, r->sigma.data(), N * sizeof(double));
-    hpos += N;
     if (N && e == hipSuccess)
-      e = hipMemcpyAsync(d_sigma, hs, N * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_stage(g, d_sigma, r->layers, stg, s);
-    WorkItem &w = items[i];
+      e = hipMemcpyAsync(d_sigma, r->h_stage, N * sizeof(double), hipMemcpyHostToDevice, s);
+    ss.h_stage[i] = make_stage_item(g, d_sigma, r->layers, stg);
+    max_n = std::max<int64_t>(max_n, g->n_sources);
+    WorkItem &w = ss.h_items[i];
     w = WorkItem{};
     w.tgt = g->tgt;
     w.idx = g->idx;
@@ -229,38 +244,17 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     for (int64_t k = 0; k < g->n_targets; k += 8 * TPW)
       units.push_back(WorkUnit{(int32_t)i, (int32_t)k,
                                (int32_t)std::min<int64_t>(8 * TPW, g->n_targets - k), 0});
-    host_out[i] = {d_out_s, d_out_d};
+    dev_out[i] = {d_out_s, d_out_d};
   }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ss.d_stage, ss.h_stage, K * sizeof(StageItem), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_stage_multi(ss.d_stage, (int)K, max_n, s);
   if (e != hipSuccess) return fail_e(e, "step upload");
   if (!units.empty()) {
-    if (ss.cap_items < items.size()) {
-      if (ss.d_items) (void)hipFree(ss.d_items);
-      if (ss.h_items) (void)hipHostFree(ss.h_items);
-      ss.d_items = nullptr;
-      ss.h_items = nullptr;
-      ss.cap_items = 0;
-      const size_t cap = std::max<size_t>(64, items.size() * 2);
-      e = hipMalloc((void **)&ss.d_items, cap * sizeof(WorkItem));
-      if (e == hipSuccess) e = hipHostMalloc((void **)&ss.h_items, cap * sizeof(WorkItem), 0);
-      if (e != hipSuccess) return fail_e(e, "step item buffers");
-      ss.cap_items = cap;
-    }
-    if (ss.cap_units < units.size()) {
-      if (ss.d_units) (void)hipFree(ss.d_units);
-      if (ss.h_units) (void)hipHostFree(ss.h_units);
-      ss.d_units = nullptr;
-      ss.h_units = nullptr;
-      ss.cap_units = 0;
-      const size_t cap = std::max<size_t>(4096, units.size() * 2);
-      e = hipMalloc((void **)&ss.d_units, cap * sizeof(WorkUnit));
-      if (e == hipSuccess) e = hipHostMalloc((void **)&ss.h_units, cap * sizeof(WorkUnit), 0);
-      if (e != hipSuccess) return fail_e(e, "step unit buffers");
-      ss.cap_units = cap;
-    }
-    std::memcpy(ss.h_items, items.data(), items.size() * sizeof(WorkItem));
+    e = grow_pair(&ss.d_units, &ss.h_units, &ss.cap_units, units.size());
+    if (e != hipSuccess) return fail_e(e, "step unit buffers");
     std::memcpy(ss.h_units, units.data(), units.size() * sizeof(WorkUnit));
-    e = hipMemcpyAsync(ss.d_items, ss.h_items, items.size() * sizeof(WorkItem),
-                       hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(ss.d_items, ss.h_items, K * sizeof(WorkItem), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(ss.d_units, ss.h_units, units.size() * sizeof(WorkUnit),
                          hipMemcpyHostToDevice, s);
@@ -270,25 +264,22 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
       const int gmax = persistent_max_grid(ctx->num_cus > 0 ? ctx->num_cus : 256, tn);
       const int grid = (int)std::max<int64_t>(
           1, std::min<int64_t>(gmax, ((int64_t)units.size() + tn.waves_per_block - 1) / tn.waves_per_block));
-      e = launch_persistent(a, grid, tn, s);
+      e = launch_persistent(a, 3u, -1, grid, tn, s);
     }
     if (e != hipSuccess) return fail_e(e, "step launch");
   }
-  // outputs back to pinned staging
-  for (size_t i = 0; i < step.reqs.size() && e == hipSuccess; ++i) {
+  // outputs straight into each request's host staging
+  for (size_t i = 0; i < K && e == hipSuccess; ++i) {
     Request *r = step.reqs[i];
-    const size_t T = (size_t)r->geom->n_targets;
+    const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
     if (!T) continue;
+    double *h = r->h_stage + N;
     if (r->layers & TSQBX_SLP) {
-      e = hipMemcpyAsync(ss.h_buf + hpos, host_out[i].first, T * sizeof(double),
-                         hipMemcpyDeviceToHost, s);
-      hpos += T;
+      e = hipMemcpyAsync(h, dev_out[i].first, T * sizeof(double), hipMemcpyDeviceToHost, s);
+      h += T;
     }
-    if (e == hipSuccess && (r->layers & TSQBX_DLP)) {
-      e = hipMemcpyAsync(ss.h_buf + hpos, host_out[i].second, T * sizeof(double),
-                         hipMemcpyDeviceToHost, s);
-      hpos += T;
-    }
+    if (e == hipSuccess && (r->layers & TSQBX_DLP))
+      e = hipMemcpyAsync(h, dev_out[i].second, T * sizeof(double), hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipEventRecord(ss.ev, s);
   if (e != hipSuccess) return fail_e(e, "step download");
@@ -355,6 +346,7 @@ void tsqbx_server::scheduler() {
         bytes_in_flight -= r->bytes;
         --reqs_in_flight;
         ++st.failed;
+        release_host_stage(r);
       }
       streams[step.stream].busy = false;
       fprintf(stderr, "tsqbx server: step failed: %s\n", err.c_str());
@@ -413,21 +405,16 @@ void tsqbx_server::completer() {
     Step step = std::move(inflight[found]);
     inflight.erase(inflight.begin() + found);
     StreamSlot &ss = streams[step.stream];
-    // outputs: pinned staging -> callers' buffers (layout mirrors launch_step)
-    size_t hpos = 0;
-    for (Request *r : step.reqs) hpos += (size_t)r->geom->n_sources;
     const double t1 = now_s();
     for (Request *r : step.reqs) {
-      const size_t T = (size_t)r->geom->n_targets;
+      const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
       if (qerr == hipSuccess) {
+        const double *h = r->h_stage + N;
         if (r->layers & TSQBX_SLP) {
-          if (T) std::memcpy(r->out_s, ss.h_buf + hpos, T * sizeof(double));
-          hpos += T;
+          if (T) std::memcpy(r->out_s, h, T * sizeof(double));
+          h += T;
         }
-        if (r->layers & TSQBX_DLP) {
-          if (T) std::memcpy(r->out_d, ss.h_buf + hpos, T * sizeof(double));
-          hpos += T;
-        }
+        if ((r->layers & TSQBX_DLP) && T) std::memcpy(r->out_d, h, T * sizeof(double));
         ++st.completed;
         st.pair_terms_completed +=
             r->geom->pairs * (int64_t)(r->p + 1) * (((r->layers & 1) ? 1 : 0) + ((r->layers & 2) ? 1 : 0));
@@ -442,8 +429,7 @@ void tsqbx_server::completer() {
       arena.release(r->arena_off, r->bytes);
       bytes_in_flight -= r->bytes;
       --reqs_in_flight;
-      r->sigma.clear();
-      r->sigma.shrink_to_fit();
+      release_host_stage(r);
     }
     ss.busy = false;
     if (inflight.empty() && busy_since >= 0) {
@@ -482,6 +468,13 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   sv->tn.unroll = 2;
   sv->st.budget_bytes = sv->budget;
   hipError_t e = hipMalloc((void **)&sv->arena_base, sv->budget);
+  // pinned host arena: densities and outputs of queued and running requests
+  sv->pinned_cap = std::min<size_t>(sv->budget, size_t(1) << 30);
+  if (e == hipSuccess && hipHostMalloc((void **)&sv->pinned_base, sv->pinned_cap, 0) != hipSuccess) {
+    sv->pinned_base = nullptr;  // requests then stage through pageable memory
+    sv->pinned_cap = 0;
+  }
+  if (sv->pinned_cap) sv->pinned.init(sv->pinned_cap);
   for (int k = 0; k < kStreams && e == hipSuccess; ++k) {
     e = hipStreamCreateWithFlags(&sv->streams[k].s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->streams[k].ev, hipEventDisableTiming);
@@ -494,6 +487,7 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
       if (ss.s) (void)hipStreamDestroy(ss.s);
     }
     if (sv->arena_base) (void)hipFree(sv->arena_base);
+    if (sv->pinned_base) (void)hipHostFree(sv->pinned_base);
     delete sv;
     if (prev >= 0) (void)hipSetDevice(prev);
     return fail_hip(e, "server setup");
@@ -521,18 +515,33 @@ int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, uns
   r->geom = geom;
   r->p = p;
   r->layers = layers;
-  r->sigma.assign(sigma_host, sigma_host + geom->n_sources);
+  const size_t N = (size_t)geom->n_sources, T = (size_t)geom->n_targets;
+  const size_t words = N + T * ((layers & TSQBX_SLP ? 1 : 0) + (layers & TSQBX_DLP ? 1 : 0));
+  r->pin_bytes = align_up(std::max<size_t>(words, 1) * sizeof(double));
+  {
+    std::lock_guard<std::mutex> g(sv->pinned_mu);
+    r->pinned = sv->pinned_cap > 0 && sv->pinned.alloc(r->pin_bytes, &r->pin_off);
+  }
+  if (r->pinned) {
+    r->h_stage = (double *)(sv->pinned_base + r->pin_off);
+  } else {
+    r->pageable.resize(std::max<size_t>(words, 1));
+    r->h_stage = r->pageable.data();
+  }
+  if (N) std::memcpy(r->h_stage, sigma_host, N * sizeof(double));
   r->out_s = out_slp_host;
   r->out_d = out_dlp_host;
   r->bytes = bytes;
   std::lock_guard<std::mutex> lk(sv->mu);
   ++sv->st.submitted;
   if (sv->stopping) {
+    sv->release_host_stage(r);
     delete r;
     return fail(TSQBX_E_STATE, "server is shutting down");
   }
   if (bytes > sv->budget) {
     ++sv->st.rejected;
+    sv->release_host_stage(r);
     delete r;
     return fail(TSQBX_E_BUDGET, "request needs %zu bytes but the budget is %zu", bytes, sv->budget);
   }
@@ -615,16 +624,18 @@ int tsqbx_server_destroy(tsqbx_server *sv) {
   for (auto &ss : sv->streams) {
     if (ss.s) (void)hipStreamSynchronize(ss.s);
     if (ss.d_items) (void)hipFree(ss.d_items);
+    if (ss.d_stage) (void)hipFree(ss.d_stage);
     if (ss.d_units) (void)hipFree(ss.d_units);
     if (ss.d_ticket) (void)hipFree(ss.d_ticket);
-    if (ss.h_buf) (void)hipHostFree(ss.h_buf);
     if (ss.h_items) (void)hipHostFree(ss.h_items);
+    if (ss.h_stage) (void)hipHostFree(ss.h_stage);
     if (ss.h_units) (void)hipHostFree(ss.h_units);
     if (ss.ev) (void)hipEventDestroy(ss.ev);
     if (ss.s) (void)hipStreamDestroy(ss.s);
   }
   if (sv->arena_base) (void)hipFree(sv->arena_base);
   for (auto &kv : sv->all) delete kv.second;
+  if (sv->pinned_base) (void)hipHostFree(sv->pinned_base);
   if (prev >= 0) (void)hipSetDevice(prev);
   delete sv;
   return TSQBX_OK;

@@ -97,7 +97,7 @@ def test_tuning_variants(ctx):
     mean = max(geom.pairs // max(geom.n_targets, 1), 1)
     base = None
     for G, U in ((64, 1), (64, 2), (64, 4), (32, 2), (16, 2)):
-        for w in (1, 4, 16):
+        for w in (1, 2, 4):
             for remap in (0, 1):
                 ctx.set_tuning(16, 3, mean, waves_per_block=w, group_lanes=G, unroll=U,
                                xcd_remap=remap)
@@ -129,10 +129,14 @@ def test_async_device_path_and_accumulate(ctx):
     torch.cuda.synchronize()
     assert np.array_equal(os_.cpu().numpy(), s_host + s_host)
     assert np.array_equal(od_.cpu().numpy(), d_host + d_host)
+    # the single layer alone runs its own recurrence (equal to 1e-12, not bitwise)
+    s_only, _ = ctx.eval(geom, g.sigma, 12, api.SLP)
+    ref = oracle.evaluate_geometry(g, p=12, layers=1)
+    assert_parity(s_only, ref["slp"], ref["abs_slp"], what="slp alone")
     base_s = np.full(g.n_targets, 0.25)
     out_s = base_s.copy()
     ctx.eval(geom, g.sigma, 12, api.SLP, out_slp=out_s, flags=api.ACCUMULATE)
-    assert np.array_equal(out_s, base_s + s_host)
+    assert np.array_equal(out_s, base_s + s_only)
     geom.close()
 
 
