@@ -44,9 +44,16 @@ def flops_per_pair(p: int, layers: int) -> int:
     return 6 * max(p, 1) + (37 if layers == 2 else 48)
 
 
-def timed_steps(fn, steps, warmup, torch):
-    for _ in range(warmup):
+def timed_steps(fn, steps, warmup, torch, min_warm_s=0.3):
+    """W warm-up calls (continued until min_warm_s of device work so that the
+    clocks settle), then `steps` timed calls between synchronisations."""
+    t0 = time.perf_counter()
+    n = 0
+    while n < warmup or time.perf_counter() - t0 < min_warm_s:
         fn()
+        n += 1
+        if n % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)

@@ -178,16 +178,9 @@ Tuning default_tuning(int p, unsigned layers, int64_t mean_list) {
   Tuning t;
   t.waves_per_block = 4;
   t.xcd_remap = 1;
-  if (mean_list < 48) {
-    t.group_lanes = 16;
-    t.unroll = 2;
-  } else if (mean_list < 160) {
-    t.group_lanes = 32;
-    t.unroll = 2;
-  } else {
-    t.group_lanes = 64;
-    t.unroll = 2;
-  }
+  // short lists: several targets per wave; long lists: one target per wave
+  t.group_lanes = mean_list < 384 ? 16 : 64;
+  t.unroll = 2;
   return t;
 }
 

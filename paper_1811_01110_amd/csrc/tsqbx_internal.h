@@ -95,6 +95,22 @@ hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const So
                        hipStream_t s);
 bool tuning_supported(const Tuning &tn);
 
+// Staging of many items in one launch (batched and served paths).
+struct StageItem {         // 64 bytes
+  const double4 *pos_w;
+  const double4 *nrm;
+  const int64_t *perm;
+  const double *sigma;
+  double4 *posq;
+  double4 *qn;
+  int64_t n;
+  int32_t want_dlp;
+  int32_t pad;
+};
+StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
+                          const SourceStage &st);
+hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
+
 // Persistent batched kernel.
 struct WorkItem {           // one (geometry, p, layers) item of a plan, 128 bytes
   const TargetRec *tgt;
@@ -115,34 +131,33 @@ struct WorkUnit {           // a run of consecutive targets of one item, 16 byte
   int32_t count;
   int32_t pad;
 };
+// Each wave of the persistent kernel works through units
+// [wave_begin[w], wave_begin[w + 1]); consecutive waves hold consecutive
+// (spatially adjacent) targets, and logical wave numbers follow the XCD
+// renumbering of blocks.
 struct PersistentArgs {
   const WorkItem *items;
   const WorkUnit *units;
-  int64_t n_units;
-  unsigned int *ticket;     // zeroed by launch_reset before each run
+  const int32_t *wave_begin;  // [n_waves + 1]
+  int32_t n_waves;
 };
-hipError_t launch_reset(unsigned int *ticket, hipStream_t s);
-
-// Staging of many items in one launch (batched and served paths).
-struct StageItem {         // 64 bytes
-  const double4 *pos_w;
-  const double4 *nrm;
-  const int64_t *perm;
-  const double *sigma;
-  double4 *posq;
-  double4 *qn;
-  int64_t n;
-  int32_t want_dlp;
-  int32_t pad;
-};
-StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
-                          const SourceStage &st);
-hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
 // layer_class: 1 or 2 if every item has that layer mask, else 3; p_all: the
 // order shared by every item, or -1.
-hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all, int grid,
+hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all,
                              const Tuning &tn, hipStream_t s);
-int persistent_max_grid(int num_cus, const Tuning &tn);
+int persistent_max_waves(int num_cus);
+
+// Static schedule for the persistent kernel: the targets of the items (in the
+// given order, device order within an item) cut into at most max_waves
+// contiguous ranges of about equal estimated cost.
+struct ScheduleItem {
+  const tsqbx_geometry *geom;
+  int p;
+  unsigned layers;
+};
+void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
+                    int group_lanes, int max_waves, std::vector<WorkUnit> *units,
+                    std::vector<int32_t> *wave_begin);
 
 Tuning default_tuning(int p, unsigned layers, int64_t mean_list);
 Tuning lookup_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list);

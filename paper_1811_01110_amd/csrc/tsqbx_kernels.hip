@@ -425,8 +425,7 @@ __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict
 }
 
 // ---- persistent batched kernel ---------------------------------------------
-// Each wave takes work units from a global ticket counter until none remain
-// (every wave reaches the exit: tickets only grow).  A unit is a run of
+// A unit is a run of
 // consecutive targets of one item; p and the layer mask are wave-uniform.
 template <int P, int L, int G, int U>
 __device__ __forceinline__ void unit_body(const WorkItem &it, int first, int count, int lane) {
@@ -466,31 +465,45 @@ __device__ __forceinline__ void unit_dispatch_p(const WorkItem &it, int first, i
 }
 
 // LC = layer class: 1 or 2 (every item has that mask) or 3 (any mask).
+// Each wave works through its own range of units (a static schedule built
+// on the host), so no wave waits on another and no atomics are needed.
 template <int LC, int PF, int G, int U>
 __global__ void __launch_bounds__(256) k_persistent(PersistentArgs a) {
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    unsigned int u = 0;
-    if (lane == 0) u = atomicAdd(a.ticket, 1u);
-    u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, 64));
-    if ((int64_t)u >= a.n_units) break;
-    const WorkUnit wu = a.units[u];
-    const WorkItem it = a.items[wu.item];
+  const int wpb = blockDim.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * wpb +
+                                               (int)(threadIdx.x >> 6));
+  if (w >= a.n_waves) return;
+  const TSQBX_GLOBAL int32_t *wb = (const TSQBX_GLOBAL int32_t *)a.wave_begin;
+  const int ub = wb[w], ue = wb[w + 1];
+  const TSQBX_GLOBAL WorkUnit *units = (const TSQBX_GLOBAL WorkUnit *)a.units;
+  const TSQBX_GLOBAL WorkItem *items = (const TSQBX_GLOBAL WorkItem *)a.items;
+  for (int u = ub; u < ue; ++u) {
+    const int item = __builtin_amdgcn_readfirstlane(units[u].item);
+    const int first = __builtin_amdgcn_readfirstlane(units[u].first);
+    const int count = __builtin_amdgcn_readfirstlane(units[u].count);
+    WorkItem it;
+    it.tgt = items[item].tgt;
+    it.idx = items[item].idx;
+    it.posq = items[item].posq;
+    it.qn = items[item].qn;
+    it.out_s = items[item].out_s;
+    it.out_d = items[item].out_d;
+    it.p = items[item].p;
+    it.layers = items[item].layers;
+    it.accumulate = items[item].accumulate;
     if constexpr (LC == 3) {
       switch (it.layers) {
-        case 1: unit_dispatch_p<1, PF, G, U>(it, wu.first, wu.count, lane); break;
-        case 2: unit_dispatch_p<2, PF, G, U>(it, wu.first, wu.count, lane); break;
-        default: unit_dispatch_p<3, PF, G, U>(it, wu.first, wu.count, lane); break;
+        case 1: unit_dispatch_p<1, PF, G, U>(it, first, count, lane); break;
+        case 2: unit_dispatch_p<2, PF, G, U>(it, first, count, lane); break;
+        default: unit_dispatch_p<3, PF, G, U>(it, first, count, lane); break;
       }
     } else {
-      unit_dispatch_p<LC, PF, G, U>(it, wu.first, wu.count, lane);
+      unit_dispatch_p<LC, PF, G, U>(it, first, count, lane);
     }
   }
 }
 
-__global__ void k_reset(unsigned int *ticket) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *ticket = 0u;
-}
 
 // ---- launch helpers -----------------------------------------------------------
 template <int P, int L, int G, int U>
@@ -587,22 +600,17 @@ hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max
   return hipGetLastError();
 }
 
-hipError_t launch_reset(unsigned int *ticket, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ticket);
-  return hipGetLastError();
-}
 
-int persistent_max_grid(int num_cus, const Tuning &tn) {
-  // enough resident waves to cover every SIMD several times over
-  const int waves = num_cus * 4 * 6;
-  return std::max(1, waves / tn.waves_per_block);
+int persistent_max_waves(int num_cus) {
+  // six resident waves per SIMD
+  return std::max(1, num_cus) * 4 * 6;
 }
 
 namespace {
 template <int LC, int PF>
-hipError_t launch_persistent_lp(const PersistentArgs &a, int grid, const Tuning &tn,
-                                hipStream_t s) {
+hipError_t launch_persistent_lp(const PersistentArgs &a, const Tuning &tn, hipStream_t s) {
   const dim3 block(64 * tn.waves_per_block);
+  const int grid = (a.n_waves + tn.waves_per_block - 1) / tn.waves_per_block;
   const int G = tn.group_lanes, U = tn.unroll;
   if (G == 64 && U == 1)
     hipLaunchKernelGGL((k_persistent<LC, PF, 64, 1>), dim3(grid), block, 0, s, a);
@@ -616,26 +624,26 @@ hipError_t launch_persistent_lp(const PersistentArgs &a, int grid, const Tuning 
 }
 
 template <int LC>
-hipError_t launch_persistent_l(const PersistentArgs &a, int p_all, int grid, const Tuning &tn,
+hipError_t launch_persistent_l(const PersistentArgs &a, int p_all, const Tuning &tn,
                                hipStream_t s) {
   switch (p_all) {
-    case 4: return launch_persistent_lp<LC, 4>(a, grid, tn, s);
-    case 8: return launch_persistent_lp<LC, 8>(a, grid, tn, s);
-    case 12: return launch_persistent_lp<LC, 12>(a, grid, tn, s);
-    case 16: return launch_persistent_lp<LC, 16>(a, grid, tn, s);
-    case 24: return launch_persistent_lp<LC, 24>(a, grid, tn, s);
-    default: return launch_persistent_lp<LC, -1>(a, grid, tn, s);
+    case 4: return launch_persistent_lp<LC, 4>(a, tn, s);
+    case 8: return launch_persistent_lp<LC, 8>(a, tn, s);
+    case 12: return launch_persistent_lp<LC, 12>(a, tn, s);
+    case 16: return launch_persistent_lp<LC, 16>(a, tn, s);
+    case 24: return launch_persistent_lp<LC, 24>(a, tn, s);
+    default: return launch_persistent_lp<LC, -1>(a, tn, s);
   }
 }
 }  // namespace
 
-hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all, int grid,
+hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all,
                              const Tuning &tn, hipStream_t s) {
-  if (!tuning_supported(tn) || grid <= 0 || tn.waves_per_block > 4) return hipErrorInvalidValue;
+  if (!tuning_supported(tn) || a.n_waves <= 0) return hipErrorInvalidValue;
   switch (layer_class) {
-    case 1: return launch_persistent_l<1>(a, p_all, grid, tn, s);
-    case 2: return launch_persistent_l<2>(a, p_all, grid, tn, s);
-    default: return launch_persistent_l<3>(a, p_all, grid, tn, s);
+    case 1: return launch_persistent_l<1>(a, p_all, tn, s);
+    case 2: return launch_persistent_l<2>(a, p_all, tn, s);
+    default: return launch_persistent_l<3>(a, p_all, tn, s);
   }
 }
 

@@ -1,11 +1,11 @@
 // Batched evaluation: many (geometry, p, layers) items in one persistent
 // kernel launch, captured once into a HIP graph and replayed.
 //
-// Work is cut into units (runs of consecutive device-order targets of one
-// item, sized so that every unit costs about the same number of pair-terms);
-// the persistent kernel's waves take units from an atomic ticket counter.
-// Items are ordered largest first and units keep their spatial (Morton) order
-// inside an item, so concurrently running waves share source records in L2.
+// The targets of all items, largest item first and in device (Morton) order
+// within an item, are cut into one contiguous range per wave of about equal
+// estimated cost (a static schedule: no atomics, no waiting).  Consecutive
+// waves hold neighbouring targets and run on the same XCD, so they share
+// source records in that XCD's L2.
 // Each target is summed by the same device routine as the plain path, so a
 // plan's results equal plain evaluations with the same group width bit for bit.
 #include <algorithm>
@@ -24,9 +24,10 @@ struct tsqbx_plan {
   std::vector<SourceStage> stages;
   WorkItem *d_items = nullptr;
   WorkUnit *d_units = nullptr;
+  int32_t *d_wave_begin = nullptr;
+  int32_t n_waves = 0;
   StageItem *d_stage = nullptr;  // staging of every item, one launch
   int64_t max_sources = 0;
-  unsigned int *d_ticket = nullptr;
   int64_t n_units = 0;
   int64_t pairs = 0, pair_terms = 0;
   int grid = 0;
@@ -66,20 +67,73 @@ void free_plan(tsqbx_plan *pl) {
   if (pl->d_items) (void)hipFree(pl->d_items);
   if (pl->d_stage) (void)hipFree(pl->d_stage);
   if (pl->d_units) (void)hipFree(pl->d_units);
-  if (pl->d_ticket) (void)hipFree(pl->d_ticket);
+  if (pl->d_wave_begin) (void)hipFree(pl->d_wave_begin);
   delete pl;
 }
 
 int layer_count(unsigned l) { return ((l & 1u) ? 1 : 0) + ((l & 2u) ? 1 : 0); }
 
-// Relative cost of one pair: per-order work plus the per-pair setup.
+// Relative cost (vector instructions) of one pair: four per recurrence
+// order plus the per-pair setup and closing sums.
 double pair_cost(int p, unsigned layers) {
-  const double per_order = (layers == 3) ? 7.0 : (layers == 2 ? 6.0 : 4.0);
-  const double setup = (layers & 2u) ? 40.0 : 22.0;
-  return per_order * std::max(p - 1, 0) + setup;
+  const double setup = (layers & 2u) ? 50.0 : 35.0;
+  return 4.0 * std::max(p - 1, 0) + setup;
 }
 
 }  // namespace
+
+namespace tsqbx {
+
+void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
+                    int group_lanes, int max_waves, std::vector<WorkUnit> *units,
+                    std::vector<int32_t> *wave_begin) {
+  const int G = group_lanes, TPW = 64 / G;
+  // the wave-steps: TPW consecutive targets of one item, costed by the
+  // longest of their lists (the group lanes run in lockstep)
+  struct WStep {
+    int32_t item, first, count;
+    double cost;
+  };
+  std::vector<WStep> steps;
+  double total = 0.0;
+  for (int32_t oi : order) {
+    const tsqbx_geometry *g = items[oi].geom;
+    const double pc = pair_cost(items[oi].p, items[oi].layers);
+    for (int64_t k = 0; k < g->n_targets; k += TPW) {
+      const int32_t cnt = (int32_t)std::min<int64_t>(TPW, g->n_targets - k);
+      int64_t chunks = 0;
+      for (int32_t x = 0; x < cnt; ++x)
+        chunks = std::max<int64_t>(chunks, (g->host_row_len[k + x] + G - 1) / G);
+      const double c = (double)chunks * pc + 60.0;
+      steps.push_back(WStep{oi, (int32_t)k, cnt, c});
+      total += c;
+    }
+  }
+  units->clear();
+  wave_begin->assign(1, 0);
+  if (steps.empty()) return;
+  const int64_t W = std::max<int64_t>(1, std::min<int64_t>(max_waves, (int64_t)steps.size()));
+  // cut the step sequence where the running cost crosses w * total / W
+  size_t sidx = 0;
+  double acc = 0.0;
+  for (int64_t w = 0; w < W; ++w) {
+    const double bound = (w + 1 == W) ? 1e300 : total * (double)(w + 1) / (double)W;
+    while (sidx < steps.size() && (acc + 0.5 * steps[sidx].cost <= bound)) {
+      const WStep &st = steps[sidx];
+      WorkUnit *last = units->empty() ? nullptr : &units->back();
+      const bool same_wave = (int64_t)units->size() > wave_begin->back();
+      if (last && same_wave && last->item == st.item && last->first + last->count == st.first)
+        last->count += st.count;  // extend the wave's current run
+      else
+        units->push_back(WorkUnit{st.item, st.first, st.count, 0});
+      acc += st.cost;
+      ++sidx;
+    }
+    wave_begin->push_back((int32_t)units->size());
+  }
+}
+
+}  // namespace tsqbx
 
 extern "C" {
 
@@ -146,35 +200,18 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   }
   std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return icost[a] > icost[b]; });
 
-  // units of roughly equal cost: aim at ~16 units per resident wave
-  const int grid_max = persistent_max_grid(ctx->num_cus > 0 ? ctx->num_cus : 256, pl->tn);
-  const double waves = (double)grid_max * pl->tn.waves_per_block;
-  const double target_cost = std::max(total / (waves * 16.0), 1.0);
+  // static schedule over the resident waves
+  std::vector<ScheduleItem> sched(n_items);
+  for (int64_t i = 0; i < n_items; ++i)
+    sched[i] = ScheduleItem{pl->items[i].geom, pl->items[i].p, pl->items[i].layers};
+  std::vector<int32_t> order32(ord.begin(), ord.end());
   std::vector<WorkUnit> units;
-  for (int64_t oi : ord) {
-    const tsqbx_geometry *g = pl->items[oi].geom;
-    const double pc = pair_cost(pl->items[oi].p, pl->items[oi].layers);
-    int64_t k = 0;
-    while (k < g->n_targets) {
-      double c = 0;
-      int64_t e = k;
-      // whole groups of TPW targets, at most 4096 targets per unit
-      while (e < g->n_targets && (e == k || c < target_cost) && e - k < 4096) {
-        const int64_t ge = std::min<int64_t>(g->n_targets, e + TPW);
-        for (int64_t x = e; x < ge; ++x) c += (double)(g->host_row_len[x] + 1) * pc;
-        e = ge;
-      }
-      units.push_back(WorkUnit{(int32_t)oi, (int32_t)k, (int32_t)(e - k), 0});
-      k = e;
-    }
-  }
+  std::vector<int32_t> wave_begin;
+  build_schedule(sched, order32, pl->tn.group_lanes,
+                 persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256), &units, &wave_begin);
   pl->n_units = (int64_t)units.size();
-  if (pl->n_units > INT32_MAX) {
-    free_plan(pl);
-    return fail(TSQBX_E_RANGE, "too many work units");
-  }
-  pl->grid = (int)std::max<int64_t>(
-      1, std::min<int64_t>(grid_max, (pl->n_units + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block));
+  pl->n_waves = (int32_t)wave_begin.size() - 1;
+  pl->grid = (pl->n_waves + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block;
 
   // per-item staging and the device copies of items and units
   std::vector<WorkItem> witems(n_items);
@@ -214,10 +251,14 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
     e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
   if (e == hipSuccess && pl->n_units)
     e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc((void **)&pl->d_ticket, sizeof(unsigned int));
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&pl->d_wave_begin, wave_begin.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->d_wave_begin, wave_begin.data(), wave_begin.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
   pl->device_bytes += n_items * (sizeof(WorkItem) + sizeof(StageItem)) +
-                      units.size() * sizeof(WorkUnit) + sizeof(unsigned);
+                      units.size() * sizeof(WorkUnit) + wave_begin.size() * sizeof(int32_t);
   if (e != hipSuccess) {
     free_plan(pl);
     return fail_hip(e, "plan setup");
@@ -231,15 +272,13 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
   Guard dg(pl->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   if (!pl->exec) {
-    // capture: staging of every item (one kernel), ticket reset (a kernel,
-    // not a memset node), then the persistent kernel
+    // capture: staging of every item (one kernel), then the persistent kernel
     hipStream_t cs = pl->cap_stream;
     TSQBX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, cs);
-    if (e == hipSuccess && pl->n_units > 0) e = launch_reset(pl->d_ticket, cs);
     if (e == hipSuccess && pl->n_units > 0) {
-      PersistentArgs a{pl->d_items, pl->d_units, pl->n_units, pl->d_ticket};
-      e = launch_persistent(a, pl->layer_class, pl->p_all, pl->grid, pl->tn, cs);
+      PersistentArgs a{pl->d_items, pl->d_units, pl->d_wave_begin, pl->n_waves};
+      e = launch_persistent(a, pl->layer_class, pl->p_all, pl->tn, cs);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);

@@ -108,8 +108,8 @@ struct StreamSlot {
   WorkItem *d_items = nullptr, *h_items = nullptr;
   StageItem *d_stage = nullptr, *h_stage = nullptr;
   WorkUnit *d_units = nullptr, *h_units = nullptr;
-  unsigned int *d_ticket = nullptr;
-  size_t cap_items = 0, cap_stage = 0, cap_units = 0;
+  int32_t *d_wave = nullptr, *h_wave = nullptr;
+  size_t cap_items = 0, cap_stage = 0, cap_units = 0, cap_wave = 0;
 };
 
 double percentile(std::vector<double> v, double q) {
@@ -199,9 +199,12 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     return TSQBX_E_DEVICE;
   };
   const size_t K = step.reqs.size();
-  // work items and units, tuned once per server (results do not depend on the mix)
-  const int TPW = 64 / tn.group_lanes;
+  // work items and a static schedule, tuned once per server (results do not
+  // depend on the mix)
   std::vector<WorkUnit> units;
+  std::vector<int32_t> wave_begin;
+  std::vector<ScheduleItem> sched(K);
+  std::vector<int32_t> order(K);
   std::vector<std::pair<double *, double *>> dev_out(K);
   int64_t max_n = 0;
   e = grow_pair(&ss.d_items, &ss.h_items, &ss.cap_items, K);
@@ -241,30 +244,32 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     w.out_d = d_out_d;
     w.p = r->p;
     w.layers = (int32_t)r->layers;
-    for (int64_t k = 0; k < g->n_targets; k += 8 * TPW)
-      units.push_back(WorkUnit{(int32_t)i, (int32_t)k,
-                               (int32_t)std::min<int64_t>(8 * TPW, g->n_targets - k), 0});
+    sched[i] = ScheduleItem{g, r->p, r->layers};
+    order[i] = (int32_t)i;
     dev_out[i] = {d_out_s, d_out_d};
   }
+  build_schedule(sched, order, tn.group_lanes,
+                 persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256), &units, &wave_begin);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ss.d_stage, ss.h_stage, K * sizeof(StageItem), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_stage_multi(ss.d_stage, (int)K, max_n, s);
   if (e != hipSuccess) return fail_e(e, "step upload");
   if (!units.empty()) {
     e = grow_pair(&ss.d_units, &ss.h_units, &ss.cap_units, units.size());
+    if (e == hipSuccess) e = grow_pair(&ss.d_wave, &ss.h_wave, &ss.cap_wave, wave_begin.size());
     if (e != hipSuccess) return fail_e(e, "step unit buffers");
     std::memcpy(ss.h_units, units.data(), units.size() * sizeof(WorkUnit));
+    std::memcpy(ss.h_wave, wave_begin.data(), wave_begin.size() * sizeof(int32_t));
     e = hipMemcpyAsync(ss.d_items, ss.h_items, K * sizeof(WorkItem), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(ss.d_units, ss.h_units, units.size() * sizeof(WorkUnit),
                          hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_reset(ss.d_ticket, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ss.d_wave, ss.h_wave, wave_begin.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-      PersistentArgs a{ss.d_items, ss.d_units, (int64_t)units.size(), ss.d_ticket};
-      const int gmax = persistent_max_grid(ctx->num_cus > 0 ? ctx->num_cus : 256, tn);
-      const int grid = (int)std::max<int64_t>(
-          1, std::min<int64_t>(gmax, ((int64_t)units.size() + tn.waves_per_block - 1) / tn.waves_per_block));
-      e = launch_persistent(a, 3u, -1, grid, tn, s);
+      PersistentArgs a{ss.d_items, ss.d_units, ss.d_wave, (int32_t)wave_begin.size() - 1};
+      e = launch_persistent(a, 3u, -1, tn, s);
     }
     if (e != hipSuccess) return fail_e(e, "step launch");
   }
@@ -463,9 +468,9 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   sv->device = ctx->device;
   sv->budget = hbm_budget / kAlign * kAlign;
   sv->max_slots = max_slots;
-  sv->tn = default_tuning(16, 3u, 1024);
-  sv->tn.group_lanes = 64;
-  sv->tn.unroll = 2;
+  // one launch shape for the server's lifetime (near-field lists of a few
+  // hundred sources); a request's result then does not depend on its step
+  sv->tn = default_tuning(16, 3u, 256);
   sv->st.budget_bytes = sv->budget;
   hipError_t e = hipMalloc((void **)&sv->arena_base, sv->budget);
   // pinned host arena: densities and outputs of queued and running requests
@@ -478,11 +483,9 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   for (int k = 0; k < kStreams && e == hipSuccess; ++k) {
     e = hipStreamCreateWithFlags(&sv->streams[k].s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->streams[k].ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipMalloc((void **)&sv->streams[k].d_ticket, sizeof(unsigned int));
   }
   if (e != hipSuccess) {
     for (auto &ss : sv->streams) {
-      if (ss.d_ticket) (void)hipFree(ss.d_ticket);
       if (ss.ev) (void)hipEventDestroy(ss.ev);
       if (ss.s) (void)hipStreamDestroy(ss.s);
     }
@@ -626,7 +629,8 @@ int tsqbx_server_destroy(tsqbx_server *sv) {
     if (ss.d_items) (void)hipFree(ss.d_items);
     if (ss.d_stage) (void)hipFree(ss.d_stage);
     if (ss.d_units) (void)hipFree(ss.d_units);
-    if (ss.d_ticket) (void)hipFree(ss.d_ticket);
+    if (ss.d_wave) (void)hipFree(ss.d_wave);
+    if (ss.h_wave) (void)hipHostFree(ss.h_wave);
     if (ss.h_items) (void)hipHostFree(ss.h_items);
     if (ss.h_stage) (void)hipHostFree(ss.h_stage);
     if (ss.h_units) (void)hipHostFree(ss.h_units);
