@@ -228,6 +228,7 @@ typedef struct {
   double latency_p50_ms, latency_p90_ms, latency_p99_ms, latency_max_ms;
   double queue_p50_ms, queue_p99_ms; /* submit -> launch */
   double busy_s;                /* wall time with at least one step on the device */
+  double host_launch_s;         /* scheduler time spent issuing steps */
 } tsqbx_server_stats;
 
 /* hbm_budget: bytes of per-request device memory that may be in flight
@@ -241,6 +242,14 @@ int tsqbx_server_request_bytes(const tsqbx_geometry *geom, unsigned layers, size
 int tsqbx_server_submit(tsqbx_server *srv, const tsqbx_geometry *geom, int p, unsigned layers,
                         const double *sigma_host, double *out_slp_host, double *out_dlp_host,
                         uint64_t *ticket);
+/* As tsqbx_server_submit, without copying: sigma_host and the outputs must be
+ * pinned host memory (hipHostMalloc, or a pinned torch tensor) and stay valid
+ * and unmodified until the ticket completes.  Densities are uploaded and
+ * outputs downloaded by DMA straight from and into these buffers.  Returns
+ * TSQBX_E_INVALID if a buffer is not pinned host memory. */
+int tsqbx_server_submit_pinned(tsqbx_server *srv, const tsqbx_geometry *geom, int p,
+                               unsigned layers, const double *sigma_host, double *out_slp_host,
+                               double *out_dlp_host, uint64_t *ticket);
 /* *done = 1 once the outputs are written (0 while pending).  Returns the
  * request's error status if it failed. */
 int tsqbx_server_poll(tsqbx_server *srv, uint64_t ticket, int *done);

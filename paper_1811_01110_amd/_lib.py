@@ -63,7 +63,8 @@ class ServerStats(ctypes.Structure):
                 ("budget_bytes", c_size_t), ("pair_terms_completed", c_int64),
                 ("latency_p50_ms", c_double), ("latency_p90_ms", c_double),
                 ("latency_p99_ms", c_double), ("latency_max_ms", c_double),
-                ("queue_p50_ms", c_double), ("queue_p99_ms", c_double), ("busy_s", c_double)]
+                ("queue_p50_ms", c_double), ("queue_p99_ms", c_double), ("busy_s", c_double),
+                ("host_launch_s", c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -94,6 +95,8 @@ _SIGNATURES = {
     "tsqbx_server_request_bytes": (c_int, [c_void_p, c_uint, P(c_size_t)]),
     "tsqbx_server_submit": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,
                                     c_void_p, P(c_uint64)]),
+    "tsqbx_server_submit_pinned": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,
+                                           c_void_p, P(c_uint64)]),
     "tsqbx_server_poll": (c_int, [c_void_p, c_uint64, P(c_int)]),
     "tsqbx_server_wait": (c_int, [c_void_p, c_uint64, c_double]),
     "tsqbx_server_drain": (c_int, [c_void_p, c_double]),

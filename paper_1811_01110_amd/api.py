@@ -295,6 +295,42 @@ class Server:
         self._live[tk.value] = (os_, od_)
         return tk.value, os_, od_
 
+    def submit_pinned(self, geom: Geometry, sigma, p: int, layers: int, out_slp=None,
+                      out_dlp=None):
+        """Queue a request on pinned host tensors (torch, float64), without copies.
+
+        sigma and the outputs (allocated pinned if not given) must stay valid
+        until the ticket completes.  Returns (ticket, out_slp, out_dlp).
+        """
+        import torch
+
+        def pinned(t, n, name):
+            if t is None:
+                return None
+            # whether the memory is pinned is checked by the library
+            if t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 CPU tensor")
+            if t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+            return t
+
+        T = geom.n_targets
+        sigma = pinned(sigma, geom.n_sources, "sigma")
+        if layers & SLP and out_slp is None:
+            out_slp = torch.empty(T, dtype=torch.float64, pin_memory=True)
+        if layers & DLP and out_dlp is None:
+            out_dlp = torch.empty(T, dtype=torch.float64, pin_memory=True)
+        out_slp = pinned(out_slp, T, "out_slp") if layers & SLP else None
+        out_dlp = pinned(out_dlp, T, "out_dlp") if layers & DLP else None
+        tk = ctypes.c_uint64()
+        _check(_lib().tsqbx_server_submit_pinned(
+            self.handle, geom.handle, int(p), int(layers),
+            sigma.data_ptr() if sigma is not None else None,
+            out_slp.data_ptr() if out_slp is not None else None,
+            out_dlp.data_ptr() if out_dlp is not None else None, ctypes.byref(tk)))
+        self._live[tk.value] = (out_slp, out_dlp, sigma)
+        return tk.value, out_slp, out_dlp
+
     def poll(self, ticket: int) -> bool:
         done = ctypes.c_int()
         _check(_lib().tsqbx_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(done)))
@@ -302,10 +338,11 @@ class Server:
 
     def wait(self, ticket: int, timeout_s: float = 60.0):
         _check(_lib().tsqbx_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s)))
-        return self._live.pop(ticket, (None, None))
+        return self._live.pop(ticket, (None, None))[:2]
 
     def drain(self, timeout_s: float = 600.0):
         _check(_lib().tsqbx_server_drain(self.handle, float(timeout_s)))
+        self._live.clear()
 
     def stats(self) -> dict:
         s = L.ServerStats()

@@ -197,7 +197,8 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 
 static void free_geometry(tsqbx_geometry *g) {
   if (!g) return;
-  void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->tgt, g->idx, g->stage.posq, g->stage.qn};
+  void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->idx,
+                  g->stage.posq, g->stage.qn};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete g;
@@ -372,6 +373,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   hipError_t e = dev_upload(&g->src_pos, pos.data(), N, &bytes);
   if (e == hipSuccess && d->normals) e = dev_upload(&g->src_nrm, nrm.data(), N, &bytes);
   if (e == hipSuccess && reorder) e = dev_upload(&g->src_perm, perm.data(), N, &bytes);
+  if (e == hipSuccess && reorder) e = dev_upload(&g->src_rank, src_rank.data(), N, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->tgt, recs.data(), T, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->idx, idx.data(), nnz_dev, &bytes);
   if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N + 1, &bytes);
@@ -459,15 +461,17 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
   const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
   TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, s));
   TSQBX_HIP(launch_eval(g, p, layers, g->stage, ds, dd, false, tn, s));
-  std::vector<double> hs((layers & TSQBX_SLP) ? T : 0), hd((layers & TSQBX_DLP) ? T : 0);
-  if (T && (layers & TSQBX_SLP))
-    TSQBX_HIP(hipMemcpyAsync(hs.data(), ds, T * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (T && (layers & TSQBX_DLP))
-    TSQBX_HIP(hipMemcpyAsync(hd.data(), dd, T * sizeof(double), hipMemcpyDeviceToHost, s));
-  TSQBX_HIP(hipStreamSynchronize(s));
+  // without ACCUMULATE the outputs go straight into the caller's arrays
   const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
-  for (size_t i = 0; i < hs.size(); ++i) out_slp[i] = acc ? out_slp[i] + hs[i] : hs[i];
-  for (size_t i = 0; i < hd.size(); ++i) out_dlp[i] = acc ? out_dlp[i] + hd[i] : hd[i];
+  std::vector<double> hs(acc && (layers & TSQBX_SLP) ? T : 0), hd(acc && (layers & TSQBX_DLP) ? T : 0);
+  double *dst_s = acc ? hs.data() : out_slp, *dst_d = acc ? hd.data() : out_dlp;
+  if (T && (layers & TSQBX_SLP))
+    TSQBX_HIP(hipMemcpyAsync(dst_s, ds, T * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (T && (layers & TSQBX_DLP))
+    TSQBX_HIP(hipMemcpyAsync(dst_d, dd, T * sizeof(double), hipMemcpyDeviceToHost, s));
+  TSQBX_HIP(hipStreamSynchronize(s));
+  for (size_t i = 0; i < hs.size(); ++i) out_slp[i] += hs[i];
+  for (size_t i = 0; i < hd.size(); ++i) out_dlp[i] += hd[i];
   return TSQBX_OK;
 }
 

@@ -69,6 +69,7 @@ struct tsqbx_geometry {
   double4 *src_pos = nullptr;    // [N] (x, y, z, w) in device order
   double4 *src_nrm = nullptr;    // [N] (nx, ny, nz, 0) or null
   int64_t *src_perm = nullptr;   // [N] device order -> caller index, null if identity
+  int32_t *src_rank = nullptr;   // [N] caller index -> device order, null if identity
   tsqbx::TargetRec *tgt = nullptr;  // [T] in device order
   int32_t *idx = nullptr;        // [nnz'] lists in device numbering, one row per target group
   tsqbx::SourceStage stage;      // staging used by the plain path
@@ -99,8 +100,8 @@ bool tuning_supported(const Tuning &tn);
 struct StageItem {         // 64 bytes
   const double4 *pos_w;
   const double4 *nrm;
-  const int64_t *perm;
-  const double *sigma;
+  const int32_t *rank;       // caller index -> device order (null: identity)
+  const double *sigma;       // caller order; device or pinned host memory
   double4 *posq;
   double4 *qn;
   int64_t n;
@@ -110,6 +111,16 @@ struct StageItem {         // 64 bytes
 StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
                           const SourceStage &st);
 hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
+
+// Many contiguous copies in one launch (device or pinned host memory on
+// either side).
+struct CopyItem {          // 32 bytes
+  const double *src;
+  double *dst;
+  int64_t n;
+  int64_t pad;
+};
+hipError_t launch_copy_multi(const CopyItem *d_items, int n_items, int64_t max_n, hipStream_t s);
 
 // Persistent batched kernel.
 struct WorkItem {           // one (geometry, p, layers) item of a plan, 128 bytes

@@ -386,42 +386,58 @@ k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict_
 }
 
 // The same staging for many items: blockIdx.y selects the item.
+// The same staging for many items (blockIdx.y selects the item), walking the
+// sources in the caller's order so that the density is read contiguously
+// (it may live in pinned host memory, read across PCIe).
 __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict__ items) {
   const TSQBX_GLOBAL StageItem *gi = (const TSQBX_GLOBAL StageItem *)items + blockIdx.y;
   const int64_t n = gi->n;
   const int want_dlp = gi->want_dlp;
   const TSQBX_GLOBAL double *pw = (const TSQBX_GLOBAL double *)gi->pos_w;  // (x, y, z, w)
   const TSQBX_GLOBAL double *nv = (const TSQBX_GLOBAL double *)gi->nrm;    // (nx, ny, nz, 0)
-  const TSQBX_GLOBAL int64_t *perm = (const TSQBX_GLOBAL int64_t *)gi->perm;
-  const TSQBX_GLOBAL double *sigma = (const TSQBX_GLOBAL double *)gi->sigma;
+  const TSQBX_GLOBAL int32_t *rank = (const TSQBX_GLOBAL int32_t *)gi->rank;
+  const double *sigma = gi->sigma;
   TSQBX_GLOBAL double *posq = (TSQBX_GLOBAL double *)gi->posq;
   TSQBX_GLOBAL double *qn = (TSQBX_GLOBAL double *)gi->qn;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    // entry n: the padding record
-    double x = 1e100, y = 1e100, z = 1e100, q = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
-    if (i < n) {
-      x = pw[4 * i];
-      y = pw[4 * i + 1];
-      z = pw[4 * i + 2];
-      q = pw[4 * i + 3] * sigma[perm ? perm[i] : i];
+    if (i == n) {  // the padding record
+      posq[4 * n] = 1e100;
+      posq[4 * n + 1] = 1e100;
+      posq[4 * n + 2] = 1e100;
+      posq[4 * n + 3] = 0.0;
       if (want_dlp) {
-        nx = q * nv[4 * i];
-        ny = q * nv[4 * i + 1];
-        nz = q * nv[4 * i + 2];
+        qn[4 * n] = 0.0;
+        qn[4 * n + 1] = 0.0;
+        qn[4 * n + 2] = 0.0;
+        qn[4 * n + 3] = 0.0;
       }
+      continue;
     }
-    posq[4 * i] = x;
-    posq[4 * i + 1] = y;
-    posq[4 * i + 2] = z;
-    posq[4 * i + 3] = q;
+    const int64_t j = rank ? (int64_t)rank[i] : i;
+    const double q = pw[4 * j + 3] * sigma[i];
+    posq[4 * j] = pw[4 * j];
+    posq[4 * j + 1] = pw[4 * j + 1];
+    posq[4 * j + 2] = pw[4 * j + 2];
+    posq[4 * j + 3] = q;
     if (want_dlp) {
-      qn[4 * i] = nx;
-      qn[4 * i + 1] = ny;
-      qn[4 * i + 2] = nz;
-      qn[4 * i + 3] = 0.0;
+      qn[4 * j] = q * nv[4 * j];
+      qn[4 * j + 1] = q * nv[4 * j + 1];
+      qn[4 * j + 2] = q * nv[4 * j + 2];
+      qn[4 * j + 3] = 0.0;
     }
   }
+}
+
+// Contiguous copies, blockIdx.y selects the item.
+__global__ void __launch_bounds__(256) k_copy_multi(const CopyItem *__restrict__ items) {
+  const TSQBX_GLOBAL CopyItem *ci = (const TSQBX_GLOBAL CopyItem *)items + blockIdx.y;
+  const int64_t n = ci->n;
+  const double *src = ci->src;
+  double *dst = ci->dst;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 // ---- persistent batched kernel ---------------------------------------------
@@ -581,7 +597,7 @@ StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsign
   StageItem it{};
   it.pos_w = g->src_pos;
   it.nrm = g->src_nrm;
-  it.perm = g->src_perm;
+  it.rank = g->src_rank;
   it.sigma = d_sigma;
   it.posq = st.posq;
   it.qn = st.qn;
@@ -601,9 +617,20 @@ hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max
 }
 
 
+hipError_t launch_copy_multi(const CopyItem *d_items, int n_items, int64_t max_n,
+                             hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (n_items > 65535) return hipErrorInvalidValue;
+  const int64_t bx = std::min<int64_t>((max_n + 255) / 256, 256);
+  hipLaunchKernelGGL(k_copy_multi, dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)n_items),
+                     dim3(256), 0, s, d_items);
+  return hipGetLastError();
+}
+
 int persistent_max_waves(int num_cus) {
-  // six resident waves per SIMD
-  return std::max(1, num_cus) * 4 * 6;
+  // eight times the waves that fit at six per SIMD: the dispatcher hands out
+  // blocks as others finish, which evens out differences in speed
+  return std::max(1, num_cus) * 4 * 6 * 8;
 }
 
 namespace {

@@ -20,6 +20,7 @@
 #include <deque>
 #include <list>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "tsqbx_internal.h"
@@ -29,6 +30,7 @@ using namespace tsqbx;
 namespace {
 
 constexpr int kStreams = 4;
+constexpr int kUnitSteps = 8;  // wave-steps (group_lanes-wide passes) per unit
 constexpr size_t kAlign = 256;
 
 double now_s() {
@@ -84,6 +86,8 @@ struct Request {
   // host staging: [sigma (N) | out_slp (T) | out_dlp (T)], pinned when it fits
   double *h_stage = nullptr;
   bool pinned = false;
+  bool borrowed = false;            // caller's pinned buffers, no staging
+  const double *sigma_src = nullptr;  // what the upload reads
   size_t pin_off = 0, pin_bytes = 0;
   std::vector<double> pageable;  // fallback staging
   double *out_s = nullptr, *out_d = nullptr;
@@ -104,12 +108,10 @@ struct StreamSlot {
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   bool busy = false;
-  // step metadata, pinned host copy and device copy (grown on demand)
-  WorkItem *d_items = nullptr, *h_items = nullptr;
-  StageItem *d_stage = nullptr, *h_stage = nullptr;
-  WorkUnit *d_units = nullptr, *h_units = nullptr;
-  int32_t *d_wave = nullptr, *h_wave = nullptr;
-  size_t cap_items = 0, cap_stage = 0, cap_units = 0, cap_wave = 0;
+  // the step's work items, staging items, copy items, units and wave ranges:
+  // one pinned host block and its device copy (grown on demand)
+  char *h_meta = nullptr, *d_meta = nullptr;
+  size_t cap_meta = 0;
 };
 
 double percentile(std::vector<double> v, double q) {
@@ -149,6 +151,7 @@ struct tsqbx_server {
   tsqbx_server_stats st{};
   std::vector<double> lat_ms, queue_ms;
   double busy_since = -1, busy_acc = 0;
+  double host_launch_s = 0;  // scheduler time spent issuing steps
   std::thread sched, comp;
 
   int launch_step(Step &step, std::string &err);
@@ -174,22 +177,10 @@ static size_t request_bytes(const tsqbx_geometry *g, unsigned layers) {
   return std::max<size_t>(b, kAlign);
 }
 
-template <class T>
-static hipError_t grow_pair(T **d, T **h, size_t *cap, size_t need) {
-  if (*cap >= need) return hipSuccess;
-  if (*d) (void)hipFree(*d);
-  if (*h) (void)hipHostFree(*h);
-  *d = nullptr;
-  *h = nullptr;
-  *cap = 0;
-  const size_t n = std::max<size_t>(need * 2, 64);
-  hipError_t e = hipMalloc((void **)d, n * sizeof(T));
-  if (e == hipSuccess) e = hipHostMalloc((void **)h, n * sizeof(T), 0);
-  if (e == hipSuccess) *cap = n;
-  return e;
-}
-
 // Launch one step (called by the scheduler with the lock released).
+// Densities in pinned host memory are read by the staging kernel directly
+// and outputs are written back by one copy kernel; only requests whose host
+// staging had to fall back to pageable memory use DMA copies.
 int tsqbx_server::launch_step(Step &step, std::string &err) {
   StreamSlot &ss = streams[step.stream];
   hipStream_t s = ss.s;
@@ -199,17 +190,15 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     return TSQBX_E_DEVICE;
   };
   const size_t K = step.reqs.size();
-  // work items and a static schedule, tuned once per server (results do not
-  // depend on the mix)
+  std::vector<WorkItem> items(K);
+  std::vector<StageItem> stage(K);
+  std::vector<CopyItem> copies;
   std::vector<WorkUnit> units;
   std::vector<int32_t> wave_begin;
-  std::vector<ScheduleItem> sched(K);
-  std::vector<int32_t> order(K);
-  std::vector<std::pair<double *, double *>> dev_out(K);
-  int64_t max_n = 0;
-  e = grow_pair(&ss.d_items, &ss.h_items, &ss.cap_items, K);
-  if (e == hipSuccess) e = grow_pair(&ss.d_stage, &ss.h_stage, &ss.cap_stage, K);
-  if (e != hipSuccess) return fail_e(e, "step item buffers");
+  // DMA copies for requests staged in pageable memory: (destination, source, count)
+  std::vector<std::tuple<double *, const double *, size_t>> pageable_up, pageable_down;
+  int64_t max_n = 0, max_t = 0;
+  const int64_t per_unit = (int64_t)kUnitSteps * (64 / tn.group_lanes);
   for (size_t i = 0; i < K; ++i) {
     Request *r = step.reqs[i];
     const tsqbx_geometry *g = r->geom;
@@ -230,11 +219,16 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
       off += align_up(T * sizeof(double));
     }
     if (r->layers & TSQBX_DLP) d_out_d = (double *)(base + off);
-    if (N && e == hipSuccess)
-      e = hipMemcpyAsync(d_sigma, r->h_stage, N * sizeof(double), hipMemcpyHostToDevice, s);
-    ss.h_stage[i] = make_stage_item(g, d_sigma, r->layers, stg);
+    const bool host_pinned = r->borrowed || r->pinned;
+    const double *sig = r->sigma_src;
+    if (!host_pinned) {
+      if (N) pageable_up.emplace_back(d_sigma, r->sigma_src, N);
+      sig = d_sigma;
+    }
+    stage[i] = make_stage_item(g, sig, r->layers, stg);
     max_n = std::max<int64_t>(max_n, g->n_sources);
-    WorkItem &w = ss.h_items[i];
+    max_t = std::max<int64_t>(max_t, g->n_targets);
+    WorkItem &w = items[i];
     w = WorkItem{};
     w.tgt = g->tgt;
     w.idx = g->idx;
@@ -244,50 +238,72 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     w.out_d = d_out_d;
     w.p = r->p;
     w.layers = (int32_t)r->layers;
-    sched[i] = ScheduleItem{g, r->p, r->layers};
-    order[i] = (int32_t)i;
-    dev_out[i] = {d_out_s, d_out_d};
+    // fixed-size units, one per wave: constant host work per unit, and the
+    // dispatcher balances the waves
+    for (int64_t k = 0; k < g->n_targets; k += per_unit) {
+      wave_begin.push_back((int32_t)units.size());
+      units.push_back(WorkUnit{(int32_t)i, (int32_t)k,
+                               (int32_t)std::min<int64_t>(per_unit, g->n_targets - k), 0});
+    }
+    // outputs: into the caller's pinned buffers or the request's host staging
+    if (T) {
+      double *hs = r->borrowed ? r->out_s : r->h_stage + N;
+      double *hd = r->borrowed ? r->out_d : r->h_stage + N + ((r->layers & TSQBX_SLP) ? T : 0);
+      const std::pair<double *, const double *> outs[2] = {
+          {(r->layers & TSQBX_SLP) ? hs : nullptr, d_out_s},
+          {(r->layers & TSQBX_DLP) ? hd : nullptr, d_out_d}};
+      for (const auto &o : outs) {
+        if (!o.first) continue;
+        if (host_pinned)
+          copies.push_back(CopyItem{o.second, o.first, (int64_t)T, 0});
+        else
+          pageable_down.emplace_back(o.first, o.second, T);
+      }
+    }
   }
-  build_schedule(sched, order, tn.group_lanes,
-                 persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256), &units, &wave_begin);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ss.d_stage, ss.h_stage, K * sizeof(StageItem), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_stage_multi(ss.d_stage, (int)K, max_n, s);
+  wave_begin.push_back((int32_t)units.size());
+  if (copies.size() > 65535) return fail_e(hipErrorInvalidValue, "too many copies in one step");
+  // one metadata block
+  const size_t o_items = 0;
+  const size_t o_stage = align_up(o_items + K * sizeof(WorkItem));
+  const size_t o_copy = align_up(o_stage + K * sizeof(StageItem));
+  const size_t o_units = align_up(o_copy + copies.size() * sizeof(CopyItem));
+  const size_t o_wave = align_up(o_units + units.size() * sizeof(WorkUnit));
+  const size_t total = align_up(o_wave + wave_begin.size() * sizeof(int32_t));
+  if (ss.cap_meta < total) {
+    if (ss.d_meta) (void)hipFree(ss.d_meta);
+    if (ss.h_meta) (void)hipHostFree(ss.h_meta);
+    ss.d_meta = ss.h_meta = nullptr;
+    ss.cap_meta = 0;
+    const size_t cap = std::max<size_t>(total * 2, size_t(1) << 20);
+    e = hipMalloc((void **)&ss.d_meta, cap);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&ss.h_meta, cap, 0);
+    if (e != hipSuccess) return fail_e(e, "step metadata buffers");
+    ss.cap_meta = cap;
+  }
+  std::memcpy(ss.h_meta + o_items, items.data(), K * sizeof(WorkItem));
+  std::memcpy(ss.h_meta + o_stage, stage.data(), K * sizeof(StageItem));
+  if (!copies.empty()) std::memcpy(ss.h_meta + o_copy, copies.data(), copies.size() * sizeof(CopyItem));
+  if (!units.empty()) std::memcpy(ss.h_meta + o_units, units.data(), units.size() * sizeof(WorkUnit));
+  std::memcpy(ss.h_meta + o_wave, wave_begin.data(), wave_begin.size() * sizeof(int32_t));
+  e = hipMemcpyAsync(ss.d_meta, ss.h_meta, total, hipMemcpyHostToDevice, s);
+  for (size_t i = 0; i < pageable_up.size() && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(std::get<0>(pageable_up[i]), std::get<1>(pageable_up[i]),
+                       std::get<2>(pageable_up[i]) * sizeof(double), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail_e(e, "step upload");
-  if (!units.empty()) {
-    e = grow_pair(&ss.d_units, &ss.h_units, &ss.cap_units, units.size());
-    if (e == hipSuccess) e = grow_pair(&ss.d_wave, &ss.h_wave, &ss.cap_wave, wave_begin.size());
-    if (e != hipSuccess) return fail_e(e, "step unit buffers");
-    std::memcpy(ss.h_units, units.data(), units.size() * sizeof(WorkUnit));
-    std::memcpy(ss.h_wave, wave_begin.data(), wave_begin.size() * sizeof(int32_t));
-    e = hipMemcpyAsync(ss.d_items, ss.h_items, K * sizeof(WorkItem), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(ss.d_units, ss.h_units, units.size() * sizeof(WorkUnit),
-                         hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(ss.d_wave, ss.h_wave, wave_begin.size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
-      PersistentArgs a{ss.d_items, ss.d_units, ss.d_wave, (int32_t)wave_begin.size() - 1};
-      e = launch_persistent(a, 3u, -1, tn, s);
-    }
-    if (e != hipSuccess) return fail_e(e, "step launch");
+  e = launch_stage_multi((const StageItem *)(ss.d_meta + o_stage), (int)K, max_n, s);
+  if (e == hipSuccess && !units.empty()) {
+    PersistentArgs a{(const WorkItem *)(ss.d_meta + o_items), (const WorkUnit *)(ss.d_meta + o_units),
+                     (const int32_t *)(ss.d_meta + o_wave), (int32_t)wave_begin.size() - 1};
+    e = launch_persistent(a, 3u, -1, tn, s);
   }
-  // outputs straight into each request's host staging
-  for (size_t i = 0; i < K && e == hipSuccess; ++i) {
-    Request *r = step.reqs[i];
-    const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
-    if (!T) continue;
-    double *h = r->h_stage + N;
-    if (r->layers & TSQBX_SLP) {
-      e = hipMemcpyAsync(h, dev_out[i].first, T * sizeof(double), hipMemcpyDeviceToHost, s);
-      h += T;
-    }
-    if (e == hipSuccess && (r->layers & TSQBX_DLP))
-      e = hipMemcpyAsync(h, dev_out[i].second, T * sizeof(double), hipMemcpyDeviceToHost, s);
-  }
+  if (e == hipSuccess)
+    e = launch_copy_multi((const CopyItem *)(ss.d_meta + o_copy), (int)copies.size(), max_t, s);
+  for (size_t i = 0; i < pageable_down.size() && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(std::get<0>(pageable_down[i]), std::get<1>(pageable_down[i]),
+                       std::get<2>(pageable_down[i]) * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(ss.ev, s);
-  if (e != hipSuccess) return fail_e(e, "step download");
+  if (e != hipSuccess) return fail_e(e, "step launch");
   step.done_ev = ss.ev;
   return TSQBX_OK;
 }
@@ -336,8 +352,11 @@ void tsqbx_server::scheduler() {
     if (busy_since < 0) busy_since = t0;
     lk.unlock();
     std::string err;
+    const double th0 = now_s();
     int rc = launch_step(step, err);
+    const double th1 = now_s();
     lk.lock();
+    host_launch_s += th1 - th0;
     if (rc != TSQBX_OK) {
       // the stream may hold partial work: wait for it, then fail the step's requests
       lk.unlock();
@@ -414,12 +433,14 @@ void tsqbx_server::completer() {
     for (Request *r : step.reqs) {
       const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
       if (qerr == hipSuccess) {
-        const double *h = r->h_stage + N;
-        if (r->layers & TSQBX_SLP) {
-          if (T) std::memcpy(r->out_s, h, T * sizeof(double));
-          h += T;
+        if (!r->borrowed) {
+          const double *h = r->h_stage + N;
+          if (r->layers & TSQBX_SLP) {
+            if (T) std::memcpy(r->out_s, h, T * sizeof(double));
+            h += T;
+          }
+          if ((r->layers & TSQBX_DLP) && T) std::memcpy(r->out_d, h, T * sizeof(double));
         }
-        if ((r->layers & TSQBX_DLP) && T) std::memcpy(r->out_d, h, T * sizeof(double));
         ++st.completed;
         st.pair_terms_completed +=
             r->geom->pairs * (int64_t)(r->p + 1) * (((r->layers & 1) ? 1 : 0) + ((r->layers & 2) ? 1 : 0));
@@ -503,9 +524,19 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   return TSQBX_OK;
 }
 
-int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
-                        const double *sigma_host, double *out_slp_host, double *out_dlp_host,
-                        uint64_t *ticket) {
+static bool is_pinned_host(const void *p) {
+  if (!p) return true;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // clear the error a pageable pointer leaves behind
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
+
+static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
+                       const double *sigma_host, double *out_slp_host, double *out_dlp_host,
+                       uint64_t *ticket, bool borrow) {
   if (!sv || !geom || !ticket) return fail(TSQBX_E_INVALID, "server, geometry or ticket is NULL");
   if (geom->ctx != sv->ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = tsqbx_check_request(geom, p, layers);
@@ -513,25 +544,39 @@ int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, uns
   if (geom->n_sources > 0 && !sigma_host) return fail(TSQBX_E_INVALID, "sigma is NULL");
   if (geom->n_targets > 0 && (((layers & TSQBX_SLP) && !out_slp_host) || ((layers & TSQBX_DLP) && !out_dlp_host)))
     return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  if (borrow) {
+    const double *bufs[3] = {geom->n_sources ? sigma_host : nullptr,
+                             (geom->n_targets && (layers & TSQBX_SLP)) ? out_slp_host : nullptr,
+                             (geom->n_targets && (layers & TSQBX_DLP)) ? out_dlp_host : nullptr};
+    for (const double *b : bufs)
+      if (!is_pinned_host(b))
+        return fail(TSQBX_E_INVALID, "submit_pinned: a buffer is not pinned host memory");
+  }
   const size_t bytes = request_bytes(geom, layers);
   auto *r = new Request;
   r->geom = geom;
   r->p = p;
   r->layers = layers;
   const size_t N = (size_t)geom->n_sources, T = (size_t)geom->n_targets;
-  const size_t words = N + T * ((layers & TSQBX_SLP ? 1 : 0) + (layers & TSQBX_DLP ? 1 : 0));
-  r->pin_bytes = align_up(std::max<size_t>(words, 1) * sizeof(double));
-  {
-    std::lock_guard<std::mutex> g(sv->pinned_mu);
-    r->pinned = sv->pinned_cap > 0 && sv->pinned.alloc(r->pin_bytes, &r->pin_off);
-  }
-  if (r->pinned) {
-    r->h_stage = (double *)(sv->pinned_base + r->pin_off);
+  if (borrow) {
+    r->borrowed = true;
+    r->sigma_src = sigma_host;
   } else {
-    r->pageable.resize(std::max<size_t>(words, 1));
-    r->h_stage = r->pageable.data();
+    const size_t words = N + T * ((layers & TSQBX_SLP ? 1 : 0) + (layers & TSQBX_DLP ? 1 : 0));
+    r->pin_bytes = align_up(std::max<size_t>(words, 1) * sizeof(double));
+    {
+      std::lock_guard<std::mutex> g(sv->pinned_mu);
+      r->pinned = sv->pinned_cap > 0 && sv->pinned.alloc(r->pin_bytes, &r->pin_off);
+    }
+    if (r->pinned) {
+      r->h_stage = (double *)(sv->pinned_base + r->pin_off);
+    } else {
+      r->pageable.resize(std::max<size_t>(words, 1));
+      r->h_stage = r->pageable.data();
+    }
+    if (N) std::memcpy(r->h_stage, sigma_host, N * sizeof(double));
+    r->sigma_src = r->h_stage;
   }
-  if (N) std::memcpy(r->h_stage, sigma_host, N * sizeof(double));
   r->out_s = out_slp_host;
   r->out_d = out_dlp_host;
   r->bytes = bytes;
@@ -555,6 +600,18 @@ int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, uns
   *ticket = r->ticket;
   sv->cv_sched.notify_all();
   return TSQBX_OK;
+}
+
+int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
+                        const double *sigma_host, double *out_slp_host, double *out_dlp_host,
+                        uint64_t *ticket) {
+  return submit_impl(sv, geom, p, layers, sigma_host, out_slp_host, out_dlp_host, ticket, false);
+}
+
+int tsqbx_server_submit_pinned(tsqbx_server *sv, const tsqbx_geometry *geom, int p,
+                               unsigned layers, const double *sigma_host, double *out_slp_host,
+                               double *out_dlp_host, uint64_t *ticket) {
+  return submit_impl(sv, geom, p, layers, sigma_host, out_slp_host, out_dlp_host, ticket, true);
 }
 
 int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {
@@ -602,6 +659,7 @@ int tsqbx_server_get_stats(tsqbx_server *sv, tsqbx_server_stats *out) {
   out->queue_p50_ms = percentile(sv->queue_ms, 0.50);
   out->queue_p99_ms = percentile(sv->queue_ms, 0.99);
   out->busy_s = sv->busy_acc + (sv->busy_since >= 0 ? now_s() - sv->busy_since : 0.0);
+  out->host_launch_s = sv->host_launch_s;
   return TSQBX_OK;
 }
 
@@ -626,14 +684,8 @@ int tsqbx_server_destroy(tsqbx_server *sv) {
   (void)hipSetDevice(sv->device);
   for (auto &ss : sv->streams) {
     if (ss.s) (void)hipStreamSynchronize(ss.s);
-    if (ss.d_items) (void)hipFree(ss.d_items);
-    if (ss.d_stage) (void)hipFree(ss.d_stage);
-    if (ss.d_units) (void)hipFree(ss.d_units);
-    if (ss.d_wave) (void)hipFree(ss.d_wave);
-    if (ss.h_wave) (void)hipHostFree(ss.h_wave);
-    if (ss.h_items) (void)hipHostFree(ss.h_items);
-    if (ss.h_stage) (void)hipHostFree(ss.h_stage);
-    if (ss.h_units) (void)hipHostFree(ss.h_units);
+    if (ss.d_meta) (void)hipFree(ss.d_meta);
+    if (ss.h_meta) (void)hipHostFree(ss.h_meta);
     if (ss.ev) (void)hipEventDestroy(ss.ev);
     if (ss.s) (void)hipStreamDestroy(ss.s);
   }

@@ -144,3 +144,31 @@ def test_server_rejects_oversized_and_respects_budget(ctx):
     for _, a, _b in ts:
         assert np.array_equal(a, ts[0][1])
     srv.close()
+
+
+def test_server_pinned_submissions_match_copying_ones(ctx):
+    import torch
+
+    geoms = W.config_e_geometries(n_geometries=3, scale=32)
+    gs = [ctx.geometry(g) for g in geoms]
+    srv = ctx.server(4 * max(api.Server.request_bytes(g, 3) for g in gs), 6)
+    rng = np.random.default_rng(11)
+    pending = []
+    for i in range(12):
+        k = i % 3
+        lay = (1, 2, 3)[i % 3]
+        s_np = rng.standard_normal(geoms[k].n_sources)
+        s_pin = torch.tensor(s_np, dtype=torch.float64).pin_memory()
+        t1, a1, b1 = srv.submit(gs[k], s_np, 8 + 8 * (i % 2), lay)
+        t2, a2, b2 = srv.submit_pinned(gs[k], s_pin, 8 + 8 * (i % 2), lay)
+        pending.append((lay, a1, b1, a2, b2))
+    srv.drain(120)
+    for lay, a1, b1, a2, b2 in pending:
+        if lay & 1:
+            assert np.array_equal(a1, a2.numpy())
+        if lay & 2:
+            assert np.array_equal(b1, b2.numpy())
+    with pytest.raises(api.TsqbxError) as ei:  # pageable memory is refused
+        srv.submit_pinned(gs[0], torch.zeros(geoms[0].n_sources, dtype=torch.float64), 8, 1)
+    assert ei.value.code == -1
+    srv.close()
