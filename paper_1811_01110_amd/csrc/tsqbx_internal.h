@@ -100,16 +100,16 @@ bool tuning_supported(const Tuning &tn);
 struct StageItem {         // 64 bytes
   const double4 *pos_w;
   const double4 *nrm;
-  const int32_t *rank;       // caller index -> device order (null: identity)
+  const void *order;         // host_sigma: rank (int32, caller -> device); else perm (int64)
   const double *sigma;       // caller order; device or pinned host memory
   double4 *posq;
   double4 *qn;
   int64_t n;
   int32_t want_dlp;
-  int32_t pad;
+  int32_t host_sigma;        // 1: walk sources in caller order (contiguous reads of sigma)
 };
-StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
-                          const SourceStage &st);
+StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned layers,
+                          const SourceStage &st, bool sigma_on_host);
 hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
 
 // Many contiguous copies in one launch (device or pinned host memory on

@@ -386,16 +386,19 @@ k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict_
 }
 
 // The same staging for many items: blockIdx.y selects the item.
-// The same staging for many items (blockIdx.y selects the item), walking the
-// sources in the caller's order so that the density is read contiguously
-// (it may live in pinned host memory, read across PCIe).
+// The same staging for many items (blockIdx.y selects the item).  A density
+// in device memory is gathered while walking the sources in device order; a
+// density in pinned host memory is read contiguously, walking the sources in
+// the caller's order, since every read then crosses PCIe.
 __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict__ items) {
   const TSQBX_GLOBAL StageItem *gi = (const TSQBX_GLOBAL StageItem *)items + blockIdx.y;
   const int64_t n = gi->n;
   const int want_dlp = gi->want_dlp;
+  const int host_sigma = gi->host_sigma;
   const TSQBX_GLOBAL double *pw = (const TSQBX_GLOBAL double *)gi->pos_w;  // (x, y, z, w)
   const TSQBX_GLOBAL double *nv = (const TSQBX_GLOBAL double *)gi->nrm;    // (nx, ny, nz, 0)
-  const TSQBX_GLOBAL int32_t *rank = (const TSQBX_GLOBAL int32_t *)gi->rank;
+  const TSQBX_GLOBAL int32_t *rank = (const TSQBX_GLOBAL int32_t *)gi->order;
+  const TSQBX_GLOBAL int64_t *perm = (const TSQBX_GLOBAL int64_t *)gi->order;
   const double *sigma = gi->sigma;
   TSQBX_GLOBAL double *posq = (TSQBX_GLOBAL double *)gi->posq;
   TSQBX_GLOBAL double *qn = (TSQBX_GLOBAL double *)gi->qn;
@@ -414,8 +417,16 @@ __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict
       }
       continue;
     }
-    const int64_t j = rank ? (int64_t)rank[i] : i;
-    const double q = pw[4 * j + 3] * sigma[i];
+    int64_t j;  // device index
+    double sg;
+    if (host_sigma) {
+      j = rank ? (int64_t)rank[i] : i;
+      sg = sigma[i];
+    } else {
+      j = i;
+      sg = sigma[perm ? perm[i] : i];
+    }
+    const double q = pw[4 * j + 3] * sg;
     posq[4 * j] = pw[4 * j];
     posq[4 * j + 1] = pw[4 * j + 1];
     posq[4 * j + 2] = pw[4 * j + 2];
@@ -592,13 +603,14 @@ hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned
   return hipGetLastError();
 }
 
-StageItem make_stage_item(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
-                          const SourceStage &st) {
+StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned layers,
+                          const SourceStage &st, bool sigma_on_host) {
   StageItem it{};
   it.pos_w = g->src_pos;
   it.nrm = g->src_nrm;
-  it.rank = g->src_rank;
-  it.sigma = d_sigma;
+  it.host_sigma = sigma_on_host ? 1 : 0;
+  it.order = sigma_on_host ? (const void *)g->src_rank : (const void *)g->src_perm;
+  it.sigma = sigma;
   it.posq = st.posq;
   it.qn = st.qn;
   it.n = g->n_sources;

@@ -227,7 +227,7 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
       e = hipMalloc((void **)&pl->stages[i].qn, N1 * sizeof(double4));
       pl->device_bytes += N1 * sizeof(double4);
     }
-    sitems[i] = make_stage_item(it.geom, it.d_sigma, it.layers, pl->stages[i]);
+    sitems[i] = make_stage_item(it.geom, it.d_sigma, it.layers, pl->stages[i], false);
     pl->max_sources = std::max<int64_t>(pl->max_sources, it.geom->n_sources);
     WorkItem &w = witems[i];
     w = WorkItem{};

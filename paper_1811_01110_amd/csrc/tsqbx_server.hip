@@ -31,6 +31,10 @@ namespace {
 
 constexpr int kStreams = 4;
 constexpr int kUnitSteps = 8;  // wave-steps (group_lanes-wide passes) per unit
+// Requests per step: small enough that the next step's density reads (PCIe)
+// overlap this step's evaluation on another stream, large enough to amortise
+// the step's launches.
+constexpr int kMaxStepRequests = 32;
 constexpr size_t kAlign = 256;
 
 double now_s() {
@@ -225,7 +229,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
       if (N) pageable_up.emplace_back(d_sigma, r->sigma_src, N);
       sig = d_sigma;
     }
-    stage[i] = make_stage_item(g, sig, r->layers, stg);
+    stage[i] = make_stage_item(g, sig, r->layers, stg, host_pinned);
     max_n = std::max<int64_t>(max_n, g->n_sources);
     max_t = std::max<int64_t>(max_t, g->n_targets);
     WorkItem &w = items[i];
@@ -328,7 +332,8 @@ void tsqbx_server::scheduler() {
         step.stream = k;
         break;
       }
-    while (!queue.empty() && reqs_in_flight < max_slots) {
+    while (!queue.empty() && reqs_in_flight < max_slots &&
+           step.reqs.size() < (size_t)kMaxStepRequests) {
       Request *r = queue.front();
       size_t off = 0;
       if (bytes_in_flight + r->bytes > budget || !arena.alloc(r->bytes, &off)) break;

@@ -1,0 +1,37 @@
+"""bench.py contract checks that need no GPU."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_flop_model_matches_kernel_structure():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    # 25 setup operations, 6 per order, the closing sums per layer mask
+    assert bench.flops_per_pair(16, 1) == 6 * 16 + 23
+    assert bench.flops_per_pair(16, 2) == 6 * 16 + 37
+    assert bench.flops_per_pair(16, 3) == 6 * 16 + 48
+    assert bench.flops_per_pair(0, 3) == bench.flops_per_pair(1, 3)
+    assert bench.flops_per_pair(0, 1) == 28
+
+
+def test_traffic_record_is_ignored_after_a_kernel_change(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+
+    rec = tmp_path / "t.json"
+    rec.write_text(json.dumps({"kernel_source_sha256": "0" * 64, "hbm_bytes_per_launch": 1.0}))
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec))
+    assert bench.measured_traffic() is None
