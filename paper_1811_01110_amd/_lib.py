@@ -10,7 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtsqbx.so")
+LIBPATH = os.environ.get("TSQBX_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                       "libtsqbx.so")
 
 c_int, c_uint, c_int64, c_uint64, c_size_t, c_double, c_void_p, c_char_p = (
     ctypes.c_int, ctypes.c_uint, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t,
