@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tsqbx_oracle.c")
 LIB = os.path.join(HERE, "liboracle_tsqbx.so")
 
-SLP, DLP = 1, 2
+SLP, DLP, SPRIME = 1, 2, 4
 
 _lib = None
 
@@ -45,6 +45,7 @@ class _Problem(ctypes.Structure):
         ("n_targets", ctypes.c_int64),
         ("targets", ctypes.c_void_p),
         ("target_center", ctypes.c_void_p),
+        ("target_normals", ctypes.c_void_p),
     ]
 
 
@@ -54,12 +55,11 @@ def _load():
         if not os.path.exists(LIB):
             build(force=False)
         lib = ctypes.CDLL(LIB)
-        lib.tsqbx_oracle_pair.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_void_p]
+        lib.tsqbx_oracle_pair.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_void_p]
         lib.tsqbx_oracle_pair.restype = None
         lib.tsqbx_oracle_eval.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_uint,
                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                          ctypes.c_void_p, ctypes.c_int]
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.tsqbx_oracle_eval.restype = ctypes.c_int
         lib.tsqbx_oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -81,21 +81,24 @@ def _f64(a, shape=None):
     return a
 
 
-def pair(t, c, s, nu, p: int):
-    """(G^(p), nu . grad_s G^(p), sum |terms| of each) for one pair."""
+def pair(t, c, s, nu, p: int, nu_t=None):
+    """One pair: [G^(p), nu . grad_s G^(p), |.| yardsticks of both,
+    nu_t . grad_t G^(p), its yardstick]."""
     t, c, s = _f64(t, 3), _f64(c, 3), _f64(s, 3)
     nu = None if nu is None else _f64(nu, 3)
-    out = np.zeros(4)
-    _load().tsqbx_oracle_pair(_ptr(t), _ptr(c), _ptr(s), _ptr(nu), int(p), _ptr(out))
+    nu_t = None if nu_t is None else _f64(nu_t, 3)
+    out = np.zeros(6)
+    _load().tsqbx_oracle_pair(_ptr(t), _ptr(c), _ptr(s), _ptr(nu), _ptr(nu_t), int(p), _ptr(out))
     return out
 
 
 def evaluate(sources, weights, normals, centers, list_offsets, list_sources, targets,
-             target_center, sigma, p: int, layers: int, select=None, n_threads: int = 0):
+             target_center, sigma, p: int, layers: int, select=None, n_threads: int = 0,
+             target_normals=None):
     """Potentials at all targets (or the `select`ed ones).
 
-    Returns dict with keys 'slp', 'dlp', 'abs_slp', 'abs_dlp' (None for a
-    layer not requested).
+    Returns dict with keys 'slp', 'dlp', 'sprime' and 'abs_' + each (None
+    for a layer not requested).
     """
     lib = _load()
     src = _f64(sources)
@@ -106,20 +109,22 @@ def evaluate(sources, weights, normals, centers, list_offsets, list_sources, tar
     idx = np.ascontiguousarray(list_sources, dtype=np.int32)
     tgt = _f64(targets)
     tc = None if target_center is None else np.ascontiguousarray(target_center, dtype=np.int32)
+    tn = None if target_normals is None else _f64(target_normals)
     sig = _f64(sigma)
     prob = _Problem(len(src), _ptr(src), _ptr(w), _ptr(nrm), len(ctr), _ptr(ctr), _ptr(off),
-                    _ptr(idx), len(tgt), _ptr(tgt), _ptr(tc))
+                    _ptr(idx), len(tgt), _ptr(tgt), _ptr(tc), _ptr(tn))
     sel = None if select is None else np.ascontiguousarray(select, dtype=np.int64)
     n_out = len(tgt) if sel is None else len(sel)
-    want_s, want_d = bool(layers & SLP), bool(layers & DLP)
-    out = {k: None for k in ("slp", "dlp", "abs_slp", "abs_dlp")}
-    if want_s:
-        out["slp"], out["abs_slp"] = np.zeros(n_out), np.zeros(n_out)
-    if want_d:
-        out["dlp"], out["abs_dlp"] = np.zeros(n_out), np.zeros(n_out)
+    names = ("slp", "dlp", "sprime")
+    out = {}
+    for bit, k in zip((SLP, DLP, SPRIME), names):
+        want = bool(layers & bit)
+        out[k] = np.zeros(n_out) if want else None
+        out["abs_" + k] = np.zeros(n_out) if want else None
+    outs = (ctypes.c_void_p * 3)(*[_ptr(out[k]) for k in names])
+    abss = (ctypes.c_void_p * 3)(*[_ptr(out["abs_" + k]) for k in names])
     rc = lib.tsqbx_oracle_eval(ctypes.byref(prob), int(p), int(layers), _ptr(sig),
-                               n_out, _ptr(sel), _ptr(out["slp"]), _ptr(out["dlp"]),
-                               _ptr(out["abs_slp"]), _ptr(out["abs_dlp"]), int(n_threads))
+                               n_out, _ptr(sel), outs, abss, int(n_threads))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return out
@@ -130,4 +135,5 @@ def evaluate_geometry(g, p=None, layers=None, sigma=None, select=None, n_threads
     return evaluate(g.sources, g.weights, g.normals, g.centers, g.list_offsets, g.list_sources,
                     g.targets, g.target_center, g.sigma if sigma is None else sigma,
                     g.p if p is None else p, g.layers if layers is None else layers,
-                    select=select, n_threads=n_threads)
+                    select=select, n_threads=n_threads,
+                    target_normals=getattr(g, "target_normals", None))

@@ -19,7 +19,7 @@ static double dot3(const double a[3], const double b[3]) {
 /* One pair, following App. A term by term: x = cos(gamma), P_n(x) and
  * P_n'(x) by recurrence, running powers |t-c|^n and |s-c|^-(n+1). */
 void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
-                       const double *nu, int p, double k[4]) {
+                       const double *nu, const double *nu_t, int p, double k[6]) {
   double dt[3] = {t[0] - c[0], t[1] - c[1], t[2] - c[2]};
   double ds[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
   double rho = sqrt(dot3(dt, dt));
@@ -32,14 +32,23 @@ void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
   }
   double shat[3] = {ds[0] / R, ds[1] / R, ds[2] / R};
   double x = dot3(that, shat);
-  double nu_s = 0.0, nu_t = 0.0, nu_len = 0.0, perp = 0.0;
+  double nu_sh = 0.0, nu_th = 0.0, nu_len = 0.0, perp = 0.0;
   if (nu) {
-    nu_s = dot3(nu, shat);
-    nu_t = dot3(nu, that);
+    nu_sh = dot3(nu, shat);
+    nu_th = dot3(nu, that);
     nu_len = sqrt(dot3(nu, nu));
-    /* |t_hat - s_hat x|: length of the P_n' direction of the gradient */
+    /* |t_hat - s_hat x|: length of the P_n' direction of the source gradient */
     double w[3] = {that[0] - shat[0] * x, that[1] - shat[1] * x, that[2] - shat[2] * x};
     perp = sqrt(dot3(w, w));
+  }
+  double m_t = 0.0, m_s = 0.0, m_len = 0.0, m_perp = 0.0;
+  if (nu_t) {
+    m_t = dot3(nu_t, that);
+    m_s = dot3(nu_t, shat);
+    m_len = sqrt(dot3(nu_t, nu_t));
+    /* |s_hat - t_hat x|: length of the P_n' direction of the target gradient */
+    double w[3] = {shat[0] - that[0] * x, shat[1] - that[1] * x, shat[2] - that[2] * x};
+    m_perp = sqrt(dot3(w, w));
   }
   double Rinv = 1.0 / R;
 
@@ -47,8 +56,9 @@ void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
   double P = 1.0;      /* P_n */
   double dP = 0.0;     /* P_n' */
   double rho_n = 1.0;  /* |t-c|^n */
+  double rho_nm1 = 1.0;/* |t-c|^(n-1), used from n = 1 on */
   double Rpow = Rinv;  /* |s-c|^-(n+1) */
-  double ks = 0.0, ks_abs = 0.0, kd = 0.0, kd_abs = 0.0;
+  double ks = 0.0, ks_abs = 0.0, kd = 0.0, kd_abs = 0.0, kt = 0.0, kt_abs = 0.0;
   for (int n = 0; n <= p; ++n) {
     double radial = rho_n * Rpow;
     double term_s = radial * P;
@@ -56,12 +66,21 @@ void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
     ks_abs += fabs(term_s);
     if (nu) {
       double radial_d = radial * Rinv;
-      double a = -(double)(n + 1) * nu_s * P;
-      double b = (nu_t - nu_s * x) * dP;
+      double a = -(double)(n + 1) * nu_sh * P;
+      double b = (nu_th - nu_sh * x) * dP;
       kd += radial_d * (a + b);
       /* yardstick: |nu| times the size of the gradient term, which bounds
        * the rounding of its projection on nu */
       kd_abs += radial_d * nu_len * ((double)(n + 1) * fabs(P) + fabs(dP) * perp);
+    }
+    if (nu_t && n >= 1) {
+      /* App. A's target gradient starts at n = 1 */
+      double radial_t = rho_nm1 * Rpow;
+      double a = (double)n * m_t * P;
+      double b = (m_s - m_t * x) * dP;
+      kt += radial_t * (a + b);
+      kt_abs += radial_t * m_len * ((double)n * fabs(P) + fabs(dP) * m_perp);
+      rho_nm1 *= rho;
     }
     /* Bonnet: (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1};  P_{n+1}' = x P_n' + (n+1) P_n */
     double P_next = ((double)(2 * n + 1) * x * P - (double)n * P_prev) / (double)(n + 1);
@@ -77,19 +96,22 @@ void tsqbx_oracle_pair(const double t[3], const double c[3], const double s[3],
   k[1] = kd * inv4pi;
   k[2] = ks_abs * inv4pi;
   k[3] = kd_abs * inv4pi;
+  k[4] = kt * inv4pi;
+  k[5] = kt_abs * inv4pi;
 }
 
 int tsqbx_oracle_max_threads(void) { return omp_get_max_threads(); }
 
 int tsqbx_oracle_eval(const tsqbx_oracle_problem *prob, int p, unsigned layers,
                       const double *sigma, int64_t n_sel, const int64_t *sel,
-                      double *out_slp, double *out_dlp, double *abs_slp,
-                      double *abs_dlp, int n_threads) {
-  if (!prob || p < 0 || !sigma) return -1;
+                      double *const out[3], double *const abs[3], int n_threads) {
+  if (!prob || p < 0 || !sigma || !out || !abs) return -1;
   if ((layers & TSQBX_ORACLE_DLP) && !prob->normals) return -1;
+  if ((layers & TSQBX_ORACLE_SPRIME) && !prob->target_normals) return -1;
   int64_t n_out = sel ? n_sel : prob->n_targets;
   int want_s = (layers & TSQBX_ORACLE_SLP) != 0;
   int want_d = (layers & TSQBX_ORACLE_DLP) != 0;
+  int want_t = (layers & TSQBX_ORACLE_SPRIME) != 0;
   if (n_threads <= 0) n_threads = omp_get_max_threads();
 
 #pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
@@ -98,26 +120,33 @@ int tsqbx_oracle_eval(const tsqbx_oracle_problem *prob, int p, unsigned layers,
     int64_t ci = prob->target_center ? (int64_t)prob->target_center[ti] : ti;
     const double *t = prob->targets + 3 * ti;
     const double *c = prob->centers + 3 * ci;
-    double s_sum = 0.0, s_abs = 0.0, d_sum = 0.0, d_abs = 0.0;
+    const double *nu_t = want_t ? prob->target_normals + 3 * ti : NULL;
+    double sum[3] = {0.0, 0.0, 0.0}, sum_abs[3] = {0.0, 0.0, 0.0};
     for (int64_t j = prob->list_offsets[ci]; j < prob->list_offsets[ci + 1]; ++j) {
       int64_t y = prob->list_sources[j];
       double q = prob->weights[y] * sigma[y];
-      double k[4];
+      double k[6];
       tsqbx_oracle_pair(t, c, prob->sources + 3 * y,
-                        want_d ? prob->normals + 3 * y : NULL, p, k);
+                        want_d ? prob->normals + 3 * y : NULL, nu_t, p, k);
       if (want_s) {
-        s_sum += q * k[0];
-        s_abs += fabs(q) * k[2];
+        sum[0] += q * k[0];
+        sum_abs[0] += fabs(q) * k[2];
       }
       if (want_d) {
-        d_sum += q * k[1];
-        d_abs += fabs(q) * k[3];
+        sum[1] += q * k[1];
+        sum_abs[1] += fabs(q) * k[3];
+      }
+      if (want_t) {
+        sum[2] += q * k[4];
+        sum_abs[2] += fabs(q) * k[5];
       }
     }
-    if (want_s && out_slp) out_slp[i] = s_sum;
-    if (want_s && abs_slp) abs_slp[i] = s_abs;
-    if (want_d && out_dlp) out_dlp[i] = d_sum;
-    if (want_d && abs_dlp) abs_dlp[i] = d_abs;
+    const int want[3] = {want_s, want_d, want_t};
+    for (int l = 0; l < 3; ++l) {
+      if (!want[l]) continue;
+      if (out[l]) out[l][i] = sum[l];
+      if (abs[l]) abs[l][i] = sum_abs[l];
+    }
   }
   return 0;
 }

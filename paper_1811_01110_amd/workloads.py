@@ -53,7 +53,9 @@ class Geometry:
     target_center (T,)  int32     center of each target (None: target i uses center i)
     sigma        (N,)   float64   density samples at the sources
     p            int              expansion order
-    layers       int              bitmask, 1 = single layer, 2 = double layer
+    layers       int              bitmask, 1 = single layer, 2 = double layer,
+                                  4 = normal derivative of the single layer at the target (S')
+    target_normals (T, 3) float64 unit normals at the targets (S'), or None
     """
 
     sources: np.ndarray
@@ -68,6 +70,7 @@ class Geometry:
     p: int
     layers: int
     name: str = ""
+    target_normals: Optional[np.ndarray] = None
 
     @property
     def n_sources(self) -> int:
@@ -324,7 +327,8 @@ def config_a(scale: int = 1) -> Geometry:
     ctr = 0.95 * tgt
     offsets = np.arange(k + 1, dtype=np.int64) * n
     idx = np.tile(np.arange(n, dtype=np.int32), k)
-    return Geometry(src, w, src.copy(), ctr, offsets, idx, tgt, None, sigma, 8, 1, "A")
+    return Geometry(src, w, src.copy(), ctr, offsets, idx, tgt, None, sigma, 8, 1, "A",
+                    target_normals=tgt.copy())
 
 
 def _on_surface_targets(surface, n_src, n_tgt, rng, offset, phase_tgt):
@@ -333,7 +337,7 @@ def _on_surface_targets(surface, n_src, n_tgt, rng, offset, phase_tgt):
     tth, tph = fibonacci_angles(n_tgt, phase=phase_tgt)
     tgt, tnrm, _ = surface.sample(tth, tph, n_tgt)
     ctr = tgt - offset * tnrm
-    return src, nrm, w, (th, ph), tgt, ctr
+    return src, nrm, w, (th, ph), tgt, ctr, tnrm
 
 
 def config_b(scale: int = 1, radius: float = 0.15) -> Geometry:
@@ -348,12 +352,13 @@ def config_b(scale: int = 1, radius: float = 0.15) -> Geometry:
     rng = rng_for("B")
     surf = PerturbedSphere(rng)
     n, k = 262144 // scale, 65536 // scale
-    src, nrm, w, (th, ph), tgt, ctr = _on_surface_targets(
+    src, nrm, w, (th, ph), tgt, ctr, tnrm = _on_surface_targets(
         surf, n, k, rng, 0.02, phase_tgt=0.5 * GOLDEN_ANGLE)
     sigma = _ys32_real(th, ph) + 0.1 * rng.standard_normal(n)
     r = radius * math.sqrt(scale)
     offsets, idx = csr_ball(ctr, src, r)
-    return Geometry(src, w, nrm, ctr, offsets, idx, tgt, None, sigma, 16, 3, "B")
+    return Geometry(src, w, nrm, ctr, offsets, idx, tgt, None, sigma, 16, 3, "B",
+                    target_normals=tnrm)
 
 
 def _random_surface(rng):
@@ -382,8 +387,8 @@ def _batched_geometry(config: str, item: int, n: int, p: int, layers: int,
     k = max(n // 4, 1)
     h = math.sqrt(area / n)
     offset = min(2.0 * h, 0.5 * curv)
-    src, nrm, w, _, tgt, ctr = _on_surface_targets(surf, n, k, rng, offset,
-                                                   phase_tgt=rng.uniform(0, 2 * math.pi))
+    src, nrm, w, _, tgt, ctr, tnrm = _on_surface_targets(surf, n, k, rng, offset,
+                                                         phase_tgt=rng.uniform(0, 2 * math.pi))
     sigma = rng.standard_normal(n)
     if knn_counts is None:
         offsets, idx = csr_ball(ctr, src, list_radius_h * h)
@@ -391,7 +396,7 @@ def _batched_geometry(config: str, item: int, n: int, p: int, layers: int,
         counts = knn_counts(rng, k)
         offsets, idx = csr_knn(ctr, src, counts)
     return Geometry(src, w, nrm, ctr, offsets, idx, tgt, None, sigma, p, layers,
-                    f"{config}{item}:{kind}")
+                    f"{config}{item}:{kind}", target_normals=tnrm)
 
 
 def config_c(n_geometries: int = 64, scale: int = 1) -> List[Geometry]:
@@ -482,4 +487,6 @@ def fuzz_geometry(seed: int, n: int, m: int, max_list: int, p: int, layers: int,
     tc = np.repeat(np.arange(m, dtype=np.int32), targets_per_center)
     rng.shuffle(tc)
     tgt = ctr[tc] + random_sphere_points(len(tc), rng) * rng.uniform(0.0, 0.3, size=(len(tc), 1))
-    return Geometry(src, w, nrm, ctr, offsets, idx, tgt, tc, sigma, p, layers, f"fuzz{seed}")
+    tnrm = random_sphere_points(len(tc), rng)  # drawn last: earlier draws stay as they were
+    return Geometry(src, w, nrm, ctr, offsets, idx, tgt, tc, sigma, p, layers, f"fuzz{seed}",
+                    target_normals=tnrm)

@@ -428,3 +428,205 @@ def test_thread_count_does_not_change_bits():
     b = _eval(g, n_threads=4)
     for k in ("slp", "dlp", "abs_slp", "abs_dlp"):
         assert np.array_equal(a[k], b[k])
+
+
+# ---------------------------------------------------------------------------
+# S': normal derivative of the single layer at the target (App. A, gradient
+# with respect to t), pinned like the double layer: by the Green's function's
+# target gradient, by a complex-step derivative in t of an independently
+# written single layer, by closed forms and by sphere eigenvalues
+# ---------------------------------------------------------------------------
+
+def test_sprime_converges_to_target_gradient_of_green():
+    rng = np.random.default_rng(15)
+    for _ in range(40):
+        c = rng.uniform(-1, 1, 3)
+        R = rng.uniform(0.5, 2.0)
+        ratio = rng.uniform(0.05, 0.6)
+        y = c + R * _rand_unit(rng)
+        t = c + ratio * R * _rand_unit(rng)
+        nt = _rand_unit(rng)
+        r = t - y
+        ref = -INV4PI * np.dot(nt, r) / np.linalg.norm(r) ** 3
+        errs = []
+        for p in (2, 8, 16, 32, 96):
+            k = oracle.pair(t, c, y, None, p, nu_t=nt)
+            errs.append(abs(k[4] - ref))
+        assert errs[-1] <= 1e-14 * max(abs(ref), INV4PI / R ** 2)
+        # the differentiated tail decays like (p+1) ratio^p
+        assert errs[2] <= 40 * 17 * ratio ** 16 * INV4PI / (R * R * (1 - ratio) ** 2) + 1e-15
+
+
+def _slp_analytic_in_t(t, c, y, p):
+    """G^(p) written so that it is complex-analytic in t: rho = sqrt(delta.delta)
+    and x = delta.d / (rho R) stay analytic, and rho^n P_n(x) is a polynomial
+    in delta (numpy's Legendre series evaluation, no recurrence of ours)."""
+    dt = t - c
+    d = y - c
+    rho = np.sqrt(np.sum(dt * dt))
+    R = math.sqrt(float(np.dot(d, d)))
+    x = np.sum(dt * d) / (rho * R)
+    total = 0.0
+    for n in range(p + 1):
+        e = np.zeros(n + 1)
+        e[n] = 1.0
+        total = total + rho ** n / R ** (n + 1) * npleg.legval(x, e)
+    return INV4PI * total
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 6, 16, 24])
+def test_sprime_is_complex_step_target_derivative(p):
+    rng = np.random.default_rng(210 + p)
+    h = 1e-30
+    for _ in range(10):
+        c = rng.uniform(-0.5, 0.5, 3)
+        y = c + rng.uniform(0.8, 1.5) * _rand_unit(rng)
+        t = c + rng.uniform(0.05, 0.7) * _rand_unit(rng)
+        nt = _rand_unit(rng)
+        deriv = _slp_analytic_in_t(t + 1j * h * nt, c, y, p).imag / h
+        k = oracle.pair(t, c, y, None, p, nu_t=nt)
+        assert abs(k[4] - deriv) <= 1e-14 * k[5] + 1e-300, (k[4], deriv)
+
+
+def test_sprime_low_orders_and_target_at_center():
+    """p = 0: constant in t, S' = 0.  At t = c only the n = 1 term is left,
+    the gradient of (t - c).(y - c) / (4 pi |y - c|^3)."""
+    rng = np.random.default_rng(16)
+    for _ in range(20):
+        c = rng.uniform(-1, 1, 3)
+        y = c + rng.uniform(0.5, 2) * _rand_unit(rng)
+        t = c + 0.3 * _rand_unit(rng)
+        nt = _rand_unit(rng)
+        d = y - c
+        R = np.linalg.norm(d)
+        assert oracle.pair(t, c, y, None, 0, nu_t=nt)[4] == 0.0
+        k1 = oracle.pair(t, c, y, None, 1, nu_t=nt)[4]
+        assert k1 == pytest.approx(INV4PI * np.dot(nt, d) / R ** 3, rel=1e-14, abs=1e-17)
+        for p in (1, 5, 17):
+            kc = oracle.pair(c, c, y, None, p, nu_t=nt)[4]
+            assert kc == pytest.approx(INV4PI * np.dot(nt, d) / R ** 3, rel=1e-14, abs=1e-17)
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_sprime_collinear_derivative_of_geometric_sum(sign):
+    """On the line through c and y, G^(p) = (1/4 pi) sum_n s^n / R^{n+1}
+    (s the signed offset of t along e); its derivative along e is
+    (1/(4 pi R^2)) (1 - (p+1) u^p + p u^{p+1}) / (1 - u)^2 with u = s/R,
+    and the gradient has no component across the line."""
+    rng = np.random.default_rng(17)
+    c = np.array([0.3, -0.2, 0.1])
+    e = _rand_unit(rng)
+    perp = np.cross(e, _rand_unit(rng))
+    perp /= np.linalg.norm(perp)
+    R, rho = 1.7, 0.6
+    y, t = c + R * e, c + sign * rho * e
+    for p in range(0, 30):
+        u = sign * rho / R
+        ref = INV4PI / R ** 2 * (1 - (p + 1) * u ** p + p * u ** (p + 1)) / (1 - u) ** 2
+        k = oracle.pair(t, c, y, None, p, nu_t=e)
+        assert k[4] == pytest.approx(ref, rel=4e-15, abs=1e-17)
+        kp = oracle.pair(t, c, y, None, p, nu_t=perp)
+        assert abs(kp[4]) <= 1e-15 * k[5]
+
+
+@pytest.mark.parametrize("l,m", [(0, 0), (1, 1), (3, 2), (5, -3), (6, 4)])
+def test_sprime_sphere_eigenvalues_center_at_origin(l, m):
+    """Unit sphere, center at the origin, nu_t = t_hat: the expansion of
+    S[Y_l^m] is rho^l Y_l^m / (2l+1) for p >= l, so S' = l rho^(l-1) Y / (2l+1)
+    (and 0 for p < l)."""
+    pts, w, th, ph = _sphere_product_rule(16, 34)
+    mu = _sph_density(l, abs(m), th, ph) if m >= 0 else sps.sph_harm_y(l, -m, th, ph).imag
+    rng = np.random.default_rng(310 + l)
+    nt = 6
+    dirs = _rand_unit(rng, nt)
+    rho = rng.uniform(0.2, 0.95, nt)
+    tgt = dirs * rho[:, None]
+    tth = np.arccos(dirs[:, 2])
+    tph = np.mod(np.arctan2(dirs[:, 1], dirs[:, 0]), 2 * math.pi)
+    yt = _sph_density(l, abs(m), tth, tph) if m >= 0 else sps.sph_harm_y(l, -m, tth, tph).imag
+    off = np.array([0, len(pts)], dtype=np.int64)
+    idx = np.arange(len(pts), dtype=np.int32)
+    for p in (max(l - 1, 0), l, l + 3, 16):
+        res = oracle.evaluate(pts, w, None, np.zeros((1, 3)), off, idx, tgt,
+                              np.zeros(nt, dtype=np.int32), mu, p, oracle.SPRIME,
+                              target_normals=dirs)
+        ref = l * rho ** (l - 1) * yt / (2 * l + 1) if (p >= l and l > 0) else np.zeros(nt)
+        assert np.max(np.abs(res["sprime"] - ref)) <= 1e-14 * (1 + np.max(res["abs_sprime"]))
+
+
+def test_sprime_on_surface_qbx_gives_interior_limit():
+    """Center 0.2 inside the unit sphere, target on the sphere, nu_t outward:
+    the interior single layer of Y_3^2 is r^3 Y / 7, so QBX at p >= 3 returns
+    its interior normal derivative 3 Y / 7 (the jump relation of Sec. 2.1:
+    principal value -Y/14 plus half the density)."""
+    l, m = 3, 2
+    pts, w, th, ph = _sphere_product_rule(200, 400)
+    mu = _sph_density(l, m, th, ph)
+    rng = np.random.default_rng(410)
+    nt = 4
+    dirs = _rand_unit(rng, nt)
+    ctr = 0.8 * dirs
+    tth = np.arccos(dirs[:, 2])
+    tph = np.mod(np.arctan2(dirs[:, 1], dirs[:, 0]), 2 * math.pi)
+    yt = _sph_density(l, m, tth, tph)
+    off = np.arange(nt + 1, dtype=np.int64) * len(pts)
+    idx = np.tile(np.arange(len(pts), dtype=np.int32), nt)
+    res = oracle.evaluate(pts, w, None, ctr, off, idx, dirs, None, mu, 16, oracle.SPRIME,
+                          target_normals=dirs)
+    scale = np.max(np.abs(yt))
+    assert np.max(np.abs(res["sprime"] - l / (2 * l + 1) * yt)) <= 1e-12 * scale
+
+
+def test_sprime_mpmath_reference_within_rounding():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(18)
+    for trial in range(12):
+        p = int(rng.integers(0, 25))
+        c = rng.uniform(-0.5, 0.5, 3)
+        y = c + rng.uniform(0.8, 1.5) * _rand_unit(rng)
+        t = c + rng.uniform(0.05, 0.95) * np.linalg.norm(y - c) * _rand_unit(rng)
+        nt = _rand_unit(rng)
+        T, C, Y, N = ([mpmath.mpf(float(v)) for v in a] for a in (t, c, y, nt))
+        dt = [a - b for a, b in zip(T, C)]
+        ds = [a - b for a, b in zip(Y, C)]
+        rho = mpmath.sqrt(sum(v * v for v in dt))
+        R = mpmath.sqrt(sum(v * v for v in ds))
+        # the gradient of rho^n P_n(x) / R^(n+1) in t, by mpmath's numerical
+        # differentiation of the literal series along nu_t
+        def g(h):
+            tt = [a + h * b for a, b in zip(dt, N)]
+            r = mpmath.sqrt(sum(v * v for v in tt))
+            x = sum(a * b for a, b in zip(tt, ds)) / (r * R)
+            return sum(r ** n / R ** (n + 1) * mpmath.legendre(n, x) for n in range(p + 1))
+        ref = mpmath.diff(g, 0) / (4 * mpmath.pi)
+        k = oracle.pair(t, c, y, None, p, nu_t=nt)
+        assert abs(k[4] - float(ref)) <= 8 * 2.2e-16 * (p + 1) * k[5] + 1e-300
+
+
+def test_sprime_rigid_motion_scaling_and_linearity():
+    g = _fuzz(6, n=60, m=12, max_list=40, p=12, layers=7)
+    ref = _eval(g)
+    rng = np.random.default_rng(19)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    shift = rng.uniform(-3, 3, 3)
+    h = _fuzz(6, n=60, m=12, max_list=40, p=12, layers=7)
+    mv = lambda a: a @ Q.T + shift
+    h.sources, h.centers, h.targets = mv(h.sources), mv(h.centers), mv(h.targets)
+    h.normals, h.target_normals = h.normals @ Q.T, h.target_normals @ Q.T
+    out = _eval(h)
+    for k in ("slp", "dlp", "sprime"):
+        assert _close(out[k], ref[k], ref["abs_" + k], 1e-12), k
+    s = 2.5
+    h = _fuzz(6, n=60, m=12, max_list=40, p=12, layers=7)
+    h.sources, h.centers, h.targets = s * h.sources, s * h.centers, s * h.targets
+    out = _eval(h)
+    assert _close(out["sprime"] * s * s, ref["sprime"], ref["abs_sprime"])
+    s2 = rng.standard_normal(g.n_sources)
+    b = _eval(g, sigma=s2)
+    ab = _eval(g, sigma=2.0 * g.sigma - 3.0 * s2)
+    assert _close(ab["sprime"], 2 * ref["sprime"] - 3 * b["sprime"],
+                  2 * ref["abs_sprime"] + 3 * b["abs_sprime"])
+    # S' alone equals S' computed beside the other layers, bit for bit
+    alone = _eval(g, layers=4)
+    assert np.array_equal(alone["sprime"], ref["sprime"])
