@@ -11,13 +11,16 @@
  * X_b close for the box b owning c, Sec. 3.3; stages 3, 5(a) and 6(a) of
  * Algorithm 1), with strength q_y = w_y sigma_y (eq. pt-pot):
  *
- *   single layer  out_slp[t] = sum_{y in L(c)} q_y G^(p)(t, y)
- *   double layer  out_dlp[t] = sum_{y in L(c)} q_y nu_y . grad_y G^(p)(t, y)
+ *   single layer  out_slp[t]    = sum_{y in L(c)} q_y G^(p)(t, y)
+ *   double layer  out_dlp[t]    = sum_{y in L(c)} q_y nu_y . grad_y G^(p)(t, y)
+ *   S'            out_sprime[t] = sum_{y in L(c)} q_y nu_t . grad_t G^(p)(t, y)
  *
  *   G^(p)(t, y) = 1/(4 pi) sum_{n=0..p} |t-c|^n / |y-c|^{n+1} P_n(cos gamma)
  *
  * with gamma the angle between t-c and y-c (eq. tsqbx, Sec. 2.7, and the
- * first formula of App. A) and grad_y the source gradient of App. A.  P_n is
+ * first formula of App. A), grad_y the source gradient and grad_t the target
+ * gradient of App. A (S' is the normal derivative of the single layer at the
+ * target, with nu_t the caller's unit normal at t).  P_n is
  * the Legendre polynomial; the expansion has p+1 terms, n = 0..p (Sec. 2.3:
  * a p-th order expansion keeps the first p+1 terms).  The factor 1/(4 pi) is
  * that of the Laplace Green's function (eq. laplace-green-function).  nu_y is
@@ -61,7 +64,7 @@ typedef enum {
 } tsqbx_status;
 
 /* Layer bitmask: which potentials to evaluate. */
-enum { TSQBX_SLP = 1u, TSQBX_DLP = 2u };
+enum { TSQBX_SLP = 1u, TSQBX_DLP = 2u, TSQBX_SPRIME = 4u };
 
 /* Flags. */
 enum {
@@ -83,8 +86,9 @@ typedef struct tsqbx_server tsqbx_server;
 
 /*
  * Geometry: sources with weights (eq. pt-pot), normals for the double layer,
- * QBX centers with their near-field source lists in CSR form, targets and the
- * target -> center association.  All pointers are host pointers.
+ * QBX centers with their near-field source lists in CSR form, targets, the
+ * target -> center association and target normals for S'.  All pointers are
+ * host pointers.
  */
 typedef struct {
   int64_t n_sources;           /* N >= 0 */
@@ -98,6 +102,7 @@ typedef struct {
   int64_t n_targets;           /* T >= 0 */
   const double *targets;       /* [T][3] target points t */
   const int32_t *target_center;/* [T] center of each target in [0, M); NULL: T == M, target i uses center i */
+  const double *target_normals;/* [T][3] unit normals at the targets, or NULL (then no TSQBX_SPRIME) */
 } tsqbx_geometry_desc;
 
 typedef struct {
@@ -107,6 +112,7 @@ typedef struct {
   int64_t max_list;     /* longest list */
   size_t device_bytes;  /* device memory held by the geometry */
   int has_normals;
+  int has_target_normals;
 } tsqbx_geometry_info;
 
 /* Library version as major*10000 + minor*100 + patch. */
@@ -122,8 +128,9 @@ const char *tsqbx_last_error(void);
 int tsqbx_validate_geometry(const tsqbx_geometry_desc *desc);
 
 /* Check (p, layers) against a geometry's capabilities without a launch:
- * p in [0, TSQBX_P_MAX], layers a nonempty subset of SLP|DLP, DLP needs
- * normals.  geom may be NULL (then the normals check is skipped). */
+ * p in [0, TSQBX_P_MAX], layers a nonempty subset of SLP|DLP|SPRIME, DLP
+ * needs source normals and SPRIME target normals.  geom may be NULL (then the
+ * normals checks are skipped). */
 int tsqbx_check_request(const tsqbx_geometry *geom, int p, unsigned layers);
 
 /* Context on one HIP device (device ordinal as hipSetDevice takes it). */
@@ -140,10 +147,11 @@ int tsqbx_geometry_destroy(tsqbx_geometry *geom);
 int tsqbx_geometry_get_info(const tsqbx_geometry *geom, tsqbx_geometry_info *out);
 
 /* Plain evaluation, host pointers, synchronous.  sigma: [N] density in the
- * caller's source order; out_slp / out_dlp: [T], required for each requested
- * layer (may be NULL for a layer not requested). */
+ * caller's source order; out_slp / out_dlp / out_sprime: [T], required for
+ * each requested layer (may be NULL for a layer not requested). */
 int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
-               const double *sigma, double *out_slp, double *out_dlp, unsigned flags);
+               const double *sigma, double *out_slp, double *out_dlp, double *out_sprime,
+               unsigned flags);
 
 /* Plain evaluation, device pointers, asynchronous on hip_stream (a
  * hipStream_t passed as void*, NULL = the null stream).  The buffers must stay
@@ -152,14 +160,14 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layer
  * different streams (calls on the same stream are ordered and safe). */
 int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
                      const double *d_sigma, double *d_out_slp, double *d_out_dlp,
-                     unsigned flags, void *hip_stream);
+                     double *d_out_sprime, unsigned flags, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
- * Launch tuning.  A target's result depends only on its list, the layer mask
- * of the call (the single layer alone runs its own recurrence; with the double
- * layer both come from one derivative recurrence) and group_lanes: it is
- * bitwise identical across every other setting, and across the plain, batched
- * and served paths at equal group_lanes and layer mask.
+ * Launch tuning.  A target's result depends only on its list, whether the
+ * single layer is evaluated alone (it then runs its own recurrence; with DLP or
+ * SPRIME every layer comes from one derivative recurrence) and group_lanes: it
+ * is bitwise identical across every other setting, and across the plain,
+ * batched and served paths at equal group_lanes.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int waves_per_block;   /* 1, 2 or 4 */
@@ -192,6 +200,7 @@ typedef struct {
   const double *d_sigma;   /* device [N] */
   double *d_out_slp;       /* device [T] or NULL */
   double *d_out_dlp;       /* device [T] or NULL */
+  double *d_out_sprime;    /* device [T] or NULL */
 } tsqbx_item;
 
 typedef struct {
@@ -241,7 +250,7 @@ int tsqbx_server_request_bytes(const tsqbx_geometry *geom, unsigned layers, size
  * buffers must stay valid until the ticket completes.  Thread-safe. */
 int tsqbx_server_submit(tsqbx_server *srv, const tsqbx_geometry *geom, int p, unsigned layers,
                         const double *sigma_host, double *out_slp_host, double *out_dlp_host,
-                        uint64_t *ticket);
+                        double *out_sprime_host, uint64_t *ticket);
 /* As tsqbx_server_submit, without copying: sigma_host and the outputs must be
  * pinned host memory (hipHostMalloc, or a pinned torch tensor) and stay valid
  * and unmodified until the ticket completes.  Densities are uploaded and
@@ -249,7 +258,7 @@ int tsqbx_server_submit(tsqbx_server *srv, const tsqbx_geometry *geom, int p, un
  * TSQBX_E_INVALID if a buffer is not pinned host memory. */
 int tsqbx_server_submit_pinned(tsqbx_server *srv, const tsqbx_geometry *geom, int p,
                                unsigned layers, const double *sigma_host, double *out_slp_host,
-                               double *out_dlp_host, uint64_t *ticket);
+                               double *out_dlp_host, double *out_sprime_host, uint64_t *ticket);
 /* *done = 1 once the outputs are written (0 while pending).  Returns the
  * request's error status if it failed. */
 int tsqbx_server_poll(tsqbx_server *srv, uint64_t ticket, int *done);

@@ -18,7 +18,7 @@ c_int, c_uint, c_int64, c_uint64, c_size_t, c_double, c_void_p, c_char_p = (
     ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p)
 
 OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_BUDGET, E_STATE, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
-SLP, DLP = 1, 2
+SLP, DLP, SPRIME = 1, 2, 4
 ACCUMULATE, NO_REORDER = 1, 2
 P_MAX = 32
 
@@ -28,14 +28,15 @@ class GeometryDesc(ctypes.Structure):
         ("n_sources", c_int64), ("sources", c_void_p), ("weights", c_void_p), ("normals", c_void_p),
         ("n_centers", c_int64), ("centers", c_void_p), ("list_offsets", c_void_p),
         ("list_sources", c_void_p), ("n_targets", c_int64), ("targets", c_void_p),
-        ("target_center", c_void_p),
+        ("target_center", c_void_p), ("target_normals", c_void_p),
     ]
 
 
 class GeometryInfo(ctypes.Structure):
     _fields_ = [("n_sources", c_int64), ("n_centers", c_int64), ("n_targets", c_int64),
                 ("nnz", c_int64), ("pairs", c_int64), ("max_list", c_int64),
-                ("device_bytes", c_size_t), ("has_normals", c_int)]
+                ("device_bytes", c_size_t), ("has_normals", c_int),
+                ("has_target_normals", c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -48,7 +49,7 @@ class Tuning(ctypes.Structure):
 
 class Item(ctypes.Structure):
     _fields_ = [("geom", c_void_p), ("p", c_int), ("layers", c_uint), ("d_sigma", c_void_p),
-                ("d_out_slp", c_void_p), ("d_out_dlp", c_void_p)]
+                ("d_out_slp", c_void_p), ("d_out_dlp", c_void_p), ("d_out_sprime", c_void_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -82,9 +83,10 @@ _SIGNATURES = {
     "tsqbx_geometry_create": (c_int, [c_void_p, P(GeometryDesc), c_uint, P(c_void_p)]),
     "tsqbx_geometry_destroy": (c_int, [c_void_p]),
     "tsqbx_geometry_get_info": (c_int, [c_void_p, P(GeometryInfo)]),
-    "tsqbx_eval": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p, c_uint]),
+    "tsqbx_eval": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p,
+                           c_void_p, c_uint]),
     "tsqbx_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p,
-                                 c_uint, c_void_p]),
+                                 c_void_p, c_uint, c_void_p]),
     "tsqbx_get_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_set_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_uint, P(Tuning), P(c_double)]),
@@ -95,9 +97,9 @@ _SIGNATURES = {
     "tsqbx_server_create": (c_int, [c_void_p, c_size_t, c_int, P(c_void_p)]),
     "tsqbx_server_request_bytes": (c_int, [c_void_p, c_uint, P(c_size_t)]),
     "tsqbx_server_submit": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,
-                                    c_void_p, P(c_uint64)]),
+                                    c_void_p, c_void_p, P(c_uint64)]),
     "tsqbx_server_submit_pinned": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,
-                                           c_void_p, P(c_uint64)]),
+                                           c_void_p, c_void_p, P(c_uint64)]),
     "tsqbx_server_poll": (c_int, [c_void_p, c_uint64, P(c_int)]),
     "tsqbx_server_wait": (c_int, [c_void_p, c_uint64, c_double]),
     "tsqbx_server_drain": (c_int, [c_void_p, c_double]),

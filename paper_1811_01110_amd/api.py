@@ -12,7 +12,9 @@ import numpy as np
 
 from . import _lib as L
 
-SLP, DLP, ACCUMULATE, NO_REORDER, P_MAX = L.SLP, L.DLP, L.ACCUMULATE, L.NO_REORDER, L.P_MAX
+SLP, DLP, SPRIME = L.SLP, L.DLP, L.SPRIME
+ACCUMULATE, NO_REORDER, P_MAX = L.ACCUMULATE, L.NO_REORDER, L.P_MAX
+LAYER_BITS = (SLP, DLP, SPRIME)  # the order of every (slp, dlp, sprime) tuple
 
 
 class TsqbxError(RuntimeError):
@@ -66,7 +68,7 @@ def _tensor_ptr(t, n, name):
 
 
 def make_desc(sources, weights, normals, centers, list_offsets, list_sources, targets,
-              target_center=None):
+              target_center=None, target_normals=None):
     """A tsqbx_geometry_desc plus the arrays it points into (keep both alive)."""
     keep = dict(
         sources=_f64(sources, 3), weights=_f64(weights),
@@ -76,12 +78,13 @@ def make_desc(sources, weights, normals, centers, list_offsets, list_sources, ta
         list_sources=np.ascontiguousarray(list_sources, dtype=np.int32),
         targets=_f64(targets, 3),
         target_center=None if target_center is None else np.ascontiguousarray(target_center, dtype=np.int32),
+        target_normals=None if target_normals is None else _f64(target_normals, 3),
     )
     d = L.GeometryDesc(
         len(keep["weights"]), _ptr(keep["sources"]), _ptr(keep["weights"]), _ptr(keep["normals"]),
         len(keep["list_offsets"]) - 1, _ptr(keep["centers"]), keep["list_offsets"].ctypes.data,
         _ptr(keep["list_sources"]), keep["targets"].shape[0] if keep["targets"].size else 0,
-        _ptr(keep["targets"]), _ptr(keep["target_center"]))
+        _ptr(keep["targets"]), _ptr(keep["target_center"]), _ptr(keep["target_normals"]))
     return d, keep
 
 
@@ -124,36 +127,41 @@ class Context:
             arrays = dict(sources=g.sources, weights=g.weights, normals=g.normals,
                           centers=g.centers, list_offsets=g.list_offsets,
                           list_sources=g.list_sources, targets=g.targets,
-                          target_center=g.target_center)
+                          target_center=g.target_center,
+                          target_normals=getattr(g, "target_normals", None))
         return Geometry(self, flags=flags, **arrays)
 
     # -- evaluation ---------------------------------------------------------
     def eval(self, geom: "Geometry", sigma, p: int, layers: int, out_slp=None, out_dlp=None,
-             flags: int = 0):
-        """Synchronous evaluation with host arrays; returns (slp, dlp)."""
+             out_sprime=None, flags: int = 0):
+        """Synchronous evaluation with host arrays; returns (slp, dlp, sprime),
+        None for a layer not requested."""
         sig = _f64(sigma)
         if sig.size != geom.n_sources:
             raise ValueError(f"sigma has {sig.size} entries, expected {geom.n_sources}")
         T = geom.n_targets
-        if layers & SLP and out_slp is None:
-            out_slp = np.zeros(T)
-        if layers & DLP and out_dlp is None:
-            out_dlp = np.zeros(T)
-        for o in (out_slp, out_dlp):
-            if o is not None and (o.dtype != np.float64 or not o.flags.c_contiguous or o.size != T):
+        outs = [out_slp, out_dlp, out_sprime]
+        for k, bit in enumerate(LAYER_BITS):
+            if not layers & bit:
+                outs[k] = None
+                continue
+            if outs[k] is None:
+                outs[k] = np.zeros(T)
+            o = outs[k]
+            if o.dtype != np.float64 or not o.flags.c_contiguous or o.size != T:
                 raise ValueError("outputs must be contiguous float64 arrays of n_targets entries")
         _check(_lib().tsqbx_eval(self.handle, geom.handle, int(p), int(layers), _ptr(sig),
-                                 _ptr(out_slp) if layers & SLP else None,
-                                 _ptr(out_dlp) if layers & DLP else None, int(flags)))
-        return (out_slp if layers & SLP else None), (out_dlp if layers & DLP else None)
+                                 *[_ptr(o) for o in outs], int(flags)))
+        return tuple(outs)
 
     def eval_async(self, geom: "Geometry", sigma, p: int, layers: int, out_slp=None,
-                   out_dlp=None, flags: int = 0, stream=None):
+                   out_dlp=None, out_sprime=None, flags: int = 0, stream=None):
         """Asynchronous evaluation on device tensors (torch, float64)."""
         s = _tensor_ptr(sigma, geom.n_sources, "sigma")
-        a = _tensor_ptr(out_slp, geom.n_targets, "out_slp") if layers & SLP else None
-        b = _tensor_ptr(out_dlp, geom.n_targets, "out_dlp") if layers & DLP else None
-        _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, a, b,
+        ptrs = [_tensor_ptr(o, geom.n_targets, name) if layers & bit else None
+                for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
+                                        ("out_slp", "out_dlp", "out_sprime"))]
+        _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, *ptrs,
                                        int(flags), _stream_handle(stream)))
 
     # -- tuning -------------------------------------------------------------
@@ -204,6 +212,7 @@ class Geometry:
         self.max_list = info.max_list
         self.device_bytes = info.device_bytes
         self.has_normals = bool(info.has_normals)
+        self.has_target_normals = bool(info.has_target_normals)
 
     def close(self):
         if self.handle:
@@ -218,13 +227,14 @@ class Geometry:
             pass
 
     def pair_terms(self, p: int, layers: int) -> int:
-        return self.pairs * (p + 1) * bin(layers).count("1")
+        return self.pairs * (p + 1) * bin(layers & 7).count("1")
 
 
 class Plan:
     """Many (geometry, p, layers) items in one persistent, graph-replayed launch.
 
-    items: dicts with geom, p, layers, sigma (device tensor), out_slp, out_dlp.
+    items: dicts with geom, p, layers, sigma (device tensor), out_slp, out_dlp,
+    out_sprime (device tensors, needed for the requested layers).
     """
 
     def __init__(self, ctx: Context, items: Sequence[dict], flags: int = 0):
@@ -239,6 +249,8 @@ class Plan:
             arr[i].d_sigma = _tensor_ptr(it["sigma"], g.n_sources, "sigma")
             arr[i].d_out_slp = _tensor_ptr(it.get("out_slp"), g.n_targets, "out_slp") if lay & SLP else None
             arr[i].d_out_dlp = _tensor_ptr(it.get("out_dlp"), g.n_targets, "out_dlp") if lay & DLP else None
+            arr[i].d_out_sprime = (_tensor_ptr(it.get("out_sprime"), g.n_targets, "out_sprime")
+                                   if lay & SPRIME else None)
         h = ctypes.c_void_p()
         _check(_lib().tsqbx_plan_create(ctx.handle, len(items), arr, int(flags), ctypes.byref(h)))
         self.handle = h
@@ -282,25 +294,25 @@ class Server:
         return n.value
 
     def submit(self, geom: Geometry, sigma, p: int, layers: int):
-        """Queue a request; returns (ticket, out_slp, out_dlp) host arrays filled on completion."""
+        """Queue a request; returns (ticket, out_slp, out_dlp, out_sprime): host
+        arrays filled on completion (None for a layer not requested)."""
         sig = _f64(sigma)
         if sig.size != geom.n_sources:
             raise ValueError("sigma has the wrong length")
         T = geom.n_targets
-        os_ = np.zeros(T) if layers & SLP else None
-        od_ = np.zeros(T) if layers & DLP else None
+        outs = tuple(np.zeros(T) if layers & bit else None for bit in LAYER_BITS)
         tk = ctypes.c_uint64()
         _check(_lib().tsqbx_server_submit(self.handle, geom.handle, int(p), int(layers), _ptr(sig),
-                                          _ptr(os_), _ptr(od_), ctypes.byref(tk)))
-        self._live[tk.value] = (os_, od_)
-        return tk.value, os_, od_
+                                          *[_ptr(o) for o in outs], ctypes.byref(tk)))
+        self._live[tk.value] = outs
+        return (tk.value,) + outs
 
     def submit_pinned(self, geom: Geometry, sigma, p: int, layers: int, out_slp=None,
-                      out_dlp=None):
+                      out_dlp=None, out_sprime=None):
         """Queue a request on pinned host tensors (torch, float64), without copies.
 
         sigma and the outputs (allocated pinned if not given) must stay valid
-        until the ticket completes.  Returns (ticket, out_slp, out_dlp).
+        until the ticket completes.  Returns (ticket, out_slp, out_dlp, out_sprime).
         """
         import torch
 
@@ -316,20 +328,22 @@ class Server:
 
         T = geom.n_targets
         sigma = pinned(sigma, geom.n_sources, "sigma")
-        if layers & SLP and out_slp is None:
-            out_slp = torch.empty(T, dtype=torch.float64, pin_memory=True)
-        if layers & DLP and out_dlp is None:
-            out_dlp = torch.empty(T, dtype=torch.float64, pin_memory=True)
-        out_slp = pinned(out_slp, T, "out_slp") if layers & SLP else None
-        out_dlp = pinned(out_dlp, T, "out_dlp") if layers & DLP else None
+        outs = []
+        for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
+                                ("out_slp", "out_dlp", "out_sprime")):
+            if not layers & bit:
+                outs.append(None)
+                continue
+            if o is None:
+                o = torch.empty(T, dtype=torch.float64, pin_memory=True)
+            outs.append(pinned(o, T, name))
         tk = ctypes.c_uint64()
         _check(_lib().tsqbx_server_submit_pinned(
             self.handle, geom.handle, int(p), int(layers),
             sigma.data_ptr() if sigma is not None else None,
-            out_slp.data_ptr() if out_slp is not None else None,
-            out_dlp.data_ptr() if out_dlp is not None else None, ctypes.byref(tk)))
-        self._live[tk.value] = (out_slp, out_dlp, sigma)
-        return tk.value, out_slp, out_dlp
+            *[o.data_ptr() if o is not None else None for o in outs], ctypes.byref(tk)))
+        self._live[tk.value] = tuple(outs) + (sigma,)
+        return (tk.value,) + tuple(outs)
 
     def poll(self, ticket: int) -> bool:
         done = ctypes.c_int()
@@ -338,7 +352,7 @@ class Server:
 
     def wait(self, ticket: int, timeout_s: float = 60.0):
         _check(_lib().tsqbx_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s)))
-        return self._live.pop(ticket, (None, None))[:2]
+        return self._live.pop(ticket, (None, None, None))[:3]
 
     def drain(self, timeout_s: float = 600.0):
         _check(_lib().tsqbx_server_drain(self.handle, float(timeout_s)))

@@ -159,10 +159,12 @@ static int validate(const tsqbx_geometry_desc *d) {
 static int check_request(const tsqbx_geometry *g, int p, unsigned layers) {
   if (p < 0 || p > TSQBX_P_MAX)
     return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
-  if (layers == 0 || (layers & ~3u))
-    return fail(TSQBX_E_INVALID, "layers = %u is not a nonempty subset of SLP|DLP", layers);
+  if (layers == 0 || (layers & ~7u))
+    return fail(TSQBX_E_INVALID, "layers = %u is not a nonempty subset of SLP|DLP|SPRIME", layers);
   if (g && (layers & TSQBX_DLP) && !g->has_normals)
     return fail(TSQBX_E_INVALID, "double layer requested but the geometry has no normals");
+  if (g && (layers & TSQBX_SPRIME) && !g->has_target_normals)
+    return fail(TSQBX_E_INVALID, "S' requested but the geometry has no target normals");
   return TSQBX_OK;
 }
 
@@ -197,7 +199,7 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 
 static void free_geometry(tsqbx_geometry *g) {
   if (!g) return;
-  void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->idx,
+  void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
                   g->stage.posq, g->stage.qn};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -221,7 +223,7 @@ using namespace tsqbx;
 
 extern "C" {
 
-int tsqbx_version(void) { return 10000; }
+int tsqbx_version(void) { return 10100; }
 
 const char *tsqbx_last_error(void) { return g_err.c_str(); }
 
@@ -325,6 +327,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   });
 
   std::vector<TargetRec> recs(T);
+  std::vector<double4> tnrm(d->target_normals ? T : 0);
   int64_t pairs = 0, max_list = 0;
   std::vector<int64_t> host_row_len(T);
   for (int64_t k = 0; k < T; ++k) {
@@ -340,6 +343,9 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
     x.row_begin = row_off[r];
     x.row_len = (int32_t)(row_off[r + 1] - row_off[r]);
     x.out_index = (int32_t)t;
+    if (d->target_normals)
+      tnrm[k] = make_double4(d->target_normals[3 * t], d->target_normals[3 * t + 1],
+                             d->target_normals[3 * t + 2], 0.0);
     pairs += len;
     max_list = std::max<int64_t>(max_list, len);
     host_row_len[k] = len;
@@ -368,6 +374,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   g->pairs = pairs;
   g->max_list = max_list;
   g->has_normals = d->normals != nullptr;
+  g->has_target_normals = d->target_normals != nullptr;
   g->host_row_len = std::move(host_row_len);
   size_t bytes = 0;
   hipError_t e = dev_upload(&g->src_pos, pos.data(), N, &bytes);
@@ -375,6 +382,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   if (e == hipSuccess && reorder) e = dev_upload(&g->src_perm, perm.data(), N, &bytes);
   if (e == hipSuccess && reorder) e = dev_upload(&g->src_rank, src_rank.data(), N, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->tgt, recs.data(), T, &bytes);
+  if (e == hipSuccess && d->target_normals) e = dev_upload(&g->tgt_nrm, tnrm.data(), T, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->idx, idx.data(), nnz_dev, &bytes);
   if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N + 1, &bytes);
   if (e == hipSuccess && d->normals) e = dev_upload<double4>(&g->stage.qn, nullptr, N + 1, &bytes);
@@ -405,38 +413,52 @@ int tsqbx_geometry_get_info(const tsqbx_geometry *g, tsqbx_geometry_info *out) {
   out->max_list = g->max_list;
   out->device_bytes = g->device_bytes;
   out->has_normals = g->has_normals ? 1 : 0;
+  out->has_target_normals = g->has_target_normals ? 1 : 0;
+  return TSQBX_OK;
+}
+
+// A NULL output for a requested layer, with targets to write, is an error.
+static int check_outputs(const tsqbx_geometry *g, unsigned layers, const double *o_s,
+                         const double *o_d, const double *o_t) {
+  if (g->n_targets > 0 && (((layers & TSQBX_SLP) && !o_s) || ((layers & TSQBX_DLP) && !o_d) ||
+                           ((layers & TSQBX_SPRIME) && !o_t)))
+    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
   return TSQBX_OK;
 }
 
 int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
-                     const double *d_sigma, double *d_out_slp, double *d_out_dlp, unsigned flags,
-                     void *hip_stream) {
+                     const double *d_sigma, double *d_out_slp, double *d_out_dlp,
+                     double *d_out_sprime, unsigned flags, void *hip_stream) {
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_request(g, p, layers);
   if (rc != TSQBX_OK) return rc;
   if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
-  if (g->n_targets > 0 && (((layers & TSQBX_SLP) && !d_out_slp) || ((layers & TSQBX_DLP) && !d_out_dlp)))
-    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  rc = check_outputs(g, layers, d_out_slp, d_out_dlp, d_out_sprime);
+  if (rc != TSQBX_OK) return rc;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)hip_stream;
   const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
+  Outputs o;
+  o.s = d_out_slp;
+  o.d = d_out_dlp;
+  o.t = d_out_sprime;
   TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, s));
-  TSQBX_HIP(launch_eval(g, p, layers, g->stage, d_out_slp, d_out_dlp,
-                        (flags & TSQBX_ACCUMULATE) != 0, tn, s));
+  TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn, s));
   return TSQBX_OK;
 }
 
 int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
-               const double *sigma, double *out_slp, double *out_dlp, unsigned flags) {
+               const double *sigma, double *out_slp, double *out_dlp, double *out_sprime,
+               unsigned flags) {
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_request(g, p, layers);
   if (rc != TSQBX_OK) return rc;
   if (g->n_sources > 0 && !sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
-  if (g->n_targets > 0 && (((layers & TSQBX_SLP) && !out_slp) || ((layers & TSQBX_DLP) && !out_dlp)))
-    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  rc = check_outputs(g, layers, out_slp, out_dlp, out_sprime);
+  if (rc != TSQBX_OK) return rc;
   std::lock_guard<std::mutex> lk(ctx->mu);
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
@@ -448,30 +470,40 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
     TSQBX_HIP(hipMalloc((void **)&ctx->d_sigma, N * sizeof(double)));
     ctx->d_sigma_cap = N;
   }
-  if (ctx->d_out_cap < 2 * T) {
+  if (ctx->d_out_cap < 3 * T) {
     if (ctx->d_out) (void)hipFree(ctx->d_out);
     ctx->d_out = nullptr;
     ctx->d_out_cap = 0;
-    TSQBX_HIP(hipMalloc((void **)&ctx->d_out, 2 * T * sizeof(double)));
-    ctx->d_out_cap = 2 * T;
+    TSQBX_HIP(hipMalloc((void **)&ctx->d_out, 3 * T * sizeof(double)));
+    ctx->d_out_cap = 3 * T;
   }
   hipStream_t s = ctx->stream;
   if (N) TSQBX_HIP(hipMemcpyAsync(ctx->d_sigma, sigma, N * sizeof(double), hipMemcpyHostToDevice, s));
-  double *ds = ctx->d_out, *dd = ctx->d_out + T;
+  Outputs o;
+  o.s = ctx->d_out;
+  o.d = ctx->d_out + T;
+  o.t = ctx->d_out + 2 * T;
   const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
   TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, s));
-  TSQBX_HIP(launch_eval(g, p, layers, g->stage, ds, dd, false, tn, s));
+  TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, false, tn, s));
   // without ACCUMULATE the outputs go straight into the caller's arrays
   const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
-  std::vector<double> hs(acc && (layers & TSQBX_SLP) ? T : 0), hd(acc && (layers & TSQBX_DLP) ? T : 0);
-  double *dst_s = acc ? hs.data() : out_slp, *dst_d = acc ? hd.data() : out_dlp;
-  if (T && (layers & TSQBX_SLP))
-    TSQBX_HIP(hipMemcpyAsync(dst_s, ds, T * sizeof(double), hipMemcpyDeviceToHost, s));
-  if (T && (layers & TSQBX_DLP))
-    TSQBX_HIP(hipMemcpyAsync(dst_d, dd, T * sizeof(double), hipMemcpyDeviceToHost, s));
+  double *const dev[3] = {o.s, o.d, o.t};
+  double *const user[3] = {out_slp, out_dlp, out_sprime};
+  const unsigned bit[3] = {TSQBX_SLP, TSQBX_DLP, TSQBX_SPRIME};
+  std::vector<double> tmp[3];
+  for (int l = 0; l < 3; ++l) {
+    if (!T || !(layers & bit[l])) continue;
+    double *dst = user[l];
+    if (acc) {
+      tmp[l].resize(T);
+      dst = tmp[l].data();
+    }
+    TSQBX_HIP(hipMemcpyAsync(dst, dev[l], T * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   TSQBX_HIP(hipStreamSynchronize(s));
-  for (size_t i = 0; i < hs.size(); ++i) out_slp[i] += hs[i];
-  for (size_t i = 0; i < hd.size(); ++i) out_dlp[i] += hd[i];
+  for (int l = 0; l < 3; ++l)
+    for (size_t i = 0; i < tmp[l].size(); ++i) user[l][i] += tmp[l][i];
   return TSQBX_OK;
 }
 
@@ -524,7 +556,7 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
     if (e1) (void)hipEventDestroy(e1);
   };
   hipError_t e = hipMalloc((void **)&sig, N * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void **)&o, 2 * T * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&o, 3 * T * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(sig, ones.data(), N * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -534,6 +566,10 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
     cleanup();
     return fail_hip(e, "autotune setup");
   }
+  Outputs outs;
+  outs.s = o;
+  outs.d = o + T;
+  outs.t = o + 2 * T;
   Tuning best;
   double best_t = 1e300;
   const int GU[][2] = {{64, 1}, {64, 2}, {64, 4}, {32, 2}, {16, 2}};
@@ -546,11 +582,11 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
         t.unroll = gu[1];
         t.waves_per_block = w;
         t.xcd_remap = remap;
-        e = launch_eval(g, p, layers, g->stage, o, o + T, false, t, s);  // warm-up
+        e = launch_eval(g, p, layers, g->stage, outs, false, t, s);  // warm-up
         float best_rep = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
           e = hipEventRecord(e0, s);
-          if (e == hipSuccess) e = launch_eval(g, p, layers, g->stage, o, o + T, false, t, s);
+          if (e == hipSuccess) e = launch_eval(g, p, layers, g->stage, outs, false, t, s);
           if (e == hipSuccess) e = hipEventRecord(e1, s);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0;

@@ -37,6 +37,14 @@ struct SourceStage {
   double4 *qn = nullptr;    // [N + 1] (q nx, q ny, q nz, 0); entry N: 0
 };
 
+// Output vectors of one evaluation (device pointers, caller's target order);
+// null for a layer not evaluated.
+struct Outputs {
+  double *s = nullptr;  // single layer
+  double *d = nullptr;  // double layer
+  double *t = nullptr;  // S', normal derivative of the single layer at the target
+};
+
 struct Tuning {
   int waves_per_block = 4;
   int group_lanes = 64;
@@ -66,11 +74,13 @@ struct tsqbx_geometry {
   int device = 0;
   int64_t n_sources = 0, n_centers = 0, n_targets = 0, nnz = 0, pairs = 0, max_list = 0;
   bool has_normals = false;
+  bool has_target_normals = false;
   double4 *src_pos = nullptr;    // [N] (x, y, z, w) in device order
   double4 *src_nrm = nullptr;    // [N] (nx, ny, nz, 0) or null
   int64_t *src_perm = nullptr;   // [N] device order -> caller index, null if identity
   int32_t *src_rank = nullptr;   // [N] caller index -> device order, null if identity
   tsqbx::TargetRec *tgt = nullptr;  // [T] in device order
+  double4 *tgt_nrm = nullptr;    // [T] (nx, ny, nz, 0) at the targets, device order, or null
   int32_t *idx = nullptr;        // [nnz'] lists in device numbering, one row per target group
   tsqbx::SourceStage stage;      // staging used by the plain path
   size_t device_bytes = 0;
@@ -92,8 +102,7 @@ int fail_hip(hipError_t e, const char *what);
 hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
                         const SourceStage &st, hipStream_t s);
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
-                       double *out_s, double *out_d, bool accumulate, const Tuning &tn,
-                       hipStream_t s);
+                       const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
 bool tuning_supported(const Tuning &tn);
 
 // Staging of many items in one launch (batched and served paths).
@@ -123,7 +132,7 @@ struct CopyItem {          // 32 bytes
 hipError_t launch_copy_multi(const CopyItem *d_items, int n_items, int64_t max_n, hipStream_t s);
 
 // Persistent batched kernel.
-struct WorkItem {           // one (geometry, p, layers) item of a plan, 128 bytes
+struct WorkItem {           // one (geometry, p, layers) item of a plan, 80 bytes
   const TargetRec *tgt;
   const int32_t *idx;
   const double4 *posq;
@@ -134,8 +143,10 @@ struct WorkItem {           // one (geometry, p, layers) item of a plan, 128 byt
   int32_t layers;
   int32_t accumulate;
   int32_t pad0;
-  int64_t pad1[2];
+  const double4 *tnrm;      // target normals (S'), device order
+  double *out_t;            // S' output
 };
+static_assert(sizeof(WorkItem) == 80, "WorkItem layout");
 struct WorkUnit {           // a run of consecutive targets of one item, 16 bytes
   int32_t item;
   int32_t first;            // first device-order target
@@ -152,8 +163,24 @@ struct PersistentArgs {
   const int32_t *wave_begin;  // [n_waves + 1]
   int32_t n_waves;
 };
-// layer_class: 1 or 2 if every item has that layer mask, else 3; p_all: the
-// order shared by every item, or -1.
+// Layer classes of the persistent kernel: 1, 2 or 3 when every item has that
+// mask, kLayersMixed when items mix masks 1..3, kLayersAny when some item
+// asks for S'.  A kernel compiled for fewer masks keeps fewer registers.
+constexpr unsigned kLayersMixed = 0, kLayersAny = 8;
+struct LayerClass {
+  unsigned first = 0, all = 0;
+  bool same = true;
+  void add(unsigned mask) {
+    if (!all) first = mask;
+    else if (mask != first) same = false;
+    all |= mask;
+  }
+  unsigned get() const {
+    if (same && first >= 1 && first <= 3) return first;
+    return (all & TSQBX_SPRIME) ? kLayersAny : kLayersMixed;
+  }
+};
+// p_all: the order shared by every item, or -1.
 hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all,
                              const Tuning &tn, hipStream_t s);
 int persistent_max_waves(int num_cus);

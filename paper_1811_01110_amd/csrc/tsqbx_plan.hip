@@ -31,7 +31,7 @@ struct tsqbx_plan {
   int64_t n_units = 0;
   int64_t pairs = 0, pair_terms = 0;
   int grid = 0;
-  unsigned layer_class = 3;  // 1 or 2 when every item has that mask
+  unsigned layer_class = kLayersMixed;  // see LayerClass
   int p_all = -1;            // the order shared by every item, or -1
   Tuning tn;
   size_t device_bytes = 0;
@@ -71,12 +71,14 @@ void free_plan(tsqbx_plan *pl) {
   delete pl;
 }
 
-int layer_count(unsigned l) { return ((l & 1u) ? 1 : 0) + ((l & 2u) ? 1 : 0); }
+int layer_count(unsigned l) { return ((l & 1u) ? 1 : 0) + ((l & 2u) ? 1 : 0) + ((l & 4u) ? 1 : 0); }
 
 // Relative cost (vector instructions) of one pair: four per recurrence
-// order plus the per-pair setup and closing sums.
+// order plus the per-pair setup and the closing sums of each layer.
 double pair_cost(int p, unsigned layers) {
-  const double setup = (layers & 2u) ? 50.0 : 35.0;
+  double setup = layers == TSQBX_SLP ? 35.0 : 42.0;
+  if (layers & TSQBX_DLP) setup += 8.0;
+  if (layers & TSQBX_SPRIME) setup += 9.0;
   return 4.0 * std::max(p - 1, 0) + setup;
 }
 
@@ -153,7 +155,8 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
     if (it.geom->n_sources > 0 && !it.d_sigma)
       return fail(TSQBX_E_INVALID, "item %lld: sigma is NULL", (long long)i);
     if (it.geom->n_targets > 0 &&
-        (((it.layers & TSQBX_SLP) && !it.d_out_slp) || ((it.layers & TSQBX_DLP) && !it.d_out_dlp)))
+        (((it.layers & TSQBX_SLP) && !it.d_out_slp) || ((it.layers & TSQBX_DLP) && !it.d_out_dlp) ||
+         ((it.layers & TSQBX_SPRIME) && !it.d_out_sprime)))
       return fail(TSQBX_E_INVALID, "item %lld: output for a requested layer is NULL", (long long)i);
   }
   Guard dg(ctx->device);
@@ -168,12 +171,10 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   int64_t tot_pairs = 0, tot_targets = 0;
   int pmax = 0;
   unsigned lay_all = 0;
-  if (!pl->items.empty()) {
-    pl->layer_class = pl->items[0].layers;
-    pl->p_all = pl->items[0].p;
-  }
+  LayerClass lc;
+  if (!pl->items.empty()) pl->p_all = pl->items[0].p;
   for (auto &it : pl->items) {
-    if (it.layers != pl->layer_class) pl->layer_class = 3;
+    lc.add(it.layers);
     if (it.p != pl->p_all) pl->p_all = -1;
     tot_pairs += it.geom->pairs;
     tot_targets += it.geom->n_targets;
@@ -182,6 +183,7 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
     pl->pairs += it.geom->pairs;
     pl->pair_terms += it.geom->pairs * (int64_t)(it.p + 1) * layer_count(it.layers);
   }
+  pl->layer_class = lc.get();
   const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
   pl->tn = lookup_tuning(ctx, pmax, lay_all ? lay_all : 1u, mean_list);
   if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent kernels keep two pairs in flight
@@ -237,6 +239,8 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
     w.qn = pl->stages[i].qn;
     w.out_s = it.d_out_slp;
     w.out_d = it.d_out_dlp;
+    w.out_t = it.d_out_sprime;
+    w.tnrm = it.geom->tgt_nrm;
     w.p = it.p;
     w.layers = (int32_t)it.layers;
     w.accumulate = (flags & TSQBX_ACCUMULATE) ? 1 : 0;

@@ -87,14 +87,15 @@ struct Request {
   const tsqbx_geometry *geom = nullptr;
   int p = 0;
   unsigned layers = 0;
-  // host staging: [sigma (N) | out_slp (T) | out_dlp (T)], pinned when it fits
+  // host staging: [sigma (N) | one T-vector per requested layer, in the order
+  // single layer, double layer, S'], pinned when it fits
   double *h_stage = nullptr;
   bool pinned = false;
   bool borrowed = false;            // caller's pinned buffers, no staging
   const double *sigma_src = nullptr;  // what the upload reads
   size_t pin_off = 0, pin_bytes = 0;
   std::vector<double> pageable;  // fallback staging
-  double *out_s = nullptr, *out_d = nullptr;
+  double *out[3] = {nullptr, nullptr, nullptr};  // caller's outputs per layer
   size_t bytes = 0, arena_off = 0;
   double t_submit = 0, t_launch = 0, t_done = 0;
   int status = TSQBX_OK;
@@ -172,12 +173,18 @@ struct tsqbx_server {
   void completer();
 };
 
+static int n_layers(unsigned layers) {
+  return ((layers & TSQBX_SLP) ? 1 : 0) + ((layers & TSQBX_DLP) ? 1 : 0) +
+         ((layers & TSQBX_SPRIME) ? 1 : 0);
+}
+
+// Device bytes of a request: [sigma (N) | posq (N+1) | qn (N+1), double layer
+// only | one T-vector per requested layer].
 static size_t request_bytes(const tsqbx_geometry *g, unsigned layers) {
   const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
   size_t b = align_up(N * sizeof(double)) + align_up((N + 1) * sizeof(double4));
   if (layers & TSQBX_DLP) b += align_up((N + 1) * sizeof(double4));
-  if (layers & TSQBX_SLP) b += align_up(T * sizeof(double));
-  if (layers & TSQBX_DLP) b += align_up(T * sizeof(double));
+  b += n_layers(layers) * align_up(T * sizeof(double));
   return std::max<size_t>(b, kAlign);
 }
 
@@ -202,6 +209,8 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
   // DMA copies for requests staged in pageable memory: (destination, source, count)
   std::vector<std::tuple<double *, const double *, size_t>> pageable_up, pageable_down;
   int64_t max_n = 0, max_t = 0;
+  LayerClass lc;
+  int p_all = K ? step.reqs[0]->p : -1;
   const int64_t per_unit = (int64_t)kUnitSteps * (64 / tn.group_lanes);
   for (size_t i = 0; i < K; ++i) {
     Request *r = step.reqs[i];
@@ -217,12 +226,12 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
       stg.qn = (double4 *)(base + off);
       off += align_up((N + 1) * sizeof(double4));
     }
-    double *d_out_s = nullptr, *d_out_d = nullptr;
-    if (r->layers & TSQBX_SLP) {
-      d_out_s = (double *)(base + off);
-      off += align_up(T * sizeof(double));
-    }
-    if (r->layers & TSQBX_DLP) d_out_d = (double *)(base + off);
+    double *d_out[3] = {nullptr, nullptr, nullptr};
+    for (int l = 0; l < 3; ++l)
+      if (r->layers & (1u << l)) {
+        d_out[l] = (double *)(base + off);
+        off += align_up(T * sizeof(double));
+      }
     const bool host_pinned = r->borrowed || r->pinned;
     const double *sig = r->sigma_src;
     if (!host_pinned) {
@@ -238,10 +247,14 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     w.idx = g->idx;
     w.posq = stg.posq;
     w.qn = stg.qn;
-    w.out_s = d_out_s;
-    w.out_d = d_out_d;
+    w.out_s = d_out[0];
+    w.out_d = d_out[1];
+    w.out_t = d_out[2];
+    w.tnrm = g->tgt_nrm;
     w.p = r->p;
     w.layers = (int32_t)r->layers;
+    lc.add(r->layers);
+    if (r->p != p_all) p_all = -1;
     // fixed-size units, one per wave: constant host work per unit, and the
     // dispatcher balances the waves
     for (int64_t k = 0; k < g->n_targets; k += per_unit) {
@@ -251,17 +264,15 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     }
     // outputs: into the caller's pinned buffers or the request's host staging
     if (T) {
-      double *hs = r->borrowed ? r->out_s : r->h_stage + N;
-      double *hd = r->borrowed ? r->out_d : r->h_stage + N + ((r->layers & TSQBX_SLP) ? T : 0);
-      const std::pair<double *, const double *> outs[2] = {
-          {(r->layers & TSQBX_SLP) ? hs : nullptr, d_out_s},
-          {(r->layers & TSQBX_DLP) ? hd : nullptr, d_out_d}};
-      for (const auto &o : outs) {
-        if (!o.first) continue;
+      double *h = r->h_stage + N;  // host staging: requested layers in order
+      for (int l = 0; l < 3; ++l) {
+        if (!(r->layers & (1u << l))) continue;
+        double *dst = r->borrowed ? r->out[l] : h;
+        if (!r->borrowed) h += T;
         if (host_pinned)
-          copies.push_back(CopyItem{o.second, o.first, (int64_t)T, 0});
+          copies.push_back(CopyItem{d_out[l], dst, (int64_t)T, 0});
         else
-          pageable_down.emplace_back(o.first, o.second, T);
+          pageable_down.emplace_back(dst, d_out[l], T);
       }
     }
   }
@@ -299,7 +310,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
   if (e == hipSuccess && !units.empty()) {
     PersistentArgs a{(const WorkItem *)(ss.d_meta + o_items), (const WorkUnit *)(ss.d_meta + o_units),
                      (const int32_t *)(ss.d_meta + o_wave), (int32_t)wave_begin.size() - 1};
-    e = launch_persistent(a, 3u, -1, tn, s);
+    e = launch_persistent(a, lc.get(), p_all, tn, s);
   }
   if (e == hipSuccess)
     e = launch_copy_multi((const CopyItem *)(ss.d_meta + o_copy), (int)copies.size(), max_t, s);
@@ -438,17 +449,16 @@ void tsqbx_server::completer() {
     for (Request *r : step.reqs) {
       const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
       if (qerr == hipSuccess) {
-        if (!r->borrowed) {
+        if (!r->borrowed && T) {
           const double *h = r->h_stage + N;
-          if (r->layers & TSQBX_SLP) {
-            if (T) std::memcpy(r->out_s, h, T * sizeof(double));
-            h += T;
-          }
-          if ((r->layers & TSQBX_DLP) && T) std::memcpy(r->out_d, h, T * sizeof(double));
+          for (int l = 0; l < 3; ++l)
+            if (r->layers & (1u << l)) {
+              std::memcpy(r->out[l], h, T * sizeof(double));
+              h += T;
+            }
         }
         ++st.completed;
-        st.pair_terms_completed +=
-            r->geom->pairs * (int64_t)(r->p + 1) * (((r->layers & 1) ? 1 : 0) + ((r->layers & 2) ? 1 : 0));
+        st.pair_terms_completed += r->geom->pairs * (int64_t)(r->p + 1) * n_layers(r->layers);
       } else {
         r->status = TSQBX_E_DEVICE;
         ++st.failed;
@@ -476,7 +486,7 @@ extern "C" {
 
 int tsqbx_server_request_bytes(const tsqbx_geometry *geom, unsigned layers, size_t *out) {
   if (!geom || !out) return fail(TSQBX_E_INVALID, "geometry or out is NULL");
-  if (layers == 0 || (layers & ~3u)) return fail(TSQBX_E_INVALID, "bad layer mask %u", layers);
+  if (layers == 0 || (layers & ~7u)) return fail(TSQBX_E_INVALID, "bad layer mask %u", layers);
   *out = request_bytes(geom, layers);
   return TSQBX_OK;
 }
@@ -540,19 +550,20 @@ static bool is_pinned_host(const void *p) {
 }
 
 static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
-                       const double *sigma_host, double *out_slp_host, double *out_dlp_host,
-                       uint64_t *ticket, bool borrow) {
+                       const double *sigma_host, double *const out_host[3], uint64_t *ticket,
+                       bool borrow) {
   if (!sv || !geom || !ticket) return fail(TSQBX_E_INVALID, "server, geometry or ticket is NULL");
   if (geom->ctx != sv->ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = tsqbx_check_request(geom, p, layers);
   if (rc != TSQBX_OK) return rc;
   if (geom->n_sources > 0 && !sigma_host) return fail(TSQBX_E_INVALID, "sigma is NULL");
-  if (geom->n_targets > 0 && (((layers & TSQBX_SLP) && !out_slp_host) || ((layers & TSQBX_DLP) && !out_dlp_host)))
-    return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
+  for (int l = 0; l < 3; ++l)
+    if (geom->n_targets > 0 && (layers & (1u << l)) && !out_host[l])
+      return fail(TSQBX_E_INVALID, "output for a requested layer is NULL");
   if (borrow) {
-    const double *bufs[3] = {geom->n_sources ? sigma_host : nullptr,
-                             (geom->n_targets && (layers & TSQBX_SLP)) ? out_slp_host : nullptr,
-                             (geom->n_targets && (layers & TSQBX_DLP)) ? out_dlp_host : nullptr};
+    const double *bufs[4] = {geom->n_sources ? sigma_host : nullptr, nullptr, nullptr, nullptr};
+    for (int l = 0; l < 3; ++l)
+      if (geom->n_targets && (layers & (1u << l))) bufs[1 + l] = out_host[l];
     for (const double *b : bufs)
       if (!is_pinned_host(b))
         return fail(TSQBX_E_INVALID, "submit_pinned: a buffer is not pinned host memory");
@@ -567,7 +578,7 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
     r->borrowed = true;
     r->sigma_src = sigma_host;
   } else {
-    const size_t words = N + T * ((layers & TSQBX_SLP ? 1 : 0) + (layers & TSQBX_DLP ? 1 : 0));
+    const size_t words = N + T * n_layers(layers);
     r->pin_bytes = align_up(std::max<size_t>(words, 1) * sizeof(double));
     {
       std::lock_guard<std::mutex> g(sv->pinned_mu);
@@ -582,8 +593,7 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
     if (N) std::memcpy(r->h_stage, sigma_host, N * sizeof(double));
     r->sigma_src = r->h_stage;
   }
-  r->out_s = out_slp_host;
-  r->out_d = out_dlp_host;
+  for (int l = 0; l < 3; ++l) r->out[l] = (layers & (1u << l)) ? out_host[l] : nullptr;
   r->bytes = bytes;
   std::lock_guard<std::mutex> lk(sv->mu);
   ++sv->st.submitted;
@@ -609,14 +619,16 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
 
 int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
                         const double *sigma_host, double *out_slp_host, double *out_dlp_host,
-                        uint64_t *ticket) {
-  return submit_impl(sv, geom, p, layers, sigma_host, out_slp_host, out_dlp_host, ticket, false);
+                        double *out_sprime_host, uint64_t *ticket) {
+  double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
+  return submit_impl(sv, geom, p, layers, sigma_host, outs, ticket, false);
 }
 
 int tsqbx_server_submit_pinned(tsqbx_server *sv, const tsqbx_geometry *geom, int p,
                                unsigned layers, const double *sigma_host, double *out_slp_host,
-                               double *out_dlp_host, uint64_t *ticket) {
-  return submit_impl(sv, geom, p, layers, sigma_host, out_slp_host, out_dlp_host, ticket, true);
+                               double *out_dlp_host, double *out_sprime_host, uint64_t *ticket) {
+  double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
+  return submit_impl(sv, geom, p, layers, sigma_host, outs, ticket, true);
 }
 
 int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {

@@ -73,7 +73,9 @@ def test_check_request_ranges():
     assert lib.tsqbx_check_request(None, 33, 1) == L.E_RANGE
     assert lib.tsqbx_check_request(None, -1, 1) == L.E_RANGE
     assert lib.tsqbx_check_request(None, 4, 0) == L.E_INVALID
-    assert lib.tsqbx_check_request(None, 4, 4) == L.E_INVALID
+    assert lib.tsqbx_check_request(None, 4, 7) == 0
+    assert lib.tsqbx_check_request(None, 4, 4) == 0
+    assert lib.tsqbx_check_request(None, 4, 8) == L.E_INVALID
     assert b"layers" in lib.tsqbx_last_error()
 
 

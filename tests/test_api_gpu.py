@@ -25,7 +25,7 @@ def test_autotune_installs_a_supported_tuning(ctx):
     assert tuning["group_lanes"] in (16, 32, 64) and tuning["waves_per_block"] in (1, 2, 4)
     mean = max(geom.pairs // geom.n_targets, 1)
     assert ctx.get_tuning(16, 3, mean) == tuning
-    s, d = ctx.eval(geom, g.sigma, 16, 3)
+    s, d, _ = ctx.eval(geom, g.sigma, 16, 3)
     ref = oracle.evaluate_geometry(g)
     assert_parity(s, ref["slp"], ref["abs_slp"], what="autotuned slp")
     assert_parity(d, ref["dlp"], ref["abs_dlp"], what="autotuned dlp")
@@ -47,7 +47,7 @@ def test_plan_accumulates(ctx):
     plan.execute()
     plan.execute()
     torch.cuda.synchronize()
-    s, d = ctx.eval(geom, g.sigma, 12, 3)
+    s, d, _ = ctx.eval(geom, g.sigma, 12, 3)
     assert np.array_equal(os_.cpu().numpy(), (0.5 + s) + s)
     assert np.array_equal(od_.cpu().numpy(), (0.5 + d) + d)
     plan.close()
@@ -70,7 +70,7 @@ def test_targets_outside_the_convergence_ball_low_order(ctx):
                    rng.standard_normal(n), 4, 3)
     geom = ctx.geometry(g)
     for p in (0, 1, 2, 4, 6):
-        s, d = ctx.eval(geom, g.sigma, p, 3)
+        s, d, _ = ctx.eval(geom, g.sigma, p, 3)
         ref = oracle.evaluate_geometry(g, p=p)
         assert_parity(s, ref["slp"], ref["abs_slp"], what=f"outside p={p} slp")
         assert_parity(d, ref["dlp"], ref["abs_dlp"], what=f"outside p={p} dlp")
@@ -92,7 +92,7 @@ def test_server_wait_times_out_and_destroy_finishes_in_flight_work(ctx):
     srv.wait(tickets[-1][0], 120.0)
     more = [srv.submit(geom, g.sigma, 16, 3) for _ in range(4)]
     srv.close()  # returns only after the in-flight requests have completed
-    for _, a, b in tickets + more:
+    for _, a, b, _t in tickets + more:
         assert np.array_equal(a, tickets[0][1])
         assert np.array_equal(b, tickets[0][2])
     ref = oracle.evaluate_geometry(g)

@@ -57,7 +57,7 @@ def test_plan_matches_plain_and_oracle(ctx):
         # plain evaluation with the same group width gives the same bits
         mean_i = max(it["geom"].pairs // max(it["geom"].n_targets, 1), 1)
         ctx.set_tuning(g.p, g.layers, mean_i, group_lanes=G, unroll=2)
-        s, d = ctx.eval(it["geom"], g.sigma, g.p, g.layers)
+        s, d, _ = ctx.eval(it["geom"], g.sigma, g.p, g.layers)
         if g.layers & 1:
             assert np.array_equal(s, it["out_slp"].cpu().numpy()), g.name
         if g.layers & 2:
@@ -82,7 +82,7 @@ def test_plan_graph_replays_follow_inputs(ctx):
         plan.execute()
         torch.cuda.synchronize()
         for it, s in zip(items, sigmas):
-            a, b = ctx.eval(it["geom"], s, it["p"], 3)
+            a, b, _ = ctx.eval(it["geom"], s, it["p"], 3)
             ref = oracle.evaluate_geometry(it["g"], sigma=s)
             assert_parity(it["out_slp"].cpu().numpy(), ref["slp"], ref["abs_slp"], what=f"replay {rep}")
             assert_parity(it["out_dlp"].cpu().numpy(), ref["dlp"], ref["abs_dlp"], what=f"replay {rep}")
@@ -103,7 +103,7 @@ def test_server_alone_equals_mix(ctx):
     srv = ctx.server(budget, 8)
     alone = []
     for k, p, lay, sig in reqs:
-        t, a, b = srv.submit(gs[k], sig, p, lay)
+        t, a, b, _ = srv.submit(gs[k], sig, p, lay)
         srv.wait(t, 60)
         alone.append((a, b))
     tickets = [srv.submit(gs[k], sig, p, lay) for k, p, lay, sig in reqs]
@@ -111,7 +111,7 @@ def test_server_alone_equals_mix(ctx):
     st = srv.stats()
     assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
     assert st["peak_bytes_in_flight"] <= budget
-    for (k, p, lay, sig), (t, a, b), (a0, b0) in zip(reqs, tickets, alone):
+    for (k, p, lay, sig), (t, a, b, _), (a0, b0) in zip(reqs, tickets, alone):
         assert srv.poll(t)
         if lay & 1:
             assert np.array_equal(a, a0)
@@ -141,7 +141,7 @@ def test_server_rejects_oversized_and_respects_budget(ctx):
     srv.drain(60)
     st = srv.stats()
     assert st["completed"] == 6 and st["peak_bytes_in_flight"] <= need + need // 2
-    for _, a, _b in ts:
+    for _, a, _b, _t in ts:
         assert np.array_equal(a, ts[0][1])
     srv.close()
 
@@ -159,8 +159,8 @@ def test_server_pinned_submissions_match_copying_ones(ctx):
         lay = (1, 2, 3)[i % 3]
         s_np = rng.standard_normal(geoms[k].n_sources)
         s_pin = torch.tensor(s_np, dtype=torch.float64).pin_memory()
-        t1, a1, b1 = srv.submit(gs[k], s_np, 8 + 8 * (i % 2), lay)
-        t2, a2, b2 = srv.submit_pinned(gs[k], s_pin, 8 + 8 * (i % 2), lay)
+        t1, a1, b1, _ = srv.submit(gs[k], s_np, 8 + 8 * (i % 2), lay)
+        t2, a2, b2, _ = srv.submit_pinned(gs[k], s_pin, 8 + 8 * (i % 2), lay)
         pending.append((lay, a1, b1, a2, b2))
     srv.drain(120)
     for lay, a1, b1, a2, b2 in pending:
@@ -171,4 +171,56 @@ def test_server_pinned_submissions_match_copying_ones(ctx):
     with pytest.raises(api.TsqbxError) as ei:  # pageable memory is refused
         srv.submit_pinned(gs[0], torch.zeros(geoms[0].n_sources, dtype=torch.float64), 8, 1)
     assert ei.value.code == -1
+    srv.close()
+
+
+def test_plan_and_server_with_sprime(ctx):
+    """Items and requests asking for S' (alone and beside other layers) run in
+    the any-mask persistent kernel and match plain evaluations bit for bit."""
+    import torch
+
+    masks = [4, 5, 6, 7, 1, 2, 3]
+    geoms = [W.fuzz_geometry(700 + i, n=600, m=150, max_list=250, p=(8, 16, 5)[i % 3], layers=lay)
+             for i, lay in enumerate(masks)]
+    items = []
+    for g in geoms:
+        geom = ctx.geometry(g)
+        it = dict(geom=geom, p=g.p, layers=g.layers, g=g,
+                  sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64))
+        for bit, key in ((1, "out_slp"), (2, "out_dlp"), (4, "out_sprime")):
+            if g.layers & bit:
+                it[key] = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
+        items.append(it)
+    plan = ctx.plan(items)
+    plan.execute()
+    torch.cuda.synchronize()
+    mean = max(sum(i["geom"].pairs for i in items) // sum(i["geom"].n_targets for i in items), 1)
+    G = ctx.get_tuning(16, 7, mean)["group_lanes"]
+    for it in items:
+        g = it["g"]
+        ref = oracle.evaluate_geometry(g)
+        mean_i = max(it["geom"].pairs // max(it["geom"].n_targets, 1), 1)
+        ctx.set_tuning(g.p, g.layers, mean_i, group_lanes=G, unroll=2)
+        plain = ctx.eval(it["geom"], g.sigma, g.p, g.layers)
+        for k, (bit, key, name) in enumerate(((1, "out_slp", "slp"), (2, "out_dlp", "dlp"),
+                                              (4, "out_sprime", "sprime"))):
+            if not g.layers & bit:
+                continue
+            got = it[key].cpu().numpy()
+            assert_parity(got, ref[name], ref["abs_" + name], what=f"plan mask {g.layers} {name}")
+            assert np.array_equal(got, plain[k]), (g.layers, name)
+    plan.close()
+    # the server: the same requests, all at once
+    gs = [it["geom"] for it in items]
+    srv = ctx.server(8 * max(api.Server.request_bytes(x, 7) for x in gs), 16)
+    tickets = [srv.submit(x, g.sigma, g.p, g.layers) for x, g in zip(gs, geoms)]
+    srv.drain(60)
+    assert srv.stats()["failed"] == 0
+    for (t, *outs), g in zip(tickets, geoms):
+        ref = oracle.evaluate_geometry(g)
+        for k, (bit, name) in enumerate(((1, "slp"), (2, "dlp"), (4, "sprime"))):
+            if g.layers & bit:
+                assert_parity(outs[k], ref[name], ref["abs_" + name], what=f"served {name}")
+            else:
+                assert outs[k] is None
     srv.close()

@@ -25,15 +25,17 @@ def _check(ctx, g, p=None, layers=None, select=None, flags=0, what=""):
     p = g.p if p is None else p
     layers = g.layers if layers is None else layers
     geom = ctx.geometry(g, flags=flags)
-    s, d = ctx.eval(geom, g.sigma, p, layers)
+    s, d, t = ctx.eval(geom, g.sigma, p, layers)
     ref = oracle.evaluate_geometry(g, p=p, layers=layers, select=select)
     sel = slice(None) if select is None else select
     if layers & api.SLP:
         assert_parity(s[sel], ref["slp"], ref["abs_slp"], what=f"{what} slp")
     if layers & api.DLP:
         assert_parity(d[sel], ref["dlp"], ref["abs_dlp"], what=f"{what} dlp")
+    if layers & api.SPRIME:
+        assert_parity(t[sel], ref["sprime"], ref["abs_sprime"], what=f"{what} sprime")
     geom.close()
-    return s, d
+    return s, d, t
 
 
 def test_config_a_dense_lists(ctx):
@@ -74,14 +76,14 @@ def test_edge_cases(ctx):
     g0 = W.Geometry(g.sources, g.weights, g.normals, g.centers, g.list_offsets, g.list_sources,
                     np.zeros((0, 3)), np.zeros(0, dtype=np.int32), g.sigma, 4, 3)
     geom = ctx.geometry(g0)
-    s, d = ctx.eval(geom, g.sigma, 4, 3)
+    s, d, _ = ctx.eval(geom, g.sigma, 4, 3)
     assert s.size == 0 and d.size == 0
     # every list empty
     off = np.zeros(g.n_centers + 1, dtype=np.int64)
     ge = W.Geometry(g.sources, g.weights, g.normals, g.centers, off, np.zeros(0, dtype=np.int32),
                     g.targets, g.target_center, g.sigma, 4, 3)
     geom = ctx.geometry(ge)
-    s, d = ctx.eval(geom, g.sigma, 4, 3)
+    s, d, _ = ctx.eval(geom, g.sigma, 4, 3)
     assert np.all(s == 0) and np.all(d == 0)
     # one source, list of length one, target at its center (rho = 0)
     one = W.Geometry(np.array([[1.0, 2.0, 0.5]]), np.array([0.7]), np.array([[0.0, 0.6, 0.8]]),
@@ -101,7 +103,7 @@ def test_tuning_variants(ctx):
             for remap in (0, 1):
                 ctx.set_tuning(16, 3, mean, waves_per_block=w, group_lanes=G, unroll=U,
                                xcd_remap=remap)
-                s, d = ctx.eval(geom, g.sigma, 16, 3)
+                s, d, _ = ctx.eval(geom, g.sigma, 16, 3)
                 assert_parity(s, ref["slp"], ref["abs_slp"], what=f"G{G}U{U}w{w}")
                 assert_parity(d, ref["dlp"], ref["abs_dlp"], what=f"G{G}U{U}w{w}")
                 if G == 64:
@@ -117,7 +119,7 @@ def test_async_device_path_and_accumulate(ctx):
 
     g = W.fuzz_geometry(12, n=800, m=200, max_list=400, p=12, layers=3)
     geom = ctx.geometry(g)
-    s_host, d_host = ctx.eval(geom, g.sigma, 12, 3)
+    s_host, d_host, _ = ctx.eval(geom, g.sigma, 12, 3)
     sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
     os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
     od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
@@ -130,7 +132,7 @@ def test_async_device_path_and_accumulate(ctx):
     assert np.array_equal(os_.cpu().numpy(), s_host + s_host)
     assert np.array_equal(od_.cpu().numpy(), d_host + d_host)
     # the single layer alone runs its own recurrence (equal to 1e-12, not bitwise)
-    s_only, _ = ctx.eval(geom, g.sigma, 12, api.SLP)
+    s_only, _, _ = ctx.eval(geom, g.sigma, 12, api.SLP)
     ref = oracle.evaluate_geometry(g, p=12, layers=1)
     assert_parity(s_only, ref["slp"], ref["abs_slp"], what="slp alone")
     base_s = np.full(g.n_targets, 0.25)
@@ -168,3 +170,66 @@ def test_config_d_geometry_sampled(ctx):
     sel = np.sort(rng.choice(g.n_targets, 256, replace=False))
     print("config D[0]", g.n_sources, g.n_targets, g.nnz, flush=True)
     _check(ctx, g, select=sel, what="D0")
+
+
+# ---------------------------------------------------------------------------
+# S': the normal derivative of the single layer at the target (App. A)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", list(range(0, 33)))
+def test_sprime_every_order_ragged_lists(ctx, p):
+    g = W.fuzz_geometry(600 + p, n=300, m=70, max_list=140, p=p, layers=7, targets_per_center=2)
+    _check(ctx, g, layers=7, what=f"fuzz p={p} all layers")
+
+
+def test_sprime_layer_masks_share_the_derivative_recurrence(ctx):
+    """Masks 4..7 against the oracle; every mask with the double layer or S'
+    runs the same recurrence, so S' (and the double layer, and the single
+    layer beside either) has the same bits in every such mask."""
+    g = W.fuzz_geometry(640, n=700, m=120, max_list=400, p=16, layers=7)
+    res = {lay: _check(ctx, g, layers=lay, what=f"mask {lay}") for lay in (2, 3, 4, 5, 6, 7)}
+    for lay in (5, 6, 7):
+        assert np.array_equal(res[lay][2], res[4][2]), lay
+    for lay in (3, 6, 7):
+        assert np.array_equal(res[lay][1], res[2][1]), lay
+    for lay in (5, 7):
+        assert np.array_equal(res[lay][0], res[3][0]), lay
+
+
+def test_sprime_config_b_full_size_sampled(ctx):
+    g = cached_workload("config_b", 1)
+    assert g.target_normals is not None
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(g.n_targets, 384, replace=False))
+    _check(ctx, g, layers=7, select=sel, what="B all layers")
+
+
+def test_sprime_at_center_and_tuning_variants(ctx):
+    g = W.fuzz_geometry(641, n=1500, m=250, max_list=600, p=12, layers=7)
+    g.targets[:5] = g.centers[g.target_center[:5]]  # t = c: only the n = 1 term
+    geom = ctx.geometry(g)
+    ref = oracle.evaluate_geometry(g, layers=4)
+    mean = max(geom.pairs // max(geom.n_targets, 1), 1)
+    base = None
+    for G, U in ((64, 1), (64, 2), (64, 4), (32, 2), (16, 2)):
+        ctx.set_tuning(12, 4, mean, group_lanes=G, unroll=U)
+        _, _, t = ctx.eval(geom, g.sigma, 12, 4)
+        assert_parity(t, ref["sprime"], ref["abs_sprime"], what=f"G{G}U{U}")
+        if G == 64:
+            base = t.copy() if base is None else base
+            assert np.array_equal(t, base)
+    geom.close()
+
+
+def test_sprime_needs_target_normals(ctx):
+    g = W.fuzz_geometry(642, n=50, m=10, max_list=20, p=4, layers=1)
+    g.target_normals = None
+    geom = ctx.geometry(g)
+    assert not geom.has_target_normals
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval(geom, g.sigma, 4, api.SPRIME)
+    assert ei.value.code == -1
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval(geom, g.sigma, 4, 8)
+    assert ei.value.code == -1
+    geom.close()
