@@ -2,15 +2,17 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-serve]
                     [--with-d] [--no-cpu] [--requests R] [--min-warm S]
-                    [--only headline|batched|high_order|serve] [--calibration-copy]
+                    [--no-sprime] [--only headline|batched|high_order|serve|sprime]
+                    [--calibration-copy]
 
 The headline `value` is the plain single- plus double-layer evaluation at
 p = 16 on the perturbed-sphere workload (262144 sources, 65536 targets,
 ball lists of radius 0.15 about centers 0.02 inside the surface), inputs
 resident in device memory, K timed steps.  One step = staging of q = w sigma
 plus the evaluation kernel.  Extra objects report the batched workload (64
-geometries, mixed p, one persistent launch vs plain per-geometry launches)
-and the served Poisson stream (p50/p99 latency).  The oracle timed on the
+geometries, mixed p, one persistent launch vs plain per-geometry launches),
+S' (the target normal derivative of the single layer) on the headline
+workload, and the served Poisson stream (p50/p99 latency).  The oracle timed on the
 host cores is reported as `cpu_baseline`.  Progress goes to stderr; one JSON
 line goes to stdout.
 """
@@ -39,28 +41,49 @@ def log(msg):
 def flops_per_pair(p: int, layers: int) -> int:
     """FP64 operations per (target, source) pair executed by the evaluation
     kernel (add/mul = 1, fma = 2, the reciprocal-square-root estimate = 1):
-    25 for the pair setup, 6 per recurrence order, and the closing sums."""
+    25 for the pair setup, 6 per recurrence order, and the closing sums of
+    each layer (single layer 10, double layer 17, S' 13, or 12 when it shares
+    1/|d|^3 with the double layer, plus one multiply for each of E_p, E_{p+1}
+    used).  S' alone never uses E_{p+1}, so the last recurrence step (4) is
+    not executed."""
     if layers == 1:
         return 28 if p == 0 else 6 * p + 23
-    return 6 * max(p, 1) + (37 if layers == 2 else 48)
+    f = 6 * max(p, 1) + 19
+    if not layers & 3:
+        f -= 4                           # no E_{p+1}
+    f += 1 if layers & 3 else 0          # E_{p+1}
+    f += 1 if layers & 5 else 0          # E_p
+    f += 10 if layers & 1 else 0
+    f += 17 if layers & 2 else 0
+    f += (12 if layers & 2 else 13) if layers & 4 else 0
+    return f
 
 
 MIN_WARM_S = 0.3
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_eval_p16_slp_dlp_sphere262144_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1811_01110_amd", "csrc", "tsqbx_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_01110_amd", "csrc", f)
+                  for f in ("tsqbx_device.h", "tsqbx_kernels.hip")]
+
+
+def kernel_source_sha256() -> str:
+    """Hash of the sources the evaluation kernel is compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the evaluation kernel from the committed
     rocprofv3 counter summary, or None when the kernel source has changed
     since the counters were taken."""
-    import hashlib
-
     try:
         rec = json.load(open(TRAFFIC_RECORD))
-        cur = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        cur = kernel_source_sha256()
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != cur:
@@ -296,6 +319,31 @@ def bench_serve(ctx, api, torch, W, n_requests):
     }
 
 
+def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
+    """S' (the target normal derivative of the single layer) on the headline
+    workload: alone, and with the single and double layer in the same pass."""
+    sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
+    outs = [torch.zeros(g.n_targets, device="cuda", dtype=torch.float64) for _ in range(3)]
+    res = {"workload": "perturbed sphere r=1+0.1f, 262144 sources, 65536 targets, ball lists "
+                       "r=0.15, p=16, target normals of the surface"}
+    p = 16
+    for name, layers in (("sprime", 4), ("all_three", 7)):
+        step = lambda: ctx.eval_async(geom, sig, p, layers, *outs)
+        log(f"timing S' ({name}) {steps} steps")
+        wall, ev = timed_steps(step, steps, warmup, torch)
+        fpp = flops_per_pair(p, layers)
+        achieved = geom.pairs * fpp / (ev / steps) / 1e12
+        res[name] = {
+            "layers": layers, "pair_terms_per_s": geom.pair_terms(p, layers) / (wall / steps),
+            "ms_per_step": wall / steps * 1e3, "event_ms_per_step": ev / steps * 1e3,
+            "flops_per_pair": fpp, "achieved_tflops": achieved,
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "kernel": f"k_eval<16, {layers}, G, U> (+ k_stage)",
+            "tuning": ctx.get_tuning(p, layers, geom.pairs // g.n_targets),
+        }
+    return res
+
+
 def calibration_copy(torch):
     """One plain 256 MiB device-to-device copy: the known-size kernel that
     hardware byte counters (FETCH_SIZE, WRITE_SIZE) are scaled against."""
@@ -319,7 +367,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--min-warm", type=float, default=0.3,
                     help="seconds of warm-up work before each timed region")
-    ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve"],
+    ap.add_argument("--no-sprime", action="store_true")
+    ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime"],
                     help="run one section (for profiling); the JSON line then carries only it")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 256 MiB device copy first (for counter calibration)")
@@ -337,7 +386,7 @@ def main():
 
     if args.calibration_copy:
         calibration_copy(torch)
-    if args.only and args.only != "headline":
+    if args.only and args.only not in ("headline", "sprime"):
         ctx = api.Context(0)
         fn = {"batched": bench_batched, "high_order": bench_d}.get(args.only)
         if fn is not None:
@@ -353,6 +402,12 @@ def main():
     p, layers = 16, 3
     ctx = api.Context(0)
     geom = ctx.geometry(g)
+    if args.only == "sprime":
+        res = bench_sprime(ctx, api, torch, g, geom, args.steps, args.warmup)
+        geom.close()
+        ctx.close()
+        print(json.dumps({"section": "sprime", "sprime": res}), flush=True)
+        return
     sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
     os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
     od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
@@ -401,6 +456,8 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on the same workload")
         out["cpu_baseline"] = cpu_baseline(g, p, layers)
+    if not args.no_sprime:
+        out["sprime"] = bench_sprime(ctx, api, torch, g, geom, args.steps, args.warmup)
     geom.close()
     del sig, os_, od_
     if not args.no_batched:

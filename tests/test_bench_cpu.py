@@ -25,6 +25,11 @@ def test_flop_model_matches_kernel_structure():
     assert bench.flops_per_pair(16, 3) == 6 * 16 + 48
     assert bench.flops_per_pair(0, 3) == bench.flops_per_pair(1, 3)
     assert bench.flops_per_pair(0, 1) == 28
+    # S': alone, beside the single layer, beside the double layer, all three
+    assert bench.flops_per_pair(16, 4) == 6 * 16 + 29
+    assert bench.flops_per_pair(16, 5) == 6 * 16 + 44
+    assert bench.flops_per_pair(16, 6) == 6 * 16 + 50
+    assert bench.flops_per_pair(16, 7) == 6 * 16 + 60
 
 
 def test_traffic_record_is_ignored_after_a_kernel_change(tmp_path, monkeypatch):
@@ -35,3 +40,14 @@ def test_traffic_record_is_ignored_after_a_kernel_change(tmp_path, monkeypatch):
     rec.write_text(json.dumps({"kernel_source_sha256": "0" * 64, "hbm_bytes_per_launch": 1.0}))
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec))
     assert bench.measured_traffic() is None
+
+
+def test_traffic_record_is_used_while_the_kernel_is_unchanged(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+
+    rec = tmp_path / "t.json"
+    rec.write_text(json.dumps({"kernel_source_sha256": bench.kernel_source_sha256(),
+                               "hbm_bytes_per_launch": 123.0}))
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec))
+    assert bench.measured_traffic() == 123.0
