@@ -66,6 +66,10 @@ typedef enum {
 /* Layer bitmask: which potentials to evaluate. */
 enum { TSQBX_SLP = 1u, TSQBX_DLP = 2u, TSQBX_SPRIME = 4u };
 
+/* Added to a layer mask in the tuning calls: the bucket of the Helmholtz
+ * kernels (tsqbx_eval_helmholtz). */
+enum { TSQBX_HELMHOLTZ = 64u };
+
 /* Flags. */
 enum {
   TSQBX_ACCUMULATE = 1u, /* eval: add into the outputs instead of overwriting */
@@ -163,6 +167,32 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned
                      double *d_out_sprime, unsigned flags, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Helmholtz kernel (App. A, Helmholtz case), real wavenumber k > 0:
+ *
+ *   G_k^(p)(t, y) = (i k / 4 pi) sum_{n=0..p} (2n+1) j_n(k|t-c|) h_n(k|y-c|) P_n(cos gamma)
+ *
+ * with j_n the spherical Bessel and h_n the spherical Hankel function of the
+ * first kind: the p-th order target-specific expansion of
+ * exp(ik|t-y|) / (4 pi |t-y|).  layers: TSQBX_SLP (q_y G_k^(p)) and/or
+ * TSQBX_DLP (q_y nu_y . grad_y G_k^(p), App. A's source gradient), the two
+ * operators of the paper's Brakhage-Werner experiment.  Densities and outputs
+ * are complex, stored as interleaved (re, im) float64 pairs (C99 double
+ * complex, numpy complex128): sigma [N][2] in the caller's source order,
+ * out_slp / out_dlp [T][2] in the caller's target order.  The first call on a
+ * geometry allocates its Helmholtz staging (64 (N + 1) + 264 T bytes).
+ * Errors as for tsqbx_eval; k <= 0 or not finite gives TSQBX_E_RANGE,
+ * TSQBX_SPRIME gives TSQBX_E_INVALID.
+ * ------------------------------------------------------------------------- */
+int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
+                         double k, const double *sigma, double *out_slp, double *out_dlp,
+                         unsigned flags);
+/* The same on device pointers, asynchronous on hip_stream. */
+int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p,
+                               unsigned layers, double k, const double *d_sigma,
+                               double *d_out_slp, double *d_out_dlp, unsigned flags,
+                               void *hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning.  A target's result depends only on its list, whether the
  * single layer is evaluated alone (it then runs its own recurrence; with DLP or
  * SPRIME every layer comes from one derivative recurrence) and group_lanes: it
@@ -176,7 +206,8 @@ typedef struct {
   int xcd_remap;         /* 1: give each XCD a contiguous range of targets */
 } tsqbx_tuning;
 
-/* The tuning the library uses for (p, layers) and a typical list length. */
+/* The tuning the library uses for (p, layers) and a typical list length
+ * (layers | TSQBX_HELMHOLTZ for the Helmholtz kernels). */
 int tsqbx_get_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
                      tsqbx_tuning *out);
 /* Override it (all later launches on ctx for this (p, layers) bucket). */

@@ -19,6 +19,7 @@ c_int, c_uint, c_int64, c_uint64, c_size_t, c_double, c_void_p, c_char_p = (
 
 OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_BUDGET, E_STATE, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 SLP, DLP, SPRIME = 1, 2, 4
+HELMHOLTZ = 64
 ACCUMULATE, NO_REORDER = 1, 2
 P_MAX = 32
 
@@ -87,6 +88,10 @@ _SIGNATURES = {
                            c_void_p, c_uint]),
     "tsqbx_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_uint, c_void_p]),
+    "tsqbx_eval_helmholtz": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double, c_void_p,
+                                     c_void_p, c_void_p, c_uint]),
+    "tsqbx_eval_helmholtz_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double, c_void_p,
+                                           c_void_p, c_void_p, c_uint, c_void_p]),
     "tsqbx_get_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_set_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_uint, P(Tuning), P(c_double)]),

@@ -12,7 +12,7 @@ import numpy as np
 
 from . import _lib as L
 
-SLP, DLP, SPRIME = L.SLP, L.DLP, L.SPRIME
+SLP, DLP, SPRIME, HELMHOLTZ = L.SLP, L.DLP, L.SPRIME, L.HELMHOLTZ
 ACCUMULATE, NO_REORDER, P_MAX = L.ACCUMULATE, L.NO_REORDER, L.P_MAX
 LAYER_BITS = (SLP, DLP, SPRIME)  # the order of every (slp, dlp, sprime) tuple
 
@@ -163,6 +163,49 @@ class Context:
                                         ("out_slp", "out_dlp", "out_sprime"))]
         _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, *ptrs,
                                        int(flags), _stream_handle(stream)))
+
+    def eval_helmholtz(self, geom: "Geometry", sigma, p: int, layers: int, k: float,
+                       out_slp=None, out_dlp=None, flags: int = 0):
+        """Helmholtz evaluation with host arrays: sigma complex (N,); returns
+        complex (slp, dlp), None for a layer not requested."""
+        sig = np.ascontiguousarray(sigma, dtype=np.complex128)
+        if sig.size != geom.n_sources:
+            raise ValueError(f"sigma has {sig.size} entries, expected {geom.n_sources}")
+        T = geom.n_targets
+        outs = [out_slp, out_dlp]
+        for i, bit in enumerate((SLP, DLP)):
+            if not layers & bit:
+                outs[i] = None
+                continue
+            if outs[i] is None:
+                outs[i] = np.zeros(T, dtype=np.complex128)
+            o = outs[i]
+            if o.dtype != np.complex128 or not o.flags.c_contiguous or o.size != T:
+                raise ValueError("outputs must be contiguous complex128 arrays of n_targets entries")
+        _check(_lib().tsqbx_eval_helmholtz(self.handle, geom.handle, int(p), int(layers), float(k),
+                                           _ptr(sig), *[_ptr(o) for o in outs], int(flags)))
+        return tuple(outs)
+
+    def eval_helmholtz_async(self, geom: "Geometry", sigma, p: int, layers: int, k: float,
+                             out_slp=None, out_dlp=None, flags: int = 0, stream=None):
+        """Helmholtz evaluation on device tensors (torch complex128)."""
+        import torch
+
+        def ptr(t, n, name):
+            if t is None:
+                return None
+            if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor")
+            if t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+            return t.data_ptr() if n else None
+
+        s = ptr(sigma, geom.n_sources, "sigma")
+        a = ptr(out_slp, geom.n_targets, "out_slp") if layers & SLP else None
+        b = ptr(out_dlp, geom.n_targets, "out_dlp") if layers & DLP else None
+        _check(_lib().tsqbx_eval_helmholtz_async(self.handle, geom.handle, int(p), int(layers),
+                                                 float(k), s, a, b, int(flags),
+                                                 _stream_handle(stream)))
 
     # -- tuning -------------------------------------------------------------
     def get_tuning(self, p: int, layers: int, mean_list: int) -> dict:

@@ -168,6 +168,19 @@ static int check_request(const tsqbx_geometry *g, int p, unsigned layers) {
   return TSQBX_OK;
 }
 
+// Tuning buckets: a Laplace layer mask, or SLP|DLP with TSQBX_HELMHOLTZ.
+static int check_tuning_key(int p, unsigned layers) {
+  if (layers & TSQBX_HELMHOLTZ) {
+    const unsigned l = layers & ~(unsigned)TSQBX_HELMHOLTZ;
+    if (p < 0 || p > TSQBX_P_MAX)
+      return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
+    if (l == 0 || (l & ~3u))
+      return fail(TSQBX_E_INVALID, "Helmholtz layers = %u is not a nonempty subset of SLP|DLP", l);
+    return TSQBX_OK;
+  }
+  return check_request(nullptr, p, layers);
+}
+
 uint64_t tuning_key(int p, unsigned layers, int64_t mean_list) {
   int bucket = 0;
   while (bucket < 40 && (int64_t(1) << (bucket + 1)) <= mean_list) ++bucket;
@@ -200,7 +213,7 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 static void free_geometry(tsqbx_geometry *g) {
   if (!g) return;
   void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
-                  g->stage.posq, g->stage.qn};
+                  g->stage.posq, g->stage.qn, g->helm.rec, g->helm.tab};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete g;
@@ -510,7 +523,7 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
 int tsqbx_get_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
                      tsqbx_tuning *out) {
   if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
-  int rc = check_request(nullptr, p, layers);
+  int rc = check_tuning_key(p, layers);
   if (rc != TSQBX_OK) return rc;
   const Tuning t = lookup_tuning(ctx, p, layers, mean_list);
   out->waves_per_block = t.waves_per_block;
@@ -523,7 +536,7 @@ int tsqbx_get_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
 int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
                      const tsqbx_tuning *tuning) {
   if (!ctx || !tuning) return fail(TSQBX_E_INVALID, "ctx or tuning is NULL");
-  int rc = check_request(nullptr, p, layers);
+  int rc = check_tuning_key(p, layers);
   if (rc != TSQBX_OK) return rc;
   Tuning t;
   t.waves_per_block = tuning->waves_per_block;
@@ -614,6 +627,112 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
     out->xcd_remap = best.xcd_remap;
   }
   if (best_ms) *best_ms = best_t;
+  return TSQBX_OK;
+}
+
+// ---- Helmholtz -------------------------------------------------------------
+
+static int check_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k) {
+  if (p < 0 || p > TSQBX_P_MAX)
+    return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
+  if (layers == 0 || (layers & ~3u))
+    return fail(TSQBX_E_INVALID, "Helmholtz layers = %u is not a nonempty subset of SLP|DLP", layers);
+  if (!(k > 0.0) || !std::isfinite(k))
+    return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
+  if (g && (layers & TSQBX_DLP) && !g->has_normals)
+    return fail(TSQBX_E_INVALID, "double layer requested but the geometry has no normals");
+  return TSQBX_OK;
+}
+
+// The geometry's Helmholtz staging, allocated on its first Helmholtz call
+// (calls on one geometry do not overlap, so no lock is needed).
+static hipError_t ensure_helm_stage(const tsqbx_geometry *cg) {
+  auto *g = const_cast<tsqbx_geometry *>(cg);
+  if (g->helm.rec) return hipSuccess;
+  size_t bytes = 0;
+  hipError_t e = dev_upload<double4>(&g->helm.rec, nullptr, 2 * ((size_t)g->n_sources + 1), &bytes);
+  if (e == hipSuccess)
+    e = dev_upload<double>(&g->helm.tab, nullptr,
+                           std::max<size_t>(1, (size_t)g->n_targets) * (TSQBX_P_MAX + 1), &bytes);
+  if (e != hipSuccess) {
+    if (g->helm.rec) (void)hipFree(g->helm.rec);
+    if (g->helm.tab) (void)hipFree(g->helm.tab);
+    g->helm = HelmStage{};
+    return e;
+  }
+  g->device_bytes += bytes;
+  return hipSuccess;
+}
+
+int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
+                               double k, const double *d_sigma, double *d_out_slp,
+                               double *d_out_dlp, unsigned flags, void *hip_stream) {
+  if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
+  if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
+  int rc = check_helmholtz(g, p, layers, k);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  rc = check_outputs(g, layers, d_out_slp, d_out_dlp, nullptr);
+  if (rc != TSQBX_OK) return rc;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  TSQBX_HIP(ensure_helm_stage(g));
+  const Tuning tn = lookup_tuning(ctx, p, layers | TSQBX_HELMHOLTZ, mean_list_of(g));
+  TSQBX_HIP(launch_helmholtz(g, p, layers, k, d_sigma, g->helm, d_out_slp, d_out_dlp,
+                             (flags & TSQBX_ACCUMULATE) != 0, tn, (hipStream_t)hip_stream));
+  return TSQBX_OK;
+}
+
+int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
+                         double k, const double *sigma, double *out_slp, double *out_dlp,
+                         unsigned flags) {
+  if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
+  if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
+  int rc = check_helmholtz(g, p, layers, k);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_sources > 0 && !sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  rc = check_outputs(g, layers, out_slp, out_dlp, nullptr);
+  if (rc != TSQBX_OK) return rc;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  TSQBX_HIP(ensure_helm_stage(g));
+  const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
+  if (ctx->d_sigma_cap < 2 * N) {
+    if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
+    ctx->d_sigma = nullptr;
+    ctx->d_sigma_cap = 0;
+    TSQBX_HIP(hipMalloc((void **)&ctx->d_sigma, 2 * N * sizeof(double)));
+    ctx->d_sigma_cap = 2 * N;
+  }
+  if (ctx->d_out_cap < 4 * T) {
+    if (ctx->d_out) (void)hipFree(ctx->d_out);
+    ctx->d_out = nullptr;
+    ctx->d_out_cap = 0;
+    TSQBX_HIP(hipMalloc((void **)&ctx->d_out, 4 * T * sizeof(double)));
+    ctx->d_out_cap = 4 * T;
+  }
+  hipStream_t s = ctx->stream;
+  if (N)
+    TSQBX_HIP(hipMemcpyAsync(ctx->d_sigma, sigma, 2 * N * sizeof(double), hipMemcpyHostToDevice, s));
+  double *const dev[2] = {ctx->d_out, ctx->d_out + 2 * T};
+  const Tuning tn = lookup_tuning(ctx, p, layers | TSQBX_HELMHOLTZ, mean_list_of(g));
+  TSQBX_HIP(launch_helmholtz(g, p, layers, k, ctx->d_sigma, g->helm, dev[0], dev[1], false, tn, s));
+  const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
+  double *const user[2] = {out_slp, out_dlp};
+  std::vector<double> tmp[2];
+  for (int l = 0; l < 2; ++l) {
+    if (!T || !(layers & (1u << l))) continue;
+    double *dst = user[l];
+    if (acc) {
+      tmp[l].resize(2 * T);
+      dst = tmp[l].data();
+    }
+    TSQBX_HIP(hipMemcpyAsync(dst, dev[l], 2 * T * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  TSQBX_HIP(hipStreamSynchronize(s));
+  for (int l = 0; l < 2; ++l)
+    for (size_t i = 0; i < tmp[l].size(); ++i) user[l][i] += tmp[l][i];
   return TSQBX_OK;
 }
 

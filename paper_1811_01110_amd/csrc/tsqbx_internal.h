@@ -45,6 +45,14 @@ struct Outputs {
   double *t = nullptr;  // S', normal derivative of the single layer at the target
 };
 
+// Helmholtz staging of one geometry (allocated by its first Helmholtz call):
+// rec[2i] = (x, y, z, Re q), rec[2i+1] = (Im q, nu), i = 0..N (N: padding);
+// tab: (2n+1) j_n(k |t - c|) per device-order target, rows of p + 1.
+struct HelmStage {
+  double4 *rec = nullptr;  // [2 (N + 1)]
+  double *tab = nullptr;   // [T (TSQBX_P_MAX + 1)]
+};
+
 struct Tuning {
   int waves_per_block = 4;
   int group_lanes = 64;
@@ -83,6 +91,7 @@ struct tsqbx_geometry {
   double4 *tgt_nrm = nullptr;    // [T] (nx, ny, nz, 0) at the targets, device order, or null
   int32_t *idx = nullptr;        // [nnz'] lists in device numbering, one row per target group
   tsqbx::SourceStage stage;      // staging used by the plain path
+  tsqbx::HelmStage helm;         // Helmholtz staging, allocated on first use
   size_t device_bytes = 0;
   std::vector<int64_t> host_row_len;  // per device-order target, for planning
 };
@@ -104,6 +113,12 @@ hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
                        const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
 bool tuning_supported(const Tuning &tn);
+// Helmholtz (tsqbx_helmholtz.hip): staging of q = w sigma (sigma complex,
+// interleaved), the per-target table and the pair kernel; outputs complex,
+// interleaved, in the caller's target order.
+hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k,
+                            const double *d_sigma, const HelmStage &st, double *out_s,
+                            double *out_d, bool accumulate, const Tuning &tn, hipStream_t s);
 
 // Staging of many items in one launch (batched and served paths).
 struct StageItem {         // 64 bytes

@@ -1,0 +1,140 @@
+"""Helmholtz target-specific expansions on the GPU against the Helmholtz oracle,
+element by element, through the C ABI (bar: 1e-12 of the per-target sum of
+term moduli, and 1e-12 of the largest output)."""
+import numpy as np
+import pytest
+
+from conftest import assert_parity, cached_workload
+from oracle import helmholtz as H
+from paper_1811_01110_amd import api
+from paper_1811_01110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _sigma(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def _check(ctx, g, k, p, layers, sigma, select=None, what=""):
+    geom = ctx.geometry(g)
+    s, d = ctx.eval_helmholtz(geom, sigma, p, layers, k)
+    ref = H.evaluate_geometry(g, k, sigma, p=p, layers=layers, select=select)
+    sel = slice(None) if select is None else select
+    if layers & api.SLP:
+        assert_parity(s[sel], ref["slp"], ref["abs_slp"], what=f"{what} slp")
+    if layers & api.DLP:
+        assert_parity(d[sel], ref["dlp"], ref["abs_dlp"], what=f"{what} dlp")
+    geom.close()
+    return s, d
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 5, 8, 12, 16, 24, 32])
+@pytest.mark.parametrize("k", [0.5, 3.0, 20.0])
+def test_orders_and_wavenumbers(ctx, p, k):
+    g = W.fuzz_geometry(800 + p, n=250, m=50, max_list=120, p=p, layers=3, targets_per_center=2)
+    _check(ctx, g, k, p, 3, _sigma(g.n_sources, p), what=f"p={p} k={k}")
+
+
+def test_layers_separately_share_the_single_layer_bits(ctx):
+    g = W.fuzz_geometry(850, n=600, m=100, max_list=300, p=16, layers=3)
+    sig = _sigma(g.n_sources, 1)
+    s3, d3 = _check(ctx, g, 20.0, 16, 3, sig, what="both")
+    s1, _ = _check(ctx, g, 20.0, 16, 1, sig, what="slp")
+    _, d2 = _check(ctx, g, 20.0, 16, 2, sig, what="dlp")
+    assert np.array_equal(s1, s3)
+    assert np.array_equal(d2, d3)
+
+
+def test_large_and_tiny_k_rho(ctx):
+    """k rho > p + 1 takes the upward recurrence for j_n; targets 1e-4 from
+    their centers at p = 32 take Miller's recurrence through its rescaling."""
+    g = W.fuzz_geometry(851, n=300, m=60, max_list=150, p=4, layers=3)
+    _check(ctx, g, 100.0, 4, 3, _sigma(g.n_sources, 2), what="k=100 p=4")
+    h = W.fuzz_geometry(852, n=300, m=60, max_list=150, p=32, layers=3)
+    rng = np.random.default_rng(3)
+    off = rng.standard_normal((h.n_targets, 3))
+    h.targets = h.centers[h.target_center] + 1e-4 * off / np.linalg.norm(off, axis=1)[:, None]
+    _check(ctx, h, 1.0, 32, 3, _sigma(h.n_sources, 4), what="rho=1e-4 p=32")
+
+
+def test_target_at_center_and_edge_lists(ctx):
+    g = W.fuzz_geometry(853, n=200, m=40, max_list=60, p=9, layers=3, targets_per_center=2)
+    g.targets[:7] = g.centers[g.target_center[:7]]
+    _check(ctx, g, 5.0, 9, 3, _sigma(g.n_sources, 5), what="t=c")
+    off = np.zeros(g.n_centers + 1, dtype=np.int64)
+    e = W.Geometry(g.sources, g.weights, g.normals, g.centers, off, np.zeros(0, dtype=np.int32),
+                   g.targets, g.target_center, g.sigma, 9, 3)
+    geom = ctx.geometry(e)
+    s, d = ctx.eval_helmholtz(geom, _sigma(g.n_sources, 6), 9, 3, 5.0)
+    assert np.all(s == 0) and np.all(d == 0)
+    geom.close()
+
+
+def test_config_b_full_size_sampled(ctx):
+    g = cached_workload("config_b", 1)
+    sig = _sigma(g.n_sources, 7)
+    rng = np.random.default_rng(8)
+    sel = np.sort(rng.choice(g.n_targets, 128, replace=False))
+    _check(ctx, g, 20.0, 16, 3, sig, select=sel, what="B k=20")
+
+
+def test_async_accumulate_and_tuning_variants(ctx):
+    import torch
+
+    g = W.fuzz_geometry(854, n=1500, m=250, max_list=500, p=12, layers=3)
+    geom = ctx.geometry(g)
+    sig = _sigma(g.n_sources, 9)
+    ref = H.evaluate_geometry(g, 8.0, sig, p=12, layers=3)
+    s_host, d_host = ctx.eval_helmholtz(geom, sig, 12, 3, 8.0)
+    ts = torch.tensor(sig, device="cuda", dtype=torch.complex128)
+    os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
+    od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
+    ctx.eval_helmholtz_async(geom, ts, 12, 3, 8.0, os_, od_)
+    torch.cuda.synchronize()
+    assert np.array_equal(os_.cpu().numpy(), s_host)
+    assert np.array_equal(od_.cpu().numpy(), d_host)
+    ctx.eval_helmholtz_async(geom, ts, 12, 3, 8.0, os_, od_, flags=api.ACCUMULATE)
+    torch.cuda.synchronize()
+    assert np.array_equal(os_.cpu().numpy(), s_host + s_host)
+    mean = max(geom.pairs // geom.n_targets, 1)
+    base = None
+    for G, U in ((64, 1), (64, 2), (32, 2), (16, 2)):
+        for w in (1, 4):
+            ctx.set_tuning(12, 3 | api.HELMHOLTZ, mean, group_lanes=G, unroll=U, waves_per_block=w)
+            s, d = ctx.eval_helmholtz(geom, sig, 12, 3, 8.0)
+            assert_parity(s, ref["slp"], ref["abs_slp"], what=f"G{G}U{U}w{w}")
+            assert_parity(d, ref["dlp"], ref["abs_dlp"], what=f"G{G}U{U}w{w}")
+            if G == 64:
+                base = (s, d) if base is None else base
+                assert np.array_equal(s, base[0]) and np.array_equal(d, base[1])
+    geom.close()
+
+
+def test_rejects_bad_requests(ctx):
+    g = W.fuzz_geometry(855, n=50, m=10, max_list=20, p=4, layers=1)
+    sig = _sigma(g.n_sources, 10)
+    geom = ctx.geometry(g)
+    for layers, k, code in ((api.SPRIME, 1.0, -1), (1, 0.0, -2), (1, -3.0, -2),
+                            (1, float("inf"), -2), (0, 1.0, -1)):
+        with pytest.raises(api.TsqbxError) as ei:
+            ctx.eval_helmholtz(geom, sig, 4, layers, k)
+        assert ei.value.code == code, (layers, k)
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval_helmholtz(geom, sig, 33, 1, 1.0)
+    assert ei.value.code == -2
+    geom.close()
+    g.normals = None
+    geom = ctx.geometry(g)
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval_helmholtz(geom, sig, 4, api.DLP, 1.0)
+    assert ei.value.code == -1
+    geom.close()
