@@ -2,7 +2,8 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-serve]
                     [--with-d] [--no-cpu] [--requests R] [--min-warm S]
-                    [--no-sprime] [--only headline|batched|high_order|serve|sprime]
+                    [--no-sprime] [--no-helmholtz]
+                    [--only headline|batched|high_order|serve|sprime|helmholtz]
                     [--calibration-copy]
 
 The headline `value` is the plain single- plus double-layer evaluation at
@@ -11,8 +12,9 @@ ball lists of radius 0.15 about centers 0.02 inside the surface), inputs
 resident in device memory, K timed steps.  One step = staging of q = w sigma
 plus the evaluation kernel.  Extra objects report the batched workload (64
 geometries, mixed p, one persistent launch vs plain per-geometry launches),
-S' (the target normal derivative of the single layer) on the headline
-workload, and the served Poisson stream (p50/p99 latency).  The oracle timed on the
+S' (the target normal derivative of the single layer) and the Helmholtz
+single + double layer (k = 20) on the headline workload, and the served
+Poisson stream (p50/p99 latency).  The oracle timed on the
 host cores is reported as `cpu_baseline`.  Progress goes to stderr; one JSON
 line goes to stdout.
 """
@@ -60,6 +62,9 @@ def flops_per_pair(p: int, layers: int) -> int:
 
 
 MIN_WARM_S = 0.3
+# FP64 operations of one double-precision sincos as executed by the device
+# library, measured with FP64 VALU counters on the Helmholtz kernel
+HELM_SINCOS_FLOPS = 60
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_eval_p16_slp_dlp_sphere262144_traffic.json")
@@ -344,6 +349,52 @@ def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
     return res
 
 
+def helm_flops_per_pair(p: int, layers: int, sincos_flops: int = HELM_SINCOS_FLOPS) -> int:
+    """FP64 operations per pair of the Helmholtz kernel (add/mul = 1,
+    fma = 2, reciprocal-square-root estimate = 1): pair setup 27, sincos
+    (as measured with FP64 counters), h_0 and h_1 8, the n = 0 and n = 1
+    terms, 13 per further order for the single layer (Legendre 3, Hankel 5,
+    term 5) and 17 for the double layer (P_n' 3, three complex sums 14), the
+    per-order table multiply once per pair, and the closing products with the
+    complex density (8 per layer, 22 more for the double layer's bracket)."""
+    f = 27 + sincos_flops + 8 + 2
+    orders = max(p - 1, 0)
+    if p >= 1:
+        f += 5
+    f += orders * (13 + 1)
+    f += 8 if layers & 1 else 0
+    if layers & 2:
+        f += 5 + 8 + (13 if p >= 1 else 0) + orders * 17 + 30
+    return f
+
+
+def bench_helmholtz(ctx, api, torch, g, geom, steps, warmup, k=20.0, p=16):
+    """Helmholtz single + double layer (the Brakhage-Werner pair of the
+    paper's large experiment, k = 20) on the headline geometry."""
+    rng = np.random.default_rng(20181101)
+    sig = torch.tensor(rng.standard_normal(g.n_sources) + 1j * rng.standard_normal(g.n_sources),
+                       device="cuda", dtype=torch.complex128)
+    os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
+    od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
+    res = {"workload": f"perturbed sphere r=1+0.1f, 262144 sources, 65536 targets, ball lists "
+                       f"r=0.15, Helmholtz k={k:g}, p={p}, complex density"}
+    for name, layers in (("slp_dlp", 3), ("slp", 1)):
+        step = lambda: ctx.eval_helmholtz_async(geom, sig, p, layers, k, os_, od_)
+        log(f"timing Helmholtz ({name}) {steps} steps")
+        wall, ev = timed_steps(step, steps, warmup, torch)
+        fpp = helm_flops_per_pair(p, layers)
+        achieved = geom.pairs * fpp / (ev / steps) / 1e12
+        res[name] = {
+            "layers": layers, "pair_terms_per_s": geom.pair_terms(p, layers) / (wall / steps),
+            "ms_per_step": wall / steps * 1e3, "event_ms_per_step": ev / steps * 1e3,
+            "flops_per_pair": fpp, "achieved_tflops": achieved,
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "kernel": f"k_helm_eval<{layers}, G, U> (+ k_helm_stage, k_helm_table)",
+            "tuning": ctx.get_tuning(p, layers | api.HELMHOLTZ, geom.pairs // g.n_targets),
+        }
+    return res
+
+
 def calibration_copy(torch):
     """One plain 256 MiB device-to-device copy: the known-size kernel that
     hardware byte counters (FETCH_SIZE, WRITE_SIZE) are scaled against."""
@@ -368,7 +419,9 @@ def main():
     ap.add_argument("--min-warm", type=float, default=0.3,
                     help="seconds of warm-up work before each timed region")
     ap.add_argument("--no-sprime", action="store_true")
-    ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime"],
+    ap.add_argument("--no-helmholtz", action="store_true")
+    ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime",
+                                       "helmholtz"],
                     help="run one section (for profiling); the JSON line then carries only it")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 256 MiB device copy first (for counter calibration)")
@@ -386,7 +439,7 @@ def main():
 
     if args.calibration_copy:
         calibration_copy(torch)
-    if args.only and args.only not in ("headline", "sprime"):
+    if args.only and args.only not in ("headline", "sprime", "helmholtz"):
         ctx = api.Context(0)
         fn = {"batched": bench_batched, "high_order": bench_d}.get(args.only)
         if fn is not None:
@@ -402,11 +455,12 @@ def main():
     p, layers = 16, 3
     ctx = api.Context(0)
     geom = ctx.geometry(g)
-    if args.only == "sprime":
-        res = bench_sprime(ctx, api, torch, g, geom, args.steps, args.warmup)
+    if args.only in ("sprime", "helmholtz"):
+        fn = bench_sprime if args.only == "sprime" else bench_helmholtz
+        res = fn(ctx, api, torch, g, geom, args.steps, args.warmup)
         geom.close()
         ctx.close()
-        print(json.dumps({"section": "sprime", "sprime": res}), flush=True)
+        print(json.dumps({"section": args.only, args.only: res}), flush=True)
         return
     sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
     os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
@@ -458,6 +512,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(g, p, layers)
     if not args.no_sprime:
         out["sprime"] = bench_sprime(ctx, api, torch, g, geom, args.steps, args.warmup)
+    if not args.no_helmholtz:
+        out["helmholtz"] = bench_helmholtz(ctx, api, torch, g, geom, args.steps, args.warmup)
     geom.close()
     del sig, os_, od_
     if not args.no_batched:

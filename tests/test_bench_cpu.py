@@ -51,3 +51,15 @@ def test_traffic_record_is_used_while_the_kernel_is_unchanged(tmp_path, monkeypa
                                "hbm_bytes_per_launch": 123.0}))
     monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(rec))
     assert bench.measured_traffic() == 123.0
+
+
+def test_helmholtz_flop_model():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    S = bench.HELM_SINCOS_FLOPS
+    # setup 27 + sincos + h_0, h_1 8 + n = 0 2 + n = 1 5 + 14 per further order + 8
+    assert bench.helm_flops_per_pair(16, 1) == 27 + S + 8 + 2 + 5 + 15 * 14 + 8
+    # the double layer: 5 + 8 + 13 + 17 per further order + 30
+    assert bench.helm_flops_per_pair(16, 3) == bench.helm_flops_per_pair(16, 1) + 5 + 8 + 13 + 15 * 17 + 30
+    assert bench.helm_flops_per_pair(0, 1) == 27 + S + 8 + 2 + 8
