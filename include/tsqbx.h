@@ -193,6 +193,28 @@ int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p
                                void *hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Near-field lists on the device.  For every center c the sources y inside
+ * the closed ball of radius r about c (the near-field source set of Sec. 3.3,
+ * taken as a ball), in ascending source index: the CSR that
+ * tsqbx_geometry_desc takes.  Membership is decided in FP64 as
+ * dx = y_x - c_x (likewise y, z), d2 = (dx*dx + dy*dy) + dz*dz, each operation
+ * rounded on its own, member iff d2 <= r*r.
+ *
+ * d_sources [N][3], d_centers [M][3]: device pointers, row-major float64.
+ * d_offsets [M+1] (int64, device) is always written.  d_indices (int32,
+ * device, `capacity` entries) receives the entries when they fit; *nnz
+ * receives their number in any case, and a call with too small a capacity
+ * returns TSQBX_E_RANGE (call again with a larger buffer).  A ball holding
+ * more than 8192 sources gives TSQBX_E_RANGE.  Work runs on hip_stream; the
+ * call allocates its own scratch (about 56 N + 8 M bytes plus a hash table
+ * of 2N to 4N cells x 28 bytes) and returns when the lists are written.
+ * ------------------------------------------------------------------------- */
+int tsqbx_ball_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *d_sources,
+                     int64_t n_centers, const double *d_centers, double radius,
+                     int64_t *d_offsets, int32_t *d_indices, int64_t capacity, int64_t *nnz,
+                     void *hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning.  A target's result depends only on its list, whether the
  * single layer is evaluated alone (it then runs its own recurrence; with DLP or
  * SPRIME every layer comes from one derivative recurrence) and group_lanes: it

@@ -207,6 +207,36 @@ class Context:
                                                  float(k), s, a, b, int(flags),
                                                  _stream_handle(stream)))
 
+    def ball_lists(self, sources, centers, radius: float, capacity=None, stream=None):
+        """Near-field lists on the device: for each center, the sources in the
+        closed ball of `radius`, ascending (CSR).  sources / centers: (N, 3) /
+        (M, 3) float64, numpy (copied to the device) or CUDA tensors.  Returns
+        torch tensors (offsets int64 [M+1], indices int32 [nnz]) on the device."""
+        import torch
+
+        def dev(a):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+            t = t.to(device=f"cuda:{self.device}", dtype=torch.float64).contiguous()
+            return t.reshape(-1, 3) if t.numel() else t.reshape(0, 3)
+
+        src, ctr = dev(sources), dev(centers)
+        M = ctr.shape[0]
+        offsets = torch.empty(M + 1, device=src.device, dtype=torch.int64)
+        cap = int(capacity) if capacity is not None else 0
+        for attempt in range(2):
+            idx = torch.empty(max(cap, 1), device=src.device, dtype=torch.int32)
+            nnz = ctypes.c_int64()
+            rc = _lib().tsqbx_ball_lists(self.handle, src.shape[0], src.data_ptr() if src.numel() else None,
+                                         M, ctr.data_ptr() if ctr.numel() else None, float(radius),
+                                         offsets.data_ptr(), idx.data_ptr(), cap, ctypes.byref(nnz),
+                                         _stream_handle(stream))
+            if rc == L.E_RANGE and nnz.value > cap and attempt == 0:
+                cap = nnz.value  # first call sized the lists
+                continue
+            _check(rc)
+            return offsets, idx[:nnz.value]
+        raise TsqbxError(L.E_RANGE, "lists did not fit after resizing")
+
     # -- tuning -------------------------------------------------------------
     def get_tuning(self, p: int, layers: int, mean_list: int) -> dict:
         t = L.Tuning()
