@@ -2,8 +2,8 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-serve]
                     [--with-d] [--no-cpu] [--requests R] [--min-warm S]
-                    [--no-sprime] [--no-helmholtz]
-                    [--only headline|batched|high_order|serve|sprime|helmholtz]
+                    [--no-sprime] [--no-helmholtz] [--no-lists]
+                    [--only headline|batched|high_order|serve|sprime|helmholtz|lists]
                     [--calibration-copy]
 
 The headline `value` is the plain single- plus double-layer evaluation at
@@ -13,8 +13,9 @@ resident in device memory, K timed steps.  One step = staging of q = w sigma
 plus the evaluation kernel.  Extra objects report the batched workload (64
 geometries, mixed p, one persistent launch vs plain per-geometry launches),
 S' (the target normal derivative of the single layer) and the Helmholtz
-single + double layer (k = 20) on the headline workload, and the served
-Poisson stream (p50/p99 latency).  The oracle timed on the
+single + double layer (k = 20) on the headline workload, the device build of
+the headline workload's near-field lists, and the served Poisson stream
+(p50/p99 latency).  The oracle timed on the
 host cores is reported as `cpu_baseline`.  Progress goes to stderr; one JSON
 line goes to stdout.
 """
@@ -395,6 +396,37 @@ def bench_helmholtz(ctx, api, torch, g, geom, steps, warmup, k=20.0, p=16):
     return res
 
 
+def bench_lists(ctx, api, torch, g, steps, with_host=True):
+    """Near-field ball lists of the headline workload (262144 sources, 65536
+    centers, r = 0.15) built on the device, against the host grid generator
+    that produced the workload's lists."""
+    src = torch.tensor(g.sources, device="cuda", dtype=torch.float64)
+    ctr = torch.tensor(g.centers, device="cuda", dtype=torch.float64)
+    off, idx = ctx.ball_lists(src, ctr, 0.15)  # sizes the output, warms up
+    cap = int(idx.numel())
+    torch.cuda.synchronize()
+    n = max(steps // 4, 3)
+    log(f"timing device ball lists, {n} builds")
+    t0 = time.perf_counter()
+    for _ in range(n):
+        off, idx = ctx.ball_lists(src, ctr, 0.15, capacity=cap)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n
+    res = {"workload": "ball lists r=0.15 of the perturbed sphere: 262144 sources, 65536 centers",
+           "entries": cap, "ms_per_build": dt * 1e3, "entries_per_s": cap / dt,
+           "same_as_host_generator": bool(np.array_equal(off.cpu().numpy(), g.list_offsets)
+                                          and np.array_equal(idx.cpu().numpy(), g.list_sources))}
+    if with_host:
+        from paper_1811_01110_amd import workloads as W
+
+        log("timing the host grid generator once")
+        t0 = time.perf_counter()
+        W.csr_ball(g.centers, g.sources, 0.15)
+        res["host_generator_s"] = time.perf_counter() - t0
+        res["host_generator_threads"] = min(16, os.cpu_count() or 1)
+    return res
+
+
 def calibration_copy(torch):
     """One plain 256 MiB device-to-device copy: the known-size kernel that
     hardware byte counters (FETCH_SIZE, WRITE_SIZE) are scaled against."""
@@ -420,8 +452,9 @@ def main():
                     help="seconds of warm-up work before each timed region")
     ap.add_argument("--no-sprime", action="store_true")
     ap.add_argument("--no-helmholtz", action="store_true")
+    ap.add_argument("--no-lists", action="store_true")
     ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime",
-                                       "helmholtz"],
+                                       "helmholtz", "lists"],
                     help="run one section (for profiling); the JSON line then carries only it")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 256 MiB device copy first (for counter calibration)")
@@ -439,7 +472,7 @@ def main():
 
     if args.calibration_copy:
         calibration_copy(torch)
-    if args.only and args.only not in ("headline", "sprime", "helmholtz"):
+    if args.only and args.only not in ("headline", "sprime", "helmholtz", "lists"):
         ctx = api.Context(0)
         fn = {"batched": bench_batched, "high_order": bench_d}.get(args.only)
         if fn is not None:
@@ -455,9 +488,12 @@ def main():
     p, layers = 16, 3
     ctx = api.Context(0)
     geom = ctx.geometry(g)
-    if args.only in ("sprime", "helmholtz"):
-        fn = bench_sprime if args.only == "sprime" else bench_helmholtz
-        res = fn(ctx, api, torch, g, geom, args.steps, args.warmup)
+    if args.only in ("sprime", "helmholtz", "lists"):
+        if args.only == "lists":
+            res = bench_lists(ctx, api, torch, g, args.steps, with_host=False)
+        else:
+            fn = bench_sprime if args.only == "sprime" else bench_helmholtz
+            res = fn(ctx, api, torch, g, geom, args.steps, args.warmup)
         geom.close()
         ctx.close()
         print(json.dumps({"section": args.only, args.only: res}), flush=True)
@@ -514,6 +550,8 @@ def main():
         out["sprime"] = bench_sprime(ctx, api, torch, g, geom, args.steps, args.warmup)
     if not args.no_helmholtz:
         out["helmholtz"] = bench_helmholtz(ctx, api, torch, g, geom, args.steps, args.warmup)
+    if not args.no_lists:
+        out["lists"] = bench_lists(ctx, api, torch, g, args.steps, with_host=not args.no_cpu)
     geom.close()
     del sig, os_, od_
     if not args.no_batched:

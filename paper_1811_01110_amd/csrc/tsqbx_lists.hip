@@ -274,9 +274,12 @@ k_ball_pass(const double *__restrict__ ctr, int64_t m, const GridParams *__restr
 // ---- row sort --------------------------------------------------------------------
 constexpr int kSortMax = 8192;
 
+// CAP: the LDS capacity, at least the longest row (smaller capacities let
+// more workgroups share a CU).
+template <int CAP>
 __global__ void __launch_bounds__(256)
 k_row_sort(const int64_t *__restrict__ offsets, int32_t *__restrict__ idx) {
-  __shared__ int32_t s[kSortMax];
+  __shared__ int32_t s[CAP];
   const int64_t b = offsets[blockIdx.x];
   const int len = (int)(offsets[blockIdx.x + 1] - b);
   if (len <= 1) return;
@@ -284,17 +287,18 @@ k_row_sort(const int64_t *__restrict__ offsets, int32_t *__restrict__ idx) {
   while (P < len) P <<= 1;
   for (int i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < len ? idx[b + i] : INT32_MAX;
   __syncthreads();
+  // bitonic network over the P/2 compare-exchange pairs of each stage
+  const int half = P >> 1;
   for (int k = 2; k <= P; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const int l = i ^ j;
-        if (l > i) {
-          const int32_t x = s[i], y = s[l];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            s[i] = y;
-            s[l] = x;
-          }
+      for (int q = threadIdx.x; q < half; q += blockDim.x) {
+        const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // lower index of pair q
+        const int l = i | j;
+        const int32_t x = s[i], y = s[l];
+        const bool up = (i & k) == 0;
+        if ((x > y) == up) {
+          s[i] = y;
+          s[l] = x;
         }
       }
       __syncthreads();
@@ -434,7 +438,13 @@ extern "C" int tsqbx_ball_lists(tsqbx_ctx *ctx, int64_t n_sources, const double 
   if (total > 0) {
     hipLaunchKernelGGL(k_ball_pass<true>, dim3(wb), dim3(256), 0, s, d_centers, M, gp.p, keys.p,
                        mask, cell_start.p, counts.p, cell_pts.p, nullptr, d_offsets, d_indices);
-    hipLaunchKernelGGL(k_row_sort, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices);
+    if (longest <= 512)
+      hipLaunchKernelGGL(k_row_sort<512>, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices);
+    else if (longest <= 2048)
+      hipLaunchKernelGGL(k_row_sort<2048>, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices);
+    else
+      hipLaunchKernelGGL(k_row_sort<kSortMax>, dim3((unsigned)M), dim3(256), 0, s, d_offsets,
+                         d_indices);
     TSQBX_HIP(hipGetLastError());
   }
   TSQBX_HIP(hipStreamSynchronize(s));
