@@ -44,13 +44,16 @@ def log(msg):
 def flops_per_pair(p: int, layers: int) -> int:
     """FP64 operations per (target, source) pair executed by the evaluation
     kernel (add/mul = 1, fma = 2, the reciprocal-square-root estimate = 1):
-    25 for the pair setup, 6 per recurrence order, and the closing sums of
+    25 for the pair setup; the single layer alone 5 per order (Clenshaw);
+    otherwise 6 per order of the derivative recurrence and the closing sums of
     each layer (single layer 10, double layer 17, S' 13, or 12 when it shares
     1/|d|^3 with the double layer, plus one multiply for each of E_p, E_{p+1}
     used).  S' alone never uses E_{p+1}, so the last recurrence step (4) is
     not executed."""
     if layers == 1:
-        return 28 if p == 0 else 6 * p + 23
+        # Clenshaw: the first two steps need no arithmetic when unrolled (one
+        # target per wave), 5 per further order, 5 to close
+        return 28 if p == 0 else (31 if p == 1 else 5 * p + 25)
     f = 6 * max(p, 1) + 19
     if not layers & 3:
         f -= 4                           # no E_{p+1}

@@ -27,11 +27,12 @@
 //   (n+1) b_{n+1} = (2n+1) beta b_n - n g2 b_{n-1},
 // and the derivative recurrence n P_{n+1}' = (2n+1) x P_n' - (n+1) P_{n-1}'
 //   n E_{n+1} = (2n+1) beta E_n - (n+1) g2 E_{n-1}.
-// Both are rescaled by per-order constants so that one order costs two
-// multiplies and one FMA, plus one FMA for the running sum.  When the double
-// layer or S' is requested only the E_n are generated; the sums of b_n and
-// (n+1) b_n then follow in closed form (see pair_terms), so all three layers
-// together cost one recurrence.
+// Both are rescaled by per-order constants.  The single layer alone sums the
+// b_n by Clenshaw's backward recurrence: a multiply and two FMAs per order.
+// When the double layer or S' is requested only the E_n are generated
+// forward (two multiplies and one FMA per order, plus one FMA for their
+// running sum), and the sums of b_n and (n+1) b_n follow in closed form (see
+// pair_terms), so all three layers together cost one recurrence.
 //
 // 1/|d| comes from v_rsq_f64 and a second-order correction.  Sums within a
 // target run in a fixed order (lane-strided over the list, then a fixed
@@ -70,6 +71,7 @@ struct CoefTable {
   double kap[TSQBX_P_MAX + 3];
   double mu[TSQBX_P_MAX + 3];
   double kapd[TSQBX_P_MAX + 3];
+  double2 clen[TSQBX_P_MAX + 3];  // (lam_k, kap_{k+1}): one Clenshaw step's pair
 };
 constexpr CoefTable make_coef_table() {
   CoefTable t{};
@@ -78,6 +80,7 @@ constexpr CoefTable make_coef_table() {
     t.kap[n] = n >= 1 ? kap_c(n) : 0.0;
     t.mu[n] = mu_c(n);
     t.kapd[n] = n >= 2 ? kapd_c(n) : 0.0;
+    t.clen[n] = double2{lam_c(n), kap_c(n + 1)};
   }
   return t;
 }
@@ -101,20 +104,34 @@ struct PairState {
   double S[U];            // running sum
 };
 
-// Single layer only: e_{n+1} for n = N..P-1 and S += lam_{n+1} e_{n+1}.
-template <int P, int U, int N>
-__device__ __forceinline__ void slp_steps(PairState<U> &st) {
-  if constexpr (N < P) {
-    constexpr double kap = kap_c(N);
-    constexpr double lam1 = lam_c(N + 1);
+// Single layer only, by Clenshaw's backward recurrence for
+// S = sum_{n=0..p} lam_n e_n with e_{n+1} = beta e_n - kap_n g2 e_{n-1},
+// e_0 = 1, e_1 = beta:
+//   c_k = lam_k + beta c_{k+1} - kap_{k+1} g2 c_{k+2}  (k = p..1, c_{p+1} = c_{p+2} = 0),
+//   S = 1 + beta c_1 - kap_1 g2 c_2.
+// One order costs a multiply and two FMAs (the sum needs no accumulator).
+// On entry (fm1, f) = (c_{K+2}, c_{K+1}); after K = 1 they hold (c_2, c_1).
+// This fully unrolled form keeps the constants in registers; the run-time
+// form below reads them from a table.  The first two steps meet zeros, which
+// the run-time form passes through exactly, so both give the same values.
+template <int P, int U, int K>
+__device__ __forceinline__ void slp_clenshaw(PairState<U> &st) {
+  if constexpr (K >= 1) {
+    constexpr double lam = lam_c(K);
+    constexpr double kap = kap_c(K + 1);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const double en1 = fma(-kap, st.g2[u] * st.fm1[u], st.beta[u] * st.f[u]);
-      st.S[u] = fma(lam1, en1, st.S[u]);
+      double ck;
+      if constexpr (K == P)
+        ck = lam;
+      else if constexpr (K == P - 1)
+        ck = fma(st.beta[u], st.f[u], lam);
+      else
+        ck = fma(st.beta[u], st.f[u], fma(-st.g2[u], kap * st.fm1[u], lam));
       st.fm1[u] = st.f[u];
-      st.f[u] = en1;
+      st.f[u] = ck;
     }
-    slp_steps<P, U, N + 1>(st);
+    slp_clenshaw<P, U, K - 1>(st);
   }
 }
 
@@ -136,19 +153,37 @@ __device__ __forceinline__ void dlp_steps(PairState<U> &st) {
   }
 }
 
-// The same steps for a run-time order p (constants from the table).
+// The same recurrences for a run-time order p (constants from the table).
 template <int U>
-__device__ __forceinline__ void slp_steps_rt(int p, PairState<U> &st) {
-  for (int n = 1; n < p; ++n) {
-    const double kap = d_coef.kap[n], lam1 = d_coef.lam[n + 1];
+__device__ __forceinline__ void clenshaw_step(const double2 c, PairState<U> &st) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double en1 = fma(-kap, st.g2[u] * st.fm1[u], st.beta[u] * st.f[u]);
-      st.S[u] = fma(lam1, en1, st.S[u]);
-      st.fm1[u] = st.f[u];
-      st.f[u] = en1;
-    }
+  for (int u = 0; u < U; ++u) {
+    const double ck = fma(st.beta[u], st.f[u], fma(-st.g2[u], c.y * st.fm1[u], c.x));
+    st.fm1[u] = st.f[u];
+    st.f[u] = ck;
   }
+}
+
+template <int U>
+__device__ __forceinline__ void slp_clenshaw_rt(int p, PairState<U> &st) {
+  // two steps per iteration, each step's constants read with one scalar load
+  // an iteration ahead: they stay out of vector registers (which would cost
+  // occupancy) and their latency hides behind the previous steps
+  if (p < 1) return;
+  int k = p;
+  double2 c0 = d_coef.clen[k];
+  double2 c1 = d_coef.clen[k - 1];  // k - 1 >= 0: entry 0 exists
+#pragma unroll 1
+  for (; k >= 3; k -= 2) {
+    const double2 n0 = d_coef.clen[k - 2];
+    const double2 n1 = d_coef.clen[k - 3];
+    clenshaw_step<U>(c0, st);
+    clenshaw_step<U>(c1, st);
+    c0 = n0;
+    c1 = n1;
+  }
+  if (k >= 1) clenshaw_step<U>(c0, st);
+  if (k >= 2) clenshaw_step<U>(c1, st);
 }
 
 template <int U>
@@ -208,7 +243,7 @@ struct TargetGeom {
 // u = 0..U-1.  Source records come from posq / qn at indices s[u]
 // (q = w sigma and q nu).  The sums leave out the factor 1/(4 pi).
 //
-// Single layer alone: S = sum_n b_n from the Legendre recurrence.
+// Single layer alone: S = sum_n b_n by Clenshaw's backward recurrence.
 // With the double layer or S', only the derivative terms E_n = (|delta|/R)^{n-1}
 // P_n'(x) are generated, by the three-term recurrence
 //   n P_{n+1}' = (2n+1) x P_n' - (n+1) P_{n-1}',
@@ -219,7 +254,10 @@ struct TargetGeom {
 //   sum_n b_n       = (1 - 2 beta + g2) S2 + E_{p+1} - g2 E_p,
 // the double layer bracket becomes (nu.delta) S2 - (nu.d)(S2 + E_{p+1}) and
 // the S' bracket (nu_t.d) S2 - (nu_t.delta)(S2 - E_p).
-template <int P, int L, int U>
+// UNROLLED_SLP: the single layer alone uses the fully unrolled Clenshaw steps
+// (constants in registers) instead of the table-driven loop; the plain kernel
+// sets it for one target per wave, where the registers are available.
+template <int P, int L, int U, bool UNROLLED_SLP>
 __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
                                            const double4 *__restrict__ posq,
                                            const double4 *__restrict__ qn, const TargetGeom &tg,
@@ -249,16 +287,20 @@ __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
   if constexpr (L == 1) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      st.fm1[u] = 1.0;
-      st.f[u] = st.beta[u];
-      st.S[u] = p >= 1 ? 1.0 + st.beta[u] : 1.0;
+      st.fm1[u] = 0.0;
+      st.f[u] = 0.0;
     }
-    if constexpr (P >= 0)
-      slp_steps<P, U, 1>(st);
+    if constexpr (P >= 0 && UNROLLED_SLP)
+      slp_clenshaw<P, U, P>(st);
     else
-      slp_steps_rt<U>(p, st);
+      slp_clenshaw_rt<U>(p, st);
+    constexpr double kap1 = kap_c(1);
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc_s = fma(a[u].w * rinv[u], st.S[u], acc_s);
+    for (int u = 0; u < U; ++u) {
+      const double S = p >= 1 ? fma(st.beta[u], st.f[u], fma(-st.g2[u], kap1 * st.fm1[u], 1.0))
+                              : 1.0;
+      acc_s = fma(a[u].w * rinv[u], S, acc_s);
+    }
   } else {
     // (fm1, f) = (F_0, F_1) for p = 0, else (F_1, F_2) = (1, beta)
 #pragma unroll
@@ -304,7 +346,7 @@ __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
 // one at a time over the rest.  The chunk loop's bounds are the same for the
 // whole group, so only the tail runs with idle lanes.  tn is the target's
 // normal (read for S' only).
-template <int P, int L, int G, int U, class NrmPtr>
+template <int P, int L, int G, int U, bool UNROLLED_SLP, class NrmPtr>
 __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr, NrmPtr tn,
                                            const int32_t *__restrict__ idx,
                                            const double4 *__restrict__ posq,
@@ -341,7 +383,7 @@ __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr
 #pragma unroll
       for (int u = 0; u < U; ++u)
         sn[u] = load_idx(row, (uint32_t)min(c0 + G * U + gl + u * G, len - 1));
-      pair_terms<P, L, U>(p_rt, s, posq, qn, tg, acc_s, acc_d, acc_t);
+      pair_terms<P, L, U, UNROLLED_SLP>(p_rt, s, posq, qn, tg, acc_s, acc_d, acc_t);
 #pragma unroll
       for (int u = 0; u < U; ++u) s[u] = sn[u];
     }
@@ -350,7 +392,7 @@ __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr
     const int j = c0 + gl;
     if (j < len) {
       const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
-      pair_terms<P, L, 1>(p_rt, s1, posq, qn, tg, acc_s, acc_d, acc_t);
+      pair_terms<P, L, 1, UNROLLED_SLP>(p_rt, s1, posq, qn, tg, acc_s, acc_d, acc_t);
     }
   }
 #pragma unroll

@@ -24,7 +24,7 @@ k_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm, int6
   if (t >= n_targets) return;
   const TargetRec tr = tgt[t];
   double v[3];
-  target_sum<P, L, G, U>(p_rt, lane % G, tr, tnrm + t, idx, posq, qn, v);
+  target_sum<P, L, G, U, G == 64>(p_rt, lane % G, tr, tnrm + t, idx, posq, qn, v);
   if (lane % G == 0) store_out<L>(tr, v, out_s, out_d, out_t, accumulate);
 }
 

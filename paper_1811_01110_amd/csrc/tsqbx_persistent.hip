@@ -11,6 +11,8 @@ namespace {
 // ---- persistent batched kernel ---------------------------------------------
 // A unit is a run of
 // consecutive targets of one item; p and the layer mask are wave-uniform.
+// The single layer alone always takes the table-driven Clenshaw loop here:
+// the unit loop around it leaves no registers for unrolled constants.
 template <int P, int L, int G, int U>
 __device__ __forceinline__ void unit_body(const WorkItem &it, int first, int count, int lane) {
   constexpr int TPW = 64 / G;
@@ -22,7 +24,8 @@ __device__ __forceinline__ void unit_body(const WorkItem &it, int first, int cou
     if (slot >= count) break;  // whole groups leave together
     const TargetRec tr = load_target(tgt + first + slot);
     double v[3];
-    target_sum<P, L, G, U>(it.p, lane % G, tr, tnrm + first + slot, it.idx, it.posq, it.qn, v);
+    target_sum<P, L, G, U, false>(it.p, lane % G, tr, tnrm + first + slot, it.idx, it.posq,
+                                  it.qn, v);
     if (lane % G == 0)
       store_out<L>(tr, v, (TSQBX_GLOBAL double *)it.out_s, (TSQBX_GLOBAL double *)it.out_d,
                    (TSQBX_GLOBAL double *)it.out_t, it.accumulate);

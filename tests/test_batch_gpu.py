@@ -224,3 +224,29 @@ def test_plan_and_server_with_sprime(ctx):
             else:
                 assert outs[k] is None
     srv.close()
+
+
+@pytest.mark.parametrize("p", [8, 16, 11])
+def test_plan_single_layer_long_lists_match_plain_bits(ctx, p):
+    """One target per wave: the plain kernel unrolls the single layer's
+    Clenshaw steps, the persistent kernel reads their constants from a table;
+    the results are the same bits."""
+    import torch
+
+    geoms = [W.fuzz_geometry(950 + i, n=3000, m=200, max_list=1500, p=p, layers=1,
+                             allow_empty=False) for i in range(3)]
+    items = _items(ctx, geoms, torch)
+    mean = max(sum(i["geom"].pairs for i in items) // sum(i["geom"].n_targets for i in items), 1)
+    assert ctx.get_tuning(p, 1, mean)["group_lanes"] == 64
+    plan = ctx.plan(items)
+    plan.execute()
+    torch.cuda.synchronize()
+    for it in items:
+        g = it["g"]
+        mean_i = max(it["geom"].pairs // max(it["geom"].n_targets, 1), 1)
+        ctx.set_tuning(p, 1, mean_i, group_lanes=64, unroll=2)
+        s, _, _ = ctx.eval(it["geom"], g.sigma, p, 1)
+        assert np.array_equal(s, it["out_slp"].cpu().numpy())
+        ref = oracle.evaluate_geometry(g)
+        assert_parity(s, ref["slp"], ref["abs_slp"], what=f"plan long lists p={p}")
+    plan.close()

@@ -20,7 +20,7 @@ def test_flop_model_matches_kernel_structure():
     import bench
 
     # 25 setup operations, 6 per order, the closing sums per layer mask
-    assert bench.flops_per_pair(16, 1) == 6 * 16 + 23
+    assert bench.flops_per_pair(16, 1) == 5 * 16 + 25
     assert bench.flops_per_pair(16, 2) == 6 * 16 + 37
     assert bench.flops_per_pair(16, 3) == 6 * 16 + 48
     assert bench.flops_per_pair(0, 3) == bench.flops_per_pair(1, 3)

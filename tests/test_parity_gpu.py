@@ -64,6 +64,22 @@ def test_every_order_ragged_lists(ctx, p):
     _check(ctx, g, what=f"fuzz p={p}")
 
 
+@pytest.mark.parametrize("p", list(range(0, 33)))
+def test_single_layer_alone_every_order(ctx, p):
+    """The single layer alone runs Clenshaw's backward recurrence: every
+    compiled and run-time order, with short and long lists (one and four
+    targets per wave)."""
+    g = W.fuzz_geometry(900 + p, n=400, m=80, max_list=700, p=p, layers=1, targets_per_center=2)
+    geom = ctx.geometry(g)
+    ref = oracle.evaluate_geometry(g, p=p, layers=1)
+    mean = max(geom.pairs // max(geom.n_targets, 1), 1)
+    for G, U in ((64, 2), (64, 1), (16, 2)):
+        ctx.set_tuning(p, 1, mean, group_lanes=G, unroll=U)
+        s, _, _ = ctx.eval(geom, g.sigma, p, 1)
+        assert_parity(s, ref["slp"], ref["abs_slp"], what=f"slp alone p={p} G{G}U{U}")
+    geom.close()
+
+
 @pytest.mark.parametrize("layers", [1, 2, 3])
 def test_layers_separately(ctx, layers):
     g = W.fuzz_geometry(100 + layers, n=500, m=90, max_list=300, p=16, layers=layers)
