@@ -195,6 +195,9 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
       }
     }
   }
+  // unrolled by two so that the three-term recurrences rotate their
+  // registers without moves
+#pragma unroll 2
   for (int n = 1; n < p; ++n) {
     // step to order n + 1
     const double kap = d_coef.kap[n];
