@@ -99,3 +99,55 @@ def test_server_wait_times_out_and_destroy_finishes_in_flight_work(ctx):
     assert_parity(tickets[0][1], ref["slp"], ref["abs_slp"], what="served slp")
     assert_parity(tickets[0][2], ref["dlp"], ref["abs_dlp"], what="served dlp")
     geom.close()
+
+
+def test_server_concurrent_submitters(ctx):
+    """Four threads submit at once (submit is thread-safe); every result
+    equals the same request served alone."""
+    import threading
+
+    geoms = W.config_e_geometries(n_geometries=3, scale=64)
+    gs = [ctx.geometry(g) for g in geoms]
+    srv = ctx.server(16 * max(api.Server.request_bytes(g, 3) for g in gs), 32)
+    rng = np.random.default_rng(77)
+    jobs = [(i % 3, (8, 16)[i % 2], (1, 2, 3)[i % 3], rng.standard_normal(geoms[i % 3].n_sources))
+            for i in range(80)]
+    alone = []
+    for k, p, lay, sig in jobs[:12]:
+        t, a, b, _ = srv.submit(gs[k], sig, p, lay)
+        srv.wait(t, 60)
+        alone.append((a, b))
+    results = [None] * len(jobs)
+    errors = []
+
+    def worker(w):
+        try:
+            for i in range(w, len(jobs), 4):
+                k, p, lay, sig = jobs[i]
+                results[i] = srv.submit(gs[k], sig, p, lay)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors
+    srv.drain(120)
+    st = srv.stats()
+    assert st["failed"] == 0 and st["completed"] == 12 + len(jobs)
+    for i, (a0, b0) in enumerate(alone):
+        _, a, b, _ = results[i]
+        lay = jobs[i][2]
+        if lay & 1:
+            assert np.array_equal(a, a0)
+        if lay & 2:
+            assert np.array_equal(b, b0)
+    for (k, p, lay, sig), (t, a, b, _) in list(zip(jobs, results))[12:30]:
+        ref = oracle.evaluate_geometry(geoms[k], p=p, layers=lay, sigma=sig)
+        if lay & 1:
+            assert_parity(a, ref["slp"], ref["abs_slp"], what="threaded slp")
+        if lay & 2:
+            assert_parity(b, ref["dlp"], ref["abs_dlp"], what="threaded dlp")
+    srv.close()
