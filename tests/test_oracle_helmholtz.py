@@ -1,9 +1,9 @@
 """Pins of the Helmholtz oracle (App. A, Helmholtz case) to facts that do not
 come from the oracle itself: the Green's function exp(ik|t-s|)/(4 pi |t-s|)
-and its source gradient (the addition theorem the expansion truncates), the
-Laplace expansion as k -> 0, sphere eigenvalues, closed forms at p = 0, and a
-50-digit mpmath evaluation with the double layer obtained by numerical
-differentiation of the single layer."""
+and its source and target gradients (the addition theorem the expansion
+truncates), the Laplace expansion as k -> 0, sphere eigenvalues, closed forms
+at p = 0 and at t = c, and a 50-digit mpmath evaluation with the double layer
+and S' obtained by numerical differentiation of the single layer."""
 import math
 
 import numpy as np
@@ -31,6 +31,53 @@ def _green_dnu_source(t, s, nu, k):
     rl = np.linalg.norm(r)
     # grad_s of exp(ik r)/(4 pi r) = (ik r - 1) exp(ik r) / (4 pi r^2) * (s - t)/r
     return (1j * k * rl - 1) * np.exp(1j * k * rl) * INV4PI / rl ** 2 * np.dot(nu, -r) / rl
+
+
+def _green_dnu_target(t, s, nu_t, k):
+    r = t - s
+    rl = np.linalg.norm(r)
+    return (1j * k * rl - 1) * np.exp(1j * k * rl) * INV4PI / rl ** 2 * np.dot(nu_t, r) / rl
+
+
+@pytest.mark.parametrize("k", [0.5, 3.0, 20.0])
+def test_sprime_converges_to_target_derivative_of_green_function(k):
+    rng = np.random.default_rng(int(k * 100) + 7)
+    for _ in range(12):
+        c = rng.uniform(-1, 1, 3)
+        R = rng.uniform(0.05, 0.3)
+        ratio = rng.uniform(0.05, 0.6)
+        s = c + R * _rand_unit(rng)
+        t = c + ratio * R * _rand_unit(rng)
+        nu_t = _rand_unit(rng)
+        ref = _green_dnu_target(t, s, nu_t, k)
+        errs = []
+        for p in (4, 16, 40, 80):
+            v, va = H.target_normal_terms(t, c, s[None, :], nu_t, k, p)
+            errs.append(abs(v[0] - ref))
+        assert errs[-1] <= 1e-12 * abs(ref) + 1e-13 * va[0]
+        assert errs[0] >= errs[2] - 1e-15
+
+
+def test_sprime_at_the_center_and_near_it():
+    """At t = c only n = 1 survives: (i k / 4 pi) k h_1(kR) (nu_t . s_hat), and
+    p = 0 gives 0 (the n = 0 term is even in t - c); a target 1e-9 from the
+    center agrees with that limit to O(k rho)."""
+    rng = np.random.default_rng(8)
+    for k in (0.7, 5.0, 20.0):
+        c = rng.uniform(-1, 1, 3)
+        s = c + 0.2 * _rand_unit(rng, 4)
+        nu_t = _rand_unit(rng)
+        d = s - c
+        R = np.linalg.norm(d, axis=1)
+        h1 = sps.spherical_jn(1, k * R) + 1j * sps.spherical_yn(1, k * R)
+        ref = 1j * k * INV4PI * k * h1 * (d @ nu_t) / R
+        for p in (1, 2, 9):
+            v, _ = H.target_normal_terms(c, c, s, nu_t, k, p)
+            assert np.all(np.abs(v - ref) <= 1e-15 * np.abs(h1) * k * k * INV4PI * 4)
+            near, _ = H.target_normal_terms(c + 1e-9 * _rand_unit(rng), c, s, nu_t, k, p)
+            assert np.all(np.abs(near - ref) <= 1e-7 * np.abs(h1) * k * k)
+        v, va = H.target_normal_terms(c, c, s, nu_t, k, 0)
+        assert np.all(v == 0) and np.all(va == 0)
 
 
 @pytest.mark.parametrize("k", [0.5, 3.0, 20.0])
@@ -67,9 +114,14 @@ def test_small_wavenumber_reduces_to_laplace():
         nu = _rand_unit(rng)
         for p in (0, 3, 12):
             g, d, _, _ = H.pair_terms(t, c, s[None, :], nu[None, :], k, p)
-            lap = oracle.pair(t, c, s, nu, p)
+            nu_t = _rand_unit(rng)
+            sp, _ = H.target_normal_terms(t, c, s[None, :], nu_t, k, p)
+            lap = oracle.pair(t, c, s, nu, p, nu_t)
             assert abs(g[0].real - lap[0]) <= 1e-8 * lap[2]
             assert abs(d[0].real - lap[1]) <= 1e-8 * lap[3]
+            # (at p = 0 the Laplace S' vanishes; the Helmholtz n = 0 term keeps
+            # k j_0'(k rho) = -k j_1(k rho) = O(k^2 rho))
+            assert abs(sp[0].real - lap[4]) <= 1e-8 * lap[5] + k * k * INV4PI
             assert abs(g[0].imag) <= 2 * k * INV4PI * (p + 1)
 
 
@@ -102,8 +154,9 @@ def _sphere_product_rule(n_theta, n_phi):
 @pytest.mark.parametrize("l,m,k", [(0, 0, 2.0), (2, 1, 5.0), (3, 2, 20.0)])
 def test_sphere_eigenvalues_center_at_origin(l, m, k):
     """Unit sphere, center at the origin, density Y_l^m: by the addition
-    theorem and orthonormality S_k[Y] = i k j_l(k rho) h_l(k) Y and, with the
-    outward normal, D_k[Y] = i k j_l(k rho) k h_l'(k) Y (0 for p < l)."""
+    theorem and orthonormality S_k[Y] = i k j_l(k rho) h_l(k) Y, with the
+    outward normal D_k[Y] = i k j_l(k rho) k h_l'(k) Y and, with the radial
+    target normal, S'_k[Y] = i k k j_l'(k rho) h_l(k) Y (all 0 for p < l)."""
     pts, w, th, ph = _sphere_product_rule(16, 34)
     mu = sps.sph_harm_y(l, m, th, ph)
     rng = np.random.default_rng(50 + l)
@@ -117,18 +170,21 @@ def test_sphere_eigenvalues_center_at_origin(l, m, k):
     hl = sps.spherical_jn(l, k) + 1j * sps.spherical_yn(l, k)
     dhl = sps.spherical_jn(l, k, True) + 1j * sps.spherical_yn(l, k, True)
     jl = sps.spherical_jn(l, k * rho)
+    djl = sps.spherical_jn(l, k * rho, True)
     off = np.array([0, len(pts)], dtype=np.int64)
     idx = np.arange(len(pts), dtype=np.int32)
     for p in (max(l - 1, 0), l, l + 4):
         res = H.evaluate(pts, w, pts, np.zeros((1, 3)), off, idx, tgt, np.zeros(nt, dtype=np.int32),
-                         mu, k, p, H.SLP | H.DLP)
+                         mu, k, p, H.SLP | H.DLP | H.SPRIME, target_normals=dirs)
         if p >= l:
             s_ref = 1j * k * jl * hl * yt
             d_ref = 1j * k * jl * k * dhl * yt
+            t_ref = 1j * k * k * djl * hl * yt
         else:
-            s_ref = d_ref = np.zeros(nt)
+            s_ref = d_ref = t_ref = np.zeros(nt)
         assert np.max(np.abs(res["slp"] - s_ref)) <= 1e-13 * (1 + np.max(res["abs_slp"]))
         assert np.max(np.abs(res["dlp"] - d_ref)) <= 1e-13 * (1 + np.max(res["abs_dlp"]))
+        assert np.max(np.abs(res["sprime"] - t_ref)) <= 1e-13 * (1 + np.max(res["abs_sprime"]))
 
 
 def test_mpmath_literal_series_and_numerical_source_derivative():
@@ -152,12 +208,13 @@ def test_mpmath_literal_series_and_numerical_source_derivative():
         s = c + rng.uniform(0.05, 0.3) * _rand_unit(rng)
         t = c + rng.uniform(0.05, 0.9) * np.linalg.norm(s - c) * _rand_unit(rng)
         nu = _rand_unit(rng)
-        T, C, S, N = ([mpmath.mpf(float(v)) for v in a] for a in (t, c, s, nu))
+        nu_t = _rand_unit(rng)
+        T, C, S, N, NT = ([mpmath.mpf(float(v)) for v in a] for a in (t, c, s, nu, nu_t))
         K = mpmath.mpf(k)
 
-        def slp(h):
+        def slp(h, ht=0):
             ss = [a + h * b for a, b in zip(S, N)]
-            dt = [a - b for a, b in zip(T, C)]
+            dt = [a + ht * e - b for a, b, e in zip(T, C, NT)]
             ds = [a - b for a, b in zip(ss, C)]
             rho = mpmath.sqrt(sum(v * v for v in dt))
             R = mpmath.sqrt(sum(v * v for v in ds))
@@ -169,9 +226,12 @@ def test_mpmath_literal_series_and_numerical_source_derivative():
 
         g_ref = complex(slp(0))
         d_ref = complex(mpmath.diff(slp, 0))
+        t_ref = complex(mpmath.diff(lambda ht: slp(0, ht), 0))
         g, d, ga, da = H.pair_terms(t, c, s[None, :], nu[None, :], k, p)
+        sp, spa = H.target_normal_terms(t, c, s[None, :], nu_t, k, p)
         assert abs(g[0] - g_ref) <= 16 * 2.2e-16 * (p + 1) * ga[0]
         assert abs(d[0] - d_ref) <= 16 * 2.2e-16 * (p + 1) * da[0]
+        assert abs(sp[0] - t_ref) <= 16 * 2.2e-16 * (p + 1) * spa[0]
 
 
 def test_rigid_motion_linearity_and_list_order():
@@ -181,24 +241,27 @@ def test_rigid_motion_linearity_and_list_order():
     rng = np.random.default_rng(31)
     sig = rng.standard_normal(g.n_sources) + 1j * rng.standard_normal(g.n_sources)
     k = 4.0
-    ref = H.evaluate_geometry(g, k, sig)
+    L = H.SLP | H.DLP | H.SPRIME
+    keys = ("slp", "dlp", "sprime")
+    ref = H.evaluate_geometry(g, k, sig, layers=L)
     Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
     shift = rng.uniform(-3, 3, 3)
     mv = lambda a: a @ Q.T + shift
     h = W.fuzz_geometry(30, n=60, m=10, max_list=30, p=10, layers=3)
     h.sources, h.centers, h.targets, h.normals = mv(h.sources), mv(h.centers), mv(h.targets), h.normals @ Q.T
-    out = H.evaluate_geometry(h, k, sig)
-    for key in ("slp", "dlp"):
+    h.target_normals = h.target_normals @ Q.T
+    out = H.evaluate_geometry(h, k, sig, layers=L)
+    for key in keys:
         assert np.all(np.abs(out[key] - ref[key]) <= 1e-12 * (ref["abs_" + key] + 1e-300))
     s2 = rng.standard_normal(g.n_sources) * (1 - 2j)
-    b = H.evaluate_geometry(g, k, s2)
-    ab = H.evaluate_geometry(g, k, (2 - 1j) * sig + 3 * s2)
-    for key in ("slp", "dlp"):
+    b = H.evaluate_geometry(g, k, s2, layers=L)
+    ab = H.evaluate_geometry(g, k, (2 - 1j) * sig + 3 * s2, layers=L)
+    for key in keys:
         scale = 3 * ref["abs_" + key] + 3 * b["abs_" + key]
         assert np.all(np.abs(ab[key] - ((2 - 1j) * ref[key] + 3 * b[key])) <= 1e-13 * (scale + 1e-300))
     for i in range(g.n_centers):
         lo, hi = g.list_offsets[i], g.list_offsets[i + 1]
         g.list_sources[lo:hi] = rng.permutation(g.list_sources[lo:hi])
-    c = H.evaluate_geometry(g, k, sig)
-    for key in ("slp", "dlp"):
+    c = H.evaluate_geometry(g, k, sig, layers=L)
+    for key in keys:
         assert np.all(np.abs(c[key] - ref[key]) <= 1e-13 * (ref["abs_" + key] + 1e-300))
