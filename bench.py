@@ -355,35 +355,48 @@ def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
 
 def helm_flops_per_pair(p: int, layers: int, sincos_flops: int = HELM_SINCOS_FLOPS) -> int:
     """FP64 operations per pair of the Helmholtz kernel (add/mul = 1,
-    fma = 2, reciprocal-square-root estimate = 1): pair setup 27, sincos
-    (as measured with FP64 counters), h_0 and h_1 8, the n = 0 and n = 1
-    terms, 13 per further order for the single layer (Legendre 3, Hankel 5,
-    term 5) and 17 for the double layer (P_n' 3, three complex sums 14), the
-    per-order table multiply once per pair, and the closing products with the
-    complex density (8 per layer, 22 more for the double layer's bracket)."""
-    f = 27 + sincos_flops + 8 + 2
+    fma = 2, reciprocal-square-root estimate = 1), by the operations each
+    layer adds.  Always: pair setup 27, sincos (as measured with FP64
+    counters), h_0 and h_1 8, and per further order the Legendre (3) and
+    Hankel (5) recurrences.  The single or double layer: the terms
+    m_n = (2n+1) j_n P_n (table multiply and product, 2 per further order,
+    1 at n = 1).  Single layer: the complex sum (2 at n = 0, 4 at n = 1 and
+    per further order) and the product with the complex density (8).  P_n'
+    (double layer or S'): 3 per further order.  Double layer: nu . d 5, the
+    n = 0 and n = 1 terms 8 and 13, three complex sums (14 per further order)
+    and the closing bracket with the density 30.  S': nu_t . d 5, the n = 0
+    and n = 1 terms 2 and 9, two complex sums with their table multiply (11
+    per further order) and the closing bracket with the density 17."""
+    f = 27 + sincos_flops + 8
     orders = max(p - 1, 0)
-    if p >= 1:
-        f += 5
-    f += orders * (13 + 1)
-    f += 8 if layers & 1 else 0
+    f += orders * 8
+    if layers & 3:
+        f += orders * 2 + (1 if p >= 1 else 0)
+    if layers & 1:
+        f += 2 + (4 if p >= 1 else 0) + orders * 4 + 8
+    if layers & 6:
+        f += orders * 3
     if layers & 2:
-        f += 5 + 8 + (13 if p >= 1 else 0) + orders * 17 + 30
+        f += 5 + 8 + (13 if p >= 1 else 0) + orders * 14 + 30
+    if layers & 4:
+        f += 5 + 2 + (9 if p >= 1 else 0) + orders * 11 + 17
     return f
 
 
 def bench_helmholtz(ctx, api, torch, g, geom, steps, warmup, k=20.0, p=16):
     """Helmholtz single + double layer (the Brakhage-Werner pair of the
-    paper's large experiment, k = 20) on the headline geometry."""
+    paper's large experiment, k = 20) on the headline geometry; then the
+    single layer alone, S' alone and all three layers."""
     rng = np.random.default_rng(20181101)
     sig = torch.tensor(rng.standard_normal(g.n_sources) + 1j * rng.standard_normal(g.n_sources),
                        device="cuda", dtype=torch.complex128)
-    os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
-    od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
+    outs = [torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128) for _ in range(3)]
     res = {"workload": f"perturbed sphere r=1+0.1f, 262144 sources, 65536 targets, ball lists "
                        f"r=0.15, Helmholtz k={k:g}, p={p}, complex density"}
-    for name, layers in (("slp_dlp", 3), ("slp", 1)):
-        step = lambda: ctx.eval_helmholtz_async(geom, sig, p, layers, k, os_, od_)
+    for name, layers in (("slp_dlp", 3), ("slp", 1), ("sprime", 4), ("all_three", 7)):
+        if layers & 4 and not geom.has_target_normals:
+            continue
+        step = lambda: ctx.eval_helmholtz_async(geom, sig, p, layers, k, *outs)
         log(f"timing Helmholtz ({name}) {steps} steps")
         wall, ev = timed_steps(step, steps, warmup, torch)
         fpp = helm_flops_per_pair(p, layers)

@@ -173,24 +173,28 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned
  *
  * with j_n the spherical Bessel and h_n the spherical Hankel function of the
  * first kind: the p-th order target-specific expansion of
- * exp(ik|t-y|) / (4 pi |t-y|).  layers: TSQBX_SLP (q_y G_k^(p)) and/or
- * TSQBX_DLP (q_y nu_y . grad_y G_k^(p), App. A's source gradient), the two
- * operators of the paper's Brakhage-Werner experiment.  Densities and outputs
+ * exp(ik|t-y|) / (4 pi |t-y|).  layers: TSQBX_SLP (q_y G_k^(p)), TSQBX_DLP
+ * (q_y nu_y . grad_y G_k^(p), App. A's source gradient; the two operators of
+ * the paper's Brakhage-Werner experiment) and TSQBX_SPRIME
+ * (q_y nu_t . grad_t G_k^(p), App. A's target gradient dotted with the
+ * geometry's target normal; at t = c its limit, the n = 1 term
+ * (i k / 4 pi) k h_1(k|y-c|) (nu_t . (y-c)/|y-c|)).  Densities and outputs
  * are complex, stored as interleaved (re, im) float64 pairs (C99 double
  * complex, numpy complex128): sigma [N][2] in the caller's source order,
- * out_slp / out_dlp [T][2] in the caller's target order.  The first call on a
- * geometry allocates its Helmholtz staging (64 (N + 1) + 264 T bytes).
- * Errors as for tsqbx_eval; k <= 0 or not finite gives TSQBX_E_RANGE,
- * TSQBX_SPRIME gives TSQBX_E_INVALID.
+ * out_slp / out_dlp / out_sprime [T][2] in the caller's target order (NULL
+ * for a layer not requested).  The first call on a geometry allocates its
+ * Helmholtz staging (64 (N + 1) + 264 T bytes), the first S' call a further
+ * 528 T bytes.  Errors as for tsqbx_eval (S' without target normals is
+ * TSQBX_E_INVALID); k <= 0 or not finite gives TSQBX_E_RANGE.
  * ------------------------------------------------------------------------- */
 int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
                          double k, const double *sigma, double *out_slp, double *out_dlp,
-                         unsigned flags);
+                         double *out_sprime, unsigned flags);
 /* The same on device pointers, asynchronous on hip_stream. */
 int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p,
                                unsigned layers, double k, const double *d_sigma,
-                               double *d_out_slp, double *d_out_dlp, unsigned flags,
-                               void *hip_stream);
+                               double *d_out_slp, double *d_out_dlp, double *d_out_sprime,
+                               unsigned flags, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Near-field lists on the device.  For every center c the sources y inside

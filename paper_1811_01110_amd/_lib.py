@@ -89,9 +89,9 @@ _SIGNATURES = {
     "tsqbx_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_uint, c_void_p]),
     "tsqbx_eval_helmholtz": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double, c_void_p,
-                                     c_void_p, c_void_p, c_uint]),
+                                     c_void_p, c_void_p, c_void_p, c_uint]),
     "tsqbx_eval_helmholtz_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double, c_void_p,
-                                           c_void_p, c_void_p, c_uint, c_void_p]),
+                                           c_void_p, c_void_p, c_void_p, c_uint, c_void_p]),
     "tsqbx_ball_lists": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_double,
                                  c_void_p, c_void_p, c_int64, P(c_int64), c_void_p]),
     "tsqbx_get_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),

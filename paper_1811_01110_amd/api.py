@@ -165,15 +165,15 @@ class Context:
                                        int(flags), _stream_handle(stream)))
 
     def eval_helmholtz(self, geom: "Geometry", sigma, p: int, layers: int, k: float,
-                       out_slp=None, out_dlp=None, flags: int = 0):
+                       out_slp=None, out_dlp=None, out_sprime=None, flags: int = 0):
         """Helmholtz evaluation with host arrays: sigma complex (N,); returns
-        complex (slp, dlp), None for a layer not requested."""
+        complex (slp, dlp, sprime), None for a layer not requested."""
         sig = np.ascontiguousarray(sigma, dtype=np.complex128)
         if sig.size != geom.n_sources:
             raise ValueError(f"sigma has {sig.size} entries, expected {geom.n_sources}")
         T = geom.n_targets
-        outs = [out_slp, out_dlp]
-        for i, bit in enumerate((SLP, DLP)):
+        outs = [out_slp, out_dlp, out_sprime]
+        for i, bit in enumerate(LAYER_BITS):
             if not layers & bit:
                 outs[i] = None
                 continue
@@ -187,7 +187,8 @@ class Context:
         return tuple(outs)
 
     def eval_helmholtz_async(self, geom: "Geometry", sigma, p: int, layers: int, k: float,
-                             out_slp=None, out_dlp=None, flags: int = 0, stream=None):
+                             out_slp=None, out_dlp=None, out_sprime=None, flags: int = 0,
+                             stream=None):
         """Helmholtz evaluation on device tensors (torch complex128)."""
         import torch
 
@@ -201,10 +202,11 @@ class Context:
             return t.data_ptr() if n else None
 
         s = ptr(sigma, geom.n_sources, "sigma")
-        a = ptr(out_slp, geom.n_targets, "out_slp") if layers & SLP else None
-        b = ptr(out_dlp, geom.n_targets, "out_dlp") if layers & DLP else None
+        outs = [ptr(o, geom.n_targets, name) if layers & bit else None
+                for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
+                                        ("out_slp", "out_dlp", "out_sprime"))]
         _check(_lib().tsqbx_eval_helmholtz_async(self.handle, geom.handle, int(p), int(layers),
-                                                 float(k), s, a, b, int(flags),
+                                                 float(k), s, *outs, int(flags),
                                                  _stream_handle(stream)))
 
     def ball_lists(self, sources, centers, radius: float, capacity=None, stream=None):

@@ -174,8 +174,8 @@ static int check_tuning_key(int p, unsigned layers) {
     const unsigned l = layers & ~(unsigned)TSQBX_HELMHOLTZ;
     if (p < 0 || p > TSQBX_P_MAX)
       return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
-    if (l == 0 || (l & ~3u))
-      return fail(TSQBX_E_INVALID, "Helmholtz layers = %u is not a nonempty subset of SLP|DLP", l);
+    if (l == 0 || (l & ~7u))
+      return fail(TSQBX_E_INVALID, "Helmholtz layers = %u is not a nonempty subset of SLP|DLP|SPRIME", l);
     return TSQBX_OK;
   }
   return check_request(nullptr, p, layers);
@@ -213,7 +213,7 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 static void free_geometry(tsqbx_geometry *g) {
   if (!g) return;
   void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
-                  g->stage.posq, g->stage.qn, g->helm.rec, g->helm.tab};
+                  g->stage.posq, g->stage.qn, g->helm.rec, g->helm.tab, g->helm.tabs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete g;
@@ -236,7 +236,7 @@ using namespace tsqbx;
 
 extern "C" {
 
-int tsqbx_version(void) { return 10100; }
+int tsqbx_version(void) { return 10200; }
 
 const char *tsqbx_last_error(void) { return g_err.c_str(); }
 
@@ -635,19 +635,35 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
 static int check_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k) {
   if (p < 0 || p > TSQBX_P_MAX)
     return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
-  if (layers == 0 || (layers & ~3u))
-    return fail(TSQBX_E_INVALID, "Helmholtz layers = %u is not a nonempty subset of SLP|DLP", layers);
+  if (layers == 0 || (layers & ~7u))
+    return fail(TSQBX_E_INVALID, "Helmholtz layers = %u is not a nonempty subset of SLP|DLP|SPRIME",
+                layers);
   if (!(k > 0.0) || !std::isfinite(k))
     return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
   if (g && (layers & TSQBX_DLP) && !g->has_normals)
     return fail(TSQBX_E_INVALID, "double layer requested but the geometry has no normals");
+  if (g && (layers & TSQBX_SPRIME) && !g->has_target_normals)
+    return fail(TSQBX_E_INVALID, "S' requested but the geometry has no target normals");
   return TSQBX_OK;
 }
 
-// The geometry's Helmholtz staging, allocated on its first Helmholtz call
-// (calls on one geometry do not overlap, so no lock is needed).
-static hipError_t ensure_helm_stage(const tsqbx_geometry *cg) {
+// The geometry's Helmholtz staging, allocated on its first Helmholtz call,
+// and its S' table on the first call that asks for S' (calls on one geometry
+// do not overlap, so no lock is needed).
+static hipError_t ensure_helm_stage(const tsqbx_geometry *cg, unsigned layers) {
   auto *g = const_cast<tsqbx_geometry *>(cg);
+  if ((layers & TSQBX_SPRIME) && !g->helm.tabs) {
+    size_t bytes = 0;
+    hipError_t e = dev_upload<double>(&g->helm.tabs, nullptr,
+                                      std::max<size_t>(1, (size_t)g->n_targets) *
+                                          2 * (TSQBX_P_MAX + 1),
+                                      &bytes);
+    if (e != hipSuccess) {
+      g->helm.tabs = nullptr;
+      return e;
+    }
+    g->device_bytes += bytes;
+  }
   if (g->helm.rec) return hipSuccess;
   size_t bytes = 0;
   hipError_t e = dev_upload<double4>(&g->helm.rec, nullptr, 2 * ((size_t)g->n_sources + 1), &bytes);
@@ -657,7 +673,8 @@ static hipError_t ensure_helm_stage(const tsqbx_geometry *cg) {
   if (e != hipSuccess) {
     if (g->helm.rec) (void)hipFree(g->helm.rec);
     if (g->helm.tab) (void)hipFree(g->helm.tab);
-    g->helm = HelmStage{};
+    g->helm.rec = nullptr;
+    g->helm.tab = nullptr;
     return e;
   }
   g->device_bytes += bytes;
@@ -666,37 +683,42 @@ static hipError_t ensure_helm_stage(const tsqbx_geometry *cg) {
 
 int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                                double k, const double *d_sigma, double *d_out_slp,
-                               double *d_out_dlp, unsigned flags, void *hip_stream) {
+                               double *d_out_dlp, double *d_out_sprime, unsigned flags,
+                               void *hip_stream) {
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_helmholtz(g, p, layers, k);
   if (rc != TSQBX_OK) return rc;
   if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
-  rc = check_outputs(g, layers, d_out_slp, d_out_dlp, nullptr);
+  rc = check_outputs(g, layers, d_out_slp, d_out_dlp, d_out_sprime);
   if (rc != TSQBX_OK) return rc;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
-  TSQBX_HIP(ensure_helm_stage(g));
+  TSQBX_HIP(ensure_helm_stage(g, layers));
   const Tuning tn = lookup_tuning(ctx, p, layers | TSQBX_HELMHOLTZ, mean_list_of(g));
-  TSQBX_HIP(launch_helmholtz(g, p, layers, k, d_sigma, g->helm, d_out_slp, d_out_dlp,
+  Outputs out;
+  out.s = d_out_slp;
+  out.d = d_out_dlp;
+  out.t = d_out_sprime;
+  TSQBX_HIP(launch_helmholtz(g, p, layers, k, d_sigma, g->helm, out,
                              (flags & TSQBX_ACCUMULATE) != 0, tn, (hipStream_t)hip_stream));
   return TSQBX_OK;
 }
 
 int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                          double k, const double *sigma, double *out_slp, double *out_dlp,
-                         unsigned flags) {
+                         double *out_sprime, unsigned flags) {
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_helmholtz(g, p, layers, k);
   if (rc != TSQBX_OK) return rc;
   if (g->n_sources > 0 && !sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
-  rc = check_outputs(g, layers, out_slp, out_dlp, nullptr);
+  rc = check_outputs(g, layers, out_slp, out_dlp, out_sprime);
   if (rc != TSQBX_OK) return rc;
   std::lock_guard<std::mutex> lk(ctx->mu);
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
-  TSQBX_HIP(ensure_helm_stage(g));
+  TSQBX_HIP(ensure_helm_stage(g, layers));
   const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
   if (ctx->d_sigma_cap < 2 * N) {
     if (ctx->d_sigma) (void)hipFree(ctx->d_sigma);
@@ -705,23 +727,27 @@ int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigne
     TSQBX_HIP(hipMalloc((void **)&ctx->d_sigma, 2 * N * sizeof(double)));
     ctx->d_sigma_cap = 2 * N;
   }
-  if (ctx->d_out_cap < 4 * T) {
+  if (ctx->d_out_cap < 6 * T) {
     if (ctx->d_out) (void)hipFree(ctx->d_out);
     ctx->d_out = nullptr;
     ctx->d_out_cap = 0;
-    TSQBX_HIP(hipMalloc((void **)&ctx->d_out, 4 * T * sizeof(double)));
-    ctx->d_out_cap = 4 * T;
+    TSQBX_HIP(hipMalloc((void **)&ctx->d_out, 6 * T * sizeof(double)));
+    ctx->d_out_cap = 6 * T;
   }
   hipStream_t s = ctx->stream;
   if (N)
     TSQBX_HIP(hipMemcpyAsync(ctx->d_sigma, sigma, 2 * N * sizeof(double), hipMemcpyHostToDevice, s));
-  double *const dev[2] = {ctx->d_out, ctx->d_out + 2 * T};
+  double *const dev[3] = {ctx->d_out, ctx->d_out + 2 * T, ctx->d_out + 4 * T};
   const Tuning tn = lookup_tuning(ctx, p, layers | TSQBX_HELMHOLTZ, mean_list_of(g));
-  TSQBX_HIP(launch_helmholtz(g, p, layers, k, ctx->d_sigma, g->helm, dev[0], dev[1], false, tn, s));
+  Outputs out;
+  out.s = dev[0];
+  out.d = dev[1];
+  out.t = dev[2];
+  TSQBX_HIP(launch_helmholtz(g, p, layers, k, ctx->d_sigma, g->helm, out, false, tn, s));
   const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
-  double *const user[2] = {out_slp, out_dlp};
-  std::vector<double> tmp[2];
-  for (int l = 0; l < 2; ++l) {
+  double *const user[3] = {out_slp, out_dlp, out_sprime};
+  std::vector<double> tmp[3];
+  for (int l = 0; l < 3; ++l) {
     if (!T || !(layers & (1u << l))) continue;
     double *dst = user[l];
     if (acc) {
@@ -731,7 +757,7 @@ int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigne
     TSQBX_HIP(hipMemcpyAsync(dst, dev[l], 2 * T * sizeof(double), hipMemcpyDeviceToHost, s));
   }
   TSQBX_HIP(hipStreamSynchronize(s));
-  for (int l = 0; l < 2; ++l)
+  for (int l = 0; l < 3; ++l)
     for (size_t i = 0; i < tmp[l].size(); ++i) user[l][i] += tmp[l][i];
   return TSQBX_OK;
 }

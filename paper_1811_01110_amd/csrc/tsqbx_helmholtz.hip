@@ -4,10 +4,15 @@
 //   G_k^(p)(t, y) = (i k / 4 pi) sum_{n=0..p} (2n+1) j_n(k rho) h_n(k R) P_n(x),
 //   nu . grad_y G_k^(p) = (i k / 4 pi) sum_n (2n+1) j_n(k rho) / R
 //                          [ k (nu.d) h_n'(k R) P_n(x) + (nu.delta/rho - (nu.d) x / R) h_n(k R) P_n'(x) ],
+//   nu_t . grad_t G_k^(p) = (i k / 4 pi) sum_n (2n+1) h_n(k R)
+//                          [ (nu_t.delta/rho) k j_n'(k rho) P_n(x)
+//                            + (nu_t.d / R - (nu_t.delta/rho) x) (j_n(k rho) / rho) P_n'(x) ],
 //
-// d = y - c, delta = t - c, R = |d|, rho = |delta|, x = cos gamma.  j_n(k rho)
-// depends on the target only, so a pre-pass (k_helm_table) stores
-// (2n+1) j_n(k rho) per target; the pair kernel runs three recurrences per
+// d = y - c, delta = t - c, R = |d|, rho = |delta|, x = cos gamma (the last
+// line is S', App. A's target gradient dotted with the target normal).  The
+// j_n(k rho) terms depend on the target only, so a pre-pass (k_helm_table)
+// stores (2n+1) j_n(k rho) per target and, for S', (2n+1) k j_n'(k rho) and
+// (2n+1) j_n(k rho) / rho (finite at rho = 0); the pair kernel runs three recurrences per
 // pair: Bonnet's for P_n (rescaled so that one order costs a multiply and an
 // FMA), the upward recurrence h_{n+1} = (2n+1)/z h_n - h_{n-1} for the
 // spherical Hankel functions (stable upward, DLMF 10.51.1), and
@@ -33,18 +38,25 @@ namespace {
 // n = p + 32 + z (where the minimal solution dominates), rescaled on the way,
 // is normalised by whichever of j_0 = sin z / z and j_1 = sin z / z^2 - cos z / z
 // is larger in magnitude (their zeros interlace, so one is well away from 0).
+// With tabs (S'), the row of 2 (p + 1) entries after it holds
+// (2n+1) k j_n'(z), from j_n' = (n/z) j_n - j_{n+1} (DLMF 10.51.2; no
+// cancellation for small z), then (2n+1) j_n(z) / rho = (2n+1) k j_n(z) / z.
+// At z = 0 these are their limits: k for n = 1 and 0 otherwise.
 __global__ void __launch_bounds__(256)
 k_helm_table(const TargetRec *__restrict__ tgt, int64_t n_targets, double k, int p,
-             double *__restrict__ tab) {
+             double *__restrict__ tab, double *__restrict__ tabs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_targets) return;
   const TargetRec tr = tgt[t];
   const double rho2 = fma(tr.d[2], tr.d[2], fma(tr.d[1], tr.d[1], tr.d[0] * tr.d[0]));
   const double z = k * sqrt(rho2);
   double *row = tab + t * (int64_t)(p + 1);
+  double *rows = tabs ? tabs + t * (int64_t)(2 * (p + 1)) : nullptr;
   if (!(z > 0.0)) {
     row[0] = 1.0;
     for (int n = 1; n <= p; ++n) row[n] = 0.0;
+    if (rows)
+      for (int n = 0; n <= p; ++n) rows[n] = rows[p + 1 + n] = n == 1 ? k : 0.0;
     return;
   }
   const double zinv = 1.0 / z;
@@ -52,38 +64,53 @@ k_helm_table(const TargetRec *__restrict__ tgt, int64_t n_targets, double k, int
   sincos(z, &sn, &cs);
   const double j0 = sn * zinv;
   const double j1 = (j0 - cs) * zinv;
+  // row[] first receives j_n (times a common factor `scale` for Miller's
+  // recurrence), jp1 the same for j_{p+1}
+  double scale = 1.0, jp1;
   if (z > (double)(p + 1)) {
     double jm1 = j0, jn = j1;
     row[0] = j0;
-    if (p >= 1) row[1] = 3.0 * j1;
-    for (int n = 1; n < p; ++n) {
-      const double jp1 = (double)(2 * n + 1) * zinv * jn - jm1;
-      row[n + 1] = (double)(2 * n + 3) * jp1;
+    for (int n = 1; n <= p; ++n) {
+      row[n] = jn;
+      const double jnext = (double)(2 * n + 1) * zinv * jn - jm1;
       jm1 = jn;
-      jn = jp1;
+      jn = jnext;
     }
-    return;
-  }
-  const int N = p + 32 + (int)z;
-  double fp1 = 0.0, f = 1.0e-280;  // f_{n+1}, f_n
-  double f0 = 0.0, f1 = 0.0;
-  for (int n = N; n >= 1; --n) {
-    const double fm1 = (double)(2 * n + 1) * zinv * f - fp1;
-    if (n - 1 <= p) row[n - 1] = fm1;
-    if (n == 2) f1 = fm1;
-    if (n == 1) f0 = fm1;
-    fp1 = f;
-    f = fm1;
-    if (fabs(f) > 1.0e250) {  // rescale everything kept so far
-      fp1 *= 1.0e-250;
-      f *= 1.0e-250;
-      f0 *= 1.0e-250;
-      f1 *= 1.0e-250;
-      for (int m = n - 1; m <= p; ++m) row[m] *= 1.0e-250;
+    jp1 = jn;
+  } else {
+    const int N = p + 32 + (int)z;
+    double fp1 = 0.0, f = 1.0e-280;  // f_{n+1}, f_n
+    double f0 = 0.0, f1 = 0.0;
+    jp1 = 0.0;
+    for (int n = N; n >= 1; --n) {
+      const double fm1 = (double)(2 * n + 1) * zinv * f - fp1;
+      if (n - 1 <= p) row[n - 1] = fm1;
+      if (n - 1 == p + 1) jp1 = fm1;
+      if (n == 2) f1 = fm1;
+      if (n == 1) f0 = fm1;
+      fp1 = f;
+      f = fm1;
+      if (fabs(f) > 1.0e250) {  // rescale everything kept so far
+        fp1 *= 1.0e-250;
+        f *= 1.0e-250;
+        f0 *= 1.0e-250;
+        f1 *= 1.0e-250;
+        jp1 *= 1.0e-250;
+        for (int m = n - 1; m <= p; ++m) row[m] *= 1.0e-250;
+      }
     }
+    scale = fabs(j0) >= fabs(j1) ? j0 / f0 : j1 / f1;
   }
-  const double scale = fabs(j0) >= fabs(j1) ? j0 / f0 : j1 / f1;
-  for (int n = 0; n <= p; ++n) row[n] = (double)(2 * n + 1) * (row[n] * scale);
+  for (int n = 0; n <= p; ++n) {
+    const double jn = row[n] * scale;
+    if (rows) {
+      const double jn1 = (n < p ? row[n + 1] : jp1) * scale;
+      const double w = (double)(2 * n + 1) * k;
+      rows[n] = w * fma((double)n * zinv, jn, -jn1);
+      rows[p + 1 + n] = w * (jn * zinv);
+    }
+    row[n] = (double)(2 * n + 1) * jn;
+  }
 }
 
 // Staging: rec[2i] = (x, y, z, Re q), rec[2i+1] = (Im q, nu) with q = w sigma
@@ -120,26 +147,31 @@ struct HelmTarget {
   double cx, cy, cz;
   double tx, ty, tz;
   double rho_inv;  // 1/|t - c|, or 0 at t = c (then only n = 0 survives)
+  double nx, ny, nz;  // target normal nu_t (S')
+  double ntt;         // nu_t . delta / rho (0 at t = c)
 };
 
-// U pairs of one target; acc = (Re, Im) of the single layer and of the double
-// layer, without the factor i k / (4 pi).
+// U pairs of one target; acc = (Re, Im) of the single layer, of the double
+// layer and of S', without the factor i k / (4 pi).  tabs: the target's S'
+// rows (k (2n+1) j_n', then (2n+1) j_n / rho).
 template <int L, int U>
 __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_t n_src,
                                            const uint32_t (&s)[U],
                                            const double4 *__restrict__ rec,
-                                           const double *__restrict__ tab, const HelmTarget &tg,
-                                           double (&acc)[4]) {
+                                           const double *__restrict__ tab,
+                                           const double *__restrict__ tabs, const HelmTarget &tg,
+                                           double (&acc)[6]) {
   double4 a[U], b[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     a[u] = load_rec(rec, s[u], 0);
     b[u] = load_rec(rec, s[u], 1);
   }
-  double x[U], zi[U], rinv[U], nd[U];
+  double x[U], zi[U], rinv[U], nd[U], nts[U];
   double em1[U], e[U], g[U];           // P_{n-1}/lam_{n-1}, P_n/lam_n, P_n'
   double hm1r[U], hm1i[U], hr[U], hi[U];  // h_{n-1}, h_n
   double Sr[U], Si[U], Ar[U], Ai[U], Br[U], Bi[U], Cr[U], Ci[U];
+  double Tr[U], Ti[U], Er[U], Ei[U];  // S': sum k (2n+1) j_n' P_n h_n, sum (2n+1) (j_n/rho) P_n' h_n
   const double A0 = tab[0];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -152,6 +184,7 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
     const double z = s[u] == n_src ? 1.0 : k * (R2 * rinv[u]);
     zi[u] = kinv * rinv[u];
     if constexpr (L & 2) nd[u] = fma(b[u].w, dz, fma(b[u].z, dy, b[u].y * dx));
+    if constexpr (L & 4) nts[u] = fma(tg.nz, dz, fma(tg.ny, dy, tg.nx * dx));
     double sn, cs;
     sincos(z, &sn, &cs);
     // h_0 = -i e^{iz} / z, h_1 = -(z + i) e^{iz} / z^2
@@ -168,6 +201,12 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
       Bi[u] = A0 * h0i;
       Cr[u] = 0.0;  // sum (2n+1) j_n P_n' h_n (P_0' = 0)
       Ci[u] = 0.0;
+    }
+    if constexpr (L & 4) {
+      Tr[u] = tabs[0] * h0r;
+      Ti[u] = tabs[0] * h0i;
+      Er[u] = 0.0;  // P_0' = 0
+      Ei[u] = 0.0;
     }
     em1[u] = 1.0;
     e[u] = x[u];
@@ -193,6 +232,13 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
         Cr[u] = fma(A1, hr[u], Cr[u]);  // P_1' = 1
         Ci[u] = fma(A1, hi[u], Ci[u]);
       }
+      if constexpr (L & 4) {
+        const double mt = tabs[1] * e[u];
+        Tr[u] = fma(mt, hr[u], Tr[u]);
+        Ti[u] = fma(mt, hi[u], Ti[u]);
+        Er[u] = fma(tabs[p + 2], hr[u], Er[u]);  // P_1' = 1
+        Ei[u] = fma(tabs[p + 2], hi[u], Ei[u]);
+      }
     }
   }
   // unrolled by two so that the three-term recurrences rotate their
@@ -207,6 +253,11 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
     const double An = tn * lam1;
     const double w2 = (double)(2 * n + 1);
     const double np2 = (double)(n + 2);
+    double Bt = 0.0, Et = 0.0;
+    if constexpr (L & 4) {
+      Bt = tabs[n + 1] * lam1;
+      Et = tabs[p + 2 + n];
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const double ep1 = fma(x[u], e[u], -kap * em1[u]);
@@ -214,10 +265,13 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
       const double hp1r = fma(w, hr[u], -hm1r[u]);
       const double hp1i = fma(w, hi[u], -hm1i[u]);
       const double m = An * ep1;
-      Sr[u] = fma(m, hp1r, Sr[u]);
-      Si[u] = fma(m, hp1i, Si[u]);
+      if constexpr (L & 1) {
+        Sr[u] = fma(m, hp1r, Sr[u]);
+        Si[u] = fma(m, hp1i, Si[u]);
+      }
+      double gp1 = 0.0;
+      if constexpr (L & 6) gp1 = fma(x[u], g[u], cn * e[u]);
       if constexpr (L & 2) {
-        const double gp1 = fma(x[u], g[u], cn * e[u]);
         Ar[u] = fma(m, hr[u], Ar[u]);
         Ai[u] = fma(m, hi[u], Ai[u]);
         const double mb = np2 * m;
@@ -226,8 +280,16 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
         const double mc = tn * gp1;
         Cr[u] = fma(mc, hp1r, Cr[u]);
         Ci[u] = fma(mc, hp1i, Ci[u]);
-        g[u] = gp1;
       }
+      if constexpr (L & 4) {
+        const double mt = Bt * ep1;
+        Tr[u] = fma(mt, hp1r, Tr[u]);
+        Ti[u] = fma(mt, hp1i, Ti[u]);
+        const double me = Et * gp1;
+        Er[u] = fma(me, hp1r, Er[u]);
+        Ei[u] = fma(me, hp1i, Ei[u]);
+      }
+      if constexpr (L & 6) g[u] = gp1;
       em1[u] = e[u];
       e[u] = ep1;
       hm1r[u] = hr[u];
@@ -255,15 +317,24 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
       acc[2] = fma(qr, Dr, fma(-qi, Di, acc[2]));
       acc[3] = fma(qr, Di, fma(qi, Dr, acc[3]));
     }
+    if constexpr (L & 4) {
+      // (nu_t.delta/rho) T + (nu_t.d / R - (nu_t.delta/rho) x) E
+      const double c2 = fma(nts[u], rinv[u], -tg.ntt * x[u]);
+      const double Vr = fma(tg.ntt, Tr[u], c2 * Er[u]);
+      const double Vi = fma(tg.ntt, Ti[u], c2 * Ei[u]);
+      acc[4] = fma(qr, Vr, fma(-qi, Vi, acc[4]));
+      acc[5] = fma(qr, Vi, fma(qi, Vr, acc[5]));
+    }
   }
 }
 
 template <int L, int G, int U>
 __global__ void __launch_bounds__(256)
-k_helm_eval(const TargetRec *__restrict__ tgt, int64_t n_targets, const int32_t *__restrict__ idx,
-            const double4 *__restrict__ rec, const double *__restrict__ tab, int p, double k,
-            uint32_t n_src, double *__restrict__ out_s, double *__restrict__ out_d, int accumulate,
-            int remap) {
+k_helm_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm,
+            int64_t n_targets, const int32_t *__restrict__ idx, const double4 *__restrict__ rec,
+            const double *__restrict__ tab, const double *__restrict__ tabs, int p, double k,
+            uint32_t n_src, double *__restrict__ out_s, double *__restrict__ out_d,
+            double *__restrict__ out_t, int accumulate, int remap) {
   constexpr int TPW = 64 / G;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -283,11 +354,20 @@ k_helm_eval(const TargetRec *__restrict__ tgt, int64_t n_targets, const int32_t 
   tg.tz = tr.d[2];
   const double rho = sqrt(fma(tg.tz, tg.tz, fma(tg.ty, tg.ty, tg.tx * tg.tx)));
   tg.rho_inv = rho > 0.0 ? 1.0 / rho : 0.0;
+  tg.nx = tg.ny = tg.nz = tg.ntt = 0.0;
+  if constexpr (L & 4) {
+    const double4 nv = tnrm[t];
+    tg.nx = nv.x;
+    tg.ny = nv.y;
+    tg.nz = nv.z;
+    tg.ntt = fma(tg.nz, tg.tz, fma(tg.ny, tg.ty, tg.nx * tg.tx)) * tg.rho_inv;
+  }
   const double kinv = 1.0 / k;
   const double *row_tab = tab + t * (int64_t)(p + 1);
+  const double *row_tabs = (L & 4) ? tabs + t * (int64_t)(2 * (p + 1)) : nullptr;
   const int32_t *__restrict__ row = idx + tr.row_begin;
   const int len = tr.row_len;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int c0 = 0;
   if constexpr (U > 1) {
     const int full = len - len % (G * U);
@@ -295,60 +375,63 @@ k_helm_eval(const TargetRec *__restrict__ tgt, int64_t n_targets, const int32_t 
       uint32_t s[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) s[u] = load_idx(row, (uint32_t)(c0 + gl + u * G));
-      helm_pairs<L, U>(p, k, kinv, n_src, s, rec, row_tab, tg, acc);
+      helm_pairs<L, U>(p, k, kinv, n_src, s, rec, row_tab, row_tabs, tg, acc);
     }
   }
   for (; c0 < len; c0 += G) {
     const int j = c0 + gl;
     if (j < len) {
       const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
-      helm_pairs<L, 1>(p, k, kinv, n_src, s1, rec, row_tab, tg, acc);
+      helm_pairs<L, 1>(p, k, kinv, n_src, s1, rec, row_tab, row_tabs, tg, acc);
     }
   }
 #pragma unroll
   for (int off = G / 2; off >= 1; off >>= 1)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+    for (int c = 0; c < 6; ++c)
+      if (L & (1 << (c / 2))) acc[c] += __shfl_xor(acc[c], off, 64);
   if (gl != 0) return;
   // times i k / (4 pi): (re, im) -> (-im, re) k / (4 pi)
   const double f = k * kInv4Pi;
   const int o = tr.out_index;
-  if constexpr (L & 1) {
-    const double vr = -acc[1] * f, vi = acc[0] * f;
-    out_s[2 * o] = accumulate ? out_s[2 * o] + vr : vr;
-    out_s[2 * o + 1] = accumulate ? out_s[2 * o + 1] + vi : vi;
-  }
-  if constexpr (L & 2) {
-    const double vr = -acc[3] * f, vi = acc[2] * f;
-    out_d[2 * o] = accumulate ? out_d[2 * o] + vr : vr;
-    out_d[2 * o + 1] = accumulate ? out_d[2 * o + 1] + vi : vi;
+  double *const outs[3] = {out_s, out_d, out_t};
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (!(L & (1 << l))) continue;
+    double *out = outs[l];
+    const double vr = -acc[2 * l + 1] * f, vi = acc[2 * l] * f;
+    out[2 * o] = accumulate ? out[2 * o] + vr : vr;
+    out[2 * o + 1] = accumulate ? out[2 * o + 1] + vi : vi;
   }
 }
 
 template <int L, int G, int U>
 hipError_t launch_helm_lgu(const tsqbx_geometry *g, int p, double k, const HelmStage &st,
-                           double *out_s, double *out_d, bool acc, const Tuning &tn,
-                           hipStream_t s) {
+                           const Outputs &o, bool acc, const Tuning &tn, hipStream_t s) {
   constexpr int TPW = 64 / G;
   const int64_t per_block = (int64_t)tn.waves_per_block * TPW;
   const int64_t blocks = (g->n_targets + per_block - 1) / per_block;
   if (blocks <= 0) return hipSuccess;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_helm_eval<L, G, U>), dim3((unsigned)blocks),
-                     dim3(64 * tn.waves_per_block), 0, s, g->tgt, g->n_targets, g->idx, st.rec,
-                     st.tab, p, k, (uint32_t)g->n_sources, out_s, out_d, acc ? 1 : 0,
-                     tn.xcd_remap);
+                     dim3(64 * tn.waves_per_block), 0, s, g->tgt, g->tgt_nrm, g->n_targets,
+                     g->idx, st.rec, st.tab, st.tabs, p, k, (uint32_t)g->n_sources, o.s, o.d, o.t,
+                     acc ? 1 : 0, tn.xcd_remap);
   return hipGetLastError();
 }
 
 template <int G, int U>
 hipError_t launch_helm_gu(const tsqbx_geometry *g, int p, unsigned layers, double k,
-                          const HelmStage &st, double *out_s, double *out_d, bool acc,
-                          const Tuning &tn, hipStream_t s) {
+                          const HelmStage &st, const Outputs &o, bool acc, const Tuning &tn,
+                          hipStream_t s) {
   switch (layers) {
-    case 1: return launch_helm_lgu<1, G, U>(g, p, k, st, out_s, out_d, acc, tn, s);
-    case 2: return launch_helm_lgu<2, G, U>(g, p, k, st, out_s, out_d, acc, tn, s);
-    case 3: return launch_helm_lgu<3, G, U>(g, p, k, st, out_s, out_d, acc, tn, s);
+    case 1: return launch_helm_lgu<1, G, U>(g, p, k, st, o, acc, tn, s);
+    case 2: return launch_helm_lgu<2, G, U>(g, p, k, st, o, acc, tn, s);
+    case 3: return launch_helm_lgu<3, G, U>(g, p, k, st, o, acc, tn, s);
+    case 4: return launch_helm_lgu<4, G, U>(g, p, k, st, o, acc, tn, s);
+    case 5: return launch_helm_lgu<5, G, U>(g, p, k, st, o, acc, tn, s);
+    case 6: return launch_helm_lgu<6, G, U>(g, p, k, st, o, acc, tn, s);
+    case 7: return launch_helm_lgu<7, G, U>(g, p, k, st, o, acc, tn, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -356,9 +439,11 @@ hipError_t launch_helm_gu(const tsqbx_geometry *g, int p, unsigned layers, doubl
 }  // namespace
 
 hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k,
-                            const double *d_sigma, const HelmStage &st, double *out_s,
-                            double *out_d, bool accumulate, const Tuning &tn, hipStream_t s) {
+                            const double *d_sigma, const HelmStage &st, const Outputs &out,
+                            bool accumulate, const Tuning &tn, hipStream_t s) {
   if (!tuning_supported(tn)) return hipErrorInvalidValue;
+  // S' needs the target normals and the geometry's S' table
+  if ((layers & TSQBX_SPRIME) && (!g->tgt_nrm || !st.tabs)) return hipErrorInvalidValue;
   const int64_t n = g->n_sources, T = g->n_targets;
   {
     const int64_t blocks = std::min<int64_t>((n + 1 + 255) / 256, 65536);
@@ -369,15 +454,15 @@ hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, dou
   }
   if (T <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_helm_table, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g->tgt, T,
-                     k, p, st.tab);
+                     k, p, st.tab, (layers & TSQBX_SPRIME) ? st.tabs : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the pair kernel keeps at most two pairs in flight
   const int G = tn.group_lanes, U = std::min(tn.unroll, 2);
-  if (G == 64 && U == 1) return launch_helm_gu<64, 1>(g, p, layers, k, st, out_s, out_d, accumulate, tn, s);
-  if (G == 64) return launch_helm_gu<64, 2>(g, p, layers, k, st, out_s, out_d, accumulate, tn, s);
-  if (G == 32) return launch_helm_gu<32, 2>(g, p, layers, k, st, out_s, out_d, accumulate, tn, s);
-  return launch_helm_gu<16, 2>(g, p, layers, k, st, out_s, out_d, accumulate, tn, s);
+  if (G == 64 && U == 1) return launch_helm_gu<64, 1>(g, p, layers, k, st, out, accumulate, tn, s);
+  if (G == 64) return launch_helm_gu<64, 2>(g, p, layers, k, st, out, accumulate, tn, s);
+  if (G == 32) return launch_helm_gu<32, 2>(g, p, layers, k, st, out, accumulate, tn, s);
+  return launch_helm_gu<16, 2>(g, p, layers, k, st, out, accumulate, tn, s);
 }
 
 }  // namespace tsqbx

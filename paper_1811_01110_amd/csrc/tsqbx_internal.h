@@ -47,10 +47,13 @@ struct Outputs {
 
 // Helmholtz staging of one geometry (allocated by its first Helmholtz call):
 // rec[2i] = (x, y, z, Re q), rec[2i+1] = (Im q, nu), i = 0..N (N: padding);
-// tab: (2n+1) j_n(k |t - c|) per device-order target, rows of p + 1.
+// tab: (2n+1) j_n(k |t - c|) per device-order target, rows of p + 1;
+// tabs (allocated by the first S' call): (2n+1) k j_n'(k |t - c|) and
+// (2n+1) j_n(k |t - c|) / |t - c|, rows of 2 (p + 1).
 struct HelmStage {
   double4 *rec = nullptr;  // [2 (N + 1)]
   double *tab = nullptr;   // [T (TSQBX_P_MAX + 1)]
+  double *tabs = nullptr;  // [T 2 (TSQBX_P_MAX + 1)] or null
 };
 
 struct Tuning {
@@ -117,8 +120,8 @@ bool tuning_supported(const Tuning &tn);
 // interleaved), the per-target table and the pair kernel; outputs complex,
 // interleaved, in the caller's target order.
 hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k,
-                            const double *d_sigma, const HelmStage &st, double *out_s,
-                            double *out_d, bool accumulate, const Tuning &tn, hipStream_t s);
+                            const double *d_sigma, const HelmStage &st, const Outputs &out,
+                            bool accumulate, const Tuning &tn, hipStream_t s);
 
 // Staging of many items in one launch (batched and served paths).
 struct StageItem {         // 64 bytes

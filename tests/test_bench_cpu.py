@@ -63,3 +63,8 @@ def test_helmholtz_flop_model():
     # the double layer: 5 + 8 + 13 + 17 per further order + 30
     assert bench.helm_flops_per_pair(16, 3) == bench.helm_flops_per_pair(16, 1) + 5 + 8 + 13 + 15 * 17 + 30
     assert bench.helm_flops_per_pair(0, 1) == 27 + S + 8 + 2 + 8
+    # S': P_n' 3 per further order, nu_t . d 5, n = 0 2, n = 1 9, 11 per further order, 17
+    assert bench.helm_flops_per_pair(16, 4) == 27 + S + 8 + 15 * 8 + 15 * 3 + 5 + 2 + 9 + 15 * 11 + 17
+    assert (bench.helm_flops_per_pair(16, 7)
+            == bench.helm_flops_per_pair(16, 3) + 5 + 2 + 9 + 15 * 11 + 17)
+    assert bench.helm_flops_per_pair(0, 4) == 27 + S + 8 + 5 + 2 + 17

@@ -1,6 +1,7 @@
-"""Helmholtz target-specific expansions on the GPU against the Helmholtz oracle,
-element by element, through the C ABI (bar: 1e-12 of the per-target sum of
-term moduli, and 1e-12 of the largest output)."""
+"""Helmholtz target-specific expansions (single layer, double layer and S') on
+the GPU against the Helmholtz oracle, element by element, through the C ABI
+(bar: 1e-12 of the per-target sum of term moduli, and 1e-12 of the largest
+output)."""
 import numpy as np
 import pytest
 
@@ -24,58 +25,64 @@ def _sigma(n, seed):
     return rng.standard_normal(n) + 1j * rng.standard_normal(n)
 
 
+ALL = api.SLP | api.DLP | api.SPRIME
+
+
 def _check(ctx, g, k, p, layers, sigma, select=None, what=""):
     geom = ctx.geometry(g)
-    s, d = ctx.eval_helmholtz(geom, sigma, p, layers, k)
+    out = ctx.eval_helmholtz(geom, sigma, p, layers, k)
     ref = H.evaluate_geometry(g, k, sigma, p=p, layers=layers, select=select)
     sel = slice(None) if select is None else select
-    if layers & api.SLP:
-        assert_parity(s[sel], ref["slp"], ref["abs_slp"], what=f"{what} slp")
-    if layers & api.DLP:
-        assert_parity(d[sel], ref["dlp"], ref["abs_dlp"], what=f"{what} dlp")
+    for o, bit, key in zip(out, (api.SLP, api.DLP, api.SPRIME), ("slp", "dlp", "sprime")):
+        if layers & bit:
+            assert_parity(o[sel], ref[key], ref["abs_" + key], what=f"{what} {key}")
+        else:
+            assert o is None
     geom.close()
-    return s, d
+    return out
 
 
 @pytest.mark.parametrize("p", [0, 1, 2, 3, 5, 8, 12, 16, 24, 32])
 @pytest.mark.parametrize("k", [0.5, 3.0, 20.0])
 def test_orders_and_wavenumbers(ctx, p, k):
     g = W.fuzz_geometry(800 + p, n=250, m=50, max_list=120, p=p, layers=3, targets_per_center=2)
-    _check(ctx, g, k, p, 3, _sigma(g.n_sources, p), what=f"p={p} k={k}")
+    _check(ctx, g, k, p, ALL, _sigma(g.n_sources, p), what=f"p={p} k={k}")
 
 
-def test_layers_separately_share_the_single_layer_bits(ctx):
+def test_layer_masks_share_bits(ctx):
+    """Every layer is computed the same way whichever others are requested."""
     g = W.fuzz_geometry(850, n=600, m=100, max_list=300, p=16, layers=3)
     sig = _sigma(g.n_sources, 1)
-    s3, d3 = _check(ctx, g, 20.0, 16, 3, sig, what="both")
-    s1, _ = _check(ctx, g, 20.0, 16, 1, sig, what="slp")
-    _, d2 = _check(ctx, g, 20.0, 16, 2, sig, what="dlp")
-    assert np.array_equal(s1, s3)
-    assert np.array_equal(d2, d3)
+    full = _check(ctx, g, 20.0, 16, ALL, sig, what="all")
+    for layers in range(1, 7):
+        out = _check(ctx, g, 20.0, 16, layers, sig, what=f"mask {layers}")
+        for i, bit in enumerate((api.SLP, api.DLP, api.SPRIME)):
+            if layers & bit:
+                assert np.array_equal(out[i], full[i]), (layers, bit)
 
 
 def test_large_and_tiny_k_rho(ctx):
     """k rho > p + 1 takes the upward recurrence for j_n; targets 1e-4 from
     their centers at p = 32 take Miller's recurrence through its rescaling."""
     g = W.fuzz_geometry(851, n=300, m=60, max_list=150, p=4, layers=3)
-    _check(ctx, g, 100.0, 4, 3, _sigma(g.n_sources, 2), what="k=100 p=4")
+    _check(ctx, g, 100.0, 4, ALL, _sigma(g.n_sources, 2), what="k=100 p=4")
     h = W.fuzz_geometry(852, n=300, m=60, max_list=150, p=32, layers=3)
     rng = np.random.default_rng(3)
     off = rng.standard_normal((h.n_targets, 3))
     h.targets = h.centers[h.target_center] + 1e-4 * off / np.linalg.norm(off, axis=1)[:, None]
-    _check(ctx, h, 1.0, 32, 3, _sigma(h.n_sources, 4), what="rho=1e-4 p=32")
+    _check(ctx, h, 1.0, 32, ALL, _sigma(h.n_sources, 4), what="rho=1e-4 p=32")
 
 
 def test_target_at_center_and_edge_lists(ctx):
     g = W.fuzz_geometry(853, n=200, m=40, max_list=60, p=9, layers=3, targets_per_center=2)
     g.targets[:7] = g.centers[g.target_center[:7]]
-    _check(ctx, g, 5.0, 9, 3, _sigma(g.n_sources, 5), what="t=c")
+    _check(ctx, g, 5.0, 9, ALL, _sigma(g.n_sources, 5), what="t=c")
     off = np.zeros(g.n_centers + 1, dtype=np.int64)
     e = W.Geometry(g.sources, g.weights, g.normals, g.centers, off, np.zeros(0, dtype=np.int32),
-                   g.targets, g.target_center, g.sigma, 9, 3)
+                   g.targets, g.target_center, g.sigma, 9, 3, target_normals=g.target_normals)
     geom = ctx.geometry(e)
-    s, d = ctx.eval_helmholtz(geom, _sigma(g.n_sources, 6), 9, 3, 5.0)
-    assert np.all(s == 0) and np.all(d == 0)
+    out = ctx.eval_helmholtz(geom, _sigma(g.n_sources, 6), 9, ALL, 5.0)
+    assert all(np.all(o == 0) for o in out)
     geom.close()
 
 
@@ -84,7 +91,7 @@ def test_config_b_full_size_sampled(ctx):
     sig = _sigma(g.n_sources, 7)
     rng = np.random.default_rng(8)
     sel = np.sort(rng.choice(g.n_targets, 128, replace=False))
-    _check(ctx, g, 20.0, 16, 3, sig, select=sel, what="B k=20")
+    _check(ctx, g, 20.0, 16, ALL, sig, select=sel, what="B k=20")
 
 
 def test_async_accumulate_and_tuning_variants(ctx):
@@ -93,29 +100,34 @@ def test_async_accumulate_and_tuning_variants(ctx):
     g = W.fuzz_geometry(854, n=1500, m=250, max_list=500, p=12, layers=3)
     geom = ctx.geometry(g)
     sig = _sigma(g.n_sources, 9)
-    ref = H.evaluate_geometry(g, 8.0, sig, p=12, layers=3)
-    s_host, d_host = ctx.eval_helmholtz(geom, sig, 12, 3, 8.0)
+    ref = H.evaluate_geometry(g, 8.0, sig, p=12, layers=ALL)
+    host = ctx.eval_helmholtz(geom, sig, 12, ALL, 8.0)
     ts = torch.tensor(sig, device="cuda", dtype=torch.complex128)
-    os_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
-    od_ = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
-    ctx.eval_helmholtz_async(geom, ts, 12, 3, 8.0, os_, od_)
+    dev = [torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128) for _ in range(3)]
+    ctx.eval_helmholtz_async(geom, ts, 12, ALL, 8.0, *dev)
     torch.cuda.synchronize()
-    assert np.array_equal(os_.cpu().numpy(), s_host)
-    assert np.array_equal(od_.cpu().numpy(), d_host)
-    ctx.eval_helmholtz_async(geom, ts, 12, 3, 8.0, os_, od_, flags=api.ACCUMULATE)
+    for o, h in zip(dev, host):
+        assert np.array_equal(o.cpu().numpy(), h)
+    ctx.eval_helmholtz_async(geom, ts, 12, ALL, 8.0, *dev, flags=api.ACCUMULATE)
     torch.cuda.synchronize()
-    assert np.array_equal(os_.cpu().numpy(), s_host + s_host)
+    for o, h in zip(dev, host):
+        assert np.array_equal(o.cpu().numpy(), h + h)
+    acc = [h.copy() for h in host]
+    ctx.eval_helmholtz(geom, sig, 12, ALL, 8.0, *acc, flags=api.ACCUMULATE)
+    for o, h in zip(acc, host):
+        assert np.array_equal(o, h + h)
     mean = max(geom.pairs // geom.n_targets, 1)
+    keys = ("slp", "dlp", "sprime")
     base = None
     for G, U in ((64, 1), (64, 2), (32, 2), (16, 2)):
         for w in (1, 4):
-            ctx.set_tuning(12, 3 | api.HELMHOLTZ, mean, group_lanes=G, unroll=U, waves_per_block=w)
-            s, d = ctx.eval_helmholtz(geom, sig, 12, 3, 8.0)
-            assert_parity(s, ref["slp"], ref["abs_slp"], what=f"G{G}U{U}w{w}")
-            assert_parity(d, ref["dlp"], ref["abs_dlp"], what=f"G{G}U{U}w{w}")
+            ctx.set_tuning(12, ALL | api.HELMHOLTZ, mean, group_lanes=G, unroll=U, waves_per_block=w)
+            out = ctx.eval_helmholtz(geom, sig, 12, ALL, 8.0)
+            for o, key in zip(out, keys):
+                assert_parity(o, ref[key], ref["abs_" + key], what=f"G{G}U{U}w{w} {key}")
             if G == 64:
-                base = (s, d) if base is None else base
-                assert np.array_equal(s, base[0]) and np.array_equal(d, base[1])
+                base = out if base is None else base
+                assert all(np.array_equal(a, b) for a, b in zip(out, base))
     geom.close()
 
 
@@ -123,7 +135,7 @@ def test_rejects_bad_requests(ctx):
     g = W.fuzz_geometry(855, n=50, m=10, max_list=20, p=4, layers=1)
     sig = _sigma(g.n_sources, 10)
     geom = ctx.geometry(g)
-    for layers, k, code in ((api.SPRIME, 1.0, -1), (1, 0.0, -2), (1, -3.0, -2),
+    for layers, k, code in ((8, 1.0, -1), (1, 0.0, -2), (1, -3.0, -2),
                             (1, float("inf"), -2), (0, 1.0, -1)):
         with pytest.raises(api.TsqbxError) as ei:
             ctx.eval_helmholtz(geom, sig, 4, layers, k)
@@ -136,5 +148,11 @@ def test_rejects_bad_requests(ctx):
     geom = ctx.geometry(g)
     with pytest.raises(api.TsqbxError) as ei:
         ctx.eval_helmholtz(geom, sig, 4, api.DLP, 1.0)
+    assert ei.value.code == -1
+    geom.close()
+    g.target_normals = None
+    geom = ctx.geometry(g)
+    with pytest.raises(api.TsqbxError) as ei:
+        ctx.eval_helmholtz(geom, sig, 4, api.SPRIME, 1.0)
     assert ei.value.code == -1
     geom.close()
