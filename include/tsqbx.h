@@ -218,6 +218,26 @@ int tsqbx_ball_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *d_sources,
                      int64_t *d_offsets, int32_t *d_indices, int64_t capacity, int64_t *nnz,
                      void *hip_stream);
 
+/* Nearest-neighbour near-field lists on the device: for every center c the
+ * d_counts[c] sources nearest to c (the near-field source set of Sec. 3.3,
+ * taken as the k_c nearest sources), in ascending source index.  "Nearest"
+ * is the order of (d2, source index) with d2 formed in FP64 exactly as for
+ * tsqbx_ball_lists, so equal distances go to the smaller index and the
+ * result is unique.
+ *
+ * d_counts [M] (int32, device): 0 <= k_c <= min(N, 8192), else
+ * TSQBX_E_RANGE.  Offsets, capacity and nnz as for tsqbx_ball_lists
+ * (nnz = sum of the counts).  The call allocates its own scratch (about
+ * 56 N bytes plus a hash table of 2N to 4N cells x 28 bytes) and returns
+ * when the lists are written.  Work grows with the number of grid cells
+ * between a center and its k_c-th neighbour, so centers far from every
+ * source are slow (never wrong).
+ * ------------------------------------------------------------------------- */
+int tsqbx_knn_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *d_sources,
+                    int64_t n_centers, const double *d_centers, const int32_t *d_counts,
+                    int64_t *d_offsets, int32_t *d_indices, int64_t capacity, int64_t *nnz,
+                    void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Launch tuning.  A target's result depends only on its list, whether the
  * single layer is evaluated alone (it then runs its own recurrence; with DLP or

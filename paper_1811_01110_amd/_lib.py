@@ -94,6 +94,8 @@ _SIGNATURES = {
                                            c_void_p, c_void_p, c_void_p, c_uint, c_void_p]),
     "tsqbx_ball_lists": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_double,
                                  c_void_p, c_void_p, c_int64, P(c_int64), c_void_p]),
+    "tsqbx_knn_lists": (c_int, [c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_int64, P(c_int64), c_void_p]),
     "tsqbx_get_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_set_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_uint, P(Tuning), P(c_double)]),

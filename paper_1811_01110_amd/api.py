@@ -216,12 +216,7 @@ class Context:
         torch tensors (offsets int64 [M+1], indices int32 [nnz]) on the device."""
         import torch
 
-        def dev(a):
-            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
-            t = t.to(device=f"cuda:{self.device}", dtype=torch.float64).contiguous()
-            return t.reshape(-1, 3) if t.numel() else t.reshape(0, 3)
-
-        src, ctr = dev(sources), dev(centers)
+        src, ctr = self._points(sources), self._points(centers)
         M = ctr.shape[0]
         offsets = torch.empty(M + 1, device=src.device, dtype=torch.int64)
         cap = int(capacity) if capacity is not None else 0
@@ -238,6 +233,38 @@ class Context:
             _check(rc)
             return offsets, idx[:nnz.value]
         raise TsqbxError(L.E_RANGE, "lists did not fit after resizing")
+
+    def knn_lists(self, sources, centers, counts, stream=None):
+        """Near-field lists on the device: for each center c, the counts[c]
+        nearest sources (ties to the smaller index), ascending (CSR).  sources /
+        centers as for ball_lists; counts (M,) integers, numpy or a CUDA
+        tensor.  Returns torch tensors (offsets int64 [M+1], indices int32)."""
+        import torch
+
+        src, ctr = self._points(sources), self._points(centers)
+        M = ctr.shape[0]
+        cnt = counts if isinstance(counts, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(counts, dtype=np.int32))
+        cnt = cnt.to(device=src.device, dtype=torch.int32).contiguous()
+        if cnt.numel() != M:
+            raise ValueError(f"counts has {cnt.numel()} entries, expected {M}")
+        cap = int(cnt.to(torch.int64).sum().item()) if M else 0
+        offsets = torch.empty(M + 1, device=src.device, dtype=torch.int64)
+        idx = torch.empty(max(cap, 1), device=src.device, dtype=torch.int32)
+        nnz = ctypes.c_int64()
+        _check(_lib().tsqbx_knn_lists(self.handle, src.shape[0], src.data_ptr() if src.numel() else None,
+                                      M, ctr.data_ptr() if M else None, cnt.data_ptr() if M else None,
+                                      offsets.data_ptr(), idx.data_ptr(), max(cap, 0),
+                                      ctypes.byref(nnz), _stream_handle(stream)))
+        return offsets, idx[:nnz.value]
+
+    def _points(self, a):
+        """(n, 3) float64 points on this context's device (copied if needed)."""
+        import torch
+
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        t = t.to(device=f"cuda:{self.device}", dtype=torch.float64).contiguous()
+        return t.reshape(-1, 3) if t.numel() else t.reshape(0, 3)
 
     # -- tuning -------------------------------------------------------------
     def get_tuning(self, p: int, layers: int, mean_list: int) -> dict:

@@ -189,17 +189,13 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent kernels keep two pairs in flight
   if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
   if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, 3u, mean_list);
-  const int TPW = 64 / pl->tn.group_lanes;
 
   // item order: largest first
   std::vector<int64_t> ord(n_items);
   std::iota(ord.begin(), ord.end(), 0);
   std::vector<double> icost(n_items);
-  double total = 0;
-  for (int64_t i = 0; i < n_items; ++i) {
+  for (int64_t i = 0; i < n_items; ++i)
     icost[i] = (double)pl->items[i].geom->pairs * pair_cost(pl->items[i].p, pl->items[i].layers);
-    total += icost[i];
-  }
   std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return icost[a] > icost[b]; });
 
   // static schedule over the resident waves

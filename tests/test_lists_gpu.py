@@ -122,3 +122,102 @@ def test_lists_feed_a_geometry(ctx):
     a = ctx.eval(ctx.geometry(g), g.sigma, 16, 3)
     b = ctx.eval(ctx.geometry(h), g.sigma, 16, 3)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---- k nearest -------------------------------------------------------------
+
+def _knn(ctx, src, ctr, counts):
+    off, idx = ctx.knn_lists(src, ctr, counts)
+    return off.cpu().numpy(), idx.cpu().numpy()
+
+
+@pytest.mark.parametrize("kmax", [1, 40, 600, 8192])
+def test_knn_random_cloud_equals_brute_force(ctx, kmax):
+    rng = np.random.default_rng(kmax)
+    src = rng.uniform(-1, 1, (9000, 3))
+    ctr = rng.uniform(-1.3, 1.3, (500, 3))
+    counts = rng.integers(0, kmax + 1, 500)
+    counts[:2] = [0, kmax]
+    off, idx = _knn(ctx, src, ctr, counts)
+    ref_off, ref_idx = LO.knn_lists(src, ctr, counts)
+    assert np.array_equal(off, ref_off)
+    assert np.array_equal(idx, ref_idx)
+
+
+def test_knn_surface_points_and_every_source(ctx):
+    """Sources on a sphere (the workloads' shape), counts up to all sources."""
+    from paper_1811_01110_amd import workloads as W
+
+    rng = np.random.default_rng(21)
+    src = W.random_sphere_points(6000, rng)
+    ctr = 0.97 * W.random_sphere_points(300, rng)
+    counts = np.exp(rng.uniform(0, np.log(6000), 300)).astype(np.int64)
+    counts[:3] = [6000, 5999, 1]
+    off, idx = _knn(ctx, src, ctr, counts)
+    ref_off, ref_idx = LO.knn_lists(src, ctr, counts)
+    assert np.array_equal(off, ref_off) and np.array_equal(idx, ref_idx)
+
+
+def test_knn_exact_ties_go_to_the_smaller_index(ctx):
+    g = np.arange(-6, 7) / 8.0
+    src = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    src = src[np.random.default_rng(22).permutation(len(src))]  # ties across index order
+    ctr = src[::29].copy()
+    counts = np.resize([1, 7, 19, 27, 33, 81, 125, 1000, 2197], len(ctr))
+    off, idx = _knn(ctx, src, ctr, counts)
+    ref_off, ref_idx = LO.knn_lists(src, ctr, counts)
+    assert np.array_equal(off, ref_off) and np.array_equal(idx, ref_idx)
+
+
+def test_knn_degenerate_inputs(ctx):
+    src = np.tile([[0.3, -0.2, 0.1]], (5000, 1))  # every source in one point
+    ctr = np.array([[0.3, -0.2, 0.1], [9.0, 9.0, 9.0], [0.0, 0.0, 0.0]])
+    counts = [5000, 300, 0]
+    off, idx = _knn(ctx, src, ctr, counts)
+    ref_off, ref_idx = LO.knn_lists(src, ctr, counts)
+    assert np.array_equal(off, ref_off) and np.array_equal(idx, ref_idx)
+    off, idx = _knn(ctx, src, np.zeros((0, 3)), np.zeros(0, dtype=np.int32))
+    assert list(off) == [0] and idx.size == 0
+    off, idx = _knn(ctx, np.zeros((0, 3)), ctr, [0, 0, 0])
+    assert list(off) == [0, 0, 0, 0] and idx.size == 0
+
+
+def test_knn_config_d_scaled_equals_the_workload_lists(ctx):
+    """Config D's lists (k-d tree on the host; continuous points, so no ties)
+    rebuilt on the device: identical CSR."""
+    from paper_1811_01110_amd import workloads as W
+
+    g = W.config_d(n_geometries=1, scale=8)[0]
+    counts = np.diff(g.list_offsets)
+    off, idx = _knn(ctx, g.sources, g.centers, counts)
+    assert np.array_equal(off, g.list_offsets)
+    assert np.array_equal(idx, g.list_sources)
+
+
+def test_knn_rejects_bad_counts(ctx):
+    import torch
+
+    rng = np.random.default_rng(23)
+    src = torch.tensor(rng.uniform(-1, 1, (3000, 3)), device="cuda", dtype=torch.float64)
+    ctr = torch.tensor(rng.uniform(-1, 1, (4, 3)), device="cuda", dtype=torch.float64)
+    off = torch.empty(5, device="cuda", dtype=torch.int64)
+    idx = torch.empty(20000, device="cuda", dtype=torch.int32)
+    nnz = ctypes.c_int64(-1)
+    lib = L.load()
+    stream = torch.cuda.current_stream().cuda_stream
+    for bad in ([5, 5, -1, 5], [5, 3001, 5, 5]):
+        cnt = torch.tensor(bad, device="cuda", dtype=torch.int32)
+        rc = lib.tsqbx_knn_lists(ctx.handle, 3000, src.data_ptr(), 4, ctr.data_ptr(),
+                                 cnt.data_ptr(), off.data_ptr(), idx.data_ptr(), 20000,
+                                 ctypes.byref(nnz), stream)
+        assert rc == L.E_RANGE, bad
+    big = torch.zeros((9000, 3), device="cuda", dtype=torch.float64)
+    cnt = torch.tensor([8193, 1, 1, 1], device="cuda", dtype=torch.int32)
+    rc = lib.tsqbx_knn_lists(ctx.handle, 9000, big.data_ptr(), 4, ctr.data_ptr(), cnt.data_ptr(),
+                             off.data_ptr(), idx.data_ptr(), 20000, ctypes.byref(nnz), stream)
+    assert rc == L.E_RANGE
+    cnt = torch.tensor([100, 200, 300, 400], device="cuda", dtype=torch.int32)
+    rc = lib.tsqbx_knn_lists(ctx.handle, 3000, src.data_ptr(), 4, ctr.data_ptr(), cnt.data_ptr(),
+                             off.data_ptr(), idx.data_ptr(), 999, ctypes.byref(nnz), stream)
+    assert rc == L.E_RANGE and nnz.value == 1000
+    assert list(off.cpu().numpy()) == [0, 100, 300, 600, 1000]
