@@ -415,7 +415,8 @@ def bench_helmholtz(ctx, api, torch, g, geom, steps, warmup, k=20.0, p=16):
 def bench_lists(ctx, api, torch, g, steps, with_host=True):
     """Near-field ball lists of the headline workload (262144 sources, 65536
     centers, r = 0.15) built on the device, against the host grid generator
-    that produced the workload's lists."""
+    that produced the workload's lists; then the k-nearest lists of one
+    config D geometry against the host k-d tree."""
     src = torch.tensor(g.sources, device="cuda", dtype=torch.float64)
     ctr = torch.tensor(g.centers, device="cuda", dtype=torch.float64)
     off, idx = ctx.ball_lists(src, ctr, 0.15)  # sizes the output, warms up
@@ -432,14 +433,41 @@ def bench_lists(ctx, api, torch, g, steps, with_host=True):
            "entries": cap, "ms_per_build": dt * 1e3, "entries_per_s": cap / dt,
            "same_as_host_generator": bool(np.array_equal(off.cpu().numpy(), g.list_offsets)
                                           and np.array_equal(idx.cpu().numpy(), g.list_sources))}
-    if with_host:
-        from paper_1811_01110_amd import workloads as W
+    from paper_1811_01110_amd import workloads as W
 
+    if with_host:
         log("timing the host grid generator once")
         t0 = time.perf_counter()
         W.csr_ball(g.centers, g.sources, 0.15)
         res["host_generator_s"] = time.perf_counter() - t0
         res["host_generator_threads"] = min(16, os.cpu_count() or 1)
+    # k nearest: one geometry of config D
+    log("generating one config D geometry for the k-nearest lists")
+    d = W.config_d(n_geometries=1)[0]
+    counts = np.diff(d.list_offsets)
+    src = torch.tensor(d.sources, device="cuda", dtype=torch.float64)
+    ctr = torch.tensor(d.centers, device="cuda", dtype=torch.float64)
+    cnt = torch.tensor(counts.astype(np.int32), device="cuda")
+    off, idx = ctx.knn_lists(src, ctr, cnt)  # warm-up
+    torch.cuda.synchronize()
+    log(f"timing device k-nearest lists, {n} builds")
+    t0 = time.perf_counter()
+    for _ in range(n):
+        off, idx = ctx.knn_lists(src, ctr, cnt)
+    torch.cuda.synchronize()
+    dk = (time.perf_counter() - t0) / n
+    knn = {"workload": "k nearest of one config D geometry: 131072 sources on a perturbed "
+                       "sphere, 32768 centers, k log-uniform 100..8000",
+           "entries": int(counts.sum()), "ms_per_build": dk * 1e3,
+           "entries_per_s": float(counts.sum()) / dk,
+           "same_as_host_kdtree": bool(np.array_equal(off.cpu().numpy(), d.list_offsets)
+                                       and np.array_equal(idx.cpu().numpy(), d.list_sources))}
+    if with_host:
+        log("timing the host k-d tree lists once")
+        t0 = time.perf_counter()
+        W.csr_knn(d.centers, d.sources, counts)
+        knn["host_kdtree_s"] = time.perf_counter() - t0
+    res["knn"] = knn
     return res
 
 
