@@ -41,6 +41,16 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def separate_recurrence_flops_per_pair(p: int, layers: int) -> int:
+    """Per-pair FP64 work of evaluating each layer with a recurrence of its
+    own: 6p + 20 for the single layer and 11p + 36 for the double layer
+    (the per-pair estimate of the work the method does, fma = 2).  The kernel
+    shares one recurrence among the layers (flops_per_pair), so this figure
+    exceeds what it executes; it is reported beside the executed rate, never
+    as the roofline's `achieved`."""
+    return (6 * p + 20 if layers & 1 else 0) + (11 * p + 36 if layers & 2 else 0)
+
+
 def flops_per_pair(p: int, layers: int) -> int:
     """FP64 operations per (target, source) pair executed by the evaluation
     kernel (add/mul = 1, fma = 2, the reciprocal-square-root estimate = 1):
@@ -580,6 +590,11 @@ def main():
             "traffic": measured_traffic(),
             "kernel": "k_eval<16, 3, G, U> (+ k_stage)", "event_ms_per_step": ev / args.steps * 1e3,
             "flops_per_pair": flops_per_pair(p, layers),
+            "separate_recurrences": {
+                "flops_per_pair": separate_recurrence_flops_per_pair(p, layers),
+                "tflops": geom.pairs * separate_recurrence_flops_per_pair(p, layers)
+                / (ev / args.steps) / 1e12,
+            },
         },
     }
     if args.only == "headline":

@@ -68,3 +68,12 @@ def test_helmholtz_flop_model():
     assert (bench.helm_flops_per_pair(16, 7)
             == bench.helm_flops_per_pair(16, 3) + 5 + 2 + 9 + 15 * 11 + 17)
     assert bench.helm_flops_per_pair(0, 4) == 27 + S + 8 + 5 + 2 + 17
+
+
+def test_separate_recurrence_figure():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert bench.separate_recurrence_flops_per_pair(16, 3) == (6 * 16 + 20) + (11 * 16 + 36) == 328
+    assert bench.separate_recurrence_flops_per_pair(16, 1) == 116
+    assert bench.separate_recurrence_flops_per_pair(24, 2) == 300
