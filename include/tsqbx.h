@@ -295,6 +295,30 @@ typedef struct {
  * staging).  flags: TSQBX_ACCUMULATE applies to every item. */
 int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items,
                       unsigned flags, tsqbx_plan **out);
+
+/* Batched Helmholtz evaluation (the kernel of tsqbx_eval_helmholtz): one
+ * item per (geometry, p, layers, k) with complex density and outputs,
+ * interleaved (re, im) float64 on the device as for
+ * tsqbx_eval_helmholtz_async.  The plan stages every item's density and
+ * per-target j_n tables and evaluates all items in one persistent launch
+ * (one target per wave), captured into a HIP graph on the first
+ * tsqbx_plan_execute; the result of every item equals
+ * tsqbx_eval_helmholtz_async with group_lanes 64 bit for bit.  Errors as for
+ * tsqbx_eval_helmholtz and tsqbx_plan_create; execute, get_info and destroy
+ * are the plan calls above.  The plan holds per item 64 (N + 1) + 264 T
+ * bytes (and 528 T more for S'). */
+typedef struct {
+  const tsqbx_geometry *geom;
+  int p;
+  unsigned layers;           /* TSQBX_SLP | TSQBX_DLP | TSQBX_SPRIME */
+  double k;                  /* wavenumber, > 0 and finite */
+  const double *d_sigma;     /* [N][2] complex, caller's source order */
+  double *d_out_slp;         /* [T][2] complex, caller's target order */
+  double *d_out_dlp;
+  double *d_out_sprime;
+} tsqbx_helm_item;
+int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_helm_item *items,
+                                unsigned flags, tsqbx_plan **out);
 /* Run every item once on hip_stream (graph replay after the first call). */
 int tsqbx_plan_execute(tsqbx_plan *plan, void *hip_stream);
 int tsqbx_plan_get_info(const tsqbx_plan *plan, tsqbx_plan_info *out);

@@ -53,6 +53,12 @@ class Item(ctypes.Structure):
                 ("d_out_slp", c_void_p), ("d_out_dlp", c_void_p), ("d_out_sprime", c_void_p)]
 
 
+class HelmItem(ctypes.Structure):
+    _fields_ = [("geom", c_void_p), ("p", c_int), ("layers", c_uint), ("k", c_double),
+                ("d_sigma", c_void_p), ("d_out_slp", c_void_p), ("d_out_dlp", c_void_p),
+                ("d_out_sprime", c_void_p)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_items", c_int64), ("n_units", c_int64), ("pairs", c_int64),
                 ("pair_terms", c_int64), ("grid_blocks", c_int), ("waves_per_block", c_int),
@@ -100,6 +106,7 @@ _SIGNATURES = {
     "tsqbx_set_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_uint, P(Tuning), P(c_double)]),
     "tsqbx_plan_create": (c_int, [c_void_p, c_int64, P(Item), c_uint, P(c_void_p)]),
+    "tsqbx_plan_create_helmholtz": (c_int, [c_void_p, c_int64, P(HelmItem), c_uint, P(c_void_p)]),
     "tsqbx_plan_execute": (c_int, [c_void_p, c_void_p]),
     "tsqbx_plan_get_info": (c_int, [c_void_p, P(PlanInfo)]),
     "tsqbx_plan_destroy": (c_int, [c_void_p]),

@@ -67,6 +67,18 @@ def _tensor_ptr(t, n, name):
     return t.data_ptr() if n else None
 
 
+def _complex_ptr(t, n, name):
+    if t is None:
+        return None
+    import torch
+
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t.data_ptr() if n else None
+
+
 def make_desc(sources, weights, normals, centers, list_offsets, list_sources, targets,
               target_center=None, target_normals=None):
     """A tsqbx_geometry_desc plus the arrays it points into (keep both alive)."""
@@ -190,19 +202,8 @@ class Context:
                              out_slp=None, out_dlp=None, out_sprime=None, flags: int = 0,
                              stream=None):
         """Helmholtz evaluation on device tensors (torch complex128)."""
-        import torch
-
-        def ptr(t, n, name):
-            if t is None:
-                return None
-            if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
-                raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor")
-            if t.numel() != n:
-                raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
-            return t.data_ptr() if n else None
-
-        s = ptr(sigma, geom.n_sources, "sigma")
-        outs = [ptr(o, geom.n_targets, name) if layers & bit else None
+        s = _complex_ptr(sigma, geom.n_sources, "sigma")
+        outs = [_complex_ptr(o, geom.n_targets, name) if layers & bit else None
                 for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
                                         ("out_slp", "out_dlp", "out_sprime"))]
         _check(_lib().tsqbx_eval_helmholtz_async(self.handle, geom.handle, int(p), int(layers),
@@ -291,6 +292,11 @@ class Context:
     def plan(self, items: Sequence[dict], flags: int = 0) -> "Plan":
         return Plan(self, items, flags)
 
+    def plan_helmholtz(self, items: Sequence[dict], flags: int = 0) -> "Plan":
+        """A Helmholtz plan: items with geom, p, layers, k, sigma and the
+        outputs as complex128 CUDA tensors."""
+        return Plan(self, items, flags, helmholtz=True)
+
     def server(self, hbm_budget: int, max_slots: int) -> "Server":
         return Server(self, hbm_budget, max_slots)
 
@@ -339,8 +345,9 @@ class Plan:
     out_sprime (device tensors, needed for the requested layers).
     """
 
-    def __init__(self, ctx: Context, items: Sequence[dict], flags: int = 0):
-        arr = (L.Item * len(items))()
+    def __init__(self, ctx: Context, items: Sequence[dict], flags: int = 0, helmholtz: bool = False):
+        arr = ((L.HelmItem if helmholtz else L.Item) * len(items))()
+        ptr = _complex_ptr if helmholtz else _tensor_ptr
         self._keep = list(items)
         for i, it in enumerate(items):
             g = it["geom"]
@@ -348,13 +355,16 @@ class Plan:
             arr[i].geom = g.handle
             arr[i].p = int(it["p"])
             arr[i].layers = lay
-            arr[i].d_sigma = _tensor_ptr(it["sigma"], g.n_sources, "sigma")
-            arr[i].d_out_slp = _tensor_ptr(it.get("out_slp"), g.n_targets, "out_slp") if lay & SLP else None
-            arr[i].d_out_dlp = _tensor_ptr(it.get("out_dlp"), g.n_targets, "out_dlp") if lay & DLP else None
-            arr[i].d_out_sprime = (_tensor_ptr(it.get("out_sprime"), g.n_targets, "out_sprime")
+            if helmholtz:
+                arr[i].k = float(it["k"])
+            arr[i].d_sigma = ptr(it["sigma"], g.n_sources, "sigma")
+            arr[i].d_out_slp = ptr(it.get("out_slp"), g.n_targets, "out_slp") if lay & SLP else None
+            arr[i].d_out_dlp = ptr(it.get("out_dlp"), g.n_targets, "out_dlp") if lay & DLP else None
+            arr[i].d_out_sprime = (ptr(it.get("out_sprime"), g.n_targets, "out_sprime")
                                    if lay & SPRIME else None)
         h = ctypes.c_void_p()
-        _check(_lib().tsqbx_plan_create(ctx.handle, len(items), arr, int(flags), ctypes.byref(h)))
+        create = _lib().tsqbx_plan_create_helmholtz if helmholtz else _lib().tsqbx_plan_create
+        _check(create(ctx.handle, len(items), arr, int(flags), ctypes.byref(h)))
         self.handle = h
         self.ctx = ctx
 

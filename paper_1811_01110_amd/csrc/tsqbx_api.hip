@@ -647,6 +647,16 @@ static int check_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, doub
   return TSQBX_OK;
 }
 
+}  // extern "C"
+
+namespace tsqbx {
+int check_helmholtz_request(const tsqbx_geometry *g, int p, unsigned layers, double k) {
+  return check_helmholtz(g, p, layers, k);
+}
+}  // namespace tsqbx
+
+extern "C" {
+
 // The geometry's Helmholtz staging, allocated on its first Helmholtz call,
 // and its S' table on the first call that asks for S' (calls on one geometry
 // do not overlap, so no lock is needed).

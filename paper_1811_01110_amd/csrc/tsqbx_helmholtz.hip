@@ -328,23 +328,12 @@ __device__ __forceinline__ void helm_pairs(int p, double k, double kinv, uint32_
   }
 }
 
+// One target t (device order) of evaluation v, summed by the G lanes of its
+// group (lane gl of G), and its outputs written.  The plain and the batched
+// kernels both run this, so their results agree bit for bit.
 template <int L, int G, int U>
-__global__ void __launch_bounds__(256)
-k_helm_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm,
-            int64_t n_targets, const int32_t *__restrict__ idx, const double4 *__restrict__ rec,
-            const double *__restrict__ tab, const double *__restrict__ tabs, int p, double k,
-            uint32_t n_src, double *__restrict__ out_s, double *__restrict__ out_d,
-            double *__restrict__ out_t, int accumulate, int remap) {
-  constexpr int TPW = 64 / G;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int wpb = blockDim.x >> 6;
-  const int blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-  int64_t t = ((int64_t)blk * wpb + wave) * TPW + lane / G;
-  if constexpr (G == 64) t = __builtin_amdgcn_readfirstlane((int)t);
-  if (t >= n_targets) return;
-  const TargetRec tr = tgt[t];
-  const int gl = lane % G;
+__device__ __forceinline__ void helm_target(const HelmWorkItem &v, int64_t t, int gl) {
+  const TargetRec tr = v.tgt[t];
   HelmTarget tg;
   tg.cx = tr.c[0];
   tg.cy = tr.c[1];
@@ -356,16 +345,18 @@ k_helm_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm,
   tg.rho_inv = rho > 0.0 ? 1.0 / rho : 0.0;
   tg.nx = tg.ny = tg.nz = tg.ntt = 0.0;
   if constexpr (L & 4) {
-    const double4 nv = tnrm[t];
+    const double4 nv = v.tnrm[t];
     tg.nx = nv.x;
     tg.ny = nv.y;
     tg.nz = nv.z;
     tg.ntt = fma(tg.nz, tg.tz, fma(tg.ny, tg.ty, tg.nx * tg.tx)) * tg.rho_inv;
   }
+  const int p = v.p;
+  const double k = v.k;
   const double kinv = 1.0 / k;
-  const double *row_tab = tab + t * (int64_t)(p + 1);
-  const double *row_tabs = (L & 4) ? tabs + t * (int64_t)(2 * (p + 1)) : nullptr;
-  const int32_t *__restrict__ row = idx + tr.row_begin;
+  const double *row_tab = v.tab + t * (int64_t)(p + 1);
+  const double *row_tabs = (L & 4) ? v.tabs + t * (int64_t)(2 * (p + 1)) : nullptr;
+  const int32_t *__restrict__ row = v.idx + tr.row_begin;
   const int len = tr.row_len;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int c0 = 0;
@@ -375,14 +366,14 @@ k_helm_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm,
       uint32_t s[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) s[u] = load_idx(row, (uint32_t)(c0 + gl + u * G));
-      helm_pairs<L, U>(p, k, kinv, n_src, s, rec, row_tab, row_tabs, tg, acc);
+      helm_pairs<L, U>(p, k, kinv, v.n_src, s, v.rec, row_tab, row_tabs, tg, acc);
     }
   }
   for (; c0 < len; c0 += G) {
     const int j = c0 + gl;
     if (j < len) {
       const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
-      helm_pairs<L, 1>(p, k, kinv, n_src, s1, rec, row_tab, row_tabs, tg, acc);
+      helm_pairs<L, 1>(p, k, kinv, v.n_src, s1, v.rec, row_tab, row_tabs, tg, acc);
     }
   }
 #pragma unroll
@@ -394,14 +385,68 @@ k_helm_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm,
   // times i k / (4 pi): (re, im) -> (-im, re) k / (4 pi)
   const double f = k * kInv4Pi;
   const int o = tr.out_index;
-  double *const outs[3] = {out_s, out_d, out_t};
+  double *const outs[3] = {v.out_s, v.out_d, v.out_t};
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     if (!(L & (1 << l))) continue;
     double *out = outs[l];
     const double vr = -acc[2 * l + 1] * f, vi = acc[2 * l] * f;
-    out[2 * o] = accumulate ? out[2 * o] + vr : vr;
-    out[2 * o + 1] = accumulate ? out[2 * o + 1] + vi : vi;
+    out[2 * o] = v.accumulate ? out[2 * o] + vr : vr;
+    out[2 * o + 1] = v.accumulate ? out[2 * o + 1] + vi : vi;
+  }
+}
+
+template <int L, int G, int U>
+__global__ void __launch_bounds__(256)
+k_helm_eval(HelmWorkItem v, int64_t n_targets, int remap) {
+  constexpr int TPW = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  int64_t t = ((int64_t)blk * wpb + wave) * TPW + lane / G;
+  if constexpr (G == 64) t = __builtin_amdgcn_readfirstlane((int)t);
+  if (t >= n_targets) return;
+  helm_target<L, G, U>(v, t, lane % G);
+}
+
+// The batched Helmholtz kernel: resident waves work through a static
+// schedule of units (runs of consecutive targets of one item), as the
+// Laplace persistent kernel does.  LC: the layer mask shared by every item
+// (1..7), or kLayersAny (a switch over the masks).
+template <int LC, int G, int U>
+__global__ void __launch_bounds__(256) k_helm_persistent(HelmPersistentArgs a) {
+  constexpr int TPW = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * wpb +
+                                               (int)(threadIdx.x >> 6));
+  if (w >= a.n_waves) return;
+  const int ub = a.wave_begin[w], ue = a.wave_begin[w + 1];
+  for (int u = ub; u < ue; ++u) {
+    const int item = __builtin_amdgcn_readfirstlane(a.units[u].item);
+    const int first = __builtin_amdgcn_readfirstlane(a.units[u].first);
+    const int count = __builtin_amdgcn_readfirstlane(a.units[u].count);
+    const HelmWorkItem v = a.items[item];
+    for (int q = 0; q < count; q += TPW) {
+      int slot = q + lane / G;
+      if constexpr (G == 64) slot = __builtin_amdgcn_readfirstlane(slot);
+      if (slot >= count) break;  // whole groups leave together
+      const int64_t t = (int64_t)first + slot;
+      if constexpr (LC != kLayersAny) {
+        helm_target<LC, G, U>(v, t, lane % G);
+      } else {
+        switch (v.layers) {
+          case 1: helm_target<1, G, U>(v, t, lane % G); break;
+          case 2: helm_target<2, G, U>(v, t, lane % G); break;
+          case 3: helm_target<3, G, U>(v, t, lane % G); break;
+          case 4: helm_target<4, G, U>(v, t, lane % G); break;
+          case 5: helm_target<5, G, U>(v, t, lane % G); break;
+          case 6: helm_target<6, G, U>(v, t, lane % G); break;
+          default: helm_target<7, G, U>(v, t, lane % G); break;
+        }
+      }
+    }
   }
 }
 
@@ -413,10 +458,23 @@ hipError_t launch_helm_lgu(const tsqbx_geometry *g, int p, double k, const HelmS
   const int64_t blocks = (g->n_targets + per_block - 1) / per_block;
   if (blocks <= 0) return hipSuccess;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  HelmWorkItem v{};
+  v.tgt = g->tgt;
+  v.tnrm = g->tgt_nrm;
+  v.idx = g->idx;
+  v.rec = st.rec;
+  v.tab = st.tab;
+  v.tabs = st.tabs;
+  v.out_s = o.s;
+  v.out_d = o.d;
+  v.out_t = o.t;
+  v.k = k;
+  v.p = p;
+  v.layers = L;
+  v.accumulate = acc ? 1 : 0;
+  v.n_src = (uint32_t)g->n_sources;
   hipLaunchKernelGGL((k_helm_eval<L, G, U>), dim3((unsigned)blocks),
-                     dim3(64 * tn.waves_per_block), 0, s, g->tgt, g->tgt_nrm, g->n_targets,
-                     g->idx, st.rec, st.tab, st.tabs, p, k, (uint32_t)g->n_sources, o.s, o.d, o.t,
-                     acc ? 1 : 0, tn.xcd_remap);
+                     dim3(64 * tn.waves_per_block), 0, s, v, g->n_targets, tn.xcd_remap);
   return hipGetLastError();
 }
 
@@ -438,11 +496,9 @@ hipError_t launch_helm_gu(const tsqbx_geometry *g, int p, unsigned layers, doubl
 
 }  // namespace
 
-hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k,
-                            const double *d_sigma, const HelmStage &st, const Outputs &out,
-                            bool accumulate, const Tuning &tn, hipStream_t s) {
-  if (!tuning_supported(tn)) return hipErrorInvalidValue;
-  // S' needs the target normals and the geometry's S' table
+hipError_t launch_helm_prepare(const tsqbx_geometry *g, int p, unsigned layers, double k,
+                               const double *d_sigma, const HelmStage &st, hipStream_t s) {
+  // S' needs the target normals and the S' table
   if ((layers & TSQBX_SPRIME) && (!g->tgt_nrm || !st.tabs)) return hipErrorInvalidValue;
   const int64_t n = g->n_sources, T = g->n_targets;
   {
@@ -455,14 +511,51 @@ hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, dou
   if (T <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_helm_table, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, g->tgt, T,
                      k, p, st.tab, (layers & TSQBX_SPRIME) ? st.tabs : nullptr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, double k,
+                            const double *d_sigma, const HelmStage &st, const Outputs &out,
+                            bool accumulate, const Tuning &tn, hipStream_t s) {
+  if (!tuning_supported(tn)) return hipErrorInvalidValue;
+  hipError_t e = launch_helm_prepare(g, p, layers, k, d_sigma, st, s);
+  if (e != hipSuccess || g->n_targets <= 0) return e;
   // the pair kernel keeps at most two pairs in flight
   const int G = tn.group_lanes, U = std::min(tn.unroll, 2);
   if (G == 64 && U == 1) return launch_helm_gu<64, 1>(g, p, layers, k, st, out, accumulate, tn, s);
   if (G == 64) return launch_helm_gu<64, 2>(g, p, layers, k, st, out, accumulate, tn, s);
   if (G == 32) return launch_helm_gu<32, 2>(g, p, layers, k, st, out, accumulate, tn, s);
   return launch_helm_gu<16, 2>(g, p, layers, k, st, out, accumulate, tn, s);
+}
+
+namespace {
+template <int LC>
+hipError_t launch_helm_persistent_l(const HelmPersistentArgs &a, const Tuning &tn,
+                                    hipStream_t s) {
+  const dim3 block(64 * tn.waves_per_block);
+  const int grid = (a.n_waves + tn.waves_per_block - 1) / tn.waves_per_block;
+  if (tn.unroll <= 1)
+    hipLaunchKernelGGL((k_helm_persistent<LC, 64, 1>), dim3(grid), block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_helm_persistent<LC, 64, 2>), dim3(grid), block, 0, s, a);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_helm_persistent(const HelmPersistentArgs &a, unsigned layer_class,
+                                  const Tuning &tn, hipStream_t s) {
+  // the batched Helmholtz kernel runs one target per wave (group_lanes 64)
+  if (!tuning_supported(tn) || tn.group_lanes != 64 || a.n_waves <= 0) return hipErrorInvalidValue;
+  switch (layer_class) {
+    case 1: return launch_helm_persistent_l<1>(a, tn, s);
+    case 2: return launch_helm_persistent_l<2>(a, tn, s);
+    case 3: return launch_helm_persistent_l<3>(a, tn, s);
+    case 4: return launch_helm_persistent_l<4>(a, tn, s);
+    case 5: return launch_helm_persistent_l<5>(a, tn, s);
+    case 6: return launch_helm_persistent_l<6>(a, tn, s);
+    case 7: return launch_helm_persistent_l<7>(a, tn, s);
+    default: return launch_helm_persistent_l<kLayersAny>(a, tn, s);
+  }
 }
 
 }  // namespace tsqbx

@@ -203,6 +203,45 @@ hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int 
                              const Tuning &tn, hipStream_t s);
 int persistent_max_waves(int num_cus);
 
+// One Helmholtz evaluation as the pair kernels read it: a geometry, its
+// Helmholtz staging and table(s), k, p and the complex outputs (null for a
+// layer not requested).  The plain path builds one per launch; a plan keeps
+// one per item on the device.
+struct HelmWorkItem {       // 96 bytes
+  const TargetRec *tgt;
+  const double4 *tnrm;      // target normals (S'), device order
+  const int32_t *idx;
+  const double4 *rec;       // staged records, 2 per source
+  const double *tab;        // (2n+1) j_n(k |t - c|), rows of p + 1
+  const double *tabs;       // S' rows of 2 (p + 1), or null
+  double *out_s;
+  double *out_d;
+  double *out_t;
+  double k;
+  int32_t p;
+  int32_t layers;
+  int32_t accumulate;
+  uint32_t n_src;           // index of the padding record
+};
+static_assert(sizeof(HelmWorkItem) == 96, "HelmWorkItem layout");
+struct HelmPersistentArgs {
+  const HelmWorkItem *items;
+  const WorkUnit *units;
+  const int32_t *wave_begin;  // [n_waves + 1]
+  int32_t n_waves;
+};
+// Staging of the density and the per-target table(s) of one Helmholtz
+// evaluation (before the pair kernel).
+hipError_t launch_helm_prepare(const tsqbx_geometry *g, int p, unsigned layers, double k,
+                               const double *d_sigma, const HelmStage &st, hipStream_t s);
+// The Helmholtz persistent kernel over a plan's units; layer_class as for
+// launch_persistent (1..7 exact masks, or kLayersAny).
+hipError_t launch_helm_persistent(const HelmPersistentArgs &a, unsigned layer_class,
+                                  const Tuning &tn, hipStream_t s);
+// Checks of a Helmholtz request (order, layer mask, k, normals) as
+// tsqbx_eval_helmholtz makes them; TSQBX_OK or the error (message set).
+int check_helmholtz_request(const tsqbx_geometry *g, int p, unsigned layers, double k);
+
 // Static schedule for the persistent kernel: the targets of the items (in the
 // given order, device order within an item) cut into at most max_waves
 // contiguous ranges of about equal estimated cost.
@@ -210,6 +249,7 @@ struct ScheduleItem {
   const tsqbx_geometry *geom;
   int p;
   unsigned layers;
+  bool helmholtz = false;  // costed with the Helmholtz kernel's work per pair
 };
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
                     int group_lanes, int max_waves, std::vector<WorkUnit> *units,

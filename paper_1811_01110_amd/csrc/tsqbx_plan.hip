@@ -1,5 +1,6 @@
 // Batched evaluation: many (geometry, p, layers) items in one persistent
-// kernel launch, captured once into a HIP graph and replayed.
+// kernel launch, captured once into a HIP graph and replayed; the Helmholtz
+// plan does the same for (geometry, p, layers, k) items.
 //
 // The targets of all items, largest item first and in device (Morton) order
 // within an item, are cut into one contiguous range per wave of about equal
@@ -38,6 +39,11 @@ struct tsqbx_plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // Helmholtz plans
+  bool helm = false;
+  std::vector<tsqbx_helm_item> hitems;
+  std::vector<HelmStage> hstages;
+  HelmWorkItem *d_hitems = nullptr;
 };
 
 namespace {
@@ -64,6 +70,12 @@ void free_plan(tsqbx_plan *pl) {
     if (s.posq) (void)hipFree(s.posq);
     if (s.qn) (void)hipFree(s.qn);
   }
+  for (auto &h : pl->hstages) {
+    if (h.rec) (void)hipFree(h.rec);
+    if (h.tab) (void)hipFree(h.tab);
+    if (h.tabs) (void)hipFree(h.tabs);
+  }
+  if (pl->d_hitems) (void)hipFree(pl->d_hitems);
   if (pl->d_items) (void)hipFree(pl->d_items);
   if (pl->d_stage) (void)hipFree(pl->d_stage);
   if (pl->d_units) (void)hipFree(pl->d_units);
@@ -80,6 +92,17 @@ double pair_cost(int p, unsigned layers) {
   if (layers & TSQBX_DLP) setup += 8.0;
   if (layers & TSQBX_SPRIME) setup += 9.0;
   return 4.0 * std::max(p - 1, 0) + setup;
+}
+
+// The same for the Helmholtz kernel: about 85 instructions of setup and
+// sincos, and per order the Legendre and Hankel recurrences with each
+// layer's complex sums.
+double helm_pair_cost(int p, unsigned layers) {
+  double per = 6.0;
+  if (layers & TSQBX_SLP) per += 4.0;
+  if (layers & TSQBX_DLP) per += 12.0;
+  if (layers & TSQBX_SPRIME) per += 8.0;
+  return 85.0 + per * std::max(p - 1, 0);
 }
 
 }  // namespace
@@ -100,7 +123,8 @@ void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<in
   double total = 0.0;
   for (int32_t oi : order) {
     const tsqbx_geometry *g = items[oi].geom;
-    const double pc = pair_cost(items[oi].p, items[oi].layers);
+    const double pc = items[oi].helmholtz ? helm_pair_cost(items[oi].p, items[oi].layers)
+                                          : pair_cost(items[oi].p, items[oi].layers);
     for (int64_t k = 0; k < g->n_targets; k += TPW) {
       const int32_t cnt = (int32_t)std::min<int64_t>(TPW, g->n_targets - k);
       int64_t chunks = 0;
@@ -267,6 +291,129 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   return TSQBX_OK;
 }
 
+int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_helm_item *items,
+                                unsigned flags, tsqbx_plan **out) {
+  if (!ctx || !out || n_items < 0 || (n_items > 0 && !items))
+    return fail(TSQBX_E_INVALID, "plan_create: ctx, out or items is NULL, or n_items < 0");
+  *out = nullptr;
+  if (n_items > 65535) return fail(TSQBX_E_RANGE, "a plan holds at most 65535 items");
+  for (int64_t i = 0; i < n_items; ++i) {
+    const tsqbx_helm_item &it = items[i];
+    if (!it.geom) return fail(TSQBX_E_INVALID, "item %lld: geometry is NULL", (long long)i);
+    if (it.geom->ctx != ctx)
+      return fail(TSQBX_E_INVALID, "item %lld: geometry belongs to another context", (long long)i);
+    int rc = check_helmholtz_request(it.geom, it.p, it.layers, it.k);
+    if (rc != TSQBX_OK) return rc;
+    if (it.geom->n_sources > 0 && !it.d_sigma)
+      return fail(TSQBX_E_INVALID, "item %lld: sigma is NULL", (long long)i);
+    if (it.geom->n_targets > 0 &&
+        (((it.layers & TSQBX_SLP) && !it.d_out_slp) || ((it.layers & TSQBX_DLP) && !it.d_out_dlp) ||
+         ((it.layers & TSQBX_SPRIME) && !it.d_out_sprime)))
+      return fail(TSQBX_E_INVALID, "item %lld: output for a requested layer is NULL", (long long)i);
+  }
+  Guard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+
+  auto *pl = new tsqbx_plan;
+  pl->ctx = ctx;
+  pl->device = ctx->device;
+  pl->helm = true;
+  pl->hitems.assign(items, items + n_items);
+
+  int64_t tot_pairs = 0, tot_targets = 0;
+  int pmax = 0;
+  unsigned lay_all = 0, first = n_items ? items[0].layers : 0;
+  bool same = true;
+  for (auto &it : pl->hitems) {
+    same = same && it.layers == first;
+    tot_pairs += it.geom->pairs;
+    tot_targets += it.geom->n_targets;
+    pmax = std::max(pmax, it.p);
+    lay_all |= it.layers;
+    pl->pairs += it.geom->pairs;
+    pl->pair_terms += it.geom->pairs * (int64_t)(it.p + 1) * layer_count(it.layers);
+  }
+  pl->layer_class = same && first >= 1 && first <= 7 ? first : kLayersAny;
+  const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
+  pl->tn = lookup_tuning(ctx, pmax, (lay_all ? lay_all : 1u) | TSQBX_HELMHOLTZ, mean_list);
+  pl->tn.group_lanes = 64;  // one target per wave
+  pl->tn.unroll = std::min(std::max(pl->tn.unroll, 1), 2);
+  if (!tuning_supported(pl->tn)) pl->tn = Tuning{};
+
+  // item order: largest first; static schedule over the resident waves
+  std::vector<int64_t> ord(n_items);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::vector<double> icost(n_items);
+  for (int64_t i = 0; i < n_items; ++i)
+    icost[i] = (double)pl->hitems[i].geom->pairs * helm_pair_cost(pl->hitems[i].p, pl->hitems[i].layers);
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return icost[a] > icost[b]; });
+  std::vector<ScheduleItem> sched(n_items);
+  for (int64_t i = 0; i < n_items; ++i)
+    sched[i] = ScheduleItem{pl->hitems[i].geom, pl->hitems[i].p, pl->hitems[i].layers, true};
+  std::vector<int32_t> order32(ord.begin(), ord.end());
+  std::vector<WorkUnit> units;
+  std::vector<int32_t> wave_begin;
+  build_schedule(sched, order32, 64, persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256),
+                 &units, &wave_begin);
+  pl->n_units = (int64_t)units.size();
+  pl->n_waves = (int32_t)wave_begin.size() - 1;
+  pl->grid = (pl->n_waves + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block;
+
+  // per-item staging, tables and the device copies of items and units
+  std::vector<HelmWorkItem> witems(n_items);
+  hipError_t e = hipSuccess;
+  pl->hstages.resize(n_items);
+  for (int64_t i = 0; i < n_items && e == hipSuccess; ++i) {
+    const tsqbx_helm_item &it = pl->hitems[i];
+    const tsqbx_geometry *g = it.geom;
+    HelmStage &st = pl->hstages[i];
+    const size_t N1 = (size_t)g->n_sources + 1, T = std::max<size_t>(1, (size_t)g->n_targets);
+    e = hipMalloc((void **)&st.rec, 2 * N1 * sizeof(double4));
+    if (e == hipSuccess) e = hipMalloc((void **)&st.tab, T * (size_t)(it.p + 1) * sizeof(double));
+    if (e == hipSuccess && (it.layers & TSQBX_SPRIME))
+      e = hipMalloc((void **)&st.tabs, 2 * T * (size_t)(it.p + 1) * sizeof(double));
+    pl->device_bytes += 2 * N1 * sizeof(double4) + T * (size_t)(it.p + 1) * sizeof(double) *
+                                                       ((it.layers & TSQBX_SPRIME) ? 3 : 1);
+    HelmWorkItem &w = witems[i];
+    w = HelmWorkItem{};
+    w.tgt = g->tgt;
+    w.tnrm = g->tgt_nrm;
+    w.idx = g->idx;
+    w.rec = st.rec;
+    w.tab = st.tab;
+    w.tabs = st.tabs;
+    w.out_s = it.d_out_slp;
+    w.out_d = it.d_out_dlp;
+    w.out_t = it.d_out_sprime;
+    w.k = it.k;
+    w.p = it.p;
+    w.layers = (int32_t)it.layers;
+    w.accumulate = (flags & TSQBX_ACCUMULATE) ? 1 : 0;
+    w.n_src = (uint32_t)g->n_sources;
+  }
+  if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_hitems, n_items * sizeof(HelmWorkItem));
+  if (e == hipSuccess && n_items)
+    e = hipMemcpy(pl->d_hitems, witems.data(), n_items * sizeof(HelmWorkItem), hipMemcpyHostToDevice);
+  if (e == hipSuccess && pl->n_units)
+    e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
+  if (e == hipSuccess && pl->n_units)
+    e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&pl->d_wave_begin, wave_begin.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->d_wave_begin, wave_begin.data(), wave_begin.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+  pl->device_bytes += n_items * sizeof(HelmWorkItem) + units.size() * sizeof(WorkUnit) +
+                      wave_begin.size() * sizeof(int32_t);
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return fail_hip(e, "plan setup");
+  }
+  *out = pl;
+  return TSQBX_OK;
+}
+
 int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
   if (!pl) return fail(TSQBX_E_INVALID, "plan is NULL");
   Guard dg(pl->device);
@@ -275,10 +422,23 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
     // capture: staging of every item (one kernel), then the persistent kernel
     hipStream_t cs = pl->cap_stream;
     TSQBX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, cs);
-    if (e == hipSuccess && pl->n_units > 0) {
-      PersistentArgs a{pl->d_items, pl->d_units, pl->d_wave_begin, pl->n_waves};
-      e = launch_persistent(a, pl->layer_class, pl->p_all, pl->tn, cs);
+    hipError_t e = hipSuccess;
+    if (pl->helm) {
+      // every item's density and tables, then one persistent launch
+      for (size_t i = 0; i < pl->hitems.size() && e == hipSuccess; ++i) {
+        const tsqbx_helm_item &it = pl->hitems[i];
+        e = launch_helm_prepare(it.geom, it.p, it.layers, it.k, it.d_sigma, pl->hstages[i], cs);
+      }
+      if (e == hipSuccess && pl->n_units > 0) {
+        HelmPersistentArgs a{pl->d_hitems, pl->d_units, pl->d_wave_begin, pl->n_waves};
+        e = launch_helm_persistent(a, pl->layer_class, pl->tn, cs);
+      }
+    } else {
+      e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, cs);
+      if (e == hipSuccess && pl->n_units > 0) {
+        PersistentArgs a{pl->d_items, pl->d_units, pl->d_wave_begin, pl->n_waves};
+        e = launch_persistent(a, pl->layer_class, pl->p_all, pl->tn, cs);
+      }
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -299,7 +459,7 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
 
 int tsqbx_plan_get_info(const tsqbx_plan *pl, tsqbx_plan_info *out) {
   if (!pl || !out) return fail(TSQBX_E_INVALID, "plan or out is NULL");
-  out->n_items = (int64_t)pl->items.size();
+  out->n_items = (int64_t)(pl->helm ? pl->hitems.size() : pl->items.size());
   out->n_units = pl->n_units;
   out->pairs = pl->pairs;
   out->pair_terms = pl->pair_terms;

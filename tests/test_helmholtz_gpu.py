@@ -156,3 +156,84 @@ def test_rejects_bad_requests(ctx):
         ctx.eval_helmholtz(geom, sig, 4, api.SPRIME, 1.0)
     assert ei.value.code == -1
     geom.close()
+
+
+def _plan_items(ctx, torch, specs, seed):
+    """Items (geometry, p, layers, k) on fuzz geometries, complex densities."""
+    items = []
+    for i, (p, lay, k, share) in enumerate(specs):
+        if share:
+            g, geom = items[-1]["g"], items[-1]["geom"]
+        else:
+            g = W.fuzz_geometry(seed + i, n=400 + 60 * i, m=90, max_list=220, p=p, layers=3,
+                                targets_per_center=2)
+            geom = ctx.geometry(g)
+        sig = _sigma(g.n_sources, seed + 100 + i)
+        it = dict(g=g, geom=geom, p=p, layers=lay, k=k, sig=sig,
+                  sigma=torch.tensor(sig, device="cuda", dtype=torch.complex128))
+        for bit, key in ((1, "out_slp"), (2, "out_dlp"), (4, "out_sprime")):
+            if lay & bit:
+                it[key] = torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)
+        items.append(it)
+    return items
+
+
+def test_plan_matches_plain_bits_and_oracle(ctx):
+    """A Helmholtz plan (mixed orders, masks and wavenumbers, two items on one
+    geometry) equals plain evaluations with 64 lanes per target bit for bit,
+    and the oracle to the parity bar; replays with new densities and the
+    accumulate flag behave as for Laplace plans."""
+    import torch
+
+    specs = [(4, 1, 2.0, False), (8, 3, 5.0, False), (12, 4, 10.0, False), (16, 7, 20.0, False),
+             (16, 7, 3.0, True), (5, 2, 1.0, False), (0, 5, 3.0, False), (24, 6, 8.0, False)]
+    items = _plan_items(ctx, torch, specs, 870)
+    plan = ctx.plan_helmholtz(items)
+    assert plan.info()["n_items"] == len(items)
+    keys = ("slp", "dlp", "sprime")
+
+    def check(its, acc=1):
+        for it in its:
+            g, geom = it["g"], it["geom"]
+            mean = max(geom.pairs // geom.n_targets, 1)
+            ctx.set_tuning(it["p"], it["layers"] | api.HELMHOLTZ, mean, group_lanes=64)
+            plain = ctx.eval_helmholtz(geom, it["sig"], it["p"], it["layers"], it["k"])
+            ref = H.evaluate_geometry(g, it["k"], it["sig"], p=it["p"], layers=it["layers"])
+            for bit, key, pl in zip((1, 2, 4), keys, plain):
+                if not it["layers"] & bit:
+                    continue
+                got = it["out_" + key].cpu().numpy()
+                assert np.array_equal(got, acc * pl), (it["p"], it["layers"], key)
+                assert_parity(got / acc, ref[key], ref["abs_" + key], what=f"plan p={it['p']} {key}")
+
+    plan.execute()
+    torch.cuda.synchronize()
+    check(items)
+    rng = np.random.default_rng(5)
+    for it in items:  # new densities, same plan (graph replay)
+        it["sig"] = rng.standard_normal(it["g"].n_sources) + 1j * rng.standard_normal(it["g"].n_sources)
+        it["sigma"].copy_(torch.tensor(it["sig"], dtype=torch.complex128))
+    torch.cuda.synchronize()
+    plan.execute()
+    plan.execute()
+    torch.cuda.synchronize()
+    check(items)
+    plan.close()
+    acc_plan = ctx.plan_helmholtz(items, flags=api.ACCUMULATE)
+    acc_plan.execute()
+    torch.cuda.synchronize()
+    check(items, acc=2)
+    acc_plan.close()
+
+
+def test_plan_rejects_bad_items(ctx):
+    import torch
+
+    items = _plan_items(ctx, torch, [(4, 1, 2.0, False)], 880)
+    for bad in (dict(k=0.0), dict(k=float("nan")), dict(p=33), dict(layers=8)):
+        it = dict(items[0], **bad)
+        with pytest.raises(api.TsqbxError):
+            ctx.plan_helmholtz([it])
+    it = dict(items[0], layers=3)  # the double layer's output is missing
+    with pytest.raises((api.TsqbxError, TypeError, KeyError)):
+        ctx.plan_helmholtz([it])
