@@ -155,9 +155,10 @@ def cpu_baseline(g, p, layers):
             "seconds_per_pass": dt}
 
 
-def bench_batched(ctx, api, torch, W, steps, warmup):
-    log("generating 64 batched geometries (mixed p, single layer)")
-    geoms = W.config_c()
+def bench_batched(ctx, api, torch, W, steps, warmup, geoms=None):
+    if geoms is None:
+        log("generating 64 batched geometries (mixed p, single layer)")
+        geoms = W.config_c()
     items = []
     for g in geoms:
         geom = ctx.geometry(g)
@@ -182,6 +183,57 @@ def bench_batched(ctx, api, torch, W, steps, warmup):
     res = {
         "workload": "64 geometries (ellipsoids / perturbed spheres), N log-uniform 2048..65536, "
                     "T=N/4, p in {4,8,12,16}, single layer, ball lists r=8h",
+        "pair_terms": pair_terms,
+        "plain_pair_terms_per_s": pair_terms * n_plain / wall_plain,
+        "batched_pair_terms_per_s": pair_terms * steps / wall_plan,
+        "plain_ms": wall_plain / n_plain * 1e3,
+        "batched_ms": wall_plan / steps * 1e3,
+        "max_abs_diff_batched_vs_plain": diff,
+        "plan": plan.info(),
+    }
+    res["speedup"] = res["batched_pair_terms_per_s"] / res["plain_pair_terms_per_s"]
+    plan.close()
+    for it in items:
+        it["geom"].close()
+    return res
+
+
+def bench_helm_batched(ctx, api, torch, W, steps, warmup, geoms=None, k=10.0):
+    """The geometries of the batched workload with the Helmholtz single and
+    double layer (k = 10, each geometry's own order): one Helmholtz plan
+    against plain launches, one per geometry, each followed by a
+    synchronisation."""
+    if geoms is None:
+        log("generating 64 batched geometries (mixed p)")
+        geoms = W.config_c()
+    rng = np.random.default_rng(20181102)
+    items = []
+    for g in geoms:
+        geom = ctx.geometry(g)
+        sig = rng.standard_normal(g.n_sources) + 1j * rng.standard_normal(g.n_sources)
+        items.append(dict(geom=geom, p=g.p, layers=3, k=k,
+                          sigma=torch.tensor(sig, device="cuda", dtype=torch.complex128),
+                          out_slp=torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128),
+                          out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)))
+    pair_terms = sum(it["geom"].pair_terms(it["p"], 3) for it in items)
+    plain_out = [(torch.zeros_like(it["out_slp"]), torch.zeros_like(it["out_dlp"])) for it in items]
+
+    def plain():
+        for it, (a, b) in zip(items, plain_out):
+            ctx.eval_helmholtz_async(it["geom"], it["sigma"], it["p"], 3, k, a, b)
+            torch.cuda.synchronize()
+
+    n_plain = max(steps // 4, 3)
+    log("timing plain per-geometry Helmholtz launches")
+    wall_plain, _ = timed_steps(plain, n_plain, 2, torch)
+    plan = ctx.plan_helmholtz(items)
+    log("timing the batched Helmholtz plan (graph replay)")
+    wall_plan, _ = timed_steps(lambda: plan.execute(), steps, warmup, torch)
+    diff = max(max(float((it["out_slp"] - a).abs().max()), float((it["out_dlp"] - b).abs().max()))
+               for it, (a, b) in zip(items, plain_out))
+    res = {
+        "workload": f"the 64 batched geometries, Helmholtz k={k:g} single + double layer, "
+                    "p in {4,8,12,16}, complex density",
         "pair_terms": pair_terms,
         "plain_pair_terms_per_s": pair_terms * n_plain / wall_plain,
         "batched_pair_terms_per_s": pair_terms * steps / wall_plan,
@@ -508,7 +560,7 @@ def main():
     ap.add_argument("--no-helmholtz", action="store_true")
     ap.add_argument("--no-lists", action="store_true")
     ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime",
-                                       "helmholtz", "lists"],
+                                       "helmholtz", "helm_batched", "lists"],
                     help="run one section (for profiling); the JSON line then carries only it")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 256 MiB device copy first (for counter calibration)")
@@ -528,7 +580,8 @@ def main():
         calibration_copy(torch)
     if args.only and args.only not in ("headline", "sprime", "helmholtz", "lists"):
         ctx = api.Context(0)
-        fn = {"batched": bench_batched, "high_order": bench_d}.get(args.only)
+        fn = {"batched": bench_batched, "high_order": bench_d,
+              "helm_batched": bench_helm_batched}.get(args.only)
         if fn is not None:
             res = fn(ctx, api, torch, W, args.steps, args.warmup)
         else:
@@ -614,7 +667,13 @@ def main():
     geom.close()
     del sig, os_, od_
     if not args.no_batched:
-        out["batched"] = bench_batched(ctx, api, torch, W, args.steps, args.warmup)
+        log("generating 64 batched geometries (mixed p)")
+        geoms_c = W.config_c()
+        out["batched"] = bench_batched(ctx, api, torch, W, args.steps, args.warmup, geoms_c)
+        if not args.no_helmholtz:
+            out["helmholtz_batched"] = bench_helm_batched(ctx, api, torch, W, args.steps,
+                                                          args.warmup, geoms_c)
+        del geoms_c
     if args.with_d:
         out["batched_high_order"] = bench_d(ctx, api, torch, W, args.steps, args.warmup)
     if not args.no_serve:

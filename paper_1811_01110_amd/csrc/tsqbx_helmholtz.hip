@@ -42,11 +42,9 @@ namespace {
 // (2n+1) k j_n'(z), from j_n' = (n/z) j_n - j_{n+1} (DLMF 10.51.2; no
 // cancellation for small z), then (2n+1) j_n(z) / rho = (2n+1) k j_n(z) / z.
 // At z = 0 these are their limits: k for n = 1 and 0 otherwise.
-__global__ void __launch_bounds__(256)
-k_helm_table(const TargetRec *__restrict__ tgt, int64_t n_targets, double k, int p,
-             double *__restrict__ tab, double *__restrict__ tabs) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_targets) return;
+__device__ __forceinline__ void helm_table_row(const TargetRec *__restrict__ tgt, int64_t t,
+                                               double k, int p, double *__restrict__ tab,
+                                               double *__restrict__ tabs) {
   const TargetRec tr = tgt[t];
   const double rho2 = fma(tr.d[2], tr.d[2], fma(tr.d[1], tr.d[1], tr.d[0] * tr.d[0]));
   const double z = k * sqrt(rho2);
@@ -113,27 +111,58 @@ k_helm_table(const TargetRec *__restrict__ tgt, int64_t n_targets, double k, int
   }
 }
 
+__global__ void __launch_bounds__(256)
+k_helm_table(const TargetRec *__restrict__ tgt, int64_t n_targets, double k, int p,
+             double *__restrict__ tab, double *__restrict__ tabs) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_targets) helm_table_row(tgt, t, k, p, tab, tabs);
+}
+
 // Staging: rec[2i] = (x, y, z, Re q), rec[2i+1] = (Im q, nu) with q = w sigma
 // and sigma complex in the caller's order; entry n is the padding record
 // (q = 0, far from every center).
+__device__ __forceinline__ void helm_stage_one(int64_t i, int64_t n,
+                                               const double4 *__restrict__ pos_w,
+                                               const double4 *__restrict__ nrm,
+                                               const int64_t *__restrict__ perm,
+                                               const double *__restrict__ sigma,
+                                               double4 *__restrict__ rec) {
+  if (i == n) {
+    rec[2 * n] = make_double4(1e100, 1e100, 1e100, 0.0);
+    rec[2 * n + 1] = make_double4(0.0, 0.0, 0.0, 0.0);
+    return;
+  }
+  const double4 a = pos_w[i];
+  const int64_t c = perm ? perm[i] : i;
+  const double sr = sigma[2 * c], si = sigma[2 * c + 1];
+  rec[2 * i] = make_double4(a.x, a.y, a.z, a.w * sr);
+  const double4 v = nrm ? nrm[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+  rec[2 * i + 1] = make_double4(a.w * si, v.x, v.y, v.z);
+}
+
 __global__ void __launch_bounds__(256)
 k_helm_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict__ nrm,
              const int64_t *__restrict__ perm, const double *__restrict__ sigma,
              double4 *__restrict__ rec) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i == n) {
-      rec[2 * n] = make_double4(1e100, 1e100, 1e100, 0.0);
-      rec[2 * n + 1] = make_double4(0.0, 0.0, 0.0, 0.0);
-      continue;
-    }
-    const double4 a = pos_w[i];
-    const int64_t c = perm ? perm[i] : i;
-    const double sr = sigma[2 * c], si = sigma[2 * c + 1];
-    rec[2 * i] = make_double4(a.x, a.y, a.z, a.w * sr);
-    const double4 v = nrm ? nrm[i] : make_double4(0.0, 0.0, 0.0, 0.0);
-    rec[2 * i + 1] = make_double4(a.w * si, v.x, v.y, v.z);
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    helm_stage_one(i, n, pos_w, nrm, perm, sigma, rec);
+}
+
+// Staging and tables of many evaluations in one launch each: item
+// blockIdx.y, its sources (or targets) strided over blockIdx.x.
+__global__ void __launch_bounds__(256) k_helm_stage_multi(const HelmPrepItem *__restrict__ items) {
+  const HelmPrepItem it = items[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= it.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    helm_stage_one(i, it.n, it.pos_w, it.nrm, it.perm, it.sigma, it.rec);
+}
+
+__global__ void __launch_bounds__(256) k_helm_table_multi(const HelmPrepItem *__restrict__ items) {
+  const HelmPrepItem it = items[blockIdx.y];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < it.n_targets;
+       t += (int64_t)gridDim.x * blockDim.x)
+    helm_table_row(it.tgt, t, it.k, it.p, it.tab, it.tabs);
 }
 
 __device__ __forceinline__ double4 load_rec(const double4 *__restrict__ base, uint32_t i,
@@ -534,18 +563,36 @@ hipError_t launch_helm_persistent_l(const HelmPersistentArgs &a, const Tuning &t
                                     hipStream_t s) {
   const dim3 block(64 * tn.waves_per_block);
   const int grid = (a.n_waves + tn.waves_per_block - 1) / tn.waves_per_block;
-  if (tn.unroll <= 1)
+  // the same (group width, pairs in flight) choices as the plain kernel
+  const int G = tn.group_lanes, U = std::min(tn.unroll, 2);
+  if (G == 64 && U == 1)
     hipLaunchKernelGGL((k_helm_persistent<LC, 64, 1>), dim3(grid), block, 0, s, a);
-  else
+  else if (G == 64)
     hipLaunchKernelGGL((k_helm_persistent<LC, 64, 2>), dim3(grid), block, 0, s, a);
+  else if (G == 32)
+    hipLaunchKernelGGL((k_helm_persistent<LC, 32, 2>), dim3(grid), block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_helm_persistent<LC, 16, 2>), dim3(grid), block, 0, s, a);
   return hipGetLastError();
 }
 }  // namespace
 
+hipError_t launch_helm_prepare_multi(const HelmPrepItem *d_items, int n_items, int64_t max_n,
+                                     int64_t max_t, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (n_items > 65535) return hipErrorInvalidValue;
+  const unsigned bs = (unsigned)std::min<int64_t>(std::max<int64_t>((max_n + 1 + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(k_helm_stage_multi, dim3(bs, (unsigned)n_items), dim3(256), 0, s, d_items);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || max_t <= 0) return e;
+  const unsigned bt = (unsigned)std::min<int64_t>(std::max<int64_t>((max_t + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(k_helm_table_multi, dim3(bt, (unsigned)n_items), dim3(256), 0, s, d_items);
+  return hipGetLastError();
+}
+
 hipError_t launch_helm_persistent(const HelmPersistentArgs &a, unsigned layer_class,
                                   const Tuning &tn, hipStream_t s) {
-  // the batched Helmholtz kernel runs one target per wave (group_lanes 64)
-  if (!tuning_supported(tn) || tn.group_lanes != 64 || a.n_waves <= 0) return hipErrorInvalidValue;
+  if (!tuning_supported(tn) || a.n_waves <= 0) return hipErrorInvalidValue;
   switch (layer_class) {
     case 1: return launch_helm_persistent_l<1>(a, tn, s);
     case 2: return launch_helm_persistent_l<2>(a, tn, s);

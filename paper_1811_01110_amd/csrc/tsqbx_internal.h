@@ -234,6 +234,25 @@ struct HelmPersistentArgs {
 // evaluation (before the pair kernel).
 hipError_t launch_helm_prepare(const tsqbx_geometry *g, int p, unsigned layers, double k,
                                const double *d_sigma, const HelmStage &st, hipStream_t s);
+// The same for many evaluations in two launches (plans).
+struct HelmPrepItem {       // 96 bytes
+  const double4 *pos_w;     // geometry sources (x, y, z, w), device order
+  const double4 *nrm;       // source normals or null
+  const int64_t *perm;      // device -> caller source order, or null
+  const double *sigma;      // complex, caller order
+  double4 *rec;             // [2 (n + 1)]
+  int64_t n;                // sources
+  const TargetRec *tgt;
+  int64_t n_targets;
+  double k;
+  int32_t p;
+  int32_t pad;
+  double *tab;
+  double *tabs;             // S' rows, or null when S' is not requested
+};
+static_assert(sizeof(HelmPrepItem) == 96, "HelmPrepItem layout");
+hipError_t launch_helm_prepare_multi(const HelmPrepItem *d_items, int n_items, int64_t max_n,
+                                     int64_t max_t, hipStream_t s);
 // The Helmholtz persistent kernel over a plan's units; layer_class as for
 // launch_persistent (1..7 exact masks, or kLayersAny).
 hipError_t launch_helm_persistent(const HelmPersistentArgs &a, unsigned layer_class,

@@ -44,6 +44,8 @@ struct tsqbx_plan {
   std::vector<tsqbx_helm_item> hitems;
   std::vector<HelmStage> hstages;
   HelmWorkItem *d_hitems = nullptr;
+  HelmPrepItem *d_hprep = nullptr;
+  int64_t max_targets = 0;
 };
 
 namespace {
@@ -76,6 +78,7 @@ void free_plan(tsqbx_plan *pl) {
     if (h.tabs) (void)hipFree(h.tabs);
   }
   if (pl->d_hitems) (void)hipFree(pl->d_hitems);
+  if (pl->d_hprep) (void)hipFree(pl->d_hprep);
   if (pl->d_items) (void)hipFree(pl->d_items);
   if (pl->d_stage) (void)hipFree(pl->d_stage);
   if (pl->d_units) (void)hipFree(pl->d_units);
@@ -336,9 +339,9 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
   pl->layer_class = same && first >= 1 && first <= 7 ? first : kLayersAny;
   const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
   pl->tn = lookup_tuning(ctx, pmax, (lay_all ? lay_all : 1u) | TSQBX_HELMHOLTZ, mean_list);
-  pl->tn.group_lanes = 64;  // one target per wave
   pl->tn.unroll = std::min(std::max(pl->tn.unroll, 1), 2);
-  if (!tuning_supported(pl->tn)) pl->tn = Tuning{};
+  if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
+  if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, lay_all, mean_list);
 
   // item order: largest first; static schedule over the resident waves
   std::vector<int64_t> ord(n_items);
@@ -353,14 +356,15 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
   std::vector<int32_t> order32(ord.begin(), ord.end());
   std::vector<WorkUnit> units;
   std::vector<int32_t> wave_begin;
-  build_schedule(sched, order32, 64, persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256),
-                 &units, &wave_begin);
+  build_schedule(sched, order32, pl->tn.group_lanes,
+                 persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256), &units, &wave_begin);
   pl->n_units = (int64_t)units.size();
   pl->n_waves = (int32_t)wave_begin.size() - 1;
   pl->grid = (pl->n_waves + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block;
 
   // per-item staging, tables and the device copies of items and units
   std::vector<HelmWorkItem> witems(n_items);
+  std::vector<HelmPrepItem> pitems(n_items);
   hipError_t e = hipSuccess;
   pl->hstages.resize(n_items);
   for (int64_t i = 0; i < n_items && e == hipSuccess; ++i) {
@@ -390,7 +394,26 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
     w.layers = (int32_t)it.layers;
     w.accumulate = (flags & TSQBX_ACCUMULATE) ? 1 : 0;
     w.n_src = (uint32_t)g->n_sources;
+    HelmPrepItem &q = pitems[i];
+    q = HelmPrepItem{};
+    q.pos_w = g->src_pos;
+    q.nrm = g->src_nrm;
+    q.perm = g->src_perm;
+    q.sigma = it.d_sigma;
+    q.rec = st.rec;
+    q.n = g->n_sources;
+    q.tgt = g->tgt;
+    q.n_targets = g->n_targets;
+    q.k = it.k;
+    q.p = it.p;
+    q.tab = st.tab;
+    q.tabs = (it.layers & TSQBX_SPRIME) ? st.tabs : nullptr;
+    pl->max_sources = std::max<int64_t>(pl->max_sources, g->n_sources);
+    pl->max_targets = std::max<int64_t>(pl->max_targets, g->n_targets);
   }
+  if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_hprep, n_items * sizeof(HelmPrepItem));
+  if (e == hipSuccess && n_items)
+    e = hipMemcpy(pl->d_hprep, pitems.data(), n_items * sizeof(HelmPrepItem), hipMemcpyHostToDevice);
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_hitems, n_items * sizeof(HelmWorkItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_hitems, witems.data(), n_items * sizeof(HelmWorkItem), hipMemcpyHostToDevice);
@@ -404,8 +427,8 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
     e = hipMemcpy(pl->d_wave_begin, wave_begin.data(), wave_begin.size() * sizeof(int32_t),
                   hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
-  pl->device_bytes += n_items * sizeof(HelmWorkItem) + units.size() * sizeof(WorkUnit) +
-                      wave_begin.size() * sizeof(int32_t);
+  pl->device_bytes += n_items * (sizeof(HelmWorkItem) + sizeof(HelmPrepItem)) +
+                      units.size() * sizeof(WorkUnit) + wave_begin.size() * sizeof(int32_t);
   if (e != hipSuccess) {
     free_plan(pl);
     return fail_hip(e, "plan setup");
@@ -424,11 +447,10 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
     TSQBX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     if (pl->helm) {
-      // every item's density and tables, then one persistent launch
-      for (size_t i = 0; i < pl->hitems.size() && e == hipSuccess; ++i) {
-        const tsqbx_helm_item &it = pl->hitems[i];
-        e = launch_helm_prepare(it.geom, it.p, it.layers, it.k, it.d_sigma, pl->hstages[i], cs);
-      }
+      // every item's density and tables (one launch each), then one
+      // persistent launch
+      e = launch_helm_prepare_multi(pl->d_hprep, (int)pl->hitems.size(), pl->max_sources,
+                                    pl->max_targets, cs);
       if (e == hipSuccess && pl->n_units > 0) {
         HelmPersistentArgs a{pl->d_hitems, pl->d_units, pl->d_wave_begin, pl->n_waves};
         e = launch_helm_persistent(a, pl->layer_class, pl->tn, cs);

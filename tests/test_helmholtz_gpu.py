@@ -178,9 +178,14 @@ def _plan_items(ctx, torch, specs, seed):
     return items
 
 
-def test_plan_matches_plain_bits_and_oracle(ctx):
+def _ceil_mean(pairs, targets):
+    return max(-(-pairs // max(targets, 1)), 1)
+
+
+@pytest.mark.parametrize("G", [16, 64])
+def test_plan_matches_plain_bits_and_oracle(ctx, G):
     """A Helmholtz plan (mixed orders, masks and wavenumbers, two items on one
-    geometry) equals plain evaluations with 64 lanes per target bit for bit,
+    geometry) equals plain evaluations with the same group width bit for bit,
     and the oracle to the parity bar; replays with new densities and the
     accumulate flag behave as for Laplace plans."""
     import torch
@@ -188,6 +193,14 @@ def test_plan_matches_plain_bits_and_oracle(ctx):
     specs = [(4, 1, 2.0, False), (8, 3, 5.0, False), (12, 4, 10.0, False), (16, 7, 20.0, False),
              (16, 7, 3.0, True), (5, 2, 1.0, False), (0, 5, 3.0, False), (24, 6, 8.0, False)]
     items = _plan_items(ctx, torch, specs, 870)
+    # the plan's launch shape comes from (largest p, union of masks, mean list)
+    pairs = sum(it["geom"].pairs for it in items)
+    targets = sum(it["geom"].n_targets for it in items)
+    ctx.set_tuning(24, 7 | api.HELMHOLTZ, _ceil_mean(pairs, targets), group_lanes=G)
+    for it in items:
+        geom = it["geom"]
+        ctx.set_tuning(it["p"], it["layers"] | api.HELMHOLTZ, _ceil_mean(geom.pairs, geom.n_targets),
+                       group_lanes=G)
     plan = ctx.plan_helmholtz(items)
     assert plan.info()["n_items"] == len(items)
     keys = ("slp", "dlp", "sprime")
@@ -195,15 +208,13 @@ def test_plan_matches_plain_bits_and_oracle(ctx):
     def check(its, acc=1):
         for it in its:
             g, geom = it["g"], it["geom"]
-            mean = max(geom.pairs // geom.n_targets, 1)
-            ctx.set_tuning(it["p"], it["layers"] | api.HELMHOLTZ, mean, group_lanes=64)
             plain = ctx.eval_helmholtz(geom, it["sig"], it["p"], it["layers"], it["k"])
             ref = H.evaluate_geometry(g, it["k"], it["sig"], p=it["p"], layers=it["layers"])
             for bit, key, pl in zip((1, 2, 4), keys, plain):
                 if not it["layers"] & bit:
                     continue
                 got = it["out_" + key].cpu().numpy()
-                assert np.array_equal(got, acc * pl), (it["p"], it["layers"], key)
+                assert np.array_equal(got, acc * pl), (G, it["p"], it["layers"], key)
                 assert_parity(got / acc, ref[key], ref["abs_" + key], what=f"plan p={it['p']} {key}")
 
     plan.execute()
