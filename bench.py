@@ -390,6 +390,27 @@ def bench_serve(ctx, api, torch, W, n_requests):
     }
 
 
+def bench_host_call(ctx, g, geom, steps, p=16, layers=3):
+    """The headline workload through the synchronous host-array call
+    (tsqbx_eval): the density upload, the evaluation and the output downloads
+    over PCIe, from and into pageable numpy arrays.  Reported beside the
+    device-resident rate, never as the headline value."""
+    sig = np.ascontiguousarray(g.sigma, dtype=np.float64)
+    outs = [np.zeros(g.n_targets) for _ in range(2)]
+    for _ in range(3):
+        ctx.eval(geom, sig, p, layers, *outs)
+    n = max(steps // 2, 5)
+    log(f"timing the host-array call, {n} calls")
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ctx.eval(geom, sig, p, layers, *outs)
+    dt = (time.perf_counter() - t0) / n
+    return {"workload": "the headline workload through tsqbx_eval with host arrays (density "
+                        "upload and output downloads over PCIe included)",
+            "ms_per_call": dt * 1e3, "pair_terms_per_s": geom.pair_terms(p, layers) / dt,
+            "host_bytes_per_call": 8 * g.n_sources + 8 * g.n_targets * 2}
+
+
 def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
     """S' (the target normal derivative of the single layer) on the headline
     workload: alone, and with the single and double layer in the same pass."""
@@ -655,6 +676,7 @@ def main():
         ctx.close()
         print(json.dumps(out), flush=True)
         return
+    out["host_call"] = bench_host_call(ctx, g, geom, args.steps, p, layers)
     if not args.no_cpu:
         log("timing the CPU oracle on the same workload")
         out["cpu_baseline"] = cpu_baseline(g, p, layers)

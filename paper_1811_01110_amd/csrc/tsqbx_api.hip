@@ -236,7 +236,7 @@ using namespace tsqbx;
 
 extern "C" {
 
-int tsqbx_version(void) { return 10200; }
+int tsqbx_version(void) { return 10300; }
 
 const char *tsqbx_last_error(void) { return g_err.c_str(); }
 
