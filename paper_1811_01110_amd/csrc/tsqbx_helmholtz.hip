@@ -527,8 +527,10 @@ hipError_t launch_helm_gu(const tsqbx_geometry *g, int p, unsigned layers, doubl
 
 hipError_t launch_helm_prepare(const tsqbx_geometry *g, int p, unsigned layers, double k,
                                const double *d_sigma, const HelmStage &st, hipStream_t s) {
-  // S' needs the target normals and the S' table
-  if ((layers & TSQBX_SPRIME) && (!g->tgt_nrm || !st.tabs)) return hipErrorInvalidValue;
+  // S' needs the target normals (none are stored when there are no targets)
+  // and the S' table
+  if ((layers & TSQBX_SPRIME) && ((g->n_targets > 0 && !g->tgt_nrm) || !st.tabs))
+    return hipErrorInvalidValue;
   const int64_t n = g->n_sources, T = g->n_targets;
   {
     const int64_t blocks = std::min<int64_t>((n + 1 + 255) / 256, 65536);

@@ -250,3 +250,34 @@ def test_plan_single_layer_long_lists_match_plain_bits(ctx, p):
         ref = oracle.evaluate_geometry(g)
         assert_parity(s, ref["slp"], ref["abs_slp"], what=f"plan long lists p={p}")
     plan.close()
+
+
+def test_plan_edge_cases(ctx):
+    """An empty plan runs and does nothing; an item with no targets or with
+    every list empty is valid (outputs 0) beside an ordinary item."""
+    import torch
+
+    empty = ctx.plan([])
+    assert empty.info()["n_items"] == 0
+    empty.execute()
+    torch.cuda.synchronize()
+    empty.close()
+    g = W.fuzz_geometry(400, n=300, m=60, max_list=120, p=8, layers=3)
+    no_lists = W.Geometry(g.sources, g.weights, g.normals, g.centers,
+                          np.zeros(g.n_centers + 1, dtype=np.int64), np.zeros(0, dtype=np.int32),
+                          g.targets, g.target_center, g.sigma, 8, 3)
+    no_targets = W.Geometry(g.sources, g.weights, g.normals, g.centers, g.list_offsets,
+                            g.list_sources, np.zeros((0, 3)), np.zeros(0, dtype=np.int32),
+                            g.sigma, 8, 3)
+    items = _items(ctx, [g, no_lists, no_targets], torch)
+    for it in items[1:2]:
+        it["out_slp"].fill_(7.0)
+        it["out_dlp"].fill_(7.0)
+    plan = ctx.plan(items)
+    plan.execute()
+    torch.cuda.synchronize()
+    ref = oracle.evaluate_geometry(g)
+    assert_parity(items[0]["out_slp"].cpu().numpy(), ref["slp"], ref["abs_slp"], what="slp")
+    assert_parity(items[0]["out_dlp"].cpu().numpy(), ref["dlp"], ref["abs_dlp"], what="dlp")
+    assert not items[1]["out_slp"].any() and not items[1]["out_dlp"].any()
+    plan.close()

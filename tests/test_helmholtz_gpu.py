@@ -248,3 +248,41 @@ def test_plan_rejects_bad_items(ctx):
     it = dict(items[0], layers=3)  # the double layer's output is missing
     with pytest.raises((api.TsqbxError, TypeError, KeyError)):
         ctx.plan_helmholtz([it])
+
+
+def test_plan_edge_cases(ctx):
+    """An empty Helmholtz plan runs and does nothing; an item with every list
+    empty gives 0 beside an ordinary item; one with no targets is valid."""
+    import torch
+
+    empty = ctx.plan_helmholtz([])
+    empty.execute()
+    torch.cuda.synchronize()
+    empty.close()
+    g = W.fuzz_geometry(890, n=300, m=60, max_list=120, p=6, layers=3)
+    no_lists = W.Geometry(g.sources, g.weights, g.normals, g.centers,
+                          np.zeros(g.n_centers + 1, dtype=np.int64), np.zeros(0, dtype=np.int32),
+                          g.targets, g.target_center, g.sigma, 6, 3,
+                          target_normals=g.target_normals)
+    no_targets = W.Geometry(g.sources, g.weights, g.normals, g.centers, g.list_offsets,
+                            g.list_sources, np.zeros((0, 3)), np.zeros(0, dtype=np.int32),
+                            g.sigma, 6, 3, target_normals=np.zeros((0, 3)))
+    sig = _sigma(g.n_sources, 11)
+    items = []
+    for geo in (g, no_lists, no_targets):
+        geom = ctx.geometry(geo)
+        it = dict(g=geo, geom=geom, p=6, layers=ALL, k=4.0,
+                  sigma=torch.tensor(sig, device="cuda", dtype=torch.complex128))
+        for key in ("out_slp", "out_dlp", "out_sprime"):
+            it[key] = torch.full((geo.n_targets,), 7.0 + 0j, device="cuda", dtype=torch.complex128)
+        items.append(it)
+    plan = ctx.plan_helmholtz(items)
+    plan.execute()
+    torch.cuda.synchronize()
+    ref = H.evaluate_geometry(g, 4.0, sig, p=6, layers=ALL)
+    for key in ("slp", "dlp", "sprime"):
+        assert_parity(items[0]["out_" + key].cpu().numpy(), ref[key], ref["abs_" + key], what=key)
+        assert not items[1]["out_" + key].any()
+    plan.close()
+    out = ctx.eval_helmholtz(items[2]["geom"], sig, 6, ALL, 4.0)  # no targets, plain path
+    assert all(o.size == 0 for o in out)
