@@ -360,6 +360,21 @@ int tsqbx_server_submit(tsqbx_server *srv, const tsqbx_geometry *geom, int p, un
 int tsqbx_server_submit_pinned(tsqbx_server *srv, const tsqbx_geometry *geom, int p,
                                unsigned layers, const double *sigma_host, double *out_slp_host,
                                double *out_dlp_host, double *out_sprime_host, uint64_t *ticket);
+/* Queue a Helmholtz request (the kernel of tsqbx_eval_helmholtz, real
+ * wavenumber k > 0): sigma_host [N][2] and the outputs [T][2] are complex,
+ * interleaved (re, im), in the caller's orders; sigma_host is copied before
+ * the call returns, the outputs must stay valid until the ticket completes.
+ * Helmholtz and Laplace requests share the server's steps; each is evaluated
+ * with the server's one launch shape, so its result does not depend on what
+ * it is batched with.  Errors as for tsqbx_eval_helmholtz and
+ * tsqbx_server_submit.  Thread-safe. */
+int tsqbx_server_submit_helmholtz(tsqbx_server *srv, const tsqbx_geometry *geom, int p,
+                                  unsigned layers, double k, const double *sigma_host,
+                                  double *out_slp_host, double *out_dlp_host,
+                                  double *out_sprime_host, uint64_t *ticket);
+/* Bytes a Helmholtz request of order p with these layers reserves. */
+int tsqbx_server_request_bytes_helmholtz(const tsqbx_geometry *geom, int p, unsigned layers,
+                                         size_t *out);
 /* *done = 1 once the outputs are written (0 while pending).  Returns the
  * request's error status if it failed. */
 int tsqbx_server_poll(tsqbx_server *srv, uint64_t ticket, int *done);

@@ -405,6 +405,13 @@ class Server:
         _check(_lib().tsqbx_server_request_bytes(geom.handle, int(layers), ctypes.byref(n)))
         return n.value
 
+    @staticmethod
+    def request_bytes_helmholtz(geom: Geometry, p: int, layers: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib().tsqbx_server_request_bytes_helmholtz(geom.handle, int(p), int(layers),
+                                                           ctypes.byref(n)))
+        return n.value
+
     def submit(self, geom: Geometry, sigma, p: int, layers: int):
         """Queue a request; returns (ticket, out_slp, out_dlp, out_sprime): host
         arrays filled on completion (None for a layer not requested)."""
@@ -416,6 +423,22 @@ class Server:
         tk = ctypes.c_uint64()
         _check(_lib().tsqbx_server_submit(self.handle, geom.handle, int(p), int(layers), _ptr(sig),
                                           *[_ptr(o) for o in outs], ctypes.byref(tk)))
+        self._live[tk.value] = outs
+        return (tk.value,) + outs
+
+    def submit_helmholtz(self, geom: Geometry, sigma, p: int, layers: int, k: float):
+        """Queue a Helmholtz request (sigma complex, copied); returns (ticket,
+        out_slp, out_dlp, out_sprime): complex host arrays filled on completion
+        (None for a layer not requested)."""
+        sig = np.ascontiguousarray(sigma, dtype=np.complex128)
+        if sig.size != geom.n_sources:
+            raise ValueError("sigma has the wrong length")
+        T = geom.n_targets
+        outs = tuple(np.zeros(T, dtype=np.complex128) if layers & bit else None for bit in LAYER_BITS)
+        tk = ctypes.c_uint64()
+        _check(_lib().tsqbx_server_submit_helmholtz(self.handle, geom.handle, int(p), int(layers),
+                                                    float(k), _ptr(sig), *[_ptr(o) for o in outs],
+                                                    ctypes.byref(tk)))
         self._live[tk.value] = outs
         return (tk.value,) + outs
 

@@ -12,7 +12,9 @@
 // the steps' events, copies outputs to the callers' buffers, releases the
 // memory and wakes the scheduler.  Every request is summed by the same device
 // routine with the same group width whatever it is batched with, so its
-// result does not depend on the mix.
+// result does not depend on the mix.  Helmholtz requests (complex density and
+// outputs) share the steps: their densities are uploaded by DMA and they get
+// their own staging, table and persistent launches in the step.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -87,6 +89,8 @@ struct Request {
   const tsqbx_geometry *geom = nullptr;
   int p = 0;
   unsigned layers = 0;
+  double k = 0.0;                   // > 0: a Helmholtz request (complex values)
+  size_t cw() const { return k > 0.0 ? 2 : 1; }  // doubles per value
   // host staging: [sigma (N) | one T-vector per requested layer, in the order
   // single layer, double layer, S'], pinned when it fits
   double *h_stage = nullptr;
@@ -188,6 +192,18 @@ static size_t request_bytes(const tsqbx_geometry *g, unsigned layers) {
   return std::max<size_t>(b, kAlign);
 }
 
+// Device bytes of a Helmholtz request: [sigma (N complex) | records (2 (N+1))
+// | table T (p+1) | S' table 2 T (p+1), S' only | one complex T-vector per
+// requested layer].
+static size_t request_bytes_helm(const tsqbx_geometry *g, int p, unsigned layers) {
+  const size_t N = (size_t)g->n_sources, T = std::max<size_t>((size_t)g->n_targets, 1);
+  size_t b = align_up(2 * N * sizeof(double)) + align_up(2 * (N + 1) * sizeof(double4));
+  b += align_up(T * (size_t)(p + 1) * sizeof(double));
+  if (layers & TSQBX_SPRIME) b += align_up(2 * T * (size_t)(p + 1) * sizeof(double));
+  b += n_layers(layers) * align_up(2 * (size_t)g->n_targets * sizeof(double));
+  return std::max<size_t>(b, kAlign);
+}
+
 // Launch one step (called by the scheduler with the lock released).
 // Densities in pinned host memory are read by the staging kernel directly
 // and outputs are written back by one copy kernel; only requests whose host
@@ -201,90 +217,160 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     return TSQBX_E_DEVICE;
   };
   const size_t K = step.reqs.size();
-  std::vector<WorkItem> items(K);
-  std::vector<StageItem> stage(K);
+  std::vector<WorkItem> items;         // Laplace requests
+  std::vector<StageItem> stage;
+  std::vector<HelmWorkItem> hitems;    // Helmholtz requests
+  std::vector<HelmPrepItem> hprep;
   std::vector<CopyItem> copies;
-  std::vector<WorkUnit> units;
-  std::vector<int32_t> wave_begin;
-  // DMA copies for requests staged in pageable memory: (destination, source, count)
-  std::vector<std::tuple<double *, const double *, size_t>> pageable_up, pageable_down;
-  int64_t max_n = 0, max_t = 0;
+  std::vector<WorkUnit> units, hunits;
+  std::vector<int32_t> wave_begin, hwave_begin;
+  // DMA copies: densities of pageable-staged and of Helmholtz requests up,
+  // outputs of pageable-staged requests down: (destination, source, doubles)
+  std::vector<std::tuple<double *, const double *, size_t>> dma_up, pageable_down;
+  int64_t max_n = 0, max_t = 0, hmax_n = 0, hmax_t = 0;
   LayerClass lc;
-  int p_all = K ? step.reqs[0]->p : -1;
+  int p_all = -1;
+  unsigned h_first = 0;
+  bool h_same = true;
   const int64_t per_unit = (int64_t)kUnitSteps * (64 / tn.group_lanes);
   for (size_t i = 0; i < K; ++i) {
     Request *r = step.reqs[i];
     const tsqbx_geometry *g = r->geom;
     const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
+    const size_t cw = r->cw();
     char *base = arena_base + r->arena_off;
     double *d_sigma = (double *)base;
-    size_t off = align_up(N * sizeof(double));
-    SourceStage stg;
-    stg.posq = (double4 *)(base + off);
-    off += align_up((N + 1) * sizeof(double4));
-    if (r->layers & TSQBX_DLP) {
-      stg.qn = (double4 *)(base + off);
-      off += align_up((N + 1) * sizeof(double4));
-    }
-    double *d_out[3] = {nullptr, nullptr, nullptr};
-    for (int l = 0; l < 3; ++l)
-      if (r->layers & (1u << l)) {
-        d_out[l] = (double *)(base + off);
-        off += align_up(T * sizeof(double));
-      }
+    size_t off = align_up(cw * N * sizeof(double));
     const bool host_pinned = r->borrowed || r->pinned;
-    const double *sig = r->sigma_src;
-    if (!host_pinned) {
-      if (N) pageable_up.emplace_back(d_sigma, r->sigma_src, N);
-      sig = d_sigma;
+    double *d_out[3] = {nullptr, nullptr, nullptr};
+    if (r->k > 0.0) {
+      HelmStage hs;
+      const size_t T1 = std::max<size_t>(T, 1);
+      hs.rec = (double4 *)(base + off);
+      off += align_up(2 * (N + 1) * sizeof(double4));
+      hs.tab = (double *)(base + off);
+      off += align_up(T1 * (size_t)(r->p + 1) * sizeof(double));
+      if (r->layers & TSQBX_SPRIME) {
+        hs.tabs = (double *)(base + off);
+        off += align_up(2 * T1 * (size_t)(r->p + 1) * sizeof(double));
+      }
+      for (int l = 0; l < 3; ++l)
+        if (r->layers & (1u << l)) {
+          d_out[l] = (double *)(base + off);
+          off += align_up(2 * T * sizeof(double));
+        }
+      if (N) dma_up.emplace_back(d_sigma, r->sigma_src, 2 * N);
+      HelmPrepItem q{};
+      q.pos_w = g->src_pos;
+      q.nrm = g->src_nrm;
+      q.perm = g->src_perm;
+      q.sigma = d_sigma;
+      q.rec = hs.rec;
+      q.n = g->n_sources;
+      q.tgt = g->tgt;
+      q.n_targets = g->n_targets;
+      q.k = r->k;
+      q.p = r->p;
+      q.tab = hs.tab;
+      q.tabs = hs.tabs;
+      HelmWorkItem w{};
+      w.tgt = g->tgt;
+      w.tnrm = g->tgt_nrm;
+      w.idx = g->idx;
+      w.rec = hs.rec;
+      w.tab = hs.tab;
+      w.tabs = hs.tabs;
+      w.out_s = d_out[0];
+      w.out_d = d_out[1];
+      w.out_t = d_out[2];
+      w.k = r->k;
+      w.p = r->p;
+      w.layers = (int32_t)r->layers;
+      w.n_src = (uint32_t)g->n_sources;
+      if (hitems.empty()) h_first = r->layers;
+      else if (r->layers != h_first) h_same = false;
+      const int32_t hi = (int32_t)hitems.size();
+      hprep.push_back(q);
+      hitems.push_back(w);
+      hmax_n = std::max<int64_t>(hmax_n, g->n_sources);
+      hmax_t = std::max<int64_t>(hmax_t, g->n_targets);
+      for (int64_t k = 0; k < g->n_targets; k += per_unit) {
+        hwave_begin.push_back((int32_t)hunits.size());
+        hunits.push_back(WorkUnit{hi, (int32_t)k, (int32_t)std::min<int64_t>(per_unit, g->n_targets - k), 0});
+      }
+    } else {
+      SourceStage stg;
+      stg.posq = (double4 *)(base + off);
+      off += align_up((N + 1) * sizeof(double4));
+      if (r->layers & TSQBX_DLP) {
+        stg.qn = (double4 *)(base + off);
+        off += align_up((N + 1) * sizeof(double4));
+      }
+      for (int l = 0; l < 3; ++l)
+        if (r->layers & (1u << l)) {
+          d_out[l] = (double *)(base + off);
+          off += align_up(T * sizeof(double));
+        }
+      const double *sig = r->sigma_src;
+      if (!host_pinned) {
+        if (N) dma_up.emplace_back(d_sigma, r->sigma_src, N);
+        sig = d_sigma;
+      }
+      stage.push_back(make_stage_item(g, sig, r->layers, stg, host_pinned));
+      max_n = std::max<int64_t>(max_n, g->n_sources);
+      WorkItem w{};
+      w.tgt = g->tgt;
+      w.idx = g->idx;
+      w.posq = stg.posq;
+      w.qn = stg.qn;
+      w.out_s = d_out[0];
+      w.out_d = d_out[1];
+      w.out_t = d_out[2];
+      w.tnrm = g->tgt_nrm;
+      w.p = r->p;
+      w.layers = (int32_t)r->layers;
+      if (items.empty()) p_all = r->p;
+      lc.add(r->layers);
+      if (r->p != p_all) p_all = -1;
+      const int32_t li = (int32_t)items.size();
+      items.push_back(w);
+      // fixed-size units, one per wave: constant host work per unit, and the
+      // dispatcher balances the waves
+      for (int64_t k = 0; k < g->n_targets; k += per_unit) {
+        wave_begin.push_back((int32_t)units.size());
+        units.push_back(WorkUnit{li, (int32_t)k, (int32_t)std::min<int64_t>(per_unit, g->n_targets - k), 0});
+      }
     }
-    stage[i] = make_stage_item(g, sig, r->layers, stg, host_pinned);
-    max_n = std::max<int64_t>(max_n, g->n_sources);
-    max_t = std::max<int64_t>(max_t, g->n_targets);
-    WorkItem &w = items[i];
-    w = WorkItem{};
-    w.tgt = g->tgt;
-    w.idx = g->idx;
-    w.posq = stg.posq;
-    w.qn = stg.qn;
-    w.out_s = d_out[0];
-    w.out_d = d_out[1];
-    w.out_t = d_out[2];
-    w.tnrm = g->tgt_nrm;
-    w.p = r->p;
-    w.layers = (int32_t)r->layers;
-    lc.add(r->layers);
-    if (r->p != p_all) p_all = -1;
-    // fixed-size units, one per wave: constant host work per unit, and the
-    // dispatcher balances the waves
-    for (int64_t k = 0; k < g->n_targets; k += per_unit) {
-      wave_begin.push_back((int32_t)units.size());
-      units.push_back(WorkUnit{(int32_t)i, (int32_t)k,
-                               (int32_t)std::min<int64_t>(per_unit, g->n_targets - k), 0});
-    }
+    max_t = std::max<int64_t>(max_t, (int64_t)(cw * T));
     // outputs: into the caller's pinned buffers or the request's host staging
     if (T) {
-      double *h = r->h_stage + N;  // host staging: requested layers in order
+      double *h = r->h_stage + cw * N;  // host staging: requested layers in order
       for (int l = 0; l < 3; ++l) {
         if (!(r->layers & (1u << l))) continue;
         double *dst = r->borrowed ? r->out[l] : h;
-        if (!r->borrowed) h += T;
+        if (!r->borrowed) h += cw * T;
         if (host_pinned)
-          copies.push_back(CopyItem{d_out[l], dst, (int64_t)T, 0});
+          copies.push_back(CopyItem{d_out[l], dst, (int64_t)(cw * T), 0});
         else
-          pageable_down.emplace_back(dst, d_out[l], T);
+          pageable_down.emplace_back(dst, d_out[l], cw * T);
       }
     }
   }
   wave_begin.push_back((int32_t)units.size());
+  hwave_begin.push_back((int32_t)hunits.size());
   if (copies.size() > 65535) return fail_e(hipErrorInvalidValue, "too many copies in one step");
   // one metadata block
+  const size_t KL = items.size(), KH = hitems.size();
   const size_t o_items = 0;
-  const size_t o_stage = align_up(o_items + K * sizeof(WorkItem));
-  const size_t o_copy = align_up(o_stage + K * sizeof(StageItem));
+  const size_t o_stage = align_up(o_items + KL * sizeof(WorkItem));
+  const size_t o_copy = align_up(o_stage + KL * sizeof(StageItem));
   const size_t o_units = align_up(o_copy + copies.size() * sizeof(CopyItem));
   const size_t o_wave = align_up(o_units + units.size() * sizeof(WorkUnit));
-  const size_t total = align_up(o_wave + wave_begin.size() * sizeof(int32_t));
+  const size_t o_hitems = align_up(o_wave + wave_begin.size() * sizeof(int32_t));
+  const size_t o_hprep = align_up(o_hitems + KH * sizeof(HelmWorkItem));
+  const size_t o_hunits = align_up(o_hprep + KH * sizeof(HelmPrepItem));
+  const size_t o_hwave = align_up(o_hunits + hunits.size() * sizeof(WorkUnit));
+  const size_t total = align_up(o_hwave + hwave_begin.size() * sizeof(int32_t));
   if (ss.cap_meta < total) {
     if (ss.d_meta) (void)hipFree(ss.d_meta);
     if (ss.h_meta) (void)hipHostFree(ss.h_meta);
@@ -296,21 +382,38 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     if (e != hipSuccess) return fail_e(e, "step metadata buffers");
     ss.cap_meta = cap;
   }
-  std::memcpy(ss.h_meta + o_items, items.data(), K * sizeof(WorkItem));
-  std::memcpy(ss.h_meta + o_stage, stage.data(), K * sizeof(StageItem));
-  if (!copies.empty()) std::memcpy(ss.h_meta + o_copy, copies.data(), copies.size() * sizeof(CopyItem));
-  if (!units.empty()) std::memcpy(ss.h_meta + o_units, units.data(), units.size() * sizeof(WorkUnit));
-  std::memcpy(ss.h_meta + o_wave, wave_begin.data(), wave_begin.size() * sizeof(int32_t));
+  auto put = [&](size_t o, const void *src, size_t n) {
+    if (n) std::memcpy(ss.h_meta + o, src, n);
+  };
+  put(o_items, items.data(), KL * sizeof(WorkItem));
+  put(o_stage, stage.data(), KL * sizeof(StageItem));
+  put(o_copy, copies.data(), copies.size() * sizeof(CopyItem));
+  put(o_units, units.data(), units.size() * sizeof(WorkUnit));
+  put(o_wave, wave_begin.data(), wave_begin.size() * sizeof(int32_t));
+  put(o_hitems, hitems.data(), KH * sizeof(HelmWorkItem));
+  put(o_hprep, hprep.data(), KH * sizeof(HelmPrepItem));
+  put(o_hunits, hunits.data(), hunits.size() * sizeof(WorkUnit));
+  put(o_hwave, hwave_begin.data(), hwave_begin.size() * sizeof(int32_t));
   e = hipMemcpyAsync(ss.d_meta, ss.h_meta, total, hipMemcpyHostToDevice, s);
-  for (size_t i = 0; i < pageable_up.size() && e == hipSuccess; ++i)
-    e = hipMemcpyAsync(std::get<0>(pageable_up[i]), std::get<1>(pageable_up[i]),
-                       std::get<2>(pageable_up[i]) * sizeof(double), hipMemcpyHostToDevice, s);
+  for (size_t i = 0; i < dma_up.size() && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(std::get<0>(dma_up[i]), std::get<1>(dma_up[i]),
+                       std::get<2>(dma_up[i]) * sizeof(double), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail_e(e, "step upload");
-  e = launch_stage_multi((const StageItem *)(ss.d_meta + o_stage), (int)K, max_n, s);
+  e = launch_stage_multi((const StageItem *)(ss.d_meta + o_stage), (int)KL, max_n, s);
+  if (e == hipSuccess && KH)
+    e = launch_helm_prepare_multi((const HelmPrepItem *)(ss.d_meta + o_hprep), (int)KH, hmax_n,
+                                  hmax_t, s);
   if (e == hipSuccess && !units.empty()) {
     PersistentArgs a{(const WorkItem *)(ss.d_meta + o_items), (const WorkUnit *)(ss.d_meta + o_units),
                      (const int32_t *)(ss.d_meta + o_wave), (int32_t)wave_begin.size() - 1};
     e = launch_persistent(a, lc.get(), p_all, tn, s);
+  }
+  if (e == hipSuccess && !hunits.empty()) {
+    HelmPersistentArgs a{(const HelmWorkItem *)(ss.d_meta + o_hitems),
+                         (const WorkUnit *)(ss.d_meta + o_hunits),
+                         (const int32_t *)(ss.d_meta + o_hwave), (int32_t)hwave_begin.size() - 1};
+    e = launch_helm_persistent(a, h_same && h_first >= 1 && h_first <= 7 ? h_first : kLayersAny,
+                               tn, s);
   }
   if (e == hipSuccess)
     e = launch_copy_multi((const CopyItem *)(ss.d_meta + o_copy), (int)copies.size(), max_t, s);
@@ -448,13 +551,14 @@ void tsqbx_server::completer() {
     const double t1 = now_s();
     for (Request *r : step.reqs) {
       const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
+      const size_t cw = r->cw();
       if (qerr == hipSuccess) {
         if (!r->borrowed && T) {
-          const double *h = r->h_stage + N;
+          const double *h = r->h_stage + cw * N;
           for (int l = 0; l < 3; ++l)
             if (r->layers & (1u << l)) {
-              std::memcpy(r->out[l], h, T * sizeof(double));
-              h += T;
+              std::memcpy(r->out[l], h, cw * T * sizeof(double));
+              h += cw * T;
             }
         }
         ++st.completed;
@@ -488,6 +592,16 @@ int tsqbx_server_request_bytes(const tsqbx_geometry *geom, unsigned layers, size
   if (!geom || !out) return fail(TSQBX_E_INVALID, "geometry or out is NULL");
   if (layers == 0 || (layers & ~7u)) return fail(TSQBX_E_INVALID, "bad layer mask %u", layers);
   *out = request_bytes(geom, layers);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_request_bytes_helmholtz(const tsqbx_geometry *geom, int p, unsigned layers,
+                                         size_t *out) {
+  if (!geom || !out) return fail(TSQBX_E_INVALID, "geometry or out is NULL");
+  if (layers == 0 || (layers & ~7u)) return fail(TSQBX_E_INVALID, "bad layer mask %u", layers);
+  if (p < 0 || p > TSQBX_P_MAX)
+    return fail(TSQBX_E_RANGE, "expansion order p = %d is outside [0, %d]", p, TSQBX_P_MAX);
+  *out = request_bytes_helm(geom, p, layers);
   return TSQBX_OK;
 }
 
@@ -549,12 +663,14 @@ static bool is_pinned_host(const void *p) {
   return a.type == hipMemoryTypeHost;
 }
 
+// k > 0: a Helmholtz request (complex density and outputs, interleaved).
 static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
-                       const double *sigma_host, double *const out_host[3], uint64_t *ticket,
-                       bool borrow) {
+                       double k, const double *sigma_host, double *const out_host[3],
+                       uint64_t *ticket, bool borrow) {
   if (!sv || !geom || !ticket) return fail(TSQBX_E_INVALID, "server, geometry or ticket is NULL");
   if (geom->ctx != sv->ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
-  int rc = tsqbx_check_request(geom, p, layers);
+  const bool helm = k != 0.0;
+  int rc = helm ? check_helmholtz_request(geom, p, layers, k) : tsqbx_check_request(geom, p, layers);
   if (rc != TSQBX_OK) return rc;
   if (geom->n_sources > 0 && !sigma_host) return fail(TSQBX_E_INVALID, "sigma is NULL");
   for (int l = 0; l < 3; ++l)
@@ -568,17 +684,19 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
       if (!is_pinned_host(b))
         return fail(TSQBX_E_INVALID, "submit_pinned: a buffer is not pinned host memory");
   }
-  const size_t bytes = request_bytes(geom, layers);
+  const size_t bytes = helm ? request_bytes_helm(geom, p, layers) : request_bytes(geom, layers);
   auto *r = new Request;
   r->geom = geom;
   r->p = p;
   r->layers = layers;
+  r->k = helm ? k : 0.0;
+  const size_t cw = r->cw();
   const size_t N = (size_t)geom->n_sources, T = (size_t)geom->n_targets;
   if (borrow) {
     r->borrowed = true;
     r->sigma_src = sigma_host;
   } else {
-    const size_t words = N + T * n_layers(layers);
+    const size_t words = cw * (N + T * n_layers(layers));
     r->pin_bytes = align_up(std::max<size_t>(words, 1) * sizeof(double));
     {
       std::lock_guard<std::mutex> g(sv->pinned_mu);
@@ -590,7 +708,7 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
       r->pageable.resize(std::max<size_t>(words, 1));
       r->h_stage = r->pageable.data();
     }
-    if (N) std::memcpy(r->h_stage, sigma_host, N * sizeof(double));
+    if (N) std::memcpy(r->h_stage, sigma_host, cw * N * sizeof(double));
     r->sigma_src = r->h_stage;
   }
   for (int l = 0; l < 3; ++l) r->out[l] = (layers & (1u << l)) ? out_host[l] : nullptr;
@@ -621,14 +739,23 @@ int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, uns
                         const double *sigma_host, double *out_slp_host, double *out_dlp_host,
                         double *out_sprime_host, uint64_t *ticket) {
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
-  return submit_impl(sv, geom, p, layers, sigma_host, outs, ticket, false);
+  return submit_impl(sv, geom, p, layers, 0.0, sigma_host, outs, ticket, false);
 }
 
 int tsqbx_server_submit_pinned(tsqbx_server *sv, const tsqbx_geometry *geom, int p,
                                unsigned layers, const double *sigma_host, double *out_slp_host,
                                double *out_dlp_host, double *out_sprime_host, uint64_t *ticket) {
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
-  return submit_impl(sv, geom, p, layers, sigma_host, outs, ticket, true);
+  return submit_impl(sv, geom, p, layers, 0.0, sigma_host, outs, ticket, true);
+}
+
+int tsqbx_server_submit_helmholtz(tsqbx_server *sv, const tsqbx_geometry *geom, int p,
+                                  unsigned layers, double k, const double *sigma_host,
+                                  double *out_slp_host, double *out_dlp_host,
+                                  double *out_sprime_host, uint64_t *ticket) {
+  if (!(k > 0.0)) return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
+  double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
+  return submit_impl(sv, geom, p, layers, k, sigma_host, outs, ticket, false);
 }
 
 int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {

@@ -281,3 +281,71 @@ def test_plan_edge_cases(ctx):
     assert_parity(items[0]["out_dlp"].cpu().numpy(), ref["dlp"], ref["abs_dlp"], what="dlp")
     assert not items[1]["out_slp"].any() and not items[1]["out_dlp"].any()
     plan.close()
+
+
+def test_server_mixes_helmholtz_and_laplace_requests(ctx):
+    """Helmholtz requests (complex density and outputs) share steps with
+    Laplace ones: each result is the same served alone or in the mix, equals
+    the plain Helmholtz call with the server's group width bit for bit, and
+    the Helmholtz oracle to the parity bar."""
+    from oracle import helmholtz as H
+
+    geoms = W.config_e_geometries(n_geometries=4, scale=32)
+    gs = [ctx.geometry(g) for g in geoms]
+    rng = np.random.default_rng(12)
+    reqs = []
+    for i in range(30):
+        j = int(rng.integers(0, len(geoms)))
+        if i % 2:
+            sig = rng.standard_normal(geoms[j].n_sources) + 1j * rng.standard_normal(geoms[j].n_sources)
+            reqs.append(("h", j, int(rng.choice([4, 8, 12])), int(rng.choice([1, 2, 3, 4, 7])),
+                         float(rng.choice([2.0, 10.0])), sig))
+        else:
+            reqs.append(("l", j, int(rng.choice([8, 16])), int(rng.choice([1, 2, 3])), 0.0,
+                         rng.standard_normal(geoms[j].n_sources)))
+    budget = 4 * max(max(api.Server.request_bytes(g, 3) for g in gs),
+                     max(api.Server.request_bytes_helmholtz(g, 12, 7) for g in gs))
+    srv = ctx.server(budget, 8)
+
+    def submit(kind, j, p, lay, k, sig):
+        if kind == "h":
+            return srv.submit_helmholtz(gs[j], sig, p, lay, k)
+        return srv.submit(gs[j], sig, p, lay)
+
+    alone = []
+    for rq in reqs:
+        t = submit(*rq)
+        srv.wait(t[0], 60)
+        alone.append(t[1:])
+    mixed = [submit(*rq) for rq in reqs]
+    srv.drain(120)
+    st = srv.stats()
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    assert st["peak_bytes_in_flight"] <= budget
+    for rq, a, m in zip(reqs, alone, mixed):
+        for x, y in zip(a, m[1:]):
+            assert (x is None and y is None) or np.array_equal(x, y), rq[:5]
+    # Helmholtz against the plain call (the server runs 16 lanes per target)
+    # and the oracle
+    checked = 0
+    for (kind, j, p, lay, k, sig), a in zip(reqs, alone):
+        if kind != "h" or checked >= 5:
+            continue
+        checked += 1
+        geom = gs[j]
+        ctx.set_tuning(p, lay | api.HELMHOLTZ, max(-(-geom.pairs // geom.n_targets), 1), group_lanes=16)
+        plain = ctx.eval_helmholtz(geom, sig, p, lay, k)
+        ref = H.evaluate_geometry(geoms[j], k, sig, p=p, layers=lay)
+        for bit, key, got, pl in zip((1, 2, 4), ("slp", "dlp", "sprime"), a, plain):
+            if lay & bit:
+                assert np.array_equal(got, pl), (p, lay, key)
+                assert_parity(got, ref[key], ref["abs_" + key], what=f"served Helmholtz {key}")
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.submit_helmholtz(gs[0], np.zeros(geoms[0].n_sources, complex), 8, 1, 0.0)
+    assert ei.value.code == -2
+    srv.close()
+    small = ctx.server(api.Server.request_bytes_helmholtz(gs[0], 8, 1) // 2, 2)
+    with pytest.raises(api.TsqbxError) as ei:
+        small.submit_helmholtz(gs[0], np.zeros(geoms[0].n_sources, complex), 8, 1, 3.0)
+    assert ei.value.code == -5
+    small.close()
