@@ -359,10 +359,12 @@ def bench_serve(ctx, api, torch, W, n_requests):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    helm = bench_serve_helmholtz(ctx, torch, gs, reqs[:300])
     for g in gs:
         g.close()
     sat_stats = st_sat
     return {
+        "helmholtz": helm,
         "workload": f"{n_requests} requests, Poisson arrivals at 0.7x saturation, 32 resident "
                     "geometries N log-uniform 4096..262144, p in {8,16}, single or double layer, "
                     "densities and outputs in pinned host memory",
@@ -388,6 +390,47 @@ def bench_serve(ctx, api, torch, W, n_requests):
         "saturation_busy_s": sat_stats["busy_s"],
         "saturation_wall_s": sat_s,
     }
+
+
+def bench_serve_helmholtz(ctx, torch, gs, reqs, k=10.0):
+    """Helmholtz requests (single + double layer, k = 10, each request's
+    geometry and order) on the serving geometries, densities and outputs in
+    pinned host memory: one plain synchronous tsqbx_eval_helmholtz per request
+    against the server at saturation (pinned submissions)."""
+    rng = np.random.default_rng(20181103)
+    sig, outs = [], []
+    for r in reqs:
+        g = gs[r.geometry]
+        t = torch.empty(g.n_sources, dtype=torch.complex128, pin_memory=True)
+        t.numpy()[:] = rng.standard_normal(g.n_sources) + 1j * rng.standard_normal(g.n_sources)
+        sig.append(t)
+        outs.append([torch.empty(g.n_targets, dtype=torch.complex128, pin_memory=True)
+                     for _ in range(2)])
+    per_req = [gs[r.geometry].pair_terms(r.p, 3) for r in reqs]
+    log(f"serving Helmholtz: {len(reqs)} plain synchronous calls")
+    for r, s_, o in list(zip(reqs, sig, outs))[:20]:  # warm-up
+        ctx.eval_helmholtz(gs[r.geometry], s_.numpy(), r.p, 3, k, o[0].numpy(), o[1].numpy())
+    t0 = time.perf_counter()
+    for r, s_, o in zip(reqs, sig, outs):
+        ctx.eval_helmholtz(gs[r.geometry], s_.numpy(), r.p, 3, k, o[0].numpy(), o[1].numpy())
+    plain_s = time.perf_counter() - t0
+    srv = ctx.server(2 << 30, SERVE_SLOTS)
+    log("serving Helmholtz: saturation run")
+    t0 = time.perf_counter()
+    for r, s_, o in zip(reqs, sig, outs):
+        srv.submit_helmholtz_pinned(gs[r.geometry], s_, r.p, 3, k, out_slp=o[0], out_dlp=o[1])
+    srv.drain(600)
+    sat_s = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return {"workload": f"{len(reqs)} Helmholtz requests (k={k:g}, single + double layer, p in "
+                        "{8,16}) on the serving geometries, densities and outputs in pinned "
+                        "host memory",
+            "plain_sequential_rps": len(reqs) / plain_s,
+            "saturation_rps": len(reqs) / sat_s,
+            "saturation_pair_terms_per_s": sum(per_req) / sat_s,
+            "speedup_saturation_vs_plain": plain_s / sat_s,
+            "failed": st["failed"]}
 
 
 def bench_host_call(ctx, g, geom, steps, p=16, layers=3):

@@ -372,6 +372,13 @@ int tsqbx_server_submit_helmholtz(tsqbx_server *srv, const tsqbx_geometry *geom,
                                   unsigned layers, double k, const double *sigma_host,
                                   double *out_slp_host, double *out_dlp_host,
                                   double *out_sprime_host, uint64_t *ticket);
+/* The same without copies: sigma_host and the outputs are the caller's
+ * pinned host buffers (as for tsqbx_server_submit_pinned), unmodified and
+ * valid until the ticket completes. */
+int tsqbx_server_submit_helmholtz_pinned(tsqbx_server *srv, const tsqbx_geometry *geom, int p,
+                                         unsigned layers, double k, const double *sigma_host,
+                                         double *out_slp_host, double *out_dlp_host,
+                                         double *out_sprime_host, uint64_t *ticket);
 /* Bytes a Helmholtz request of order p with these layers reserves. */
 int tsqbx_server_request_bytes_helmholtz(const tsqbx_geometry *geom, int p, unsigned layers,
                                          size_t *out);

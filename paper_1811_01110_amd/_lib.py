@@ -119,6 +119,9 @@ _SIGNATURES = {
     "tsqbx_server_submit_helmholtz": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double,
                                               c_void_p, c_void_p, c_void_p, c_void_p,
                                               P(c_uint64)]),
+    "tsqbx_server_submit_helmholtz_pinned": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double,
+                                                     c_void_p, c_void_p, c_void_p, c_void_p,
+                                                     P(c_uint64)]),
     "tsqbx_server_request_bytes_helmholtz": (c_int, [c_void_p, c_int, c_uint, P(c_size_t)]),
     "tsqbx_server_poll": (c_int, [c_void_p, c_uint64, P(c_int)]),
     "tsqbx_server_wait": (c_int, [c_void_p, c_uint64, c_double]),

@@ -449,14 +449,24 @@ class Server:
         sigma and the outputs (allocated pinned if not given) must stay valid
         until the ticket completes.  Returns (ticket, out_slp, out_dlp, out_sprime).
         """
+        return self._submit_pinned(geom, sigma, p, layers, (out_slp, out_dlp, out_sprime), None)
+
+    def submit_helmholtz_pinned(self, geom: Geometry, sigma, p: int, layers: int, k: float,
+                                out_slp=None, out_dlp=None, out_sprime=None):
+        """submit_pinned for a Helmholtz request (complex128 pinned tensors)."""
+        return self._submit_pinned(geom, sigma, p, layers, (out_slp, out_dlp, out_sprime), k)
+
+    def _submit_pinned(self, geom, sigma, p, layers, outs_in, k):
         import torch
+
+        dtype = torch.float64 if k is None else torch.complex128
 
         def pinned(t, n, name):
             if t is None:
                 return None
             # whether the memory is pinned is checked by the library
-            if t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
-                raise ValueError(f"{name} must be a contiguous float64 CPU tensor")
+            if t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dtype} CPU tensor")
             if t.numel() != n:
                 raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
             return t
@@ -464,19 +474,22 @@ class Server:
         T = geom.n_targets
         sigma = pinned(sigma, geom.n_sources, "sigma")
         outs = []
-        for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
-                                ("out_slp", "out_dlp", "out_sprime")):
+        for o, bit, name in zip(outs_in, LAYER_BITS, ("out_slp", "out_dlp", "out_sprime")):
             if not layers & bit:
                 outs.append(None)
                 continue
             if o is None:
-                o = torch.empty(T, dtype=torch.float64, pin_memory=True)
+                o = torch.empty(T, dtype=dtype, pin_memory=True)
             outs.append(pinned(o, T, name))
         tk = ctypes.c_uint64()
-        _check(_lib().tsqbx_server_submit_pinned(
-            self.handle, geom.handle, int(p), int(layers),
-            sigma.data_ptr() if sigma is not None else None,
-            *[o.data_ptr() if o is not None else None for o in outs], ctypes.byref(tk)))
+        ptrs = [sigma.data_ptr() if sigma is not None else None] + \
+            [o.data_ptr() if o is not None else None for o in outs]
+        if k is None:
+            _check(_lib().tsqbx_server_submit_pinned(self.handle, geom.handle, int(p), int(layers),
+                                                     *ptrs, ctypes.byref(tk)))
+        else:
+            _check(_lib().tsqbx_server_submit_helmholtz_pinned(
+                self.handle, geom.handle, int(p), int(layers), float(k), *ptrs, ctypes.byref(tk)))
         self._live[tk.value] = tuple(outs) + (sigma,)
         return (tk.value,) + tuple(outs)
 

@@ -758,6 +758,15 @@ int tsqbx_server_submit_helmholtz(tsqbx_server *sv, const tsqbx_geometry *geom, 
   return submit_impl(sv, geom, p, layers, k, sigma_host, outs, ticket, false);
 }
 
+int tsqbx_server_submit_helmholtz_pinned(tsqbx_server *sv, const tsqbx_geometry *geom, int p,
+                                         unsigned layers, double k, const double *sigma_host,
+                                         double *out_slp_host, double *out_dlp_host,
+                                         double *out_sprime_host, uint64_t *ticket) {
+  if (!(k > 0.0)) return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
+  double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
+  return submit_impl(sv, geom, p, layers, k, sigma_host, outs, ticket, true);
+}
+
 int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {
   if (!sv || !done) return fail(TSQBX_E_INVALID, "server or done is NULL");
   std::lock_guard<std::mutex> lk(sv->mu);

@@ -349,3 +349,26 @@ def test_server_mixes_helmholtz_and_laplace_requests(ctx):
         small.submit_helmholtz(gs[0], np.zeros(geoms[0].n_sources, complex), 8, 1, 3.0)
     assert ei.value.code == -5
     small.close()
+
+
+def test_server_pinned_helmholtz_submissions_match_copying_ones(ctx):
+    import torch
+
+    geoms = W.config_e_geometries(n_geometries=3, scale=32)
+    gs = [ctx.geometry(g) for g in geoms]
+    srv = ctx.server(4 * max(api.Server.request_bytes_helmholtz(g, 16, 7) for g in gs), 6)
+    rng = np.random.default_rng(13)
+    runs = []
+    for i in range(9):
+        j, p, lay = i % 3, (8, 16)[i % 2], (1, 3, 7)[i % 3]
+        sig = rng.standard_normal(geoms[j].n_sources) + 1j * rng.standard_normal(geoms[j].n_sources)
+        pin = torch.empty(geoms[j].n_sources, dtype=torch.complex128, pin_memory=True)
+        pin.numpy()[:] = sig
+        runs.append((srv.submit_helmholtz(gs[j], sig, p, lay, 6.0),
+                     srv.submit_helmholtz_pinned(gs[j], pin, p, lay, 6.0), pin))
+    srv.drain(120)
+    assert srv.stats()["failed"] == 0
+    for copied, pinned, _ in runs:
+        for a, b in zip(copied[1:], pinned[1:]):
+            assert (a is None and b is None) or np.array_equal(a, b.numpy())
+    srv.close()
