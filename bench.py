@@ -479,6 +479,49 @@ def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
     return res
 
 
+def bench_conventional(ctx, api, torch, W, g, geom, steps, warmup):
+    """Target-specific single layer against conventional QBX (local coefficients
+    formed per center from its list, then evaluated; the first approach of
+    Sec. 2.4) on the same geometry, order and outputs.  The paper's claim is
+    the cost ratio: O(p+1) per source-target pair against O((p+1)^2) per
+    source-center pair."""
+    res = {}
+    cases = [("sphere262144", g, geom, (5, 8, 16))]
+    ga = W.config_a()
+    geom_a = ctx.geometry(ga)
+    cases.append(("dense4096", ga, geom_a, (8,)))
+    for name, gg, gm, orders in cases:
+        sig = torch.tensor(gg.sigma, device="cuda", dtype=torch.float64)
+        o1 = torch.zeros(gg.n_targets, device="cuda", dtype=torch.float64)
+        o2 = torch.zeros(gg.n_targets, device="cuda", dtype=torch.float64)
+        for p in orders:
+            ts = lambda: ctx.eval_async(gm, sig, p, 1, o1)
+            cv = lambda: ctx.eval_conventional_async(gm, sig, p, o2)
+            log(f"timing target-specific vs conventional, {name} p={p}")
+            w_ts, ev_ts = timed_steps(ts, steps, warmup, torch)
+            w_cv, ev_cv = timed_steps(cv, max(steps // 4, 3), 2, torch)
+            n_cv = max(steps // 4, 3)
+            torch.cuda.synchronize()
+            d = (o1 - o2).abs().max().item()
+            scale = o1.abs().max().item()
+            res[f"{name}_p{p}"] = {
+                "pairs": gm.pairs, "n_targets": gg.n_targets, "p": p,
+                "target_specific_ms": ev_ts / steps * 1e3,
+                "conventional_ms": ev_cv / n_cv * 1e3,
+                "speedup_target_specific": (ev_cv / n_cv) / (ev_ts / steps),
+                "target_specific_pair_terms_per_s": gm.pair_terms(p, 1) / (ev_ts / steps),
+                "max_abs_diff_over_max_abs": d / scale if scale > 0 else 0.0,
+            }
+        del sig, o1, o2
+    geom_a.close()
+    res["workload"] = ("single layer through tsqbx_eval_async (target-specific) and "
+                       "tsqbx_eval_conventional_async (coefficients formed per center and "
+                       "evaluated in one launch) on the p=16 perturbed sphere (262144 sources, "
+                       "65536 targets) and the dense 4096-source sphere; times from HIP events, "
+                       "staging included in both")
+    return res
+
+
 def helm_flops_per_pair(p: int, layers: int, sincos_flops: int = HELM_SINCOS_FLOPS) -> int:
     """FP64 operations per pair of the Helmholtz kernel (add/mul = 1,
     fma = 2, reciprocal-square-root estimate = 1), by the operations each
@@ -623,8 +666,9 @@ def main():
     ap.add_argument("--no-sprime", action="store_true")
     ap.add_argument("--no-helmholtz", action="store_true")
     ap.add_argument("--no-lists", action="store_true")
+    ap.add_argument("--no-conventional", action="store_true")
     ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime",
-                                       "helmholtz", "helm_batched", "lists"],
+                                       "helmholtz", "helm_batched", "lists", "conventional"],
                     help="run one section (for profiling); the JSON line then carries only it")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 256 MiB device copy first (for counter calibration)")
@@ -642,7 +686,8 @@ def main():
 
     if args.calibration_copy:
         calibration_copy(torch)
-    if args.only and args.only not in ("headline", "sprime", "helmholtz", "lists"):
+    if args.only and args.only not in ("headline", "sprime", "helmholtz", "lists",
+                                       "conventional"):
         ctx = api.Context(0)
         fn = {"batched": bench_batched, "high_order": bench_d,
               "helm_batched": bench_helm_batched}.get(args.only)
@@ -659,9 +704,11 @@ def main():
     p, layers = 16, 3
     ctx = api.Context(0)
     geom = ctx.geometry(g)
-    if args.only in ("sprime", "helmholtz", "lists"):
+    if args.only in ("sprime", "helmholtz", "lists", "conventional"):
         if args.only == "lists":
             res = bench_lists(ctx, api, torch, g, args.steps, with_host=False)
+        elif args.only == "conventional":
+            res = bench_conventional(ctx, api, torch, W, g, geom, args.steps, args.warmup)
         else:
             fn = bench_sprime if args.only == "sprime" else bench_helmholtz
             res = fn(ctx, api, torch, g, geom, args.steps, args.warmup)
@@ -729,6 +776,9 @@ def main():
         out["helmholtz"] = bench_helmholtz(ctx, api, torch, g, geom, args.steps, args.warmup)
     if not args.no_lists:
         out["lists"] = bench_lists(ctx, api, torch, g, args.steps, with_host=not args.no_cpu)
+    if not args.no_conventional:
+        out["conventional"] = bench_conventional(ctx, api, torch, W, g, geom, args.steps,
+                                                 args.warmup)
     geom.close()
     del sig, os_, od_
     if not args.no_batched:

@@ -167,6 +167,47 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned
                      double *d_out_sprime, unsigned flags, void *hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Conventional QBX, Laplace single layer (Sec. 2.3; the first approach of
+ * Sec. 2.4): the comparator of the target-specific evaluation, O((p+1)^2)
+ * work per (source, center) instead of O(p+1) per (source, target).
+ *
+ * Local coefficients of a center c (eq. local-coeffs summed over its list
+ * with q_y = w_y sigma_y, eq. pt-pot):
+ *   L_n^m(c) = sum_{y in L(c)} q_y Y_n^{-m}(y - c) / ((2n+1) |y - c|^{n+1}),
+ * n = 0..p, Y_n^m of eq. sph-harm with P_n^{|m|} taken without the
+ * Condon-Shortley factor, so that L_n^{-m} = conj(L_n^m) for real sigma.
+ * Evaluation at a target t of center c (eq. local-expansion truncated after
+ * n = p):  u(t) = sum_n sum_{|m|<=n} L_n^m |t - c|^n Y_n^m(t - c), which
+ * equals the target-specific single layer of tsqbx_eval (eq. tsqbx) up to
+ * rounding.
+ *
+ * d_coeffs: [n_centers][(p+1)^2] float64, device memory, compact real
+ * layout: degree n at offset n^2 holds Re L_n^0, then Re L_n^m, Im L_n^m for
+ * m = 1..n.  Only the rows of centers that at least one target uses are
+ * written or read; the others are left untouched.  d_sigma [N] (caller's
+ * source order) and d_out [T] (caller's target order) are device pointers;
+ * work runs asynchronously on hip_stream and the buffers must stay valid
+ * until it completes.  TSQBX_ACCUMULATE adds into d_coeffs (form) or d_out
+ * (evaluate, form-and-evaluate) instead of overwriting.  Errors as for
+ * tsqbx_eval_async: p outside [0, TSQBX_P_MAX] is TSQBX_E_RANGE, a NULL buffer
+ * that would be touched is TSQBX_E_INVALID.  The form and the
+ * form-and-evaluate calls use the geometry's staging buffer, as
+ * tsqbx_eval_async does (same overlap rule).
+ * ------------------------------------------------------------------------- */
+/* P2QBXL: form the coefficients of every center that a target uses. */
+int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p,
+                          const double *d_sigma, double *d_coeffs, unsigned flags,
+                          void *hip_stream);
+/* QBXL2P: evaluate given coefficients at every target. */
+int tsqbx_qbxl_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p,
+                          const double *d_coeffs, double *d_out, unsigned flags,
+                          void *hip_stream);
+/* Both in one launch; the coefficients stay on chip and are not written. */
+int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p,
+                                  const double *d_sigma, double *d_out, unsigned flags,
+                                  void *hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Helmholtz kernel (App. A, Helmholtz case), real wavenumber k > 0:
  *
  *   G_k^(p)(t, y) = (i k / 4 pi) sum_{n=0..p} (2n+1) j_n(k|t-c|) h_n(k|y-c|) P_n(cos gamma)

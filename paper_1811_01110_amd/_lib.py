@@ -94,6 +94,12 @@ _SIGNATURES = {
                            c_void_p, c_uint]),
     "tsqbx_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_uint, c_void_p]),
+    "tsqbx_qbxl_form_async": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_uint,
+                                      c_void_p]),
+    "tsqbx_qbxl_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_uint,
+                                      c_void_p]),
+    "tsqbx_eval_conventional_async": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p,
+                                              c_uint, c_void_p]),
     "tsqbx_eval_helmholtz": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_uint]),
     "tsqbx_eval_helmholtz_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_double, c_void_p,

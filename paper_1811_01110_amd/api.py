@@ -176,6 +176,32 @@ class Context:
         _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, *ptrs,
                                        int(flags), _stream_handle(stream)))
 
+    def qbxl_form_async(self, geom: "Geometry", sigma, p: int, coeffs, flags: int = 0,
+                        stream=None):
+        """Conventional QBX: local coefficients of every center a target uses
+        into coeffs, a float64 CUDA tensor of n_centers * (p+1)^2 entries
+        (compact real layout)."""
+        s = _tensor_ptr(sigma, geom.n_sources, "sigma")
+        c = _tensor_ptr(coeffs, geom.n_centers * (p + 1) ** 2, "coeffs")
+        _check(_lib().tsqbx_qbxl_form_async(self.handle, geom.handle, int(p), s, c, int(flags),
+                                            _stream_handle(stream)))
+
+    def qbxl_eval_async(self, geom: "Geometry", coeffs, p: int, out, flags: int = 0,
+                        stream=None):
+        """Conventional QBX: the local expansions in coeffs evaluated at the targets."""
+        c = _tensor_ptr(coeffs, geom.n_centers * (p + 1) ** 2, "coeffs")
+        o = _tensor_ptr(out, geom.n_targets, "out")
+        _check(_lib().tsqbx_qbxl_eval_async(self.handle, geom.handle, int(p), c, o, int(flags),
+                                            _stream_handle(stream)))
+
+    def eval_conventional_async(self, geom: "Geometry", sigma, p: int, out, flags: int = 0,
+                                stream=None):
+        """Conventional QBX single layer, formation and evaluation in one launch."""
+        s = _tensor_ptr(sigma, geom.n_sources, "sigma")
+        o = _tensor_ptr(out, geom.n_targets, "out")
+        _check(_lib().tsqbx_eval_conventional_async(self.handle, geom.handle, int(p), s, o,
+                                                    int(flags), _stream_handle(stream)))
+
     def eval_helmholtz(self, geom: "Geometry", sigma, p: int, layers: int, k: float,
                        out_slp=None, out_dlp=None, out_sprime=None, flags: int = 0):
         """Helmholtz evaluation with host arrays: sigma complex (N,); returns

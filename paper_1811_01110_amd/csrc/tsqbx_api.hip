@@ -213,7 +213,7 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 static void free_geometry(tsqbx_geometry *g) {
   if (!g) return;
   void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
-                  g->stage.posq, g->stage.qn, g->helm.rec, g->helm.tab, g->helm.tabs};
+                  g->ctr, g->row_tgts, g->stage.posq, g->stage.qn, g->helm.rec, g->helm.tab, g->helm.tabs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete g;
@@ -364,6 +364,28 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
     host_row_len[k] = len;
   }
 
+  // rows for the conventional path: center, unpadded list, targets by row
+  std::vector<CenterRec> crec(R);
+  std::vector<int32_t> row_tgts(T);
+  {
+    std::vector<int64_t> cnt(R + 1, 0);
+    for (int64_t k = 0; k < T; ++k) ++cnt[row_of_center[tc[tgt_ord[k]]] + 1];
+    for (int64_t r = 0; r < R; ++r) cnt[r + 1] += cnt[r];
+    for (int64_t r = 0; r < R; ++r) {
+      const int32_t c = (int32_t)row_center[r];
+      CenterRec &x = crec[r];
+      for (int a = 0; a < 3; ++a) x.c[a] = d->centers[3 * c + a];
+      x.row_begin = row_off[r];
+      x.len = (int32_t)(d->list_offsets[c + 1] - d->list_offsets[c]);
+      x.center = c;
+      x.tgt_begin = (int32_t)cnt[r];
+      x.tgt_count = (int32_t)(cnt[r + 1] - cnt[r]);
+      x.pad = 0;
+    }
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t k = 0; k < T; ++k) row_tgts[fill[row_of_center[tc[tgt_ord[k]]]]++] = (int32_t)k;
+  }
+
   std::vector<double4> pos(N), nrm(d->normals ? N : 0);
   std::vector<int64_t> perm(reorder ? N : 0);
   for (int64_t i = 0; i < N; ++i) {
@@ -397,6 +419,9 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   if (e == hipSuccess) e = dev_upload(&g->tgt, recs.data(), T, &bytes);
   if (e == hipSuccess && d->target_normals) e = dev_upload(&g->tgt_nrm, tnrm.data(), T, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->idx, idx.data(), nnz_dev, &bytes);
+  g->n_rows = R;
+  if (e == hipSuccess) e = dev_upload(&g->ctr, crec.data(), R, &bytes);
+  if (e == hipSuccess) e = dev_upload(&g->row_tgts, row_tgts.data(), T, &bytes);
   if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N + 1, &bytes);
   if (e == hipSuccess && d->normals) e = dev_upload<double4>(&g->stage.qn, nullptr, N + 1, &bytes);
   if (e != hipSuccess) {
@@ -459,6 +484,57 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned la
   o.t = d_out_sprime;
   TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, s));
   TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn, s));
+  return TSQBX_OK;
+}
+
+// Conventional QBX (Sec. 2.3): checks shared by the three entry points.
+static int check_conventional(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p) {
+  if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
+  if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
+  return check_request(g, p, TSQBX_SLP);
+}
+
+int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const double *d_sigma,
+                          double *d_coeffs, unsigned flags, void *hip_stream) {
+  int rc = check_conventional(ctx, g, p);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  if (g->n_rows > 0 && !d_coeffs) return fail(TSQBX_E_INVALID, "coefficient buffer is NULL");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
+  TSQBX_HIP(launch_qbxl(g, p, 1, g->stage.posq, nullptr, d_coeffs, nullptr,
+                        (flags & TSQBX_ACCUMULATE) != 0, s));
+  return TSQBX_OK;
+}
+
+int tsqbx_qbxl_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const double *d_coeffs,
+                          double *d_out, unsigned flags, void *hip_stream) {
+  int rc = check_conventional(ctx, g, p);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_rows > 0 && !d_coeffs) return fail(TSQBX_E_INVALID, "coefficient buffer is NULL");
+  if (g->n_targets > 0 && !d_out) return fail(TSQBX_E_INVALID, "output is NULL");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  TSQBX_HIP(launch_qbxl(g, p, 2, nullptr, d_coeffs, nullptr, d_out,
+                        (flags & TSQBX_ACCUMULATE) != 0, (hipStream_t)hip_stream));
+  return TSQBX_OK;
+}
+
+int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p,
+                                  const double *d_sigma, double *d_out, unsigned flags,
+                                  void *hip_stream) {
+  int rc = check_conventional(ctx, g, p);
+  if (rc != TSQBX_OK) return rc;
+  if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
+  if (g->n_targets > 0 && !d_out) return fail(TSQBX_E_INVALID, "output is NULL");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
+  TSQBX_HIP(launch_qbxl(g, p, 3, g->stage.posq, nullptr, nullptr, d_out,
+                        (flags & TSQBX_ACCUMULATE) != 0, s));
   return TSQBX_OK;
 }
 

@@ -26,6 +26,20 @@ struct alignas(64) TargetRec {
 };
 static_assert(sizeof(TargetRec) == 64, "TargetRec layout");
 
+// One device row (a center that at least one target uses) for the
+// conventional path: the center, its list (unpadded length), the caller's
+// center index and the row's targets in row_tgts[tgt_begin ..].
+struct alignas(64) CenterRec {
+  double c[3];
+  int64_t row_begin;
+  int32_t len;
+  int32_t center;
+  int32_t tgt_begin;
+  int32_t tgt_count;
+  int64_t pad;
+};
+static_assert(sizeof(CenterRec) == 64, "CenterRec layout");
+
 // Device rows are padded to a multiple of this many entries with index N,
 // which names a zero-strength staging record.
 constexpr int kRowPad = 16;
@@ -93,6 +107,9 @@ struct tsqbx_geometry {
   tsqbx::TargetRec *tgt = nullptr;  // [T] in device order
   double4 *tgt_nrm = nullptr;    // [T] (nx, ny, nz, 0) at the targets, device order, or null
   int32_t *idx = nullptr;        // [nnz'] lists in device numbering, one row per target group
+  int64_t n_rows = 0;            // rows = distinct centers with targets
+  tsqbx::CenterRec *ctr = nullptr;  // [n_rows]
+  int32_t *row_tgts = nullptr;   // [T] device-order targets grouped by row
   tsqbx::SourceStage stage;      // staging used by the plain path
   tsqbx::HelmStage helm;         // Helmholtz staging, allocated on first use
   size_t device_bytes = 0;
@@ -116,6 +133,14 @@ hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
                        const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
 bool tuning_supported(const Tuning &tn);
+// Conventional QBX (tsqbx_conventional.hip): mode 1 forms the local
+// coefficients of every row's center from the staged sources into
+// coeffs_out, mode 2 evaluates coeffs_in at the targets into out, mode 3
+// forms and evaluates in one launch.  Coefficients: [n_centers][(p+1)^2],
+// compact real layout; out in the caller's target order.
+hipError_t launch_qbxl(const tsqbx_geometry *g, int p, int mode, const double4 *posq,
+                       const double *coeffs_in, double *coeffs_out, double *out, bool accumulate,
+                       hipStream_t s);
 // Helmholtz (tsqbx_helmholtz.hip): staging of q = w sigma (sigma complex,
 // interleaved), the per-target table and the pair kernel; outputs complex,
 // interleaved, in the caller's target order.
