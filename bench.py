@@ -479,6 +479,30 @@ def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
     return res
 
 
+def _cpow_flops(m: int) -> int:
+    """FP64 operations of (w)^m by the kernel's squaring chain."""
+    if m <= 1:
+        return 0
+    return _cpow_flops(m // 2) + 5 if m % 2 == 0 else _cpow_flops(m - 1) + 6
+
+
+def conventional_flops_per_pair(p: int) -> int:
+    """FP64 operations (fma = 2) per (source, center) pair of the conventional
+    kernel's formation: for each order m, the source geometry and 1/|y-c|
+    (21), (d_x - i d_y)^m / |y-c|^(2m+1) (4 + the squaring chain), the first
+    two degrees and then 9 per further degree (5 for m = 0, which is real).
+    The per-center lane sums and the per-target evaluation, O((p+1)^2) each,
+    are left out (under 0.1 % on the workloads here)."""
+    tot = 0
+    for m in range(p + 1):
+        f = 21 + (4 + _cpow_flops(m) if m else 0) + (2 if m else 1)
+        if m < p:
+            f += 4 if m else 2
+        f += max(p - m - 1, 0) * (9 if m else 5)
+        tot += f
+    return tot
+
+
 def bench_conventional(ctx, api, torch, W, g, geom, steps, warmup):
     """Target-specific single layer against conventional QBX (local coefficients
     formed per center from its list, then evaluated; the first approach of
@@ -510,6 +534,11 @@ def bench_conventional(ctx, api, torch, W, g, geom, steps, warmup):
                 "conventional_ms": ev_cv / n_cv * 1e3,
                 "speedup_target_specific": (ev_cv / n_cv) / (ev_ts / steps),
                 "target_specific_pair_terms_per_s": gm.pair_terms(p, 1) / (ev_ts / steps),
+                "target_specific_flops_per_pair": flops_per_pair(p, 1),
+                "target_specific_tflops": gm.pairs * flops_per_pair(p, 1) / (ev_ts / steps) / 1e12,
+                "conventional_flops_per_pair": conventional_flops_per_pair(p),
+                "conventional_tflops": gm.pairs * conventional_flops_per_pair(p)
+                / (ev_cv / n_cv) / 1e12,
                 "max_abs_diff_over_max_abs": d / scale if scale > 0 else 0.0,
             }
         del sig, o1, o2
