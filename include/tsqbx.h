@@ -331,6 +331,24 @@ typedef struct {
   size_t device_bytes;   /* plan-owned device memory */
 } tsqbx_plan_info;
 
+/* Host-only preview of the static schedule a Laplace plan runs (touches no
+ * device; the batch decomposition of the batched path).  Item i has
+ * n_targets[i] targets whose list lengths follow one another in row_len (in
+ * the geometry's device order of targets; all items concatenated), order
+ * p[i] and layer mask layers[i].  Items are taken largest first (pairs times
+ * the cost of one pair) and cut into units, runs of consecutive targets of
+ * one item, dealt to at most max_waves waves of group_lanes-lane groups
+ * (16, 32 or 64) at about equal estimated cost.  On return *n_units units
+ * fill units[k] = (item, first target, count) ([units_cap][3] int32) and
+ * wave w works through units wave_begin[w] .. wave_begin[w+1]-1
+ * (wave_begin: max_waves + 1 entries; *n_waves waves used).  A units buffer
+ * that is too small gives TSQBX_E_RANGE with *n_units set; NULL inputs or a
+ * bad group width TSQBX_E_INVALID; p, layers as tsqbx_check_request. */
+int tsqbx_schedule_preview(int64_t n_items, const int64_t *n_targets, const int64_t *row_len,
+                           const int32_t *p, const uint32_t *layers, int group_lanes,
+                           int max_waves, int32_t *units, int64_t units_cap, int64_t *n_units,
+                           int32_t *wave_begin, int32_t *n_waves);
+
 /* Build a plan.  Items' geometries and device buffers must outlive the plan;
  * the same geometry may appear in several items (each item gets its own
  * staging).  flags: TSQBX_ACCUMULATE applies to every item. */

@@ -111,6 +111,9 @@ _SIGNATURES = {
     "tsqbx_get_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_set_tuning": (c_int, [c_void_p, c_int, c_uint, c_int64, P(Tuning)]),
     "tsqbx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_uint, P(Tuning), P(c_double)]),
+    "tsqbx_schedule_preview": (c_int, [c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                       c_int, c_void_p, c_int64, P(c_int64), c_void_p,
+                                       P(ctypes.c_int32)]),
     "tsqbx_plan_create": (c_int, [c_void_p, c_int64, P(Item), c_uint, P(c_void_p)]),
     "tsqbx_plan_create_helmholtz": (c_int, [c_void_p, c_int64, P(HelmItem), c_uint, P(c_void_p)]),
     "tsqbx_plan_execute": (c_int, [c_void_p, c_void_p]),

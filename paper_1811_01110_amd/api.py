@@ -106,6 +106,30 @@ def validate_geometry(**arrays) -> None:
     _check(_lib().tsqbx_validate_geometry(ctypes.byref(d)))
 
 
+def schedule_preview(items, group_lanes: int = 16, max_waves: int = 49152):
+    """Host-only preview of a plan's static schedule (no device needed).
+
+    items: sequence of (row_len, p, layers), row_len the list length of each
+    target in device order.  Returns (units, wave_begin): units an (n, 3)
+    int32 array of (item, first target, count), wave w working through
+    units[wave_begin[w]:wave_begin[w + 1]]."""
+    n = len(items)
+    nt = np.array([len(r) for r, _, _ in items], dtype=np.int64)
+    rl = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.int64) for r, _, _ in items])
+                              if n else np.zeros(0, dtype=np.int64))
+    ps = np.array([p for _, p, _ in items], dtype=np.int32)
+    ls = np.array([l for _, _, l in items], dtype=np.uint32)
+    cap = int(nt.sum()) + 1
+    units = np.zeros((cap, 3), dtype=np.int32)
+    wb = np.zeros(max_waves + 1, dtype=np.int32)
+    nu = ctypes.c_int64(0)
+    nw = ctypes.c_int32(0)
+    _check(_lib().tsqbx_schedule_preview(n, _ptr(nt), _ptr(rl), _ptr(ps), _ptr(ls),
+                                         int(group_lanes), int(max_waves), _ptr(units), cap,
+                                         ctypes.byref(nu), _ptr(wb), ctypes.byref(nw)))
+    return units[:nu.value].copy(), wb[:nw.value + 1].copy()
+
+
 class Context:
     """A library context on one HIP device."""
 

@@ -112,6 +112,18 @@ double helm_pair_cost(int p, unsigned layers) {
 
 namespace tsqbx {
 
+// Items by estimated cost (pairs times the cost of one pair), largest first;
+// ties keep their order.
+std::vector<int32_t> order_largest_first(const std::vector<ScheduleItem> &items) {
+  std::vector<int32_t> ord(items.size());
+  std::iota(ord.begin(), ord.end(), 0);
+  std::vector<double> icost(items.size());
+  for (size_t i = 0; i < items.size(); ++i)
+    icost[i] = (double)items[i].geom->pairs * pair_cost(items[i].p, items[i].layers);
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return icost[a] > icost[b]; });
+  return ord;
+}
+
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
                     int group_lanes, int max_waves, std::vector<WorkUnit> *units,
                     std::vector<int32_t> *wave_begin) {
@@ -166,6 +178,54 @@ void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<in
 
 extern "C" {
 
+int tsqbx_schedule_preview(int64_t n_items, const int64_t *n_targets, const int64_t *row_len,
+                           const int32_t *p, const uint32_t *layers, int group_lanes,
+                           int max_waves, int32_t *units, int64_t units_cap, int64_t *n_units,
+                           int32_t *wave_begin, int32_t *n_waves) {
+  if (n_items < 0 || n_items > 65535)
+    return fail(TSQBX_E_RANGE, "schedule_preview: n_items = %lld is outside [0, 65535]",
+                (long long)n_items);
+  if (!n_units || !n_waves || !wave_begin || (n_items > 0 && (!n_targets || !p || !layers)))
+    return fail(TSQBX_E_INVALID, "schedule_preview: a required pointer is NULL");
+  if (!(group_lanes == 16 || group_lanes == 32 || group_lanes == 64))
+    return fail(TSQBX_E_INVALID, "schedule_preview: group_lanes = %d is not 16, 32 or 64",
+                group_lanes);
+  if (max_waves < 1) return fail(TSQBX_E_RANGE, "schedule_preview: max_waves < 1");
+  // host-only stand-ins for the geometries: target counts and list lengths
+  std::vector<tsqbx_geometry> geo(n_items);
+  std::vector<ScheduleItem> sched(n_items);
+  int64_t off = 0;
+  for (int64_t i = 0; i < n_items; ++i) {
+    if (n_targets[i] < 0) return fail(TSQBX_E_RANGE, "schedule_preview: n_targets < 0");
+    int rc = tsqbx_check_request(nullptr, p[i], layers[i]);
+    if (rc != TSQBX_OK) return rc;
+    if (n_targets[i] > 0 && !row_len) return fail(TSQBX_E_INVALID, "row_len is NULL");
+    geo[i].n_targets = n_targets[i];
+    geo[i].host_row_len.assign(row_len + off, row_len + off + n_targets[i]);
+    for (int64_t v : geo[i].host_row_len) {
+      if (v < 0) return fail(TSQBX_E_RANGE, "schedule_preview: a list length is negative");
+      geo[i].pairs += v;
+    }
+    off += n_targets[i];
+    sched[i] = ScheduleItem{&geo[i], p[i], layers[i]};
+  }
+  std::vector<WorkUnit> u;
+  std::vector<int32_t> wb;
+  build_schedule(sched, order_largest_first(sched), group_lanes, max_waves, &u, &wb);
+  *n_units = (int64_t)u.size();
+  *n_waves = (int32_t)wb.size() - 1;
+  if ((int64_t)u.size() > units_cap || (u.size() && !units))
+    return fail(TSQBX_E_RANGE, "schedule_preview: %lld units do not fit the buffer of %lld",
+                (long long)u.size(), (long long)units_cap);
+  for (size_t k = 0; k < u.size(); ++k) {
+    units[3 * k] = u[k].item;
+    units[3 * k + 1] = u[k].first;
+    units[3 * k + 2] = u[k].count;
+  }
+  std::copy(wb.begin(), wb.end(), wave_begin);
+  return TSQBX_OK;
+}
+
 int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, unsigned flags,
                       tsqbx_plan **out) {
   if (!ctx || !out || n_items < 0 || (n_items > 0 && !items))
@@ -217,19 +277,11 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
   if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, 3u, mean_list);
 
-  // item order: largest first
-  std::vector<int64_t> ord(n_items);
-  std::iota(ord.begin(), ord.end(), 0);
-  std::vector<double> icost(n_items);
-  for (int64_t i = 0; i < n_items; ++i)
-    icost[i] = (double)pl->items[i].geom->pairs * pair_cost(pl->items[i].p, pl->items[i].layers);
-  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return icost[a] > icost[b]; });
-
-  // static schedule over the resident waves
+  // static schedule over the resident waves, items largest first
   std::vector<ScheduleItem> sched(n_items);
   for (int64_t i = 0; i < n_items; ++i)
     sched[i] = ScheduleItem{pl->items[i].geom, pl->items[i].p, pl->items[i].layers};
-  std::vector<int32_t> order32(ord.begin(), ord.end());
+  const std::vector<int32_t> order32 = order_largest_first(sched);
   std::vector<WorkUnit> units;
   std::vector<int32_t> wave_begin;
   build_schedule(sched, order32, pl->tn.group_lanes,
