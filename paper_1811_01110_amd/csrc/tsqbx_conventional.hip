@@ -25,10 +25,10 @@
 // each (zeta, eta = d_z/R^2, 1/R^2 or delta_z, rho^2).
 //
 // Layout: one wave per center row.  For each order m the lanes stride over
-// the row's list; each recomputes the source's geometry and (d_x - i d_y)^m
-// by a fixed chain of squarings, runs the degrees n = m..p and adds into
-// registers; a xor butterfly then sums the lanes and lane 0 stores the
-// scaled coefficients into LDS.  The evaluation reads them from LDS, one
+// the row's list, two entries at a time; each recomputes the source's
+// geometry and (d_x - i d_y)^m by a fixed chain of squarings, runs the
+// degrees n = m..p and adds into registers; a xor butterfly then sums the
+// lanes and lane 0 stores the scaled coefficients into LDS.  The evaluation reads them from LDS, one
 // target per lane.  Coefficients in memory use the compact real layout:
 // (p+1)^2 doubles per center, degree n at offset n^2, holding Re L_n^0 and
 // then Re L_n^m, Im L_n^m for m = 1..n.
@@ -101,30 +101,73 @@ __device__ __forceinline__ void cpow(double wr, double wi, double &pr, double &p
   }
 }
 
-// Degrees n = N..PC of order M (stopping after p unless EXACT); (r1, i1) and
-// (r2, i2) hold the rescaled harmonics of degrees n-1 and n-2.  Adds each
-// degree's value into (ar, ai)[n - M].  REAL: order 0, imaginary parts zero.
-template <int PC, bool EXACT, int M, int N, bool REAL>
-__device__ __forceinline__ void irr_steps(int p, double zz, double ii, double r1, double i1,
-                                          double r2, double i2, double (&ar)[PC - M + 1],
-                                          double (&ai)[PC - M + 1]) {
+// Degrees n = N..PC of order M (stopping after p unless EXACT) for U list
+// entries whose recurrences interleave; (r1, i1) and (r2, i2) hold the
+// rescaled harmonics of degrees n-1 and n-2.  Adds each degree's values into
+// (ar, ai)[n - M], entry 0 first.  REAL: order 0, imaginary parts zero.
+template <int PC, bool EXACT, int M, int N, bool REAL, int U>
+__device__ __forceinline__ void irr_steps(int p, const double (&zz)[U], const double (&ii)[U],
+                                          const double (&r1)[U], const double (&i1)[U],
+                                          const double (&r2)[U], const double (&i2)[U],
+                                          double (&ar)[PC - M + 1], double (&ai)[PC - M + 1]) {
   if constexpr (N <= PC) {
     if constexpr (!EXACT)
       if (N > p) return;
-    double r, i = 0.0;
-    if constexpr (N == M + 1) {
-      r = zz * r1;
-      if constexpr (!REAL) i = zz * i1;
-    } else {
-      constexpr double kap = sh_kap(N, M);
-      const double t = kap * ii;
-      r = fma(zz, r1, -(t * r2));
-      if constexpr (!REAL) i = fma(zz, i1, -(t * i2));
+    double r[U], i[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      i[u] = 0.0;
+      if constexpr (N == M + 1) {
+        r[u] = zz[u] * r1[u];
+        if constexpr (!REAL) i[u] = zz[u] * i1[u];
+      } else {
+        constexpr double kap = sh_kap(N, M);
+        const double t = kap * ii[u];
+        r[u] = fma(zz[u], r1[u], -(t * r2[u]));
+        if constexpr (!REAL) i[u] = fma(zz[u], i1[u], -(t * i2[u]));
+      }
     }
-    ar[N - M] += r;
-    if constexpr (!REAL) ai[N - M] += i;
-    irr_steps<PC, EXACT, M, N + 1, REAL>(p, zz, ii, r, i, r1, i1, ar, ai);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ar[N - M] += r[u];
+      if constexpr (!REAL) ai[N - M] += i[u];
+    }
+    irr_steps<PC, EXACT, M, N + 1, REAL, U>(p, zz, ii, r, i, r1, i1, ar, ai);
   }
+}
+
+// The terms of order M of U list entries (sources s[u]), added into (ar, ai).
+template <int PC, bool EXACT, int M, int U>
+__device__ __forceinline__ void order_terms(int p, const uint32_t (&s)[U], double cx, double cy,
+                                            double cz, const double4 *__restrict__ posq,
+                                            double (&ar)[PC - M + 1], double (&ai)[PC - M + 1]) {
+  double zz[U], ii[U], tr[U], ti[U], z0[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const double4 a = load4(posq, s[u]);
+    const double dx = a.x - cx, dy = a.y - cy, dz = a.z - cz;
+    const double R2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const double rinv = rsqrt_nr(R2);
+    ii[u] = rinv * rinv;
+    zz[u] = dz * ii[u];
+    z0[u] = 0.0;
+    const double qr = a.w * rinv;  // q / R
+    ti[u] = 0.0;                   // (tr, ti) = q (d_x - i d_y)^M / R^{2M+1}
+    if constexpr (M == 0) {
+      tr[u] = qr;
+    } else {
+      double pr, pi;
+      cpow<M>(dx * ii[u], -(dy * ii[u]), pr, pi);
+      tr[u] = qr * pr;
+      ti[u] = qr * pi;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    ar[0] += tr[u];
+    if constexpr (M > 0) ai[0] += ti[u];
+  }
+  irr_steps<PC, EXACT, M, M + 1, M == 0, U>(p, zz, ii, tr, ti, z0, z0, ar, ai);
 }
 
 // Lane 0 stores the summed degrees n = N..min(p, PC) of order M into coef.
@@ -157,26 +200,15 @@ __device__ __forceinline__ void form_orders(int p, int lane, const int32_t *__re
     double ar[K], ai[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) ar[k] = ai[k] = 0.0;
-    for (int j = lane; j < len; j += 64) {
-      const double4 a = load4(posq, load_idx(row, (uint32_t)j));
-      const double dx = a.x - cx, dy = a.y - cy, dz = a.z - cz;
-      const double R2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      const double rinv = rsqrt_nr(R2);
-      const double ii = rinv * rinv;
-      const double zz = dz * ii;
-      const double qr = a.w * rinv;  // q / R
-      double tr, ti = 0.0;           // q (d_x - i d_y)^M / R^{2M+1}
-      if constexpr (M == 0) {
-        tr = qr;
-      } else {
-        double pr, pi;
-        cpow<M>(dx * ii, -(dy * ii), pr, pi);
-        tr = qr * pr;
-        ti = qr * pi;
-      }
-      ar[0] += tr;
-      if constexpr (M > 0) ai[0] += ti;
-      irr_steps<PC, EXACT, M, M + 1, M == 0>(p, zz, ii, tr, ti, 0.0, 0.0, ar, ai);
+    // lane l takes the entries l, l + 64, l + 128, ..., two at a time
+    int j = lane;
+    for (; j + 64 < len; j += 128) {
+      const uint32_t s2[2] = {load_idx(row, (uint32_t)j), load_idx(row, (uint32_t)(j + 64))};
+      order_terms<PC, EXACT, M, 2>(p, s2, cx, cy, cz, posq, ar, ai);
+    }
+    if (j < len) {
+      const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
+      order_terms<PC, EXACT, M, 1>(p, s1, cx, cy, cz, posq, ar, ai);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
