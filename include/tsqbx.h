@@ -166,6 +166,24 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned
                      const double *d_sigma, double *d_out_slp, double *d_out_dlp,
                      double *d_out_sprime, unsigned flags, void *hip_stream);
 
+/* The same evaluation in two steps on device pointers: tsqbx_stage_async
+ * forms the strengths q_y = w_y sigma_y (and q_y nu_y when layers include
+ * TSQBX_DLP) in the geometry's staging buffer (eq. pt-pot); then
+ * tsqbx_eval_staged_async sums the near field from them, as often as wanted
+ * (for instance several orders or layer masks on one density).  Both run
+ * asynchronously on hip_stream; the staging buffer is the one
+ * tsqbx_eval_async uses, with the same overlap rule.  tsqbx_stage_async
+ * checks layers as tsqbx_check_request does (any valid p).
+ * tsqbx_eval_staged_async returns TSQBX_E_STATE when the geometry has not
+ * been staged, or when it asks for the double layer and the last staging did
+ * not include it; other errors as for tsqbx_eval_async.  The results equal
+ * those of tsqbx_eval_async bit for bit. */
+int tsqbx_stage_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, unsigned layers,
+                      const double *d_sigma, void *hip_stream);
+int tsqbx_eval_staged_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
+                            double *d_out_slp, double *d_out_dlp, double *d_out_sprime,
+                            unsigned flags, void *hip_stream);
+
 /* ---------------------------------------------------------------------------
  * Conventional QBX, Laplace single layer (Sec. 2.3; the first approach of
  * Sec. 2.4): the comparator of the target-specific evaluation, O((p+1)^2)
@@ -303,7 +321,8 @@ int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
 
 /* Time every candidate tuning on geom (device-resident sigma of ones) and
  * install the fastest for its (p, layers, list-length) bucket.  *out receives
- * it; best_ms (nullable) the kernel time. */
+ * it; best_ms (nullable) the kernel time.  The geometry's staging buffer is
+ * overwritten, so tsqbx_eval_staged_async needs a new tsqbx_stage_async. */
 int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
                    tsqbx_tuning *out, double *best_ms);
 

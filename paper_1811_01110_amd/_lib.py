@@ -94,6 +94,9 @@ _SIGNATURES = {
                            c_void_p, c_uint]),
     "tsqbx_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_uint, c_void_p]),
+    "tsqbx_stage_async": (c_int, [c_void_p, c_void_p, c_uint, c_void_p, c_void_p]),
+    "tsqbx_eval_staged_async": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,
+                                        c_void_p, c_uint, c_void_p]),
     "tsqbx_qbxl_form_async": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_uint,
                                       c_void_p]),
     "tsqbx_qbxl_eval_async": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_uint,

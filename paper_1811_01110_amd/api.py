@@ -200,6 +200,22 @@ class Context:
         _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, *ptrs,
                                        int(flags), _stream_handle(stream)))
 
+    def stage_async(self, geom: "Geometry", sigma, layers: int, stream=None):
+        """Strengths q = w sigma (and q nu for the double layer) into the
+        geometry's staging buffer, for eval_staged_async."""
+        s = _tensor_ptr(sigma, geom.n_sources, "sigma")
+        _check(_lib().tsqbx_stage_async(self.handle, geom.handle, int(layers), s,
+                                        _stream_handle(stream)))
+
+    def eval_staged_async(self, geom: "Geometry", p: int, layers: int, out_slp=None,
+                          out_dlp=None, out_sprime=None, flags: int = 0, stream=None):
+        """Evaluation from the strengths stage_async left in the geometry."""
+        ptrs = [_tensor_ptr(o, geom.n_targets, name) if layers & bit else None
+                for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
+                                        ("out_slp", "out_dlp", "out_sprime"))]
+        _check(_lib().tsqbx_eval_staged_async(self.handle, geom.handle, int(p), int(layers),
+                                              *ptrs, int(flags), _stream_handle(stream)))
+
     def qbxl_form_async(self, geom: "Geometry", sigma, p: int, coeffs, flags: int = 0,
                         stream=None):
         """Conventional QBX: local coefficients of every center a target uses

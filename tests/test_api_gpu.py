@@ -151,3 +151,40 @@ def test_server_concurrent_submitters(ctx):
         if lay & 2:
             assert_parity(b, ref["dlp"], ref["abs_dlp"], what="threaded dlp")
     srv.close()
+
+
+def test_stage_then_eval_staged_equals_eval(ctx):
+    """Strengths staged once, then several evaluations from them: the same
+    bits as the one-call evaluation; errors when nothing (or not the double
+    layer) was staged, and after the autotuner overwrote the staging."""
+    import torch
+
+    from paper_1811_01110_amd import _lib as L
+
+    g = W.fuzz_geometry(503, n=2000, m=300, max_list=700, p=16, layers=7)
+    geom = ctx.geometry(g)
+    sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
+    T = g.n_targets
+    outs = [torch.zeros(T, device="cuda", dtype=torch.float64) for _ in range(3)]
+    ref = [torch.zeros(T, device="cuda", dtype=torch.float64) for _ in range(3)]
+    with pytest.raises(api.TsqbxError) as e:
+        ctx.eval_staged_async(geom, 16, 1, *outs)
+    assert e.value.code == L.E_STATE
+    ctx.stage_async(geom, sig, 1)
+    with pytest.raises(api.TsqbxError) as e:
+        ctx.eval_staged_async(geom, 16, 3, *outs)
+    assert e.value.code == L.E_STATE
+    ctx.stage_async(geom, sig, 7)
+    for p, layers in ((16, 7), (8, 3), (0, 1), (24, 4), (13, 2)):
+        ctx.eval_staged_async(geom, p, layers, *outs)
+        ctx.eval_async(geom, sig, p, layers, *ref)
+        ctx.stage_async(geom, sig, 7)  # eval_async restaged with its own layers
+        torch.cuda.synchronize()
+        for k in range(3):
+            if layers & (1 << k):
+                assert torch.equal(outs[k], ref[k]), (p, layers, k)
+    ctx.autotune(geom, 16, 3)
+    with pytest.raises(api.TsqbxError) as e:
+        ctx.eval_staged_async(geom, 16, 1, *outs)
+    assert e.value.code == L.E_STATE
+    geom.close()
