@@ -87,3 +87,64 @@ def test_context_without_device_fails_cleanly():
     with pytest.raises(api.TsqbxError) as ei:
         api.Context(0)
     assert ei.value.code in (L.E_DEVICE, L.E_RANGE)
+
+
+C_PROGRAM = r"""
+#include <stdio.h>
+#include <string.h>
+#include "tsqbx.h"
+
+int main(void) {
+  /* two sources, one center listing both, one target */
+  const double src[6] = {1.0, 0.0, 0.0, 0.0, 1.5, 0.0};
+  const double w[2] = {0.5, 0.25};
+  const double ctr[3] = {0.0, 0.0, 0.1};
+  const int64_t off[2] = {0, 2};
+  const int32_t lst[2] = {0, 1};
+  const double tgt[3] = {0.0, 0.1, 0.1};
+  tsqbx_geometry_desc d = {2, src, w, NULL, 1, ctr, off, lst, 1, tgt, NULL, NULL};
+  if (tsqbx_validate_geometry(&d) != TSQBX_OK) return 1;
+  int32_t bad[2] = {0, 7};
+  d.list_sources = bad;
+  if (tsqbx_validate_geometry(&d) != TSQBX_E_RANGE) return 2;
+  if (strlen(tsqbx_last_error()) == 0) return 3;
+  if (tsqbx_check_request(NULL, TSQBX_P_MAX + 1, TSQBX_SLP) != TSQBX_E_RANGE) return 4;
+  /* the batch decomposition of two items on the host */
+  const int64_t nt[2] = {3, 2};
+  const int64_t rl[5] = {10, 20, 30, 5, 5};
+  const int32_t p[2] = {8, 16};
+  const uint32_t lay[2] = {TSQBX_SLP, TSQBX_SLP | TSQBX_DLP};
+  int32_t units[5 * 3], wb[5];
+  int64_t n_units = 0;
+  int32_t n_waves = 0;
+  if (tsqbx_schedule_preview(2, nt, rl, p, lay, 64, 4, units, 5, &n_units, wb, &n_waves)
+      != TSQBX_OK) return 5;
+  if (n_units < 2 || n_waves < 1 || wb[0] != 0 || wb[n_waves] != n_units) return 6;
+  printf("ok %d %lld %d\n", tsqbx_version(), (long long)n_units, n_waves);
+  return 0;
+}
+"""
+
+
+def test_header_compiles_as_c99_and_links(tmp_path):
+    """A C99 program includes tsqbx.h, links libtsqbx.so and calls the entry
+    points that touch no device."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "abi.c"
+    src.write_text(C_PROGRAM)
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(L.LIBPATH)
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                        "-L", libdir, "-l:" + os.path.basename(L.LIBPATH),
+                        "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ)
+    env["LD_LIBRARY_PATH"] = "/opt/rocm/lib:" + env.get("LD_LIBRARY_PATH", "")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert r.stdout.startswith("ok ")
