@@ -151,11 +151,22 @@ def cpu_baseline(g, p, layers):
     for _ in range(reps):
         oracle.evaluate_geometry(g, p=p, layers=layers)
     dt = (time.perf_counter() - t0) / reps
+    # one core on a slice of the targets, for a per-core rate
+    sel = np.arange(0, g.n_targets, 32)
+    t0 = time.perf_counter()
+    oracle.evaluate_geometry(g, p=p, layers=layers, select=sel, n_threads=1)
+    dt1 = time.perf_counter() - t0
+    off = np.asarray(g.list_offsets)
+    tc = (np.asarray(g.target_center) if g.target_center is not None
+          else np.arange(g.n_targets))[sel]
+    slice_terms = int((off[tc + 1] - off[tc]).sum()) * (p + 1) * bin(layers).count("1")
     return {"value": g.pair_terms(p, layers) / dt, "unit": "pair-terms/s",
             "cores": oracle.max_threads(), "kind": "oracle",
             "sample": f"the whole timed workload (all {g.n_targets} targets, p={p}, "
                       f"layers={layers}) evaluated {reps}x by the FP64 C oracle, OpenMP over targets",
-            "seconds_per_pass": dt}
+            "seconds_per_pass": dt,
+            "one_core": {"pair_terms_per_s": slice_terms / dt1, "sample":
+                         f"every 32nd target ({len(sel)}), one thread"}}
 
 
 def bench_batched(ctx, api, torch, W, steps, warmup, geoms=None):
