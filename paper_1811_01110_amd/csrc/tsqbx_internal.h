@@ -209,20 +209,23 @@ struct PersistentArgs {
   int32_t n_waves;
 };
 // Layer classes of the persistent kernel: 1, 2 or 3 when every item has that
-// mask, kLayersMixed when items mix masks 1..3, kLayersAny when some item
+// mask, kLayersSingle when items mix the single masks 1 and 2 (one layer
+// each), kLayersMixed when items mix masks 1..3, kLayersAny when some item
 // asks for S'.  A kernel compiled for fewer masks keeps fewer registers.
-constexpr unsigned kLayersMixed = 0, kLayersAny = 8;
+constexpr unsigned kLayersMixed = 0, kLayersAny = 8, kLayersSingle = 9;
 struct LayerClass {
   unsigned first = 0, all = 0;
-  bool same = true;
+  bool same = true, both = false;  // both: some item has mask 3
   void add(unsigned mask) {
     if (!all) first = mask;
     else if (mask != first) same = false;
     all |= mask;
+    both |= mask == (TSQBX_SLP | TSQBX_DLP);
   }
   unsigned get() const {
     if (same && first >= 1 && first <= 3) return first;
-    return (all & TSQBX_SPRIME) ? kLayersAny : kLayersMixed;
+    if (all & TSQBX_SPRIME) return kLayersAny;
+    return both ? kLayersMixed : kLayersSingle;
   }
 };
 // p_all: the order shared by every item, or -1.

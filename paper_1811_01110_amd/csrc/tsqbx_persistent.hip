@@ -52,8 +52,9 @@ __device__ __forceinline__ void unit_dispatch_p(const WorkItem &it, int first, i
   }
 }
 
-// LC = layer class: 1, 2 or 3 (every item has that mask), kLayersMixed (any
-// of masks 1..3) or kLayersAny (any mask, S' included).
+// LC = layer class: 1, 2 or 3 (every item has that mask), kLayersSingle
+// (masks 1 and 2), kLayersMixed (any of masks 1..3) or kLayersAny (any mask,
+// S' included).
 // Each wave works through its own range of units (a static schedule built
 // on the host), so no wave waits on another and no atomics are needed.
 template <int LC, int PF, int G, int U>
@@ -83,7 +84,12 @@ __global__ void __launch_bounds__(256) k_persistent(PersistentArgs a) {
     it.accumulate = items[item].accumulate;
     it.tnrm = items[item].tnrm;
     it.out_t = items[item].out_t;
-    if constexpr (LC == kLayersMixed) {
+    if constexpr (LC == kLayersSingle) {
+      if (it.layers == 1)
+        unit_dispatch_p<1, PF, G, U>(it, first, count, lane);
+      else
+        unit_dispatch_p<2, PF, G, U>(it, first, count, lane);
+    } else if constexpr (LC == kLayersMixed) {
       switch (it.layers) {
         case 1: unit_dispatch_p<1, PF, G, U>(it, first, count, lane); break;
         case 2: unit_dispatch_p<2, PF, G, U>(it, first, count, lane); break;
@@ -153,6 +159,7 @@ hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int 
     case 2: return launch_persistent_l<2>(a, p_all, tn, s);
     case 3: return launch_persistent_l<3>(a, p_all, tn, s);
     case kLayersMixed: return launch_persistent_l<kLayersMixed>(a, p_all, tn, s);
+    case kLayersSingle: return launch_persistent_l<kLayersSingle>(a, p_all, tn, s);
     default: return launch_persistent_l<kLayersAny>(a, p_all, tn, s);
   }
 }
