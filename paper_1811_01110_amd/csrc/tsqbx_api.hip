@@ -483,7 +483,7 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned la
   o.d = d_out_dlp;
   o.t = d_out_sprime;
   TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, s));
-  const_cast<tsqbx_geometry *>(g)->staged_layers.store(layers);
+  g->staged_layers.store(layers);
   TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn, s));
   return TSQBX_OK;
 }
@@ -498,7 +498,7 @@ int tsqbx_stage_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, unsigned layers,
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, (hipStream_t)hip_stream));
-  const_cast<tsqbx_geometry *>(g)->staged_layers.store(layers);
+  g->staged_layers.store(layers);
   return TSQBX_OK;
 }
 
@@ -543,7 +543,7 @@ int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const 
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)hip_stream;
   TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
-  const_cast<tsqbx_geometry *>(g)->staged_layers.store(TSQBX_SLP);
+  g->staged_layers.store(TSQBX_SLP);
   TSQBX_HIP(launch_qbxl(g, p, 1, g->stage.posq, nullptr, d_coeffs, nullptr,
                         (flags & TSQBX_ACCUMULATE) != 0, s));
   return TSQBX_OK;
@@ -573,7 +573,7 @@ int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)hip_stream;
   TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
-  const_cast<tsqbx_geometry *>(g)->staged_layers.store(TSQBX_SLP);
+  g->staged_layers.store(TSQBX_SLP);
   TSQBX_HIP(launch_qbxl(g, p, 3, g->stage.posq, nullptr, nullptr, d_out,
                         (flags & TSQBX_ACCUMULATE) != 0, s));
   return TSQBX_OK;
@@ -615,7 +615,7 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
   o.t = ctx->d_out + 2 * T;
   const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
   TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, s));
-  const_cast<tsqbx_geometry *>(g)->staged_layers.store(layers);
+  g->staged_layers.store(layers);
   TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, false, tn, s));
   // without ACCUMULATE the outputs go straight into the caller's arrays
   const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
@@ -695,7 +695,7 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
   if (e == hipSuccess) e = launch_stage(g, sig, layers, g->stage, s);
   // the staging buffer now holds a density of ones: a later
   // tsqbx_eval_staged_async must stage again
-  const_cast<tsqbx_geometry *>(g)->staged_layers.store(0);
+  g->staged_layers.store(0);
   if (e != hipSuccess) {
     cleanup();
     return fail_hip(e, "autotune setup");

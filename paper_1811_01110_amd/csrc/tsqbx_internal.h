@@ -112,7 +112,7 @@ struct tsqbx_geometry {
   int32_t *row_tgts = nullptr;   // [T] device-order targets grouped by row
   tsqbx::SourceStage stage;      // staging used by the plain path
   // layers the last tsqbx_stage_async call staged for (0: none yet)
-  std::atomic<unsigned> staged_layers{0};
+  mutable std::atomic<unsigned> staged_layers{0};
   tsqbx::HelmStage helm;         // Helmholtz staging, allocated on first use
   size_t device_bytes = 0;
   std::vector<int64_t> host_row_len;  // per device-order target, for planning
