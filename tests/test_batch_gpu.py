@@ -372,3 +372,36 @@ def test_server_pinned_helmholtz_submissions_match_copying_ones(ctx):
         for a, b in zip(copied[1:], pinned[1:]):
             assert (a is None and b is None) or np.array_equal(a, b.numpy())
     srv.close()
+
+
+def test_schedule_preview_matches_plan(ctx):
+    """The host-only preview yields the schedule a plan builds (units counted by
+    the plan), for geometries kept in the caller's order."""
+    import torch
+
+    geoms = [W.fuzz_geometry(300 + i, n=500, m=120, max_list=250, p=p, layers=lay)
+             for i, (p, lay) in enumerate([(8, 1), (16, 3), (4, 2), (12, 1)])]
+    items = []
+    for g in geoms:
+        geom = ctx.geometry(g, flags=api.NO_REORDER)
+        items.append(dict(
+            geom=geom, p=g.p, layers=g.layers,
+            sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64),
+            out_slp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64),
+            out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)))
+    plan = ctx.plan(items)
+    info = plan.info()
+    mean = max(sum(it["geom"].pairs for it in items) // sum(it["geom"].n_targets for it in items), 1)
+    G = ctx.get_tuning(max(g.p for g in geoms), 3, mean)["group_lanes"]
+    rows = []
+    for g in geoms:
+        tc = g.target_center if g.target_center is not None else np.arange(g.n_targets)
+        lens = (g.list_offsets[1:] - g.list_offsets[:-1])[tc]
+        rows.append((lens, g.p, g.layers))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    units, wb = api.schedule_preview(rows, group_lanes=G, max_waves=cus * 4 * 6 * 8)
+    print("plan units", info["n_units"], "preview units", len(units), "G", G, flush=True)
+    assert info["n_units"] == len(units)
+    plan.close()
+    for it in items:
+        it["geom"].close()
