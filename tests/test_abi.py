@@ -148,3 +148,24 @@ def test_header_compiles_as_c99_and_links(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=60)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert r.stdout.startswith("ok ")
+
+
+def test_size_limits_are_checked_before_any_array_is_read():
+    """N >= 2^27 sources (per-source byte offsets must fit 32 bits) and 2^31
+    targets or centers are refused from the counts alone."""
+    import ctypes
+
+    lib = L.load()
+    d = L.GeometryDesc()
+    d.n_sources = 1 << 27  # TSQBX_MAX_SOURCES
+    assert lib.tsqbx_validate_geometry(ctypes.byref(d)) == L.E_RANGE
+    d.n_sources = (1 << 27) - 1  # in range: now the NULL arrays are the error
+    assert lib.tsqbx_validate_geometry(ctypes.byref(d)) == L.E_INVALID
+    d.n_sources = 0
+    d.n_targets = 1 << 31
+    assert lib.tsqbx_validate_geometry(ctypes.byref(d)) == L.E_RANGE
+    d.n_targets = 0
+    d.n_centers = 1 << 31
+    assert lib.tsqbx_validate_geometry(ctypes.byref(d)) == L.E_RANGE
+    d.n_centers = -1
+    assert lib.tsqbx_validate_geometry(ctypes.byref(d)) == L.E_INVALID
