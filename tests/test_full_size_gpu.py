@@ -1,4 +1,4 @@
-"""The batched and served workloads at full size, in the configurations the
+"""The batched (Laplace and Helmholtz) and served workloads at full size, in the configurations the
 benchmark times (one plan over all geometries; the server with pinned
 submissions), checked against the oracle on sampled targets."""
 import numpy as np
@@ -108,3 +108,38 @@ def test_server_full_size_geometries(ctx):
                       sigma=s.numpy())
     for g in gs:
         g.close()
+
+
+def test_helmholtz_batched_64_geometries_full_size(ctx):
+    """The 64 batched geometries with the Helmholtz single and double layer
+    (k = 10, each geometry's own order) in one Helmholtz plan, as the
+    benchmark times it; sampled targets against the Helmholtz oracle."""
+    from oracle import helmholtz as H
+
+    geoms = W.config_c()
+    rng = np.random.default_rng(20181102)
+    items = []
+    for g in geoms:
+        sig = rng.standard_normal(g.n_sources) + 1j * rng.standard_normal(g.n_sources)
+        items.append(dict(
+            geom=ctx.geometry(g), p=g.p, layers=3, k=10.0, g=g, sig=sig,
+            sigma=torch.tensor(sig, device="cuda", dtype=torch.complex128),
+            out_slp=torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128),
+            out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.complex128)))
+    plan = ctx.plan_helmholtz(items)
+    plan.execute()
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(65)
+    for it in items:
+        g = it["g"]
+        sel = np.sort(pick.choice(g.n_targets, min(8, g.n_targets), replace=False))
+        ref = H.evaluate_geometry(g, 10.0, it["sig"], p=g.p, layers=3, select=sel)
+        for key, name in (("out_slp", "slp"), ("out_dlp", "dlp")):
+            got = it[key].cpu().numpy()[sel]
+            err = np.abs(got - ref[name])
+            scale = np.max(np.abs(ref[name]))
+            assert err.max() <= 1e-12 * max(scale, 1e-300), (g.name, name, err.max() / scale)
+            assert np.all(err <= 1e-12 * ref["abs_" + name]), (g.name, name)
+    plan.close()
+    for it in items:
+        it["geom"].close()
