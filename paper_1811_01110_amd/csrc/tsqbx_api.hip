@@ -281,6 +281,7 @@ int tsqbx_ctx_destroy(tsqbx_ctx *ctx) {
 
 int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned flags,
                           tsqbx_geometry **out) {
+  TraceRange trace_("tsqbx_geometry_create");
   if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
   *out = nullptr;
   int rc = validate(d);
@@ -467,6 +468,7 @@ static int check_outputs(const tsqbx_geometry *g, unsigned layers, const double 
 int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                      const double *d_sigma, double *d_out_slp, double *d_out_dlp,
                      double *d_out_sprime, unsigned flags, void *hip_stream) {
+  TraceRange trace_("tsqbx_eval_async");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_request(g, p, layers);
@@ -490,6 +492,7 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned la
 
 int tsqbx_stage_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, unsigned layers,
                       const double *d_sigma, void *hip_stream) {
+  TraceRange trace_("tsqbx_stage_async");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_request(g, 0, layers);
@@ -505,6 +508,7 @@ int tsqbx_stage_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, unsigned layers,
 int tsqbx_eval_staged_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                             double *d_out_slp, double *d_out_dlp, double *d_out_sprime,
                             unsigned flags, void *hip_stream) {
+  TraceRange trace_("tsqbx_eval_staged_async");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_request(g, p, layers);
@@ -535,6 +539,7 @@ static int check_conventional(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p) {
 
 int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const double *d_sigma,
                           double *d_coeffs, unsigned flags, void *hip_stream) {
+  TraceRange trace_("tsqbx_qbxl_form_async");
   int rc = check_conventional(ctx, g, p);
   if (rc != TSQBX_OK) return rc;
   if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
@@ -551,6 +556,7 @@ int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const 
 
 int tsqbx_qbxl_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const double *d_coeffs,
                           double *d_out, unsigned flags, void *hip_stream) {
+  TraceRange trace_("tsqbx_qbxl_eval_async");
   int rc = check_conventional(ctx, g, p);
   if (rc != TSQBX_OK) return rc;
   if (g->n_rows > 0 && !d_coeffs) return fail(TSQBX_E_INVALID, "coefficient buffer is NULL");
@@ -565,6 +571,7 @@ int tsqbx_qbxl_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const 
 int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p,
                                   const double *d_sigma, double *d_out, unsigned flags,
                                   void *hip_stream) {
+  TraceRange trace_("tsqbx_eval_conventional_async");
   int rc = check_conventional(ctx, g, p);
   if (rc != TSQBX_OK) return rc;
   if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
@@ -582,6 +589,7 @@ int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p
 int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                const double *sigma, double *out_slp, double *out_dlp, double *out_sprime,
                unsigned flags) {
+  TraceRange trace_("tsqbx_eval");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_request(g, p, layers);
@@ -671,6 +679,7 @@ int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
 
 int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                    tsqbx_tuning *out, double *best_ms) {
+  TraceRange trace_("tsqbx_autotune");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   int rc = check_request(g, p, layers);
   if (rc != TSQBX_OK) return rc;
@@ -816,6 +825,7 @@ int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, u
                                double k, const double *d_sigma, double *d_out_slp,
                                double *d_out_dlp, double *d_out_sprime, unsigned flags,
                                void *hip_stream) {
+  TraceRange trace_("tsqbx_eval_helmholtz_async");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_helmholtz(g, p, layers, k);
@@ -839,6 +849,7 @@ int tsqbx_eval_helmholtz_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, u
 int tsqbx_eval_helmholtz(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
                          double k, const double *sigma, double *out_slp, double *out_dlp,
                          double *out_sprime, unsigned flags) {
+  TraceRange trace_("tsqbx_eval_helmholtz");
   if (!ctx || !g) return fail(TSQBX_E_INVALID, "ctx or geometry is NULL");
   if (g->ctx != ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   int rc = check_helmholtz(g, p, layers, k);

@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "tsqbx.h"
 
 namespace tsqbx {
@@ -119,6 +121,14 @@ struct tsqbx_geometry {
 };
 
 namespace tsqbx {
+
+// A roctx range around one entry point, visible in rocprofv3 --marker-trace.
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // error reporting (thread-local message)
 int fail(int code, const char *fmt, ...);

@@ -228,6 +228,7 @@ int tsqbx_schedule_preview(int64_t n_items, const int64_t *n_targets, const int6
 
 int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, unsigned flags,
                       tsqbx_plan **out) {
+  TraceRange trace_("tsqbx_plan_create");
   if (!ctx || !out || n_items < 0 || (n_items > 0 && !items))
     return fail(TSQBX_E_INVALID, "plan_create: ctx, out or items is NULL, or n_items < 0");
   *out = nullptr;
@@ -348,6 +349,7 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
 
 int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_helm_item *items,
                                 unsigned flags, tsqbx_plan **out) {
+  TraceRange trace_("tsqbx_plan_create_helmholtz");
   if (!ctx || !out || n_items < 0 || (n_items > 0 && !items))
     return fail(TSQBX_E_INVALID, "plan_create: ctx, out or items is NULL, or n_items < 0");
   *out = nullptr;
@@ -490,6 +492,7 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
 }
 
 int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
+  TraceRange trace_("tsqbx_plan_execute");
   if (!pl) return fail(TSQBX_E_INVALID, "plan is NULL");
   Guard dg(pl->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");

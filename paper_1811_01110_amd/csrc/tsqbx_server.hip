@@ -472,7 +472,11 @@ void tsqbx_server::scheduler() {
     lk.unlock();
     std::string err;
     const double th0 = now_s();
-    int rc = launch_step(step, err);
+    int rc;
+    {
+      TraceRange trace_("tsqbx server step launch");
+      rc = launch_step(step, err);
+    }
     const double th1 = now_s();
     lk.lock();
     host_launch_s += th1 - th0;
@@ -738,6 +742,7 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
 int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
                         const double *sigma_host, double *out_slp_host, double *out_dlp_host,
                         double *out_sprime_host, uint64_t *ticket) {
+  TraceRange trace_("tsqbx_server_submit");
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
   return submit_impl(sv, geom, p, layers, 0.0, sigma_host, outs, ticket, false);
 }
@@ -745,6 +750,7 @@ int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, uns
 int tsqbx_server_submit_pinned(tsqbx_server *sv, const tsqbx_geometry *geom, int p,
                                unsigned layers, const double *sigma_host, double *out_slp_host,
                                double *out_dlp_host, double *out_sprime_host, uint64_t *ticket) {
+  TraceRange trace_("tsqbx_server_submit_pinned");
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
   return submit_impl(sv, geom, p, layers, 0.0, sigma_host, outs, ticket, true);
 }
@@ -753,6 +759,7 @@ int tsqbx_server_submit_helmholtz(tsqbx_server *sv, const tsqbx_geometry *geom, 
                                   unsigned layers, double k, const double *sigma_host,
                                   double *out_slp_host, double *out_dlp_host,
                                   double *out_sprime_host, uint64_t *ticket) {
+  TraceRange trace_("tsqbx_server_submit_helmholtz");
   if (!(k > 0.0)) return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
   return submit_impl(sv, geom, p, layers, k, sigma_host, outs, ticket, false);
@@ -762,6 +769,7 @@ int tsqbx_server_submit_helmholtz_pinned(tsqbx_server *sv, const tsqbx_geometry 
                                          unsigned layers, double k, const double *sigma_host,
                                          double *out_slp_host, double *out_dlp_host,
                                          double *out_sprime_host, uint64_t *ticket) {
+  TraceRange trace_("tsqbx_server_submit_helmholtz_pinned");
   if (!(k > 0.0)) return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
   return submit_impl(sv, geom, p, layers, k, sigma_host, outs, ticket, true);
@@ -779,6 +787,7 @@ int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {
 }
 
 int tsqbx_server_wait(tsqbx_server *sv, uint64_t ticket, double timeout_s) {
+  TraceRange trace_("tsqbx_server_wait");
   if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
   std::unique_lock<std::mutex> lk(sv->mu);
   auto it = sv->all.find(ticket);
@@ -791,6 +800,7 @@ int tsqbx_server_wait(tsqbx_server *sv, uint64_t ticket, double timeout_s) {
 }
 
 int tsqbx_server_drain(tsqbx_server *sv, double timeout_s) {
+  TraceRange trace_("tsqbx_server_drain");
   if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
   std::unique_lock<std::mutex> lk(sv->mu);
   if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
