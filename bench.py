@@ -722,7 +722,7 @@ def main():
     MIN_WARM_S = args.min_warm
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the evaluation shards by "
-              "targets across GPUs but this build measures the single-GPU path", file=sys.stderr)
+              "targets across GPUs, and this benchmark measures one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch
