@@ -358,21 +358,33 @@ def bench_serve(ctx, api, torch, W, n_requests):
     srv.drain(600)
     copy_rps = k1 / (time.perf_counter() - t0)
     srv.close()
-    # open loop at 0.7 x saturation
-    rate = 0.7 * sat_rps
-    arrivals = np.array([r.arrival_s for r in reqs]) / rate  # unit-rate schedule scaled
-    srv = ctx.server(budget, SERVE_SLOTS)
-    log(f"serving: Poisson stream at {rate:.0f} requests/s")
-    t0 = time.perf_counter()
-    for r, s_, o, ta in zip(reqs, sig, outs, arrivals):
-        while time.perf_counter() - t0 < ta:
-            pass
-        a, b = out_args(r, o)
-        srv.submit_pinned(gs[r.geometry], s_, r.p, r.layers, out_slp=a, out_dlp=b)
-    srv.drain(600)
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    srv.close()
+    def open_loop(factor):
+        """Poisson arrivals at factor x the saturation rate; returns (rate, wall, stats)."""
+        rate = factor * sat_rps
+        arrivals = np.array([r.arrival_s for r in reqs]) / rate  # unit-rate schedule scaled
+        srv = ctx.server(budget, SERVE_SLOTS)
+        log(f"serving: Poisson stream at {rate:.0f} requests/s ({factor}x saturation)")
+        t0 = time.perf_counter()
+        for r, s_, o, ta in zip(reqs, sig, outs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                pass
+            a, b = out_args(r, o)
+            srv.submit_pinned(gs[r.geometry], s_, r.p, r.layers, out_slp=a, out_dlp=b)
+        srv.drain(600)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return rate, wall, st
+
+    rate, wall, st = open_loop(0.7)
+    sweep = []
+    for factor in (0.5, 0.9):
+        rate_f, wall_f, st_f = open_loop(factor)
+        sweep.append({"factor": factor, "offered_rps": rate_f,
+                      "served_pair_terms_per_s": st_f["pair_terms_completed"] / wall_f,
+                      "latency_p50_ms": st_f["latency_p50_ms"],
+                      "latency_p99_ms": st_f["latency_p99_ms"],
+                      "queue_p99_ms": st_f["queue_p99_ms"]})
     helm = bench_serve_helmholtz(ctx, torch, gs, reqs[:300])
     for g in gs:
         g.close()
@@ -396,6 +408,7 @@ def bench_serve(ctx, api, torch, W, n_requests):
         "latency_max_ms": st["latency_max_ms"],
         "queue_p50_ms": st["queue_p50_ms"],
         "queue_p99_ms": st["queue_p99_ms"],
+        "other_loads": sweep,
         "steps": st["steps"],
         "peak_bytes_in_flight": st["peak_bytes_in_flight"],
         "budget_bytes": st["budget_bytes"],
