@@ -140,6 +140,17 @@ def timed_steps(fn, steps, warmup, torch, min_warm_s=None):
     return wall, e0.elapsed_time(e1) / 1e3
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(g, p, layers):
     import oracle
 
@@ -161,7 +172,7 @@ def cpu_baseline(g, p, layers):
           else np.arange(g.n_targets))[sel]
     slice_terms = int((off[tc + 1] - off[tc]).sum()) * (p + 1) * bin(layers).count("1")
     return {"value": g.pair_terms(p, layers) / dt, "unit": "pair-terms/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": oracle.max_threads(), "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"the whole timed workload (all {g.n_targets} targets, p={p}, "
                       f"layers={layers}) evaluated {reps}x by the FP64 C oracle, OpenMP over targets",
             "seconds_per_pass": dt,
