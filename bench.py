@@ -113,6 +113,20 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def per_launch_ms(fn, n, torch):
+    """n further calls, each between its own pair of events on the current
+    stream; the durations in ms."""
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
 def timed_steps(fn, steps, warmup, torch, min_warm_s=None):
     """W warm-up calls (continued until min_warm_s of device work so that the
     clocks settle), then `steps` timed calls between synchronisations."""
@@ -801,6 +815,7 @@ def main():
     kern = lambda: ctx.eval_staged_async(geom, p, layers, os_, od_)
     _, ev_k = timed_steps(kern, args.steps, args.warmup, torch)
     achieved = flops / (ev_k / args.steps) / 1e12
+    per_launch = per_launch_ms(kern, args.steps, torch)
     tuning = ctx.get_tuning(p, layers, geom.pairs // geom.n_targets)
 
     out = {
@@ -828,6 +843,7 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": measured_traffic(),
             "kernel": "k_eval<16, 3, G, U>", "kernel_ms_per_launch": ev_k / args.steps * 1e3,
+            "kernel_ms_median": float(np.median(per_launch)), "kernel_ms_min": min(per_launch),
             "event_ms_per_step": ev / args.steps * 1e3,
             "flops_per_pair": flops_per_pair(p, layers),
             "separate_recurrences": {
