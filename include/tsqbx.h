@@ -41,6 +41,9 @@
  *  - Preconditions not checked: |y - c| > 0 for every listed pair, and
  *    finite inputs.  |t - c| < |y - c| is needed for the truncated series to
  *    approximate the kernel (App. A), not for the sum to be defined.
+ *  - Tracing: every call that launches work, builds a geometry or a plan, or
+ *    waits on a server opens a roctx range named after the function
+ *    (rocprofv3 --marker-trace); the library links librocprofiler-sdk-roctx.
  */
 #ifndef TSQBX_H
 #define TSQBX_H
