@@ -18,18 +18,26 @@ LIB = os.path.join(HERE, "liboracle_tsqbx.so")
 
 SLP, DLP, SPRIME = 1, 2, 4
 
-_lib = None
+_libs = {}
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc: plain FP64, no fast-math, no FMA contraction."""
     if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
-               "-shared", "-std=c11", "-Wall", "-o", tmp, SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
+        compile_source(SRC, LIB)
     return LIB
+
+
+def compile_source(src: str, out: str) -> str:
+    """Compile one C source of the oracle's form into the shared library
+    `out`, with the oracle's flags (the tests also build deliberately broken
+    copies this way, to show that the pins catch them)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-std=c11", "-Wall", "-I", HERE, "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
 
 
 class _Problem(ctypes.Structure):
@@ -49,12 +57,15 @@ class _Problem(ctypes.Structure):
     ]
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
+def _load(path: str = None):
+    """The oracle library at `path` (default: the oracle itself, built on
+    first use), with its function signatures declared."""
+    path = LIB if path is None else path
+    lib = _libs.get(path)
+    if lib is None:
+        if path == LIB and not os.path.exists(LIB):
             build(force=False)
-        lib = ctypes.CDLL(LIB)
+        lib = ctypes.CDLL(path)
         lib.tsqbx_oracle_pair.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int, ctypes.c_void_p]
         lib.tsqbx_oracle_pair.restype = None
         lib.tsqbx_oracle_eval.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_uint,
@@ -62,8 +73,8 @@ def _load():
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.tsqbx_oracle_eval.restype = ctypes.c_int
         lib.tsqbx_oracle_max_threads.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return lib
 
 
 def max_threads() -> int:
@@ -81,26 +92,27 @@ def _f64(a, shape=None):
     return a
 
 
-def pair(t, c, s, nu, p: int, nu_t=None):
+def pair(t, c, s, nu, p: int, nu_t=None, library: str = None):
     """One pair: [G^(p), nu . grad_s G^(p), |.| yardsticks of both,
-    nu_t . grad_t G^(p), its yardstick]."""
+    nu_t . grad_t G^(p), its yardstick].  `library` names another build of
+    the oracle's source (default: the oracle)."""
     t, c, s = _f64(t, 3), _f64(c, 3), _f64(s, 3)
     nu = None if nu is None else _f64(nu, 3)
     nu_t = None if nu_t is None else _f64(nu_t, 3)
     out = np.zeros(6)
-    _load().tsqbx_oracle_pair(_ptr(t), _ptr(c), _ptr(s), _ptr(nu), _ptr(nu_t), int(p), _ptr(out))
+    _load(library).tsqbx_oracle_pair(_ptr(t), _ptr(c), _ptr(s), _ptr(nu), _ptr(nu_t), int(p), _ptr(out))
     return out
 
 
 def evaluate(sources, weights, normals, centers, list_offsets, list_sources, targets,
              target_center, sigma, p: int, layers: int, select=None, n_threads: int = 0,
-             target_normals=None):
+             target_normals=None, library: str = None):
     """Potentials at all targets (or the `select`ed ones).
 
     Returns dict with keys 'slp', 'dlp', 'sprime' and 'abs_' + each (None
-    for a layer not requested).
+    for a layer not requested).  `library` as for pair().
     """
-    lib = _load()
+    lib = _load(library)
     src = _f64(sources)
     w = _f64(weights)
     nrm = None if normals is None else _f64(normals)
