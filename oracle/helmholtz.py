@@ -214,3 +214,54 @@ def evaluate_geometry(g, k: float, sigma, p=None, layers=None, select=None):
                     g.targets, g.target_center, sigma, k, g.p if p is None else p,
                     g.layers if layers is None else layers, select=select,
                     target_normals=getattr(g, "target_normals", None))
+
+
+def _evaluate_rows(args):
+    (sources, weights, normals, centers, offsets, rows, targets, sigma, k, p, layers,
+     target_normals) = args
+    return evaluate(sources, weights, normals, centers, offsets, rows, targets, None, sigma, k, p,
+                    layers, target_normals=target_normals)
+
+
+def process_pool(workers: int):
+    """A pool of fresh interpreter processes (spawned, so that nothing of the
+    caller's process state, a GPU runtime included, is inherited)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    return cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
+def evaluate_parallel(g, k: float, sigma, p=None, layers=None, select=None, workers: int = 8,
+                      pool=None):
+    """evaluate_geometry() split over `workers` processes by target: each
+    process evaluates a slice of the selected targets (with their centers' rows
+    cut out of the CSR), one target at a time as evaluate() does, so the
+    results are those of evaluate_geometry() bit for bit.  `pool` (from
+    process_pool) is used if given, else one is made for the call."""
+    p = g.p if p is None else p
+    layers = g.layers if layers is None else layers
+    tsel = np.arange(g.n_targets) if select is None else np.asarray(select)
+    tc = np.arange(g.n_targets) if g.target_center is None else np.asarray(g.target_center)
+    tn = getattr(g, "target_normals", None)
+    jobs = []
+    for part in np.array_split(tsel, max(1, min(workers, len(tsel)))):
+        cs = tc[part]
+        lo = np.asarray(g.list_offsets)[cs]
+        hi = np.asarray(g.list_offsets)[cs + 1]
+        offs = np.zeros(len(part) + 1, dtype=np.int64)
+        np.cumsum(hi - lo, out=offs[1:])
+        rows = (np.concatenate([np.asarray(g.list_sources[a:b]) for a, b in zip(lo, hi)])
+                if len(part) else np.zeros(0, dtype=np.int32))
+        jobs.append((g.sources, g.weights, g.normals, np.asarray(g.centers)[cs], offs, rows,
+                     np.asarray(g.targets)[part], sigma, k, p, layers,
+                     None if tn is None else np.asarray(tn)[part]))
+    if pool is None:
+        with process_pool(len(jobs)) as ex:
+            parts = list(ex.map(_evaluate_rows, jobs))
+    else:
+        parts = list(pool.map(_evaluate_rows, jobs))
+    out = {}
+    for key in ("slp", "dlp", "sprime", "abs_slp", "abs_dlp", "abs_sprime"):
+        out[key] = None if parts[0][key] is None else np.concatenate([q[key] for q in parts])
+    return out

@@ -30,7 +30,8 @@ import scipy.special as sps
 SEED_BASE = 20181101
 GOLDEN_ANGLE = math.pi * (3.0 - math.sqrt(5.0))
 
-CONFIG_IDS = {"A": 0, "B": 1, "C": 2, "D": 3, "E": 4, "fuzz": 90, "sphere": 91}
+CONFIG_IDS = {"A": 0, "B": 1, "C": 2, "D": 3, "E": 4, "fuzz": 90, "sphere": 91,
+              "boundary": 92}
 
 
 def rng_for(config: str, item: int = 0) -> np.random.Generator:
@@ -490,3 +491,48 @@ def fuzz_geometry(seed: int, n: int, m: int, max_list: int, p: int, layers: int,
     tnrm = random_sphere_points(len(tc), rng)  # drawn last: earlier draws stay as they were
     return Geometry(src, w, nrm, ctr, offsets, idx, tgt, tc, sigma, p, layers, f"fuzz{seed}",
                     target_normals=tnrm)
+
+
+def fuzz_near_boundary(seed: int, n: int, m: int, max_list: int, p: int, layers: int,
+                       ratio: float = 0.99, targets_per_center: int = 2) -> Geometry:
+    """Pairs close to the edge of the expansion's convergence (App. A needs
+    |t - c| < |y - c|), where the terms decay slowest.
+
+    Sources lie on the unit sphere and centers within 0.05 of the origin, so
+    every |y - c| is within 0.95..1.05; each target sits at
+    |t - c| = ratio * (the smallest |y - c| of its center's list), which puts
+    every listed pair's |t - c| / |y - c| between about 0.9 * ratio and ratio.
+    One target in three points from its center at its nearest listed source
+    (cos gamma = 1), one in three away from it (cos gamma = -1), the rest in
+    random directions.  ratio > 1 gives pairs outside convergence, for small p
+    only.  Lists are ragged with empty rows and duplicates; a target of an
+    empty list lies 0.5 from its center.
+    """
+    rng = rng_for("boundary", seed)
+    src = random_sphere_points(n, rng)
+    nrm = random_sphere_points(n, rng)
+    w = rng.uniform(0.1, 1.0, size=n)
+    sigma = rng.standard_normal(n)
+    ctr = random_sphere_points(m, rng) * rng.uniform(0.0, 0.05, size=(m, 1))
+    lens = rng.integers(0, max_list + 1, size=m)
+    offsets = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    idx = rng.integers(0, n, size=int(offsets[-1])).astype(np.int32)
+    tc = np.repeat(np.arange(m, dtype=np.int32), targets_per_center)
+    rng.shuffle(tc)
+    dirs = random_sphere_points(len(tc), rng)
+    tgt = np.empty((len(tc), 3))
+    for i, c in enumerate(tc):
+        lo, hi = int(offsets[c]), int(offsets[c + 1])
+        if hi == lo:
+            tgt[i] = ctr[c] + 0.5 * dirs[i]
+            continue
+        d = src[idx[lo:hi]] - ctr[c]
+        R = np.sqrt(np.einsum("ij,ij->i", d, d))
+        j = int(np.argmin(R))
+        u = d[j] / R[j]
+        v = u if i % 3 == 0 else (-u if i % 3 == 1 else dirs[i])
+        tgt[i] = ctr[c] + (ratio * R[j]) * v
+    tnrm = random_sphere_points(len(tc), rng)
+    return Geometry(src, w, nrm, ctr, offsets, idx, tgt, tc, sigma, p, layers,
+                    f"boundary{seed}", target_normals=tnrm)

@@ -2,6 +2,8 @@
 the GPU against the Helmholtz oracle, element by element, through the C ABI
 (bar: 1e-12 of the per-target sum of term moduli, and 1e-12 of the largest
 output)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -28,10 +30,16 @@ def _sigma(n, seed):
 ALL = api.SLP | api.DLP | api.SPRIME
 
 
-def _check(ctx, g, k, p, layers, sigma, select=None, what=""):
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _check(ctx, g, k, p, layers, sigma, select=None, what="", parallel=False):
     geom = ctx.geometry(g)
     out = ctx.eval_helmholtz(geom, sigma, p, layers, k)
-    ref = H.evaluate_geometry(g, k, sigma, p=p, layers=layers, select=select)
+    if parallel:
+        ref = H.evaluate_parallel(g, k, sigma, p=p, layers=layers, select=select, workers=WORKERS)
+    else:
+        ref = H.evaluate_geometry(g, k, sigma, p=p, layers=layers, select=select)
     sel = slice(None) if select is None else select
     for o, bit, key in zip(out, (api.SLP, api.DLP, api.SPRIME), ("slp", "dlp", "sprime")):
         if layers & bit:
@@ -86,12 +94,32 @@ def test_target_at_center_and_edge_lists(ctx):
     geom.close()
 
 
+def _morton_keys(points):
+    """63-bit Morton keys of points over their bounding box (21 bits per axis)."""
+    lo = points.min(axis=0)
+    ext = max(float((points.max(axis=0) - lo).max()), 1e-300)
+    q = np.minimum(((points - lo) / ext * (1 << 21)).astype(np.int64), (1 << 21) - 1)
+    key = np.zeros(len(points), dtype=np.int64)
+    for b in range(21):
+        for a in range(3):
+            key |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    return key
+
+
 def test_config_b_full_size_sampled(ctx):
+    """4096 of the 65536 targets, k = 20, p = 16, all three layers: the 512
+    targets whose centers come first and the 512 that come last along a Morton
+    curve (the first and last blocks of the kernel's target order) and 3072
+    drawn at random."""
     g = cached_workload("config_b", 1)
     sig = _sigma(g.n_sources, 7)
+    tc = np.arange(g.n_targets) if g.target_center is None else g.target_center
+    order = np.argsort(_morton_keys(g.centers[tc]), kind="stable")
+    ends = np.concatenate([order[:512], order[-512:]])
+    rest = np.setdiff1d(np.arange(g.n_targets), ends)
     rng = np.random.default_rng(8)
-    sel = np.sort(rng.choice(g.n_targets, 128, replace=False))
-    _check(ctx, g, 20.0, 16, ALL, sig, select=sel, what="B k=20")
+    sel = np.sort(np.concatenate([ends, rng.choice(rest, 3072, replace=False)]))
+    _check(ctx, g, 20.0, 16, ALL, sig, select=sel, what="B k=20 p=16 layers=7", parallel=True)
 
 
 def test_async_accumulate_and_tuning_variants(ctx):

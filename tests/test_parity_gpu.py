@@ -50,18 +50,38 @@ def test_config_b_scaled(ctx):
     _check(ctx, g, what="B/64")
 
 
-def test_config_b_full_size_sampled(ctx):
+def test_config_b_full_size(ctx):
+    """Every one of the 65536 targets of the 262144-source perturbed sphere,
+    p = 16, single + double layer (the benchmark's workload)."""
     g = cached_workload("config_b", 1)
-    rng = np.random.default_rng(5)
-    sel = np.sort(rng.choice(g.n_targets, 512, replace=False))
     print("config B full", g.n_sources, g.n_targets, g.nnz, flush=True)
-    _check(ctx, g, select=sel, what="B")
+    _check(ctx, g, what="B p=16 layers=3")
 
 
 @pytest.mark.parametrize("p", list(range(0, 33)))
 def test_every_order_ragged_lists(ctx, p):
     g = W.fuzz_geometry(p, n=300, m=70, max_list=140, p=p, layers=3, targets_per_center=2)
     _check(ctx, g, what=f"fuzz p={p}")
+
+
+@pytest.mark.parametrize("p", list(range(24, 33)))
+def test_near_convergence_edge_high_order(ctx, p):
+    """|t - c| / |y - c| up to 0.99 at p = 24..32, with targets aimed at and
+    away from their nearest source (cos gamma = +-1): the closed forms of the
+    sums of b_n and (n+1) b_n cancel most there.  All three layers, every
+    mask class, and the single layer alone (Clenshaw)."""
+    g = W.fuzz_near_boundary(p, n=400, m=80, max_list=300, p=p, layers=7)
+    for lay in (7, 3, 1):
+        _check(ctx, g, layers=lay, what=f"boundary 0.99 p={p} layers={lay}")
+
+
+@pytest.mark.parametrize("p", list(range(0, 5)))
+def test_outside_convergence_low_order(ctx, p):
+    """|t - c| = 1.3 |y - c|_min: pairs outside the expansion's convergence
+    (a finite sum all the same) at p <= 4."""
+    g = W.fuzz_near_boundary(100 + p, n=300, m=60, max_list=200, p=p, layers=7, ratio=1.3)
+    for lay in (7, 1):
+        _check(ctx, g, layers=lay, what=f"boundary 1.3 p={p} layers={lay}")
 
 
 @pytest.mark.parametrize("p", list(range(0, 33)))
@@ -180,12 +200,12 @@ def test_rejects_bad_requests(ctx):
     geom.close()
 
 
-def test_config_d_geometry_sampled(ctx):
+def test_config_d_geometry_full(ctx):
+    """Every target of one high-order geometry (131072 sources, k-nearest
+    lists of 100..8000), p = 24, double layer, in a plain launch."""
     g = cached_workload("config_d", 1)[0]
-    rng = np.random.default_rng(6)
-    sel = np.sort(rng.choice(g.n_targets, 256, replace=False))
     print("config D[0]", g.n_sources, g.n_targets, g.nnz, flush=True)
-    _check(ctx, g, select=sel, what="D0")
+    _check(ctx, g, what="D[0] plain p=24 layers=2")
 
 
 # ---------------------------------------------------------------------------
@@ -212,12 +232,13 @@ def test_sprime_layer_masks_share_the_derivative_recurrence(ctx):
         assert np.array_equal(res[lay][0], res[3][0]), lay
 
 
-def test_sprime_config_b_full_size_sampled(ctx):
+def test_sprime_config_b_full_size(ctx):
+    """Every target of the perturbed sphere with all three layers, and S'
+    alone, p = 16."""
     g = cached_workload("config_b", 1)
     assert g.target_normals is not None
-    rng = np.random.default_rng(7)
-    sel = np.sort(rng.choice(g.n_targets, 384, replace=False))
-    _check(ctx, g, layers=7, select=sel, what="B all layers")
+    _check(ctx, g, layers=7, what="B p=16 layers=7")
+    _check(ctx, g, layers=4, what="B p=16 layers=4")
 
 
 def test_sprime_at_center_and_tuning_variants(ctx):

@@ -113,3 +113,30 @@ def test_fuzz_geometry_ragged():
     assert g.n_targets == 40
     assert np.all(np.bincount(g.target_center, minlength=20) == 2)
     assert (g.row_lengths() == 0).any()
+
+
+def test_near_boundary_generator_reaches_the_edge():
+    """Every listed pair of the near-boundary generator has |t - c| / |y - c|
+    between 0.85 * ratio and ratio, and the aimed targets sit on the line of
+    their nearest source (cos gamma = +1 and -1)."""
+    for ratio in (0.99, 1.3):
+        g = W.fuzz_near_boundary(3, n=300, m=60, max_list=150, p=30, layers=7, ratio=ratio)
+        assert np.array_equal(g.list_offsets, np.sort(g.list_offsets))
+        seen = {0: 0, 1: 0}
+        for i, c in enumerate(g.target_center):
+            lo, hi = int(g.list_offsets[c]), int(g.list_offsets[c + 1])
+            if hi == lo:
+                continue
+            d = g.sources[g.list_sources[lo:hi]] - g.centers[c]
+            R = np.linalg.norm(d, axis=1)
+            delta = g.targets[i] - g.centers[c]
+            rho = np.linalg.norm(delta)
+            q = rho / R
+            assert q.max() <= ratio * (1 + 1e-12) and q.max() >= ratio * (1 - 1e-12)
+            assert q.min() >= 0.85 * ratio
+            j = int(np.argmin(R))
+            cosg = float(delta @ d[j]) / (rho * R[j])
+            if i % 3 in (0, 1):
+                assert abs(cosg - (1.0 if i % 3 == 0 else -1.0)) < 1e-12
+                seen[i % 3] += 1
+        assert seen[0] > 5 and seen[1] > 5
