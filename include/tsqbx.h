@@ -405,6 +405,64 @@ int tsqbx_plan_execute(tsqbx_plan *plan, void *hip_stream);
 int tsqbx_plan_get_info(const tsqbx_plan *plan, tsqbx_plan_info *out);
 int tsqbx_plan_destroy(tsqbx_plan *plan);
 
+/* Launch shape and static schedule of a plan's persistent kernel (the batch
+ * decomposition; the paper leaves the evaluation's schedule to the
+ * implementation).  A target's result depends only on group_lanes (as for
+ * tsqbx_tuning): a plan equals tsqbx_eval_async at the same group_lanes bit
+ * for bit whatever the other fields are. */
+typedef struct {
+  int group_lanes;       /* lanes per target: 64, 32 or 16 */
+  int unroll;            /* pairs in flight per lane: 2, or 1 with 64 lanes */
+  int waves_per_block;   /* 1, 2 or 4 */
+  int oversubscription;  /* schedule ranges per resident wave slot (6 per SIMD), 1..32 */
+  int step_cost;         /* fixed cost of one wave-step in the schedule's cost model,
+                            in the units of one pair's instruction count, 0..100000 */
+} tsqbx_plan_tuning;
+
+/* The tuning a plan runs with: taken at creation from the context's table
+ * for the plan's bucket (set by tsqbx_plan_autotune or tsqbx_tuning_load:
+ * kernel, orders present, layers, list length and size, each rounded to a
+ * power of two), else the defaults. */
+int tsqbx_plan_get_tuning(const tsqbx_plan *plan, tsqbx_plan_tuning *out);
+/* Rebuild the schedule for another tuning (TSQBX_E_INVALID if a field is out
+ * of range).  Waits for the device to finish the plan's earlier work; the
+ * next tsqbx_plan_execute captures a new graph. */
+int tsqbx_plan_set_tuning(tsqbx_plan *plan, const tsqbx_plan_tuning *tuning);
+
+/* Durations of a plan's kernels: the plan's launches run reps + 1 times on
+ * hip_stream without the graph (the first run untimed), each kernel between
+ * its own pair of HIP events; out receives the mean per-run milliseconds.
+ * Synchronous.  Each run writes (or, with TSQBX_ACCUMULATE, adds to) the
+ * outputs as tsqbx_plan_execute does.  reps in [1, 1000]. */
+typedef struct {
+  double stage_ms;       /* staging of every item's density (Helmholtz: and the j_n tables) */
+  double eval_ms;        /* the persistent evaluation kernel */
+  int reps;
+} tsqbx_plan_timing;
+int tsqbx_plan_profile(tsqbx_plan *plan, int reps, void *hip_stream, tsqbx_plan_timing *out);
+
+/* Time the plan's evaluation kernel (tsqbx_plan_profile, 3 runs each) over
+ * its candidate tunings, one field at a time: group_lanes with unroll, then
+ * waves_per_block, oversubscription and step_cost, each starting from the best
+ * so far; keep the fastest, install it in the context's table for the plan's
+ * bucket (later plans of that bucket start from it) and return it in *out
+ * (nullable) with its time in *best_ms (nullable).  Synchronous; runs the
+ * plan about 60 times, so outputs of a TSQBX_ACCUMULATE plan must be reset
+ * afterwards.  A later tsqbx_plan_set_tuning may choose another group width
+ * and with it other bits (see tsqbx_plan_tuning). */
+int tsqbx_plan_autotune(tsqbx_plan *plan, void *hip_stream, tsqbx_plan_tuning *out,
+                        double *best_ms);
+
+/* Persist the context's tuning tables (plain-kernel tunings from
+ * tsqbx_autotune / tsqbx_set_tuning, and plan tunings) to a text file of JSON
+ * lines, each tagged with the device's architecture name and the HIP runtime
+ * version; tsqbx_tuning_load reads such a file and installs the entries made
+ * on the same architecture and runtime (*n_loaded, nullable, counts them) and
+ * skips the others.  TSQBX_E_INVALID for a file that cannot be opened or a
+ * line that is not of this form. */
+int tsqbx_tuning_save(tsqbx_ctx *ctx, const char *path);
+int tsqbx_tuning_load(tsqbx_ctx *ctx, const char *path, int *n_loaded);
+
 /* ---------------------------------------------------------------------------
  * Serving: requests against device-resident geometries, admitted under a
  * device-memory budget and batched continuously: requests that arrive while
@@ -464,12 +522,18 @@ int tsqbx_server_submit_helmholtz_pinned(tsqbx_server *srv, const tsqbx_geometry
 int tsqbx_server_request_bytes_helmholtz(const tsqbx_geometry *geom, int p, unsigned layers,
                                          size_t *out);
 /* *done = 1 once the outputs are written (0 while pending).  Returns the
- * request's error status if it failed. */
+ * request's error status if it failed.  The server remembers the tickets of
+ * pending requests and of the last 4096 completed ones (a long-running server
+ * holds bounded host memory); an older ticket gives TSQBX_E_INVALID, as an
+ * unknown one does. */
 int tsqbx_server_poll(tsqbx_server *srv, uint64_t ticket, int *done);
-/* Block until the ticket completes or timeout_s passes (TSQBX_E_TIMEOUT). */
+/* Block until the ticket completes or timeout_s passes (TSQBX_E_TIMEOUT).
+ * Tickets as for tsqbx_server_poll (one being waited on is not forgotten). */
 int tsqbx_server_wait(tsqbx_server *srv, uint64_t ticket, double timeout_s);
 /* Block until every submitted request has completed. */
 int tsqbx_server_drain(tsqbx_server *srv, double timeout_s);
+/* Counters since creation; latency and queueing percentiles over the last
+ * 65536 completed requests. */
 int tsqbx_server_get_stats(tsqbx_server *srv, tsqbx_server_stats *out);
 /* Stop accepting requests, finish the ones in flight, free everything. */
 int tsqbx_server_destroy(tsqbx_server *srv);

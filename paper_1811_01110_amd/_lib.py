@@ -65,6 +65,18 @@ class PlanInfo(ctypes.Structure):
                 ("device_bytes", c_size_t)]
 
 
+class PlanTuning(ctypes.Structure):
+    _fields_ = [("group_lanes", c_int), ("unroll", c_int), ("waves_per_block", c_int),
+                ("oversubscription", c_int), ("step_cost", c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PlanTiming(ctypes.Structure):
+    _fields_ = [("stage_ms", c_double), ("eval_ms", c_double), ("reps", c_int)]
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_uint64), ("admitted", c_uint64), ("completed", c_uint64),
                 ("failed", c_uint64), ("rejected", c_uint64), ("steps", c_uint64),
@@ -122,6 +134,12 @@ _SIGNATURES = {
     "tsqbx_plan_execute": (c_int, [c_void_p, c_void_p]),
     "tsqbx_plan_get_info": (c_int, [c_void_p, P(PlanInfo)]),
     "tsqbx_plan_destroy": (c_int, [c_void_p]),
+    "tsqbx_plan_get_tuning": (c_int, [c_void_p, P(PlanTuning)]),
+    "tsqbx_plan_set_tuning": (c_int, [c_void_p, P(PlanTuning)]),
+    "tsqbx_plan_profile": (c_int, [c_void_p, c_int, c_void_p, P(PlanTiming)]),
+    "tsqbx_plan_autotune": (c_int, [c_void_p, c_void_p, P(PlanTuning), P(c_double)]),
+    "tsqbx_tuning_save": (c_int, [c_void_p, ctypes.c_char_p]),
+    "tsqbx_tuning_load": (c_int, [c_void_p, ctypes.c_char_p, P(c_int)]),
     "tsqbx_server_create": (c_int, [c_void_p, c_size_t, c_int, P(c_void_p)]),
     "tsqbx_server_request_bytes": (c_int, [c_void_p, c_uint, P(c_size_t)]),
     "tsqbx_server_submit": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,

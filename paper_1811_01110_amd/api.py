@@ -6,6 +6,7 @@ supplies device memory and streams for the asynchronous entry points.
 from __future__ import annotations
 
 import ctypes
+import os
 from typing import Optional, Sequence
 
 import numpy as np
@@ -354,6 +355,14 @@ class Context:
                                      ctypes.byref(t), ctypes.byref(ms)))
         return t.as_dict(), ms.value
 
+    def tuning_save(self, path: str) -> None:
+        _check(_lib().tsqbx_tuning_save(self.handle, os.fsencode(path)))
+
+    def tuning_load(self, path: str) -> int:
+        n = ctypes.c_int()
+        _check(_lib().tsqbx_tuning_load(self.handle, os.fsencode(path), ctypes.byref(n)))
+        return n.value
+
     # -- batched and served -------------------------------------------------
     def plan(self, items: Sequence[dict], flags: int = 0) -> "Plan":
         return Plan(self, items, flags)
@@ -441,6 +450,32 @@ class Plan:
         i = L.PlanInfo()
         _check(_lib().tsqbx_plan_get_info(self.handle, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in i._fields_}
+
+    def get_tuning(self) -> dict:
+        t = L.PlanTuning()
+        _check(_lib().tsqbx_plan_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **tuning) -> None:
+        cur = self.get_tuning()
+        cur.update(tuning)
+        t = L.PlanTuning(**cur)
+        _check(_lib().tsqbx_plan_set_tuning(self.handle, ctypes.byref(t)))
+
+    def profile(self, reps: int = 5, stream=None) -> dict:
+        """Mean per-run milliseconds of the staging and evaluation kernels."""
+        t = L.PlanTiming()
+        _check(_lib().tsqbx_plan_profile(self.handle, int(reps), _stream_handle(stream),
+                                         ctypes.byref(t)))
+        return {"stage_ms": t.stage_ms, "eval_ms": t.eval_ms, "reps": t.reps}
+
+    def autotune(self, stream=None):
+        """Time the candidate tunings, keep the fastest: (tuning, eval ms)."""
+        t = L.PlanTuning()
+        ms = ctypes.c_double()
+        _check(_lib().tsqbx_plan_autotune(self.handle, _stream_handle(stream), ctypes.byref(t),
+                                          ctypes.byref(ms)))
+        return t.as_dict(), ms.value
 
     def close(self):
         if self.handle:

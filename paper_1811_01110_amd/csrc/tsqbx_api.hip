@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -213,7 +214,8 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 static void free_geometry(tsqbx_geometry *g) {
   if (!g) return;
   void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
-                  g->ctr, g->row_tgts, g->stage.posq, g->stage.qn, g->helm.rec, g->helm.tab, g->helm.tabs};
+                  g->ctr, g->row_tgts, g->stage.xy, g->stage.nxy, g->helm.rec, g->helm.tab,
+                  g->helm.tabs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete g;
@@ -261,6 +263,7 @@ int tsqbx_ctx_create(int device, tsqbx_ctx **out) {
   e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
+    if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return fail_hip(e, "context setup");
   }
@@ -423,8 +426,11 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   g->n_rows = R;
   if (e == hipSuccess) e = dev_upload(&g->ctr, crec.data(), R, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->row_tgts, row_tgts.data(), T, &bytes);
-  if (e == hipSuccess) e = dev_upload<double4>(&g->stage.posq, nullptr, N + 1, &bytes);
-  if (e == hipSuccess && d->normals) e = dev_upload<double4>(&g->stage.qn, nullptr, N + 1, &bytes);
+  // staging blocks of the plain path (see SourceStage)
+  char *spos = nullptr, *snrm = nullptr;
+  if (e == hipSuccess) e = dev_upload<char>(&spos, nullptr, stage_pos_bytes(N), &bytes);
+  if (e == hipSuccess && d->normals) e = dev_upload<char>(&snrm, nullptr, stage_nrm_bytes(N), &bytes);
+  g->stage = stage_views(spos, snrm, N);
   if (e != hipSuccess) {
     free_geometry(g);
     return fail_hip(e, "geometry upload");
@@ -549,7 +555,7 @@ int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const 
   hipStream_t s = (hipStream_t)hip_stream;
   TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
   g->staged_layers.store(TSQBX_SLP);
-  TSQBX_HIP(launch_qbxl(g, p, 1, g->stage.posq, nullptr, d_coeffs, nullptr,
+  TSQBX_HIP(launch_qbxl(g, p, 1, g->stage, nullptr, d_coeffs, nullptr,
                         (flags & TSQBX_ACCUMULATE) != 0, s));
   return TSQBX_OK;
 }
@@ -563,7 +569,7 @@ int tsqbx_qbxl_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const 
   if (g->n_targets > 0 && !d_out) return fail(TSQBX_E_INVALID, "output is NULL");
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
-  TSQBX_HIP(launch_qbxl(g, p, 2, nullptr, d_coeffs, nullptr, d_out,
+  TSQBX_HIP(launch_qbxl(g, p, 2, SourceStage{}, d_coeffs, nullptr, d_out,
                         (flags & TSQBX_ACCUMULATE) != 0, (hipStream_t)hip_stream));
   return TSQBX_OK;
 }
@@ -581,7 +587,7 @@ int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p
   hipStream_t s = (hipStream_t)hip_stream;
   TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
   g->staged_layers.store(TSQBX_SLP);
-  TSQBX_HIP(launch_qbxl(g, p, 3, g->stage.posq, nullptr, nullptr, d_out,
+  TSQBX_HIP(launch_qbxl(g, p, 3, g->stage, nullptr, nullptr, d_out,
                         (flags & TSQBX_ACCUMULATE) != 0, s));
   return TSQBX_OK;
 }
@@ -674,6 +680,118 @@ int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
                 t.waves_per_block, t.group_lanes, t.unroll, t.xcd_remap);
   std::lock_guard<std::mutex> lk(ctx->tuning_mu);
   ctx->tuning[tuning_key(p, layers, mean_list)] = t;
+  return TSQBX_OK;
+}
+
+// The device's architecture name and the HIP runtime version: the tag of a
+// saved tuning entry.
+static int tuning_tag(const tsqbx_ctx *ctx, std::string *arch, int *runtime) {
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, ctx->device);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceProperties");
+  arch->assign(prop.gcnArchName);
+  for (char &c : *arch)
+    if (c == '"' || c == '\\' || (unsigned char)c < 32) c = '_';
+  e = hipRuntimeGetVersion(runtime);
+  if (e != hipSuccess) return fail_hip(e, "hipRuntimeGetVersion");
+  return TSQBX_OK;
+}
+
+int tsqbx_tuning_save(tsqbx_ctx *ctx, const char *path) {
+  if (!ctx || !path) return fail(TSQBX_E_INVALID, "ctx or path is NULL");
+  std::string arch;
+  int rt = 0;
+  int rc = tuning_tag(ctx, &arch, &rt);
+  if (rc != TSQBX_OK) return rc;
+  std::map<uint64_t, Tuning> plain;
+  std::map<uint64_t, PlanTuning> plans;
+  {
+    std::lock_guard<std::mutex> lk(ctx->tuning_mu);
+    plain = ctx->tuning;
+    plans = ctx->plan_tuning;
+  }
+  FILE *f = std::fopen(path, "w");
+  if (!f) return fail(TSQBX_E_INVALID, "tuning_save: cannot open %s for writing", path);
+  for (auto &kv : plain)
+    std::fprintf(f,
+                 "{\"kind\": \"plain\", \"arch\": \"%s\", \"runtime\": %d, \"key\": %llu, "
+                 "\"group_lanes\": %d, \"unroll\": %d, \"waves_per_block\": %d, "
+                 "\"xcd_remap\": %d}\n",
+                 arch.c_str(), rt, (unsigned long long)kv.first, kv.second.group_lanes,
+                 kv.second.unroll, kv.second.waves_per_block, kv.second.xcd_remap);
+  for (auto &kv : plans)
+    std::fprintf(f,
+                 "{\"kind\": \"plan\", \"arch\": \"%s\", \"runtime\": %d, \"key\": %llu, "
+                 "\"group_lanes\": %d, \"unroll\": %d, \"waves_per_block\": %d, "
+                 "\"oversubscription\": %d, \"step_cost\": %d}\n",
+                 arch.c_str(), rt, (unsigned long long)kv.first, kv.second.tn.group_lanes,
+                 kv.second.tn.unroll, kv.second.tn.waves_per_block, kv.second.oversub,
+                 kv.second.step_cost);
+  const bool ok = std::fflush(f) == 0;
+  std::fclose(f);
+  if (!ok) return fail(TSQBX_E_INVALID, "tuning_save: writing %s failed", path);
+  return TSQBX_OK;
+}
+
+int tsqbx_tuning_load(tsqbx_ctx *ctx, const char *path, int *n_loaded) {
+  if (!ctx || !path) return fail(TSQBX_E_INVALID, "ctx or path is NULL");
+  if (n_loaded) *n_loaded = 0;
+  std::string arch;
+  int rt = 0;
+  int rc = tuning_tag(ctx, &arch, &rt);
+  if (rc != TSQBX_OK) return rc;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(TSQBX_E_INVALID, "tuning_load: cannot open %s", path);
+  std::map<uint64_t, Tuning> plain;
+  std::map<uint64_t, PlanTuning> plans;
+  char line[512];
+  int lineno = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (line[0] == '\n' || line[0] == 0) continue;
+    char kind[16] = {0}, a[128] = {0};
+    int r = 0, n = 0;
+    unsigned long long key = 0;
+    if (std::sscanf(line, "{\"kind\": \"%15[a-z]\", \"arch\": \"%127[^\"]\", \"runtime\": %d, "
+                          "\"key\": %llu, %n",
+                    kind, a, &r, &key, &n) != 4 || n <= 0) {
+      std::fclose(f);
+      return fail(TSQBX_E_INVALID, "tuning_load: %s line %d is not a tuning entry", path, lineno);
+    }
+    const char *rest = line + n;
+    bool ok = false;
+    if (!std::strcmp(kind, "plain")) {
+      Tuning t;
+      ok = std::sscanf(rest,
+                       "\"group_lanes\": %d, \"unroll\": %d, \"waves_per_block\": %d, "
+                       "\"xcd_remap\": %d}",
+                       &t.group_lanes, &t.unroll, &t.waves_per_block, &t.xcd_remap) == 4 &&
+           tuning_supported(t);
+      if (ok && arch == a && rt == r) plain[key] = t;
+    } else if (!std::strcmp(kind, "plan")) {
+      PlanTuning t;
+      ok = std::sscanf(rest,
+                       "\"group_lanes\": %d, \"unroll\": %d, \"waves_per_block\": %d, "
+                       "\"oversubscription\": %d, \"step_cost\": %d}",
+                       &t.tn.group_lanes, &t.tn.unroll, &t.tn.waves_per_block, &t.oversub,
+                       &t.step_cost) == 5 &&
+           tuning_supported(t.tn) && t.tn.unroll <= 2 && t.oversub >= 1 && t.oversub <= 32 &&
+           t.step_cost >= 0 && t.step_cost <= 100000;
+      if (ok && arch == a && rt == r) plans[key] = t;
+    }
+    if (!ok) {
+      std::fclose(f);
+      return fail(TSQBX_E_INVALID, "tuning_load: %s line %d is not a valid %s entry", path,
+                  lineno, kind);
+    }
+  }
+  std::fclose(f);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tuning_mu);
+    for (auto &kv : plain) ctx->tuning[kv.first] = kv.second;
+    for (auto &kv : plans) ctx->plan_tuning[kv.first] = kv.second;
+  }
+  if (n_loaded) *n_loaded = (int)(plain.size() + plans.size());
   return TSQBX_OK;
 }
 

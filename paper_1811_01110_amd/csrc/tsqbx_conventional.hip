@@ -139,19 +139,20 @@ __device__ __forceinline__ void irr_steps(int p, const double (&zz)[U], const do
 // The terms of order M of U list entries (sources s[u]), added into (ar, ai).
 template <int PC, bool EXACT, int M, int U>
 __device__ __forceinline__ void order_terms(int p, const uint32_t (&s)[U], double cx, double cy,
-                                            double cz, const double4 *__restrict__ posq,
+                                            double cz, const SrcView &src,
                                             double (&ar)[PC - M + 1], double (&ai)[PC - M + 1]) {
   double zz[U], ii[U], tr[U], ti[U], z0[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const double4 a = load4(posq, s[u]);
-    const double dx = a.x - cx, dy = a.y - cy, dz = a.z - cz;
+    const double2 a = load2(src.xy, s[u]);
+    const double2 aq = load2(src.zq, s[u]);  // (z, q)
+    const double dx = a.x - cx, dy = a.y - cy, dz = aq.x - cz;
     const double R2 = fma(dz, dz, fma(dy, dy, dx * dx));
     const double rinv = rsqrt_nr(R2);
     ii[u] = rinv * rinv;
     zz[u] = dz * ii[u];
     z0[u] = 0.0;
-    const double qr = a.w * rinv;  // q / R
+    const double qr = aq.y * rinv;  // q / R
     ti[u] = 0.0;                   // (tr, ti) = q (d_x - i d_y)^M / R^{2M+1}
     if constexpr (M == 0) {
       tr[u] = qr;
@@ -192,7 +193,7 @@ __device__ __forceinline__ void store_order(int p, const double (&ar)[PC - M + 1
 template <int PC, bool EXACT, int M>
 __device__ __forceinline__ void form_orders(int p, int lane, const int32_t *__restrict__ row,
                                             int len, double cx, double cy, double cz,
-                                            const double4 *__restrict__ posq, double *coef) {
+                                            const SrcView &src, double *coef) {
   if constexpr (M <= PC) {
     if constexpr (!EXACT)
       if (M > p) return;
@@ -204,11 +205,11 @@ __device__ __forceinline__ void form_orders(int p, int lane, const int32_t *__re
     int j = lane;
     for (; j + 64 < len; j += 128) {
       const uint32_t s2[2] = {load_idx(row, (uint32_t)j), load_idx(row, (uint32_t)(j + 64))};
-      order_terms<PC, EXACT, M, 2>(p, s2, cx, cy, cz, posq, ar, ai);
+      order_terms<PC, EXACT, M, 2>(p, s2, cx, cy, cz, src, ar, ai);
     }
     if (j < len) {
       const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
-      order_terms<PC, EXACT, M, 1>(p, s1, cx, cy, cz, posq, ar, ai);
+      order_terms<PC, EXACT, M, 1>(p, s1, cx, cy, cz, src, ar, ai);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -221,7 +222,7 @@ __device__ __forceinline__ void form_orders(int p, int lane, const int32_t *__re
       }
     }
     if (lane == 0) store_order<PC, EXACT, M, M>(p, ar, ai, coef);
-    form_orders<PC, EXACT, M + 1>(p, lane, row, len, cx, cy, cz, posq, coef);
+    form_orders<PC, EXACT, M + 1>(p, lane, row, len, cx, cy, cz, src, coef);
   }
 }
 
@@ -276,13 +277,13 @@ __device__ __forceinline__ void eval_orders(int p, double dx, double dy, double 
 constexpr int kModeForm = 1, kModeEval = 2;
 
 // One wave (block of 64) per center row.  MODE & kModeForm: form the
-// coefficients from the staged sources (posq); else read them from
+// coefficients from the staged sources; else read them from
 // coeffs_in.  MODE & kModeEval: evaluate at the row's targets into out;
 // else write the coefficients to coeffs_out.
 template <int PC, bool EXACT, int MODE>
 __global__ void __launch_bounds__(64)
 k_qbxl(const CenterRec *__restrict__ rows, int64_t n_rows, const int32_t *__restrict__ idx,
-       const double4 *__restrict__ posq, const int32_t *__restrict__ row_tgts,
+       SrcView src, const int32_t *__restrict__ row_tgts,
        const TargetRec *__restrict__ tgt, const double *__restrict__ coeffs_in,
        double *__restrict__ coeffs_out, double *__restrict__ out, int p_rt, int accumulate,
        int remap) {
@@ -296,7 +297,7 @@ k_qbxl(const CenterRec *__restrict__ rows, int64_t n_rows, const int32_t *__rest
   const double cx = cr->c[0], cy = cr->c[1], cz = cr->c[2];
   const int64_t center = cr->center;
   if constexpr ((MODE & kModeForm) != 0) {
-    form_orders<PC, EXACT, 0>(p, lane, idx + cr->row_begin, cr->len, cx, cy, cz, posq, coef);
+    form_orders<PC, EXACT, 0>(p, lane, idx + cr->row_begin, cr->len, cx, cy, cz, src, coef);
   } else {
     for (int k = lane; k < nc; k += 64) coef[k] = coeffs_in[center * nc + k];
   }
@@ -320,41 +321,43 @@ k_qbxl(const CenterRec *__restrict__ rows, int64_t n_rows, const int32_t *__rest
 }
 
 template <int PC, bool EXACT, int MODE>
-hipError_t launch_mode(const tsqbx_geometry *g, int p, const double4 *posq, const double *cin,
+hipError_t launch_mode(const tsqbx_geometry *g, int p, const SrcView &src, const double *cin,
                        double *cout, double *out, bool acc, hipStream_t s) {
   const int64_t blocks = g->n_rows;
   if (blocks <= 0) return hipSuccess;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_qbxl<PC, EXACT, MODE>), dim3((unsigned)blocks), dim3(64), 0, s, g->ctr,
-                     g->n_rows, g->idx, posq, g->row_tgts, g->tgt, cin, cout, out, p, acc ? 1 : 0,
+                     g->n_rows, g->idx, src, g->row_tgts, g->tgt, cin, cout, out, p, acc ? 1 : 0,
                      1);
   return hipGetLastError();
 }
 
 template <int MODE>
-hipError_t launch_p(const tsqbx_geometry *g, int p, const double4 *posq, const double *cin,
+hipError_t launch_p(const tsqbx_geometry *g, int p, const SrcView &src, const double *cin,
                     double *cout, double *out, bool acc, hipStream_t s) {
   switch (p) {
-    case 5: return launch_mode<5, true, MODE>(g, p, posq, cin, cout, out, acc, s);
-    case 8: return launch_mode<8, true, MODE>(g, p, posq, cin, cout, out, acc, s);
-    case 16: return launch_mode<16, true, MODE>(g, p, posq, cin, cout, out, acc, s);
+    case 5: return launch_mode<5, true, MODE>(g, p, src, cin, cout, out, acc, s);
+    case 8: return launch_mode<8, true, MODE>(g, p, src, cin, cout, out, acc, s);
+    case 16: return launch_mode<16, true, MODE>(g, p, src, cin, cout, out, acc, s);
     default:
-      if (p <= 16) return launch_mode<16, false, MODE>(g, p, posq, cin, cout, out, acc, s);
-      return launch_mode<32, false, MODE>(g, p, posq, cin, cout, out, acc, s);
+      if (p <= 16) return launch_mode<16, false, MODE>(g, p, src, cin, cout, out, acc, s);
+      return launch_mode<32, false, MODE>(g, p, src, cin, cout, out, acc, s);
   }
 }
 
 }  // namespace
 
-hipError_t launch_qbxl(const tsqbx_geometry *g, int p, int mode, const double4 *posq,
+hipError_t launch_qbxl(const tsqbx_geometry *g, int p, int mode, const SourceStage &st,
                        const double *coeffs_in, double *coeffs_out, double *out, bool accumulate,
                        hipStream_t s) {
   if (p < 0 || p > TSQBX_P_MAX) return hipErrorInvalidValue;
+  const SrcView src{st.xy, st.zq, nullptr, nullptr};
+  const SrcView none{nullptr, nullptr, nullptr, nullptr};
   switch (mode) {
-    case kModeForm: return launch_p<kModeForm>(g, p, posq, nullptr, coeffs_out, nullptr, accumulate, s);
-    case kModeEval: return launch_p<kModeEval>(g, p, nullptr, coeffs_in, nullptr, out, accumulate, s);
+    case kModeForm: return launch_p<kModeForm>(g, p, src, nullptr, coeffs_out, nullptr, accumulate, s);
+    case kModeEval: return launch_p<kModeEval>(g, p, none, coeffs_in, nullptr, out, accumulate, s);
     case kModeForm | kModeEval:
-      return launch_p<kModeForm | kModeEval>(g, p, posq, nullptr, nullptr, out, accumulate, s);
+      return launch_p<kModeForm | kModeEval>(g, p, src, nullptr, nullptr, out, accumulate, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -209,13 +209,29 @@ __device__ __forceinline__ uint32_t load_idx(const int32_t *__restrict__ row, ui
   return *(const TSQBX_GLOBAL uint32_t *)(base + (size_t)(j * 4u));
 }
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ double4 load4(const double4 *__restrict__ base, uint32_t i) {
+// Element i of a staging array (byte offsets stay within 32 bits: a geometry
+// holds fewer than 2^27 sources).
+__device__ __forceinline__ double2 load2(const double2 *__restrict__ base, uint32_t i) {
   const TSQBX_GLOBAL char *b = (const TSQBX_GLOBAL char *)base;
-  const f64x4 v = *(const TSQBX_GLOBAL f64x4 *)(b + (size_t)(i * 32u));
-  return make_double4(v.x, v.y, v.z, v.w);
+  const f64x2 v = *(const TSQBX_GLOBAL f64x2 *)(b + (size_t)(i * 16u));
+  return make_double2(v.x, v.y);
 }
+__device__ __forceinline__ double load1(const double *__restrict__ base, uint32_t i) {
+  const TSQBX_GLOBAL char *b = (const TSQBX_GLOBAL char *)base;
+  return *(const TSQBX_GLOBAL double *)(b + (size_t)(i * 8u));
+}
+
+// The staged sources of one evaluation as the pair loops read them (the
+// arrays of SourceStage).
+struct SrcView {
+  const double2 *xy;   // (x, y)
+  const double2 *zq;   // (z, q)
+  const double2 *nxy;  // (q nx, q ny), double layer
+  const double *nz;    // q nz, double layer
+};
 
 __device__ __forceinline__ TargetRec load_target(const TSQBX_GLOBAL TargetRec *p) {
   TargetRec t;
@@ -240,7 +256,7 @@ struct TargetGeom {
 };
 
 // U pairs of one target, added to acc_s / acc_d / acc_t in the order
-// u = 0..U-1.  Source records come from posq / qn at indices s[u]
+// u = 0..U-1.  Sources come from the staged arrays at indices s[u]
 // (q = w sigma and q nu).  The sums leave out the factor 1/(4 pi).
 //
 // Single layer alone: S = sum_n b_n by Clenshaw's backward recurrence.
@@ -258,16 +274,22 @@ struct TargetGeom {
 // (constants in registers) instead of the table-driven loop; the plain kernel
 // sets it for one target per wave, where the registers are available.
 template <int P, int L, int U, bool UNROLLED_SLP>
-__device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
-                                           const double4 *__restrict__ posq,
-                                           const double4 *__restrict__ qn, const TargetGeom &tg,
-                                           double &acc_s, double &acc_d, double &acc_t) {
-  double4 a[U], b[U];
+__device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U], const SrcView &src,
+                                           const TargetGeom &tg, double &acc_s, double &acc_d,
+                                           double &acc_t) {
+  double2 a[U], aq[U], b[U];
+  double bz[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) a[u] = load4(posq, s[u]);
+  for (int u = 0; u < U; ++u) {
+    a[u] = load2(src.xy, s[u]);
+    aq[u] = load2(src.zq, s[u]);
+  }
   if constexpr (L & 2) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) b[u] = load4(qn, s[u]);
+    for (int u = 0; u < U; ++u) {
+      b[u] = load2(src.nxy, s[u]);
+      bz[u] = load1(src.nz, s[u]);
+    }
   }
   const int p = P >= 0 ? P : p_rt;
   PairState<U> st;
@@ -276,7 +298,7 @@ __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
   for (int u = 0; u < U; ++u) {
     dx[u] = a[u].x - tg.cx;
     dy[u] = a[u].y - tg.cy;
-    dz[u] = a[u].z - tg.cz;
+    dz[u] = aq[u].x - tg.cz;
     const double R2 = fma(dz[u], dz[u], fma(dy[u], dy[u], dx[u] * dx[u]));
     const double dd = fma(tg.tz, dz[u], fma(tg.ty, dy[u], tg.tx * dx[u]));
     rinv[u] = rsqrt_nr(R2);
@@ -299,7 +321,7 @@ __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
     for (int u = 0; u < U; ++u) {
       const double S = p >= 1 ? fma(st.beta[u], st.f[u], fma(-st.g2[u], kap1 * st.fm1[u], 1.0))
                               : 1.0;
-      acc_s = fma(a[u].w * rinv[u], S, acc_s);
+      acc_s = fma(aq[u].y * rinv[u], S, acc_s);
     }
   } else {
     // (fm1, f) = (F_0, F_1) for p = 0, else (F_1, F_2) = (1, beta)
@@ -323,18 +345,18 @@ __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
       if constexpr (L & 1) {
         const double w = fma(-2.0, st.beta[u], 1.0 + st.g2[u]);
         const double S0 = fma(w, S2, fma(-st.g2[u], Ep, Ep1));
-        acc_s = fma(a[u].w * rinv[u], S0, acc_s);
+        acc_s = fma(aq[u].y * rinv[u], S0, acc_s);
       }
       if constexpr (L & 2) {
-        const double nd = fma(b[u].z, dz[u], fma(b[u].y, dy[u], b[u].x * dx[u]));
-        const double nt = fma(b[u].z, tg.tz, fma(b[u].y, tg.ty, b[u].x * tg.tx));
+        const double nd = fma(bz[u], dz[u], fma(b[u].y, dy[u], b[u].x * dx[u]));
+        const double nt = fma(bz[u], tg.tz, fma(b[u].y, tg.ty, b[u].x * tg.tx));
         const double val = fma(nt, S2, -nd * (S2 + Ep1));
         acc_d = fma(val, rinv[u] * inv[u], acc_d);
       }
       if constexpr (L & 4) {
         const double ndt = fma(tg.nz, dz[u], fma(tg.ny, dy[u], tg.nx * dx[u]));
         const double vt = fma(ndt, S2, -tg.ntd * (S2 - Ep));
-        acc_t = fma(a[u].w * (rinv[u] * inv[u]), vt, acc_t);
+        acc_t = fma(aq[u].y * (rinv[u] * inv[u]), vt, acc_t);
       }
     }
   }
@@ -348,9 +370,8 @@ __device__ __forceinline__ void pair_terms(int p_rt, const uint32_t (&s)[U],
 // normal (read for S' only).
 template <int P, int L, int G, int U, bool UNROLLED_SLP, class NrmPtr>
 __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr, NrmPtr tn,
-                                           const int32_t *__restrict__ idx,
-                                           const double4 *__restrict__ posq,
-                                           const double4 *__restrict__ qn, double (&out)[3]) {
+                                           const int32_t *__restrict__ idx, const SrcView &src,
+                                           double (&out)[3]) {
   TargetGeom tg;
   tg.cx = tr.c[0];
   tg.cy = tr.c[1];
@@ -383,7 +404,7 @@ __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr
 #pragma unroll
       for (int u = 0; u < U; ++u)
         sn[u] = load_idx(row, (uint32_t)min(c0 + G * U + gl + u * G, len - 1));
-      pair_terms<P, L, U, UNROLLED_SLP>(p_rt, s, posq, qn, tg, acc_s, acc_d, acc_t);
+      pair_terms<P, L, U, UNROLLED_SLP>(p_rt, s, src, tg, acc_s, acc_d, acc_t);
 #pragma unroll
       for (int u = 0; u < U; ++u) s[u] = sn[u];
     }
@@ -392,7 +413,7 @@ __device__ __forceinline__ void target_sum(int p_rt, int gl, const TargetRec &tr
     const int j = c0 + gl;
     if (j < len) {
       const uint32_t s1[1] = {load_idx(row, (uint32_t)j)};
-      pair_terms<P, L, 1, UNROLLED_SLP>(p_rt, s1, posq, qn, tg, acc_s, acc_d, acc_t);
+      pair_terms<P, L, 1, UNROLLED_SLP>(p_rt, s1, src, tg, acc_s, acc_d, acc_t);
     }
   }
 #pragma unroll

@@ -46,12 +46,33 @@ static_assert(sizeof(CenterRec) == 64, "CenterRec layout");
 // which names a zero-strength staging record.
 constexpr int kRowPad = 16;
 
-// Per-source staging built for each evaluation: position and strength
-// q = w sigma, and q times the normal (double layer).
+// Per-source staging built for each evaluation: the position, the strength
+// q = w sigma and, for the double layer, q times the normal, in four arrays
+// of 16 or 8 bytes per source.  A wave's gather of one array then reads, for
+// a run of consecutive sources, consecutive bytes across its lanes: a
+// 16-byte load over 64 lanes touches half the 64-byte sectors that the two
+// halves of a 32-byte record would, and the vector memory pipeline's cost
+// follows the sectors a load touches.  Entry N is the padding record: far
+// from every center, with q = 0.  xy and zq share one block of
+// stage_pos_bytes(N), nxy and nz one of stage_nrm_bytes(N) (xy and nxy are
+// the blocks' bases).
 struct SourceStage {
-  double4 *posq = nullptr;  // [N + 1] (x, y, z, q); entry N: far away, q = 0
-  double4 *qn = nullptr;    // [N + 1] (q nx, q ny, q nz, 0); entry N: 0
+  double2 *xy = nullptr;    // [N + 1] (x, y)
+  double2 *zq = nullptr;    // [N + 1] (z, q)
+  double2 *nxy = nullptr;   // [N + 1] (q nx, q ny)
+  double *nz = nullptr;     // [N + 1] q nz
 };
+inline size_t stage_pos_bytes(int64_t n) { return (size_t)(n + 1) * 32; }
+inline size_t stage_nrm_bytes(int64_t n) { return (size_t)(n + 1) * 24; }
+// The four arrays inside blocks of those sizes (nrm may be null).
+inline SourceStage stage_views(void *pos, void *nrm, int64_t n) {
+  SourceStage s;
+  s.xy = (double2 *)pos;
+  s.zq = pos ? s.xy + (n + 1) : nullptr;
+  s.nxy = (double2 *)nrm;
+  s.nz = nrm ? (double *)(s.nxy + (n + 1)) : nullptr;
+  return s;
+}
 
 // Output vectors of one evaluation (device pointers, caller's target order);
 // null for a layer not evaluated.
@@ -79,6 +100,15 @@ struct Tuning {
   int xcd_remap = 1;
 };
 
+// Tuning of a plan's persistent kernel: its launch shape and the two knobs of
+// its static schedule (ranges per resident wave slot, fixed cost of a
+// wave-step).
+struct PlanTuning {
+  Tuning tn;
+  int oversub = 8;
+  int step_cost = 60;
+};
+
 }  // namespace tsqbx
 
 struct tsqbx_ctx {
@@ -93,6 +123,8 @@ struct tsqbx_ctx {
   size_t d_out_cap = 0;
   // tuning table: key = (p, layers, list bucket)
   std::map<uint64_t, tsqbx::Tuning> tuning;
+  // plan tunings: key = plan bucket (see plan_tuning_key)
+  std::map<uint64_t, tsqbx::PlanTuning> plan_tuning;
   std::mutex tuning_mu;
 };
 
@@ -150,7 +182,7 @@ bool tuning_supported(const Tuning &tn);
 // coeffs_out, mode 2 evaluates coeffs_in at the targets into out, mode 3
 // forms and evaluates in one launch.  Coefficients: [n_centers][(p+1)^2],
 // compact real layout; out in the caller's target order.
-hipError_t launch_qbxl(const tsqbx_geometry *g, int p, int mode, const double4 *posq,
+hipError_t launch_qbxl(const tsqbx_geometry *g, int p, int mode, const SourceStage &st,
                        const double *coeffs_in, double *coeffs_out, double *out, bool accumulate,
                        hipStream_t s);
 // Helmholtz (tsqbx_helmholtz.hip): staging of q = w sigma (sigma complex,
@@ -161,17 +193,20 @@ hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, dou
                             bool accumulate, const Tuning &tn, hipStream_t s);
 
 // Staging of many items in one launch (batched and served paths).
-struct StageItem {         // 64 bytes
+struct StageItem {         // 80 bytes
   const double4 *pos_w;
   const double4 *nrm;
   const void *order;         // host_sigma: rank (int32, caller -> device); else perm (int64)
   const double *sigma;       // caller order; device or pinned host memory
-  double4 *posq;
-  double4 *qn;
+  double2 *xy;               // the item's SourceStage arrays
+  double2 *zq;
+  double2 *nxy;
+  double *nz;
   int64_t n;
   int32_t want_dlp;
   int32_t host_sigma;        // 1: walk sources in caller order (contiguous reads of sigma)
 };
+static_assert(sizeof(StageItem) == 80, "StageItem layout");
 StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned layers,
                           const SourceStage &st, bool sigma_on_host);
 hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
@@ -187,11 +222,13 @@ struct CopyItem {          // 32 bytes
 hipError_t launch_copy_multi(const CopyItem *d_items, int n_items, int64_t max_n, hipStream_t s);
 
 // Persistent batched kernel.
-struct WorkItem {           // one (geometry, p, layers) item of a plan, 80 bytes
+struct WorkItem {           // one (geometry, p, layers) item of a plan, 96 bytes
   const TargetRec *tgt;
   const int32_t *idx;
-  const double4 *posq;
-  const double4 *qn;
+  const double2 *xy;        // the item's SourceStage arrays
+  const double2 *zq;
+  const double2 *nxy;
+  const double *nz;
   double *out_s;
   double *out_d;
   int32_t p;
@@ -201,7 +238,7 @@ struct WorkItem {           // one (geometry, p, layers) item of a plan, 80 byte
   const double4 *tnrm;      // target normals (S'), device order
   double *out_t;            // S' output
 };
-static_assert(sizeof(WorkItem) == 80, "WorkItem layout");
+static_assert(sizeof(WorkItem) == 96, "WorkItem layout");
 struct WorkUnit {           // a run of consecutive targets of one item, 16 bytes
   int32_t item;
   int32_t first;            // first device-order target
@@ -241,7 +278,9 @@ struct LayerClass {
 // p_all: the order shared by every item, or -1.
 hipError_t launch_persistent(const PersistentArgs &a, unsigned layer_class, int p_all,
                              const Tuning &tn, hipStream_t s);
-int persistent_max_waves(int num_cus);
+// Waves of a static schedule: oversub ranges per resident wave slot (six
+// waves per SIMD, four SIMDs per CU).
+int persistent_max_waves(int num_cus, int oversub);
 
 // One Helmholtz evaluation as the pair kernels read it: a geometry, its
 // Helmholtz staging and table(s), k, p and the complex outputs (null for a
@@ -310,8 +349,9 @@ struct ScheduleItem {
   unsigned layers;
   bool helmholtz = false;  // costed with the Helmholtz kernel's work per pair
 };
+// step_cost: the fixed cost of a wave-step beyond its pairs.
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
-                    int group_lanes, int max_waves, std::vector<WorkUnit> *units,
+                    int group_lanes, int max_waves, double step_cost, std::vector<WorkUnit> *units,
                     std::vector<int32_t> *wave_begin);
 
 Tuning default_tuning(int p, unsigned layers, int64_t mean_list);

@@ -11,9 +11,9 @@ namespace {
 template <int P, int L, int G, int U>
 __global__ void __launch_bounds__(256)
 k_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm, int64_t n_targets,
-       const int32_t *__restrict__ idx, const double4 *__restrict__ posq,
-       const double4 *__restrict__ qn, double *__restrict__ out_s, double *__restrict__ out_d,
-       double *__restrict__ out_t, int accumulate, int p_rt, int remap) {
+       const int32_t *__restrict__ idx, SrcView src, double *__restrict__ out_s,
+       double *__restrict__ out_d, double *__restrict__ out_t, int accumulate, int p_rt,
+       int remap) {
   constexpr int TPW = 64 / G;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -24,64 +24,83 @@ k_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm, int6
   if (t >= n_targets) return;
   const TargetRec tr = tgt[t];
   double v[3];
-  target_sum<P, L, G, U, G == 64>(p_rt, lane % G, tr, tnrm + t, idx, posq, qn, v);
+  target_sum<P, L, G, U, G == 64>(p_rt, lane % G, tr, tnrm + t, idx, src, v);
   if (lane % G == 0) store_out<L>(tr, v, out_s, out_d, out_t, accumulate);
 }
 
-// Staging: q = w sigma in device source order, and q nu for the double layer.
-// Entry n is the padding record: finite and far from every center, q = 0, so
-// a padded list entry contributes exactly zero.
-__global__ void __launch_bounds__(256)
-k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict__ nrm,
-        const int64_t *__restrict__ perm, const double *__restrict__ sigma,
-        double4 *__restrict__ posq, double4 *__restrict__ qn, int want_dlp) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i == n) {
-      posq[n] = make_double4(1e100, 1e100, 1e100, 0.0);
-      if (want_dlp) qn[n] = make_double4(0.0, 0.0, 0.0, 0.0);
-      continue;
-    }
-    const double4 a = pos_w[i];
-    const double q = a.w * sigma[perm ? perm[i] : i];
-    posq[i] = make_double4(a.x, a.y, a.z, q);
-    if (want_dlp) {
-      const double4 v = nrm[i];
-      qn[i] = make_double4(q * v.x, q * v.y, q * v.z, 0.0);
-    }
+// Staging of one source: (x, y), (z, q) with q = w sigma and, for the double
+// layer, (q nx, q ny) and q nz, at device index j; pw holds (x, y, z, w) and
+// nv (nx, ny, nz, 0) per source.
+template <class PR, class PD>
+__device__ __forceinline__ void stage_one(int64_t j, PR pw, PR nv, double sg, PD xy, PD zq,
+                                          PD nxy, PD nz, int want_dlp) {
+  const double q = pw[4 * j + 3] * sg;
+  xy[2 * j] = pw[4 * j];
+  xy[2 * j + 1] = pw[4 * j + 1];
+  zq[2 * j] = pw[4 * j + 2];
+  zq[2 * j + 1] = q;
+  if (want_dlp) {
+    nxy[2 * j] = q * nv[4 * j];
+    nxy[2 * j + 1] = q * nv[4 * j + 1];
+    nz[j] = q * nv[4 * j + 2];
   }
 }
 
-// The same staging for many items: blockIdx.y selects the item.
+// Entry n, the padding record: finite and far from every center, q = 0, so
+// a padded list entry contributes exactly zero.
+template <class PD>
+__device__ __forceinline__ void stage_pad(int64_t n, PD xy, PD zq, PD nxy, PD nz, int want_dlp) {
+  xy[2 * n] = 1e100;
+  xy[2 * n + 1] = 1e100;
+  zq[2 * n] = 1e100;
+  zq[2 * n + 1] = 0.0;
+  if (want_dlp) {
+    nxy[2 * n] = 0.0;
+    nxy[2 * n + 1] = 0.0;
+    nz[n] = 0.0;
+  }
+}
+
+// Staging in device source order.
+__global__ void __launch_bounds__(256)
+k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict__ nrm,
+        const int64_t *__restrict__ perm, const double *__restrict__ sigma, double2 *xy2,
+        double2 *zq2, double2 *nxy2, double *nz, int want_dlp) {
+  typedef TSQBX_GLOBAL double *GD;
+  typedef const TSQBX_GLOBAL double *GR;
+  const GR pw = (GR)pos_w, nv = (GR)nrm;
+  const GD xy = (GD)xy2, zq = (GD)zq2, nxy = (GD)nxy2, nzg = (GD)nz;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == n) {
+      stage_pad(n, xy, zq, nxy, nzg, want_dlp);
+      continue;
+    }
+    stage_one(i, pw, nv, sigma[perm ? perm[i] : i], xy, zq, nxy, nzg, want_dlp);
+  }
+}
+
 // The same staging for many items (blockIdx.y selects the item).  A density
 // in device memory is gathered while walking the sources in device order; a
 // density in pinned host memory is read contiguously, walking the sources in
 // the caller's order, since every read then crosses PCIe.
 __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict__ items) {
+  typedef TSQBX_GLOBAL double *GD;
+  typedef const TSQBX_GLOBAL double *GR;
   const TSQBX_GLOBAL StageItem *gi = (const TSQBX_GLOBAL StageItem *)items + blockIdx.y;
   const int64_t n = gi->n;
   const int want_dlp = gi->want_dlp;
   const int host_sigma = gi->host_sigma;
-  const TSQBX_GLOBAL double *pw = (const TSQBX_GLOBAL double *)gi->pos_w;  // (x, y, z, w)
-  const TSQBX_GLOBAL double *nv = (const TSQBX_GLOBAL double *)gi->nrm;    // (nx, ny, nz, 0)
+  const GR pw = (GR)gi->pos_w;  // (x, y, z, w)
+  const GR nv = (GR)gi->nrm;    // (nx, ny, nz, 0)
   const TSQBX_GLOBAL int32_t *rank = (const TSQBX_GLOBAL int32_t *)gi->order;
   const TSQBX_GLOBAL int64_t *perm = (const TSQBX_GLOBAL int64_t *)gi->order;
-  const double *sigma = gi->sigma;
-  TSQBX_GLOBAL double *posq = (TSQBX_GLOBAL double *)gi->posq;
-  TSQBX_GLOBAL double *qn = (TSQBX_GLOBAL double *)gi->qn;
+  const double *sigma = gi->sigma;  // device or pinned host memory
+  const GD xy = (GD)gi->xy, zq = (GD)gi->zq, nxy = (GD)gi->nxy, nz = (GD)gi->nz;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    if (i == n) {  // the padding record
-      posq[4 * n] = 1e100;
-      posq[4 * n + 1] = 1e100;
-      posq[4 * n + 2] = 1e100;
-      posq[4 * n + 3] = 0.0;
-      if (want_dlp) {
-        qn[4 * n] = 0.0;
-        qn[4 * n + 1] = 0.0;
-        qn[4 * n + 2] = 0.0;
-        qn[4 * n + 3] = 0.0;
-      }
+    if (i == n) {
+      stage_pad(n, xy, zq, nxy, nz, want_dlp);
       continue;
     }
     int64_t j;  // device index
@@ -93,17 +112,7 @@ __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict
       j = i;
       sg = sigma[perm ? perm[i] : i];
     }
-    const double q = pw[4 * j + 3] * sg;
-    posq[4 * j] = pw[4 * j];
-    posq[4 * j + 1] = pw[4 * j + 1];
-    posq[4 * j + 2] = pw[4 * j + 2];
-    posq[4 * j + 3] = q;
-    if (want_dlp) {
-      qn[4 * j] = q * nv[4 * j];
-      qn[4 * j + 1] = q * nv[4 * j + 1];
-      qn[4 * j + 2] = q * nv[4 * j + 2];
-      qn[4 * j + 3] = 0.0;
-    }
+    stage_one(j, pw, nv, sg, xy, zq, nxy, nz, want_dlp);
   }
 }
 
@@ -127,9 +136,10 @@ hipError_t launch_one(const tsqbx_geometry *g, int p, const SourceStage &st, con
   const int64_t blocks = (g->n_targets + per_block - 1) / per_block;
   if (blocks <= 0) return hipSuccess;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  const SrcView src{st.xy, st.zq, st.nxy, st.nz};
   hipLaunchKernelGGL((k_eval<P, L, G, U>), dim3((unsigned)blocks), dim3(64 * tn.waves_per_block),
-                     0, s, g->tgt, g->tgt_nrm, g->n_targets, g->idx, st.posq, st.qn, o.s, o.d,
-                     o.t, acc ? 1 : 0, p, tn.xcd_remap);
+                     0, s, g->tgt, g->tgt_nrm, g->n_targets, g->idx, src, o.s, o.d, o.t,
+                     acc ? 1 : 0, p, tn.xcd_remap);
   return hipGetLastError();
 }
 
@@ -188,7 +198,8 @@ hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned
   if (n < 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 1 + 255) / 256, 65536);
   hipLaunchKernelGGL(k_stage, dim3((unsigned)blocks), dim3(256), 0, s, n, g->src_pos, g->src_nrm,
-                     g->src_perm, d_sigma, st.posq, st.qn, (layers & TSQBX_DLP) ? 1 : 0);
+                     g->src_perm, d_sigma, st.xy, st.zq, st.nxy, st.nz,
+                     (layers & TSQBX_DLP) ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -200,8 +211,10 @@ StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned
   it.host_sigma = sigma_on_host ? 1 : 0;
   it.order = sigma_on_host ? (const void *)g->src_rank : (const void *)g->src_perm;
   it.sigma = sigma;
-  it.posq = st.posq;
-  it.qn = st.qn;
+  it.xy = st.xy;
+  it.zq = st.zq;
+  it.nxy = st.nxy;
+  it.nz = st.nz;
   it.n = g->n_sources;
   it.want_dlp = (layers & TSQBX_DLP) ? 1 : 0;
   return it;

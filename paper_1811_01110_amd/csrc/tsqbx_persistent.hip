@@ -24,8 +24,8 @@ __device__ __forceinline__ void unit_body(const WorkItem &it, int first, int cou
     if (slot >= count) break;  // whole groups leave together
     const TargetRec tr = load_target(tgt + first + slot);
     double v[3];
-    target_sum<P, L, G, U, false>(it.p, lane % G, tr, tnrm + first + slot, it.idx, it.posq,
-                                  it.qn, v);
+    const SrcView src{it.xy, it.zq, it.nxy, it.nz};
+    target_sum<P, L, G, U, false>(it.p, lane % G, tr, tnrm + first + slot, it.idx, src, v);
     if (lane % G == 0)
       store_out<L>(tr, v, (TSQBX_GLOBAL double *)it.out_s, (TSQBX_GLOBAL double *)it.out_d,
                    (TSQBX_GLOBAL double *)it.out_t, it.accumulate);
@@ -75,8 +75,10 @@ __global__ void __launch_bounds__(256) k_persistent(PersistentArgs a) {
     WorkItem it;
     it.tgt = items[item].tgt;
     it.idx = items[item].idx;
-    it.posq = items[item].posq;
-    it.qn = items[item].qn;
+    it.xy = items[item].xy;
+    it.zq = items[item].zq;
+    it.nxy = items[item].nxy;
+    it.nz = items[item].nz;
     it.out_s = items[item].out_s;
     it.out_d = items[item].out_d;
     it.p = items[item].p;
@@ -114,10 +116,10 @@ __global__ void __launch_bounds__(256) k_persistent(PersistentArgs a) {
 
 }  // namespace
 
-int persistent_max_waves(int num_cus) {
-  // eight times the waves that fit at six per SIMD: the dispatcher hands out
-  // blocks as others finish, which evens out differences in speed
-  return std::max(1, num_cus) * 4 * 6 * 8;
+int persistent_max_waves(int num_cus, int oversub) {
+  // oversub times the waves that fit at six per SIMD: the dispatcher hands
+  // out blocks as others finish, which evens out differences in speed
+  return std::max(1, num_cus) * 4 * 6 * std::max(1, oversub);
 }
 
 namespace {

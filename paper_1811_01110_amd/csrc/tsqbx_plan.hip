@@ -35,6 +35,12 @@ struct tsqbx_plan {
   unsigned layer_class = kLayersMixed;  // see LayerClass
   int p_all = -1;            // the order shared by every item, or -1
   Tuning tn;
+  int oversub = 8;           // schedule ranges per resident wave slot
+  int step_cost = 60;        // fixed cost of a wave-step in the schedule
+  uint64_t tune_key = 0;     // the plan's bucket in the context's plan-tuning table
+  std::vector<ScheduleItem> sched;  // items as the schedule sees them
+  std::vector<int32_t> order;       // items largest first
+  size_t sched_bytes = 0;           // device bytes of units and wave_begin
   size_t device_bytes = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -69,8 +75,8 @@ void free_plan(tsqbx_plan *pl) {
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   for (auto &s : pl->stages) {
-    if (s.posq) (void)hipFree(s.posq);
-    if (s.qn) (void)hipFree(s.qn);
+    if (s.xy) (void)hipFree(s.xy);    // the blocks' bases
+    if (s.nxy) (void)hipFree(s.nxy);
   }
   for (auto &h : pl->hstages) {
     if (h.rec) (void)hipFree(h.rec);
@@ -125,7 +131,7 @@ std::vector<int32_t> order_largest_first(const std::vector<ScheduleItem> &items)
 }
 
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
-                    int group_lanes, int max_waves, std::vector<WorkUnit> *units,
+                    int group_lanes, int max_waves, double step_cost, std::vector<WorkUnit> *units,
                     std::vector<int32_t> *wave_begin) {
   const int G = group_lanes, TPW = 64 / G;
   // the wave-steps: TPW consecutive targets of one item, costed by the
@@ -145,7 +151,7 @@ void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<in
       int64_t chunks = 0;
       for (int32_t x = 0; x < cnt; ++x)
         chunks = std::max<int64_t>(chunks, (g->host_row_len[k + x] + G - 1) / G);
-      const double c = (double)chunks * pc + 60.0;
+      const double c = (double)chunks * pc + step_cost;
       steps.push_back(WStep{oi, (int32_t)k, cnt, c});
       total += c;
     }
@@ -175,6 +181,110 @@ void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<in
 }
 
 }  // namespace tsqbx
+
+namespace {
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while (b < 40 && (int64_t(1) << (b + 1)) <= v) ++b;
+  return b;
+}
+
+// A plan's bucket in the context's plan-tuning table: kernel family, the
+// orders present (one bit each), the union of the layer masks, and the mean
+// list length and target count rounded down to powers of two.
+uint64_t plan_tuning_key(bool helm, uint64_t pmask, unsigned layers, int64_t mean_list,
+                         int64_t targets) {
+  return (uint64_t)(helm ? 1 : 0) | (uint64_t)(layers & 7u) << 1 |
+         (uint64_t)log2_bucket(mean_list) << 4 | (uint64_t)log2_bucket(targets) << 10 |
+         (pmask & ((uint64_t(1) << (TSQBX_P_MAX + 1)) - 1)) << 16;
+}
+
+bool plan_tuning_valid(const PlanTuning &t) {
+  const int G = t.tn.group_lanes, U = t.tn.unroll, W = t.tn.waves_per_block;
+  if (!((G == 64 && (U == 1 || U == 2)) || ((G == 32 || G == 16) && U == 2))) return false;
+  if (!(W == 1 || W == 2 || W == 4)) return false;
+  return t.oversub >= 1 && t.oversub <= 32 && t.step_cost >= 0 && t.step_cost <= 100000;
+}
+
+PlanTuning plan_tuning_of(const tsqbx_plan *pl) {
+  PlanTuning t;
+  t.tn = pl->tn;
+  t.oversub = pl->oversub;
+  t.step_cost = pl->step_cost;
+  return t;
+}
+
+// (Re)build the static schedule for the plan's current tuning and upload it.
+// A captured graph is dropped: the next execute captures the new launch.
+hipError_t plan_schedule(tsqbx_plan *pl) {
+  std::vector<WorkUnit> units;
+  std::vector<int32_t> wave_begin;
+  const int cus = pl->ctx->num_cus > 0 ? pl->ctx->num_cus : 256;
+  build_schedule(pl->sched, pl->order, pl->tn.group_lanes, persistent_max_waves(cus, pl->oversub),
+                 (double)pl->step_cost, &units, &wave_begin);
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->d_units) (void)hipFree(pl->d_units);
+  if (pl->d_wave_begin) (void)hipFree(pl->d_wave_begin);
+  pl->exec = nullptr;
+  pl->graph = nullptr;
+  pl->d_units = nullptr;
+  pl->d_wave_begin = nullptr;
+  pl->device_bytes -= pl->sched_bytes;
+  pl->n_units = (int64_t)units.size();
+  pl->n_waves = (int32_t)wave_begin.size() - 1;
+  pl->grid = (pl->n_waves + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block;
+  pl->sched_bytes = units.size() * sizeof(WorkUnit) + wave_begin.size() * sizeof(int32_t);
+  pl->device_bytes += pl->sched_bytes;
+  hipError_t e = hipSuccess;
+  if (pl->n_units) e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
+  if (e == hipSuccess && pl->n_units)
+    e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&pl->d_wave_begin, wave_begin.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->d_wave_begin, wave_begin.data(), wave_begin.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice);
+  return e;
+}
+
+// The plan's launches on s: staging (Helmholtz: and the j_n tables), then
+// the persistent kernel.  ev (nullable): three events recorded before the
+// staging, between the two and after the evaluation.
+hipError_t plan_launch(tsqbx_plan *pl, hipStream_t s, hipEvent_t *ev) {
+  hipError_t e = ev ? hipEventRecord(ev[0], s) : hipSuccess;
+  if (e != hipSuccess) return e;
+  if (pl->helm)
+    e = launch_helm_prepare_multi(pl->d_hprep, (int)pl->hitems.size(), pl->max_sources,
+                                  pl->max_targets, s);
+  else
+    e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, s);
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess && pl->n_units > 0) {
+    if (pl->helm) {
+      HelmPersistentArgs a{pl->d_hitems, pl->d_units, pl->d_wave_begin, pl->n_waves};
+      e = launch_helm_persistent(a, pl->layer_class, pl->tn, s);
+    } else {
+      PersistentArgs a{pl->d_items, pl->d_units, pl->d_wave_begin, pl->n_waves};
+      e = launch_persistent(a, pl->layer_class, pl->p_all, pl->tn, s);
+    }
+  }
+  if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
+  return e;
+}
+
+// Take the context's tuning for the plan's bucket, if one was installed.
+void apply_cached_tuning(tsqbx_plan *pl) {
+  std::lock_guard<std::mutex> lk(pl->ctx->tuning_mu);
+  auto it = pl->ctx->plan_tuning.find(pl->tune_key);
+  if (it == pl->ctx->plan_tuning.end() || !plan_tuning_valid(it->second)) return;
+  pl->tn = it->second.tn;
+  pl->oversub = it->second.oversub;
+  pl->step_cost = it->second.step_cost;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -211,7 +321,7 @@ int tsqbx_schedule_preview(int64_t n_items, const int64_t *n_targets, const int6
   }
   std::vector<WorkUnit> u;
   std::vector<int32_t> wb;
-  build_schedule(sched, order_largest_first(sched), group_lanes, max_waves, &u, &wb);
+  build_schedule(sched, order_largest_first(sched), group_lanes, max_waves, 60.0, &u, &wb);
   *n_units = (int64_t)u.size();
   *n_waves = (int32_t)wb.size() - 1;
   if ((int64_t)u.size() > units_cap || (u.size() && !units))
@@ -277,19 +387,16 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent kernels keep two pairs in flight
   if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
   if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, 3u, mean_list);
+  uint64_t pmask = 0;
+  for (auto &it : pl->items) pmask |= uint64_t(1) << it.p;
+  pl->tune_key = plan_tuning_key(false, pmask, lay_all, mean_list, tot_targets);
+  apply_cached_tuning(pl);
 
   // static schedule over the resident waves, items largest first
-  std::vector<ScheduleItem> sched(n_items);
+  pl->sched.resize(n_items);
   for (int64_t i = 0; i < n_items; ++i)
-    sched[i] = ScheduleItem{pl->items[i].geom, pl->items[i].p, pl->items[i].layers};
-  const std::vector<int32_t> order32 = order_largest_first(sched);
-  std::vector<WorkUnit> units;
-  std::vector<int32_t> wave_begin;
-  build_schedule(sched, order32, pl->tn.group_lanes,
-                 persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256), &units, &wave_begin);
-  pl->n_units = (int64_t)units.size();
-  pl->n_waves = (int32_t)wave_begin.size() - 1;
-  pl->grid = (pl->n_waves + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block;
+    pl->sched[i] = ScheduleItem{pl->items[i].geom, pl->items[i].p, pl->items[i].layers};
+  pl->order = order_largest_first(pl->sched);
 
   // per-item staging and the device copies of items and units
   std::vector<WorkItem> witems(n_items);
@@ -298,21 +405,25 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   pl->stages.resize(n_items);
   for (int64_t i = 0; i < n_items && e == hipSuccess; ++i) {
     const tsqbx_item &it = pl->items[i];
-    const size_t N1 = (size_t)it.geom->n_sources + 1;  // + the padding record
-    e = hipMalloc((void **)&pl->stages[i].posq, N1 * sizeof(double4));
-    pl->device_bytes += N1 * sizeof(double4);
+    const int64_t N = it.geom->n_sources;
+    void *spos = nullptr, *snrm = nullptr;
+    e = hipMalloc(&spos, stage_pos_bytes(N));
+    pl->device_bytes += stage_pos_bytes(N);
     if (e == hipSuccess && (it.layers & TSQBX_DLP)) {
-      e = hipMalloc((void **)&pl->stages[i].qn, N1 * sizeof(double4));
-      pl->device_bytes += N1 * sizeof(double4);
+      e = hipMalloc(&snrm, stage_nrm_bytes(N));
+      pl->device_bytes += stage_nrm_bytes(N);
     }
+    pl->stages[i] = stage_views(spos, snrm, N);
     sitems[i] = make_stage_item(it.geom, it.d_sigma, it.layers, pl->stages[i], false);
     pl->max_sources = std::max<int64_t>(pl->max_sources, it.geom->n_sources);
     WorkItem &w = witems[i];
     w = WorkItem{};
     w.tgt = it.geom->tgt;
     w.idx = it.geom->idx;
-    w.posq = pl->stages[i].posq;
-    w.qn = pl->stages[i].qn;
+    w.xy = pl->stages[i].xy;
+    w.zq = pl->stages[i].zq;
+    w.nxy = pl->stages[i].nxy;
+    w.nz = pl->stages[i].nz;
     w.out_s = it.d_out_slp;
     w.out_d = it.d_out_dlp;
     w.out_t = it.d_out_sprime;
@@ -327,18 +438,9 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_stage, n_items * sizeof(StageItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_stage, sitems.data(), n_items * sizeof(StageItem), hipMemcpyHostToDevice);
-  if (e == hipSuccess && pl->n_units)
-    e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
-  if (e == hipSuccess && pl->n_units)
-    e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMalloc((void **)&pl->d_wave_begin, wave_begin.size() * sizeof(int32_t));
-  if (e == hipSuccess)
-    e = hipMemcpy(pl->d_wave_begin, wave_begin.data(), wave_begin.size() * sizeof(int32_t),
-                  hipMemcpyHostToDevice);
+  pl->device_bytes += n_items * (sizeof(WorkItem) + sizeof(StageItem));
+  if (e == hipSuccess) e = plan_schedule(pl);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
-  pl->device_bytes += n_items * (sizeof(WorkItem) + sizeof(StageItem)) +
-                      units.size() * sizeof(WorkUnit) + wave_begin.size() * sizeof(int32_t);
   if (e != hipSuccess) {
     free_plan(pl);
     return fail_hip(e, "plan setup");
@@ -396,6 +498,10 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
   pl->tn.unroll = std::min(std::max(pl->tn.unroll, 1), 2);
   if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
   if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, lay_all, mean_list);
+  uint64_t pmask = 0;
+  for (auto &it : pl->hitems) pmask |= uint64_t(1) << it.p;
+  pl->tune_key = plan_tuning_key(true, pmask, lay_all, mean_list, tot_targets);
+  apply_cached_tuning(pl);
 
   // item order: largest first; static schedule over the resident waves
   std::vector<int64_t> ord(n_items);
@@ -404,17 +510,10 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
   for (int64_t i = 0; i < n_items; ++i)
     icost[i] = (double)pl->hitems[i].geom->pairs * helm_pair_cost(pl->hitems[i].p, pl->hitems[i].layers);
   std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return icost[a] > icost[b]; });
-  std::vector<ScheduleItem> sched(n_items);
+  pl->sched.resize(n_items);
   for (int64_t i = 0; i < n_items; ++i)
-    sched[i] = ScheduleItem{pl->hitems[i].geom, pl->hitems[i].p, pl->hitems[i].layers, true};
-  std::vector<int32_t> order32(ord.begin(), ord.end());
-  std::vector<WorkUnit> units;
-  std::vector<int32_t> wave_begin;
-  build_schedule(sched, order32, pl->tn.group_lanes,
-                 persistent_max_waves(ctx->num_cus > 0 ? ctx->num_cus : 256), &units, &wave_begin);
-  pl->n_units = (int64_t)units.size();
-  pl->n_waves = (int32_t)wave_begin.size() - 1;
-  pl->grid = (pl->n_waves + pl->tn.waves_per_block - 1) / pl->tn.waves_per_block;
+    pl->sched[i] = ScheduleItem{pl->hitems[i].geom, pl->hitems[i].p, pl->hitems[i].layers, true};
+  pl->order.assign(ord.begin(), ord.end());
 
   // per-item staging, tables and the device copies of items and units
   std::vector<HelmWorkItem> witems(n_items);
@@ -471,18 +570,9 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_hitems, n_items * sizeof(HelmWorkItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_hitems, witems.data(), n_items * sizeof(HelmWorkItem), hipMemcpyHostToDevice);
-  if (e == hipSuccess && pl->n_units)
-    e = hipMalloc((void **)&pl->d_units, units.size() * sizeof(WorkUnit));
-  if (e == hipSuccess && pl->n_units)
-    e = hipMemcpy(pl->d_units, units.data(), units.size() * sizeof(WorkUnit), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMalloc((void **)&pl->d_wave_begin, wave_begin.size() * sizeof(int32_t));
-  if (e == hipSuccess)
-    e = hipMemcpy(pl->d_wave_begin, wave_begin.data(), wave_begin.size() * sizeof(int32_t),
-                  hipMemcpyHostToDevice);
+  pl->device_bytes += n_items * (sizeof(HelmWorkItem) + sizeof(HelmPrepItem));
+  if (e == hipSuccess) e = plan_schedule(pl);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
-  pl->device_bytes += n_items * (sizeof(HelmWorkItem) + sizeof(HelmPrepItem)) +
-                      units.size() * sizeof(WorkUnit) + wave_begin.size() * sizeof(int32_t);
   if (e != hipSuccess) {
     free_plan(pl);
     return fail_hip(e, "plan setup");
@@ -497,26 +587,11 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
   Guard dg(pl->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   if (!pl->exec) {
-    // capture: staging of every item (one kernel), then the persistent kernel
+    // capture: staging of every item (one kernel; Helmholtz: and the tables),
+    // then the persistent kernel
     hipStream_t cs = pl->cap_stream;
     TSQBX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    if (pl->helm) {
-      // every item's density and tables (one launch each), then one
-      // persistent launch
-      e = launch_helm_prepare_multi(pl->d_hprep, (int)pl->hitems.size(), pl->max_sources,
-                                    pl->max_targets, cs);
-      if (e == hipSuccess && pl->n_units > 0) {
-        HelmPersistentArgs a{pl->d_hitems, pl->d_units, pl->d_wave_begin, pl->n_waves};
-        e = launch_helm_persistent(a, pl->layer_class, pl->tn, cs);
-      }
-    } else {
-      e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, cs);
-      if (e == hipSuccess && pl->n_units > 0) {
-        PersistentArgs a{pl->d_items, pl->d_units, pl->d_wave_begin, pl->n_waves};
-        e = launch_persistent(a, pl->layer_class, pl->p_all, pl->tn, cs);
-      }
-    }
+    hipError_t e = plan_launch(pl, cs, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -531,6 +606,140 @@ int tsqbx_plan_execute(tsqbx_plan *pl, void *hip_stream) {
     }
   }
   TSQBX_HIP(hipGraphLaunch(pl->exec, (hipStream_t)hip_stream));
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_get_tuning(const tsqbx_plan *pl, tsqbx_plan_tuning *out) {
+  if (!pl || !out) return fail(TSQBX_E_INVALID, "plan or out is NULL");
+  out->group_lanes = pl->tn.group_lanes;
+  out->unroll = pl->tn.unroll;
+  out->waves_per_block = pl->tn.waves_per_block;
+  out->oversubscription = pl->oversub;
+  out->step_cost = pl->step_cost;
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_set_tuning(tsqbx_plan *pl, const tsqbx_plan_tuning *t) {
+  TraceRange trace_("tsqbx_plan_set_tuning");
+  if (!pl || !t) return fail(TSQBX_E_INVALID, "plan or tuning is NULL");
+  PlanTuning pt = plan_tuning_of(pl);
+  pt.tn.group_lanes = t->group_lanes;
+  pt.tn.unroll = t->unroll;
+  pt.tn.waves_per_block = t->waves_per_block;
+  pt.oversub = t->oversubscription;
+  pt.step_cost = t->step_cost;
+  if (!plan_tuning_valid(pt))
+    return fail(TSQBX_E_INVALID,
+                "plan tuning (group_lanes %d, unroll %d, waves_per_block %d, oversubscription "
+                "%d, step_cost %d) is not supported",
+                t->group_lanes, t->unroll, t->waves_per_block, t->oversubscription, t->step_cost);
+  Guard dg(pl->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  TSQBX_HIP(hipDeviceSynchronize());  // earlier launches may still read the schedule
+  pl->tn = pt.tn;
+  pl->oversub = pt.oversub;
+  pl->step_cost = pt.step_cost;
+  TSQBX_HIP(plan_schedule(pl));
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_profile(tsqbx_plan *pl, int reps, void *hip_stream, tsqbx_plan_timing *out) {
+  TraceRange trace_("tsqbx_plan_profile");
+  if (!pl || !out) return fail(TSQBX_E_INVALID, "plan or out is NULL");
+  if (reps < 1 || reps > 1000) return fail(TSQBX_E_RANGE, "reps = %d is outside [1, 1000]", reps);
+  Guard dg(pl->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+  double st = 0.0, ev_ms = 0.0;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    e = plan_launch(pl, s, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+    float a = 0.f, b = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
+    if (r > 0) {  // the first run warms up
+      st += a;
+      ev_ms += b;
+    }
+  }
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return fail_hip(e, "plan profile");
+  out->stage_ms = st / reps;
+  out->eval_ms = ev_ms / reps;
+  out->reps = reps;
+  return TSQBX_OK;
+}
+
+int tsqbx_plan_autotune(tsqbx_plan *pl, void *hip_stream, tsqbx_plan_tuning *out,
+                        double *best_ms) {
+  TraceRange trace_("tsqbx_plan_autotune");
+  if (!pl) return fail(TSQBX_E_INVALID, "plan is NULL");
+  Guard dg(pl->device);
+  if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
+  TSQBX_HIP(hipDeviceSynchronize());
+  PlanTuning best = plan_tuning_of(pl);
+  double best_t = 1e300;
+  // time one candidate; keep it if it beats the best so far
+  auto trial = [&](const PlanTuning &c) -> int {
+    if (!plan_tuning_valid(c)) return TSQBX_OK;
+    pl->tn = c.tn;
+    pl->oversub = c.oversub;
+    pl->step_cost = c.step_cost;
+    hipError_t e = plan_schedule(pl);
+    if (e != hipSuccess) return fail_hip(e, "plan autotune schedule");
+    tsqbx_plan_timing tm;
+    int rc = tsqbx_plan_profile(pl, 3, hip_stream, &tm);
+    if (rc != TSQBX_OK) return rc;
+    if (tm.eval_ms < best_t) {
+      best_t = tm.eval_ms;
+      best = c;
+    }
+    return TSQBX_OK;
+  };
+  int rc = trial(best);  // the current tuning first
+  static const int GU[][2] = {{64, 1}, {64, 2}, {32, 2}, {16, 2}};
+  for (auto &gu : GU) {
+    if (rc != TSQBX_OK) break;
+    PlanTuning c = best;
+    c.tn.group_lanes = gu[0];
+    c.tn.unroll = gu[1];
+    rc = trial(c);
+  }
+  for (int w : {1, 2, 4}) {
+    if (rc != TSQBX_OK) break;
+    PlanTuning c = best;
+    c.tn.waves_per_block = w;
+    rc = trial(c);
+  }
+  for (int o : {1, 2, 4, 8, 16}) {
+    if (rc != TSQBX_OK) break;
+    PlanTuning c = best;
+    c.oversub = o;
+    rc = trial(c);
+  }
+  for (int sc : {0, 15, 60, 240, 1000}) {
+    if (rc != TSQBX_OK) break;
+    PlanTuning c = best;
+    c.step_cost = sc;
+    rc = trial(c);
+  }
+  // leave the plan on the best tuning (also after a failure)
+  pl->tn = best.tn;
+  pl->oversub = best.oversub;
+  pl->step_cost = best.step_cost;
+  hipError_t e = plan_schedule(pl);
+  if (rc != TSQBX_OK) return rc;
+  if (e != hipSuccess) return fail_hip(e, "plan autotune schedule");
+  {
+    std::lock_guard<std::mutex> lk(pl->ctx->tuning_mu);
+    pl->ctx->plan_tuning[pl->tune_key] = best;
+  }
+  if (out) tsqbx_plan_get_tuning(pl, out);
+  if (best_ms) *best_ms = best_t;
   return TSQBX_OK;
 }
 

@@ -38,6 +38,11 @@ constexpr int kUnitSteps = 8;  // wave-steps (group_lanes-wide passes) per unit
 // the step's launches.
 constexpr int kMaxStepRequests = 32;
 constexpr size_t kAlign = 256;
+// Completed requests whose status stays queryable (poll, wait); older ones
+// are forgotten, so that a long-running server holds bounded host memory.
+constexpr size_t kKeepDone = 4096;
+// Latency percentiles cover the most recent completions, at most this many.
+constexpr size_t kLatWindow = 65536;
 
 double now_s() {
   using namespace std::chrono;
@@ -104,6 +109,7 @@ struct Request {
   double t_submit = 0, t_launch = 0, t_done = 0;
   int status = TSQBX_OK;
   bool done = false;
+  int waiters = 0;                  // threads blocked in tsqbx_server_wait on it
 };
 
 struct Step {
@@ -158,12 +164,37 @@ struct tsqbx_server {
   size_t bytes_in_flight = 0, peak_bytes = 0;
   int reqs_in_flight = 0;
   tsqbx_server_stats st{};
-  std::vector<double> lat_ms, queue_ms;
+  std::vector<double> lat_ms, queue_ms;  // rings of the last kLatWindow completions
+  size_t lat_next = 0;
+  std::deque<uint64_t> retired;          // completed tickets, oldest first
   double busy_since = -1, busy_acc = 0;
   double host_launch_s = 0;  // scheduler time spent issuing steps
   std::thread sched, comp;
 
   int launch_step(Step &step, std::string &err);
+  // Record a completion (caller holds mu): latency rings, and forget the
+  // oldest completed requests beyond kKeepDone (not one a waiter still holds).
+  void retire(Request *r) {
+    const double lat = (r->t_done - r->t_submit) * 1e3, qu = (r->t_launch - r->t_submit) * 1e3;
+    if (lat_ms.size() < kLatWindow) {
+      lat_ms.push_back(lat);
+      queue_ms.push_back(qu);
+    } else {
+      lat_ms[lat_next] = lat;
+      queue_ms[lat_next] = qu;
+    }
+    lat_next = (lat_next + 1) % kLatWindow;
+    retired.push_back(r->ticket);
+    while (retired.size() > kKeepDone) {
+      auto it = all.find(retired.front());
+      if (it != all.end()) {
+        if (it->second->waiters > 0) break;
+        delete it->second;
+        all.erase(it);
+      }
+      retired.pop_front();
+    }
+  }
   void release_host_stage(Request *r) {
     if (r->pinned) {
       std::lock_guard<std::mutex> g(pinned_mu);
@@ -182,12 +213,13 @@ static int n_layers(unsigned layers) {
          ((layers & TSQBX_SPRIME) ? 1 : 0);
 }
 
-// Device bytes of a request: [sigma (N) | posq (N+1) | qn (N+1), double layer
-// only | one T-vector per requested layer].
+// Device bytes of a request: [sigma (N) | positions and strengths
+// (stage_pos_bytes) | strength-weighted normals (stage_nrm_bytes), double
+// layer only | one T-vector per requested layer].
 static size_t request_bytes(const tsqbx_geometry *g, unsigned layers) {
   const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
-  size_t b = align_up(N * sizeof(double)) + align_up((N + 1) * sizeof(double4));
-  if (layers & TSQBX_DLP) b += align_up((N + 1) * sizeof(double4));
+  size_t b = align_up(N * sizeof(double)) + align_up(stage_pos_bytes(g->n_sources));
+  if (layers & TSQBX_DLP) b += align_up(stage_nrm_bytes(g->n_sources));
   b += n_layers(layers) * align_up(T * sizeof(double));
   return std::max<size_t>(b, kAlign);
 }
@@ -299,13 +331,13 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
         hunits.push_back(WorkUnit{hi, (int32_t)k, (int32_t)std::min<int64_t>(per_unit, g->n_targets - k), 0});
       }
     } else {
-      SourceStage stg;
-      stg.posq = (double4 *)(base + off);
-      off += align_up((N + 1) * sizeof(double4));
+      char *spos = base + off, *snrm = nullptr;
+      off += align_up(stage_pos_bytes(g->n_sources));
       if (r->layers & TSQBX_DLP) {
-        stg.qn = (double4 *)(base + off);
-        off += align_up((N + 1) * sizeof(double4));
+        snrm = base + off;
+        off += align_up(stage_nrm_bytes(g->n_sources));
       }
+      const SourceStage stg = stage_views(spos, snrm, g->n_sources);
       for (int l = 0; l < 3; ++l)
         if (r->layers & (1u << l)) {
           d_out[l] = (double *)(base + off);
@@ -321,8 +353,10 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
       WorkItem w{};
       w.tgt = g->tgt;
       w.idx = g->idx;
-      w.posq = stg.posq;
-      w.qn = stg.qn;
+      w.xy = stg.xy;
+      w.zq = stg.zq;
+      w.nxy = stg.nxy;
+      w.nz = stg.nz;
       w.out_s = d_out[0];
       w.out_d = d_out[1];
       w.out_t = d_out[2];
@@ -573,12 +607,11 @@ void tsqbx_server::completer() {
       }
       r->t_done = t1;
       r->done = true;
-      lat_ms.push_back((r->t_done - r->t_submit) * 1e3);
-      queue_ms.push_back((r->t_launch - r->t_submit) * 1e3);
       arena.release(r->arena_off, r->bytes);
       bytes_in_flight -= r->bytes;
       --reqs_in_flight;
       release_host_stage(r);
+      retire(r);
     }
     ss.busy = false;
     if (inflight.empty() && busy_since >= 0) {
@@ -793,7 +826,11 @@ int tsqbx_server_wait(tsqbx_server *sv, uint64_t ticket, double timeout_s) {
   auto it = sv->all.find(ticket);
   if (it == sv->all.end()) return fail(TSQBX_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
   Request *r = it->second;
-  if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; }))
+  ++r->waiters;  // keeps r from being forgotten while this thread waits
+  const bool ok =
+      sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; });
+  --r->waiters;
+  if (!ok)
     return fail(TSQBX_E_TIMEOUT, "request %llu not done after %.3f s", (unsigned long long)ticket, timeout_s);
   if (r->status != TSQBX_OK) return fail(r->status, "request %llu failed", (unsigned long long)ticket);
   return TSQBX_OK;

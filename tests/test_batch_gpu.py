@@ -405,3 +405,34 @@ def test_schedule_preview_matches_plan(ctx):
     plan.close()
     for it in items:
         it["geom"].close()
+
+
+def test_server_keeps_a_bounded_history(ctx):
+    """A long-running server forgets the tickets of old completed requests
+    (the last 4096 stay queryable), so its host memory stays bounded; the
+    counters still count every request and the results stay right."""
+    g = W.fuzz_geometry(700, n=120, m=12, max_list=24, p=4, layers=1, allow_empty=False)
+    geom = ctx.geometry(g)
+    srv = ctx.server(64 * api.Server.request_bytes(geom, 1), 64)
+    n = 4300
+    rng = np.random.default_rng(70)
+    tickets, outs, sigmas = [], [], []
+    for i in range(n):
+        s = rng.standard_normal(g.n_sources)
+        t, o, _, _ = srv.submit(geom, s, 4, api.SLP)
+        tickets.append(t)
+        if i >= n - 3:
+            outs.append(o)
+            sigmas.append(s)
+    srv.drain(300)
+    st = srv.stats()
+    assert st["completed"] == n and st["failed"] == 0
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.poll(tickets[0])
+    assert ei.value.code == -1
+    assert srv.poll(tickets[-1]) and srv.poll(tickets[n - 4096])
+    for o, s in zip(outs, sigmas):
+        ref = oracle.evaluate_geometry(g, p=4, layers=1, sigma=s)
+        assert_parity(o, ref["slp"], ref["abs_slp"], what="bounded history")
+    srv.close()
+    geom.close()
