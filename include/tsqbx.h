@@ -134,6 +134,30 @@ const char *tsqbx_last_error(void);
  * TSQBX_E_RANGE.  geometry_create performs the same checks. */
 int tsqbx_validate_geometry(const tsqbx_geometry_desc *desc);
 
+/* Host-only preview of the device layout tsqbx_geometry_create builds for
+ * desc (touches no device; same checks as tsqbx_validate_geometry).  Sources
+ * are ordered along a Morton curve, targets by the Morton key of their
+ * center (then center, then index), unless flags has TSQBX_NO_REORDER.  Each
+ * distinct center that a target uses gets one row, in order of first use in
+ * the target order; a row holds its center's list (Sec. 3.3 near-field sets)
+ * in device source numbers, sorted ascending and padded to a multiple of 16
+ * entries with the padding index N.  Outputs (each nullable):
+ *   source_order [N]   device position -> caller source index
+ *   target_order [T]   device position -> caller target index
+ *   target_row   [T]   device position -> row
+ *   row_offsets  [row_offsets_cap >= n_rows + 1] padded row offsets
+ *   rows         [rows_cap >= nnz] the padded rows
+ * info (required) receives n_rows, nnz (padded entries), pairs (list
+ * entries over all targets) and max_list.  Buffers too small for rows or
+ * offsets give TSQBX_E_RANGE with info filled in. */
+typedef struct {
+  int64_t n_rows, nnz, pairs, max_list;
+} tsqbx_layout_info;
+int tsqbx_geometry_layout(const tsqbx_geometry_desc *desc, unsigned flags, int64_t *source_order,
+                          int64_t *target_order, int64_t *target_row, int64_t *row_offsets,
+                          int64_t row_offsets_cap, int32_t *rows, int64_t rows_cap,
+                          tsqbx_layout_info *info);
+
 /* Check (p, layers) against a geometry's capabilities without a launch:
  * p in [0, TSQBX_P_MAX], layers a nonempty subset of SLP|DLP|SPRIME, DLP
  * needs source normals and SPRIME target normals.  geom may be NULL (then the

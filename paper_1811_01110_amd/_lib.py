@@ -65,6 +65,10 @@ class PlanInfo(ctypes.Structure):
                 ("device_bytes", c_size_t)]
 
 
+class LayoutInfo(ctypes.Structure):
+    _fields_ = [("n_rows", c_int64), ("nnz", c_int64), ("pairs", c_int64), ("max_list", c_int64)]
+
+
 class PlanTuning(ctypes.Structure):
     _fields_ = [("group_lanes", c_int), ("unroll", c_int), ("waves_per_block", c_int),
                 ("oversubscription", c_int), ("step_cost", c_int)]
@@ -134,6 +138,8 @@ _SIGNATURES = {
     "tsqbx_plan_execute": (c_int, [c_void_p, c_void_p]),
     "tsqbx_plan_get_info": (c_int, [c_void_p, P(PlanInfo)]),
     "tsqbx_plan_destroy": (c_int, [c_void_p]),
+    "tsqbx_geometry_layout": (c_int, [P(GeometryDesc), c_uint, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_int64, c_void_p, c_int64, P(LayoutInfo)]),
     "tsqbx_plan_get_tuning": (c_int, [c_void_p, P(PlanTuning)]),
     "tsqbx_plan_set_tuning": (c_int, [c_void_p, P(PlanTuning)]),
     "tsqbx_plan_profile": (c_int, [c_void_p, c_int, c_void_p, P(PlanTiming)]),

@@ -107,6 +107,28 @@ def validate_geometry(**arrays) -> None:
     _check(_lib().tsqbx_validate_geometry(ctypes.byref(d)))
 
 
+def geometry_layout(flags: int = 0, **arrays) -> dict:
+    """Host-only preview of the device layout of a geometry (no device):
+    source_order, target_order, target_row, row_offsets and rows as numpy
+    arrays, with the counts of tsqbx_layout_info."""
+    d, keep = make_desc(**arrays)
+    info = L.LayoutInfo()
+    lib = _lib()
+    _check(lib.tsqbx_geometry_layout(ctypes.byref(d), int(flags), None, None, None, None, 0,
+                                     None, 0, ctypes.byref(info)))
+    N, T = int(d.n_sources), int(d.n_targets)
+    out = {"source_order": np.zeros(N, dtype=np.int64), "target_order": np.zeros(T, dtype=np.int64),
+           "target_row": np.zeros(T, dtype=np.int64),
+           "row_offsets": np.zeros(info.n_rows + 1, dtype=np.int64),
+           "rows": np.zeros(info.nnz, dtype=np.int32)}
+    _check(lib.tsqbx_geometry_layout(ctypes.byref(d), int(flags), _ptr(out["source_order"]),
+                                     _ptr(out["target_order"]), _ptr(out["target_row"]),
+                                     _ptr(out["row_offsets"]), info.n_rows + 1, _ptr(out["rows"]),
+                                     info.nnz, ctypes.byref(info)))
+    out.update({k: getattr(info, k) for k, _ in info._fields_})
+    return out
+
+
 def schedule_preview(items, group_lanes: int = 16, max_waves: int = 49152):
     """Host-only preview of a plan's static schedule (no device needed).
 

@@ -282,27 +282,36 @@ int tsqbx_ctx_destroy(tsqbx_ctx *ctx) {
   return TSQBX_OK;
 }
 
-int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned flags,
-                          tsqbx_geometry **out) {
-  TraceRange trace_("tsqbx_geometry_create");
-  if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
-  *out = nullptr;
-  int rc = validate(d);
-  if (rc != TSQBX_OK) return rc;
-  const int64_t N = d->n_sources, M = d->n_centers, T = d->n_targets;
-  const bool reorder = !(flags & TSQBX_NO_REORDER);
+// The device layout of a geometry, computed on the host (see
+// tsqbx_geometry_layout): source and target orders, one row per distinct
+// center in order of first use, rows padded to kRowPad with the padding
+// record N, entries remapped to device source numbers and sorted.
+struct HostLayout {
+  std::vector<int64_t> src_ord;        // device -> caller source
+  std::vector<int32_t> src_rank;       // caller -> device source
+  std::vector<int32_t> tc;             // caller target -> center
+  std::vector<int64_t> tgt_ord;        // device -> caller target
+  std::vector<int64_t> row_of_center;  // center -> row, -1 if no target uses it
+  std::vector<int64_t> row_center;     // row -> center
+  std::vector<int64_t> row_off;        // [R + 1] padded offsets
+  std::vector<int32_t> idx;            // [nnz_dev]
+};
 
+static void build_layout(const tsqbx_geometry_desc *d, bool reorder, HostLayout *L) {
+  const int64_t N = d->n_sources, M = d->n_centers, T = d->n_targets;
   // device order of sources (Morton) and its inverse
-  std::vector<int64_t> src_ord(N);
-  std::iota(src_ord.begin(), src_ord.end(), 0);
-  if (reorder && N > 1) src_ord = order_by_key(morton_keys(d->sources, N));
-  std::vector<int32_t> src_rank(N);
-  for (int64_t i = 0; i < N; ++i) src_rank[src_ord[i]] = (int32_t)i;
+  L->src_ord.resize(N);
+  std::iota(L->src_ord.begin(), L->src_ord.end(), 0);
+  if (reorder && N > 1) L->src_ord = order_by_key(morton_keys(d->sources, N));
+  L->src_rank.resize(N);
+  for (int64_t i = 0; i < N; ++i) L->src_rank[L->src_ord[i]] = (int32_t)i;
 
   // device order of targets: by Morton key of their center, then center, then index
-  std::vector<int32_t> tc(T);
+  std::vector<int32_t> &tc = L->tc;
+  tc.resize(T);
   for (int64_t t = 0; t < T; ++t) tc[t] = d->target_center ? d->target_center[t] : (int32_t)t;
-  std::vector<int64_t> tgt_ord(T);
+  std::vector<int64_t> &tgt_ord = L->tgt_ord;
+  tgt_ord.resize(T);
   std::iota(tgt_ord.begin(), tgt_ord.end(), 0);
   if (reorder && T > 1) {
     std::vector<uint64_t> ckey = morton_keys(d->centers, M);
@@ -315,33 +324,85 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   }
 
   // one device row per distinct center, in order of first use
-  std::vector<int64_t> row_of_center(M, -1);
-  std::vector<int64_t> row_center;
+  L->row_of_center.assign(M, -1);
+  L->row_center.clear();
   for (int64_t k = 0; k < T; ++k) {
     const int32_t c = tc[tgt_ord[k]];
-    if (row_of_center[c] < 0) {
-      row_of_center[c] = (int64_t)row_center.size();
-      row_center.push_back(c);
+    if (L->row_of_center[c] < 0) {
+      L->row_of_center[c] = (int64_t)L->row_center.size();
+      L->row_center.push_back(c);
     }
   }
-  const int64_t R = (int64_t)row_center.size();
-  std::vector<int64_t> row_off(R + 1, 0);
+  const int64_t R = (int64_t)L->row_center.size();
+  L->row_off.assign(R + 1, 0);
   // rows padded to a multiple of kRowPad with the zero-strength record N
   for (int64_t r = 0; r < R; ++r) {
-    const int32_t c = (int32_t)row_center[r];
+    const int64_t c = L->row_center[r];
     const int64_t len = d->list_offsets[c + 1] - d->list_offsets[c];
-    row_off[r + 1] = row_off[r] + (len + kRowPad - 1) / kRowPad * kRowPad;
+    L->row_off[r + 1] = L->row_off[r] + (len + kRowPad - 1) / kRowPad * kRowPad;
   }
-  const int64_t nnz_dev = row_off[R];
-  std::vector<int32_t> idx(nnz_dev);
+  L->idx.resize(L->row_off[R]);
   parallel_for(R, [&](int64_t r) {
-    const int32_t c = (int32_t)row_center[r];
+    const int64_t c = L->row_center[r];
     const int64_t b = d->list_offsets[c], e = d->list_offsets[c + 1];
-    int32_t *dst = idx.data() + row_off[r];
-    for (int64_t j = b; j < e; ++j) dst[j - b] = src_rank[d->list_sources[j]];
+    int32_t *dst = L->idx.data() + L->row_off[r];
+    for (int64_t j = b; j < e; ++j) dst[j - b] = L->src_rank[d->list_sources[j]];
     std::sort(dst, dst + (e - b));
-    for (int64_t j = e - b; j < row_off[r + 1] - row_off[r]; ++j) dst[j] = (int32_t)N;
+    for (int64_t j = e - b; j < L->row_off[r + 1] - L->row_off[r]; ++j) dst[j] = (int32_t)N;
   });
+}
+
+int tsqbx_geometry_layout(const tsqbx_geometry_desc *d, unsigned flags, int64_t *source_order,
+                          int64_t *target_order, int64_t *target_row, int64_t *row_offsets,
+                          int64_t row_offsets_cap, int32_t *rows, int64_t rows_cap,
+                          tsqbx_layout_info *info) {
+  TraceRange trace_("tsqbx_geometry_layout");
+  if (!info) return fail(TSQBX_E_INVALID, "geometry_layout: info is NULL");
+  int rc = validate(d);
+  if (rc != TSQBX_OK) return rc;
+  HostLayout L;
+  build_layout(d, !(flags & TSQBX_NO_REORDER), &L);
+  const int64_t R = (int64_t)L.row_center.size(), nnz = L.row_off[R];
+  info->n_rows = R;
+  info->nnz = nnz;
+  info->pairs = 0;
+  info->max_list = 0;
+  for (int64_t t = 0; t < d->n_targets; ++t) {
+    const int64_t len = d->list_offsets[L.tc[t] + 1] - d->list_offsets[L.tc[t]];
+    info->pairs += len;
+    info->max_list = std::max(info->max_list, len);
+  }
+  if ((row_offsets && row_offsets_cap < R + 1) || (rows && rows_cap < nnz))
+    return fail(TSQBX_E_RANGE, "geometry_layout: %lld rows of %lld entries do not fit the buffers",
+                (long long)R, (long long)nnz);
+  if (source_order) std::copy(L.src_ord.begin(), L.src_ord.end(), source_order);
+  if (target_order) std::copy(L.tgt_ord.begin(), L.tgt_ord.end(), target_order);
+  if (target_row)
+    for (int64_t k = 0; k < d->n_targets; ++k) target_row[k] = L.row_of_center[L.tc[L.tgt_ord[k]]];
+  if (row_offsets) std::copy(L.row_off.begin(), L.row_off.end(), row_offsets);
+  if (rows) std::copy(L.idx.begin(), L.idx.end(), rows);
+  return TSQBX_OK;
+}
+
+int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned flags,
+                          tsqbx_geometry **out) {
+  TraceRange trace_("tsqbx_geometry_create");
+  if (!ctx || !out) return fail(TSQBX_E_INVALID, "ctx or out is NULL");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc != TSQBX_OK) return rc;
+  const int64_t N = d->n_sources, M = d->n_centers, T = d->n_targets;
+  const bool reorder = !(flags & TSQBX_NO_REORDER);
+  HostLayout L;
+  build_layout(d, reorder, &L);
+  const std::vector<int64_t> &src_ord = L.src_ord, &tgt_ord = L.tgt_ord;
+  const std::vector<int32_t> &src_rank = L.src_rank, &tc = L.tc;
+  const std::vector<int64_t> &row_of_center = L.row_of_center, &row_center = L.row_center;
+  const std::vector<int64_t> &row_off = L.row_off;
+  std::vector<int32_t> &idx = L.idx;
+  const int64_t R = (int64_t)row_center.size();
+  const int64_t nnz_dev = row_off[R];
+  (void)M;
 
   std::vector<TargetRec> recs(T);
   std::vector<double4> tnrm(d->target_normals ? T : 0);

@@ -25,6 +25,7 @@
 #include <tuple>
 #include <vector>
 
+#include "tsqbx_arena.h"
 #include "tsqbx_internal.h"
 
 using namespace tsqbx;
@@ -50,44 +51,6 @@ double now_s() {
 }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// First-fit allocator over [0, size) with coalescing on free.
-class Arena {
- public:
-  void init(size_t size) { free_.assign(1, {0, size}); }
-  bool alloc(size_t n, size_t *off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it)
-      if (it->second >= n) {
-        *off = it->first;
-        it->first += n;
-        it->second -= n;
-        if (it->second == 0) free_.erase(it);
-        return true;
-      }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    auto it = free_.begin();
-    while (it != free_.end() && it->first < off) ++it;
-    it = free_.insert(it, {off, n});
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-        it = pv;
-      }
-    }
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-  }
-
- private:
-  std::list<std::pair<size_t, size_t>> free_;  // (offset, length), sorted by offset
-};
 
 struct Request {
   uint64_t ticket = 0;
@@ -528,6 +491,7 @@ void tsqbx_server::scheduler() {
         --reqs_in_flight;
         ++st.failed;
         release_host_stage(r);
+        retire(r);
       }
       streams[step.stream].busy = false;
       fprintf(stderr, "tsqbx server: step failed: %s\n", err.c_str());
