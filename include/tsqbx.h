@@ -193,6 +193,26 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned
                      const double *d_sigma, double *d_out_slp, double *d_out_dlp,
                      double *d_out_sprime, unsigned flags, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * tsqbx_eval_async with the strengths staged in a static device array of the
+ * library instead of the geometry's staging buffer; the call allocates
+ * nothing.  The array holds TSQBX_NOALLOC_SCRATCH_BYTES on every GPU that
+ * loads the library, until the process ends.  A request needs
+ * 32 (N + 1) bytes, rounded up to a multiple of 256, plus 24 (N + 1) with
+ * TSQBX_DLP (N = sources), at most that size (N + 1 <= 299592 with the
+ * double layer, 524288 without); a larger one gives TSQBX_E_RANGE and
+ * launches nothing.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (each call writes all it reads): calls that
+ * overlap in time on one GPU (on different streams, or unordered across
+ * threads) race and give wrong results; calls on one stream are ordered and
+ * safe.  Results equal tsqbx_eval_async's bit for bit; arguments, flags and
+ * the other errors as for tsqbx_eval_async. */
+#define TSQBX_NOALLOC_SCRATCH_BYTES (16u << 20)
+int tsqbx_eval_async_noalloc(tsqbx_ctx *ctx, const tsqbx_geometry *geom, int p, unsigned layers,
+                             const double *d_sigma, double *d_out_slp, double *d_out_dlp,
+                             double *d_out_sprime, unsigned flags, void *hip_stream);
+
 /* The same evaluation in two steps on device pointers: tsqbx_stage_async
  * forms the strengths q_y = w_y sigma_y (and q_y nu_y when layers include
  * TSQBX_DLP) in the geometry's staging buffer (eq. pt-pot); then

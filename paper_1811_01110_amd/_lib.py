@@ -138,6 +138,8 @@ _SIGNATURES = {
     "tsqbx_plan_execute": (c_int, [c_void_p, c_void_p]),
     "tsqbx_plan_get_info": (c_int, [c_void_p, P(PlanInfo)]),
     "tsqbx_plan_destroy": (c_int, [c_void_p]),
+    "tsqbx_eval_async_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_uint, c_void_p, c_void_p,
+                                         c_void_p, c_void_p, c_uint, c_void_p]),
     "tsqbx_geometry_layout": (c_int, [P(GeometryDesc), c_uint, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_int64, c_void_p, c_int64, P(LayoutInfo)]),
     "tsqbx_plan_get_tuning": (c_int, [c_void_p, P(PlanTuning)]),

@@ -223,6 +223,17 @@ class Context:
         _check(_lib().tsqbx_eval_async(self.handle, geom.handle, int(p), int(layers), s, *ptrs,
                                        int(flags), _stream_handle(stream)))
 
+    def eval_async_noalloc(self, geom: "Geometry", sigma, p: int, layers: int, out_slp=None,
+                           out_dlp=None, out_sprime=None, flags: int = 0, stream=None):
+        """eval_async staged in the library's static scratch array: the call
+        allocates nothing (calls overlapping on one GPU race)."""
+        s = _tensor_ptr(sigma, geom.n_sources, "sigma")
+        ptrs = [_tensor_ptr(o, geom.n_targets, name) if layers & bit else None
+                for o, bit, name in zip((out_slp, out_dlp, out_sprime), LAYER_BITS,
+                                        ("out_slp", "out_dlp", "out_sprime"))]
+        _check(_lib().tsqbx_eval_async_noalloc(self.handle, geom.handle, int(p), int(layers), s,
+                                               *ptrs, int(flags), _stream_handle(stream)))
+
     def stage_async(self, geom: "Geometry", sigma, layers: int, stream=None):
         """Strengths q = w sigma (and q nu for the double layer) into the
         geometry's staging buffer, for eval_staged_async."""

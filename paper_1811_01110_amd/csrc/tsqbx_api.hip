@@ -262,6 +262,7 @@ int tsqbx_ctx_create(int device, tsqbx_ctx **out) {
   c->device = device;
   e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = noalloc_scratch_init(device, &c->scratch);
   if (e != hipSuccess) {
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

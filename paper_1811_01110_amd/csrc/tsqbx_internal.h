@@ -126,6 +126,8 @@ struct tsqbx_ctx {
   // plan tunings: key = plan bucket (see plan_tuning_key)
   std::map<uint64_t, tsqbx::PlanTuning> plan_tuning;
   std::mutex tuning_mu;
+  // device address of the GPU's scratch array of tsqbx_eval_async_noalloc
+  void *scratch = nullptr;
 };
 
 struct tsqbx_geometry {
@@ -353,6 +355,9 @@ struct ScheduleItem {
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
                     int group_lanes, int max_waves, double step_cost, std::vector<WorkUnit> *units,
                     std::vector<int32_t> *wave_begin);
+
+// The device address of device's scratch array (tsqbx_noalloc.hip).
+hipError_t noalloc_scratch_init(int device, void **out);
 
 Tuning default_tuning(int p, unsigned layers, int64_t mean_list);
 Tuning lookup_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list);
