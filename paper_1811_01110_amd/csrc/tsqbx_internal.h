@@ -207,11 +207,18 @@ struct StageItem {         // 80 bytes
   int64_t n;
   int32_t want_dlp;
   int32_t host_sigma;        // 1: walk sources in caller order (contiguous reads of sigma)
+  int64_t begin;             // first element of the item in the launch's index space
 };
-static_assert(sizeof(StageItem) == 80, "StageItem layout");
+static_assert(sizeof(StageItem) == 88, "StageItem layout");
 StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned layers,
                           const SourceStage &st, bool sigma_on_host);
-hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n, hipStream_t s);
+// Lay the items' n + 1 elements end to end, each item starting at a multiple
+// of kStageBlock, in begin; returns the total (a multiple of kStageBlock).
+constexpr int64_t kStageBlock = 256;
+int64_t assign_stage_blocks(StageItem *items, int n_items);
+// Staging of every item in one launch: one block of kStageBlock threads per
+// kStageBlock elements of one item (total from assign_stage_blocks).
+hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t total, hipStream_t s);
 
 // Many contiguous copies in one launch (device or pinned host memory on
 // either side).
@@ -355,6 +362,9 @@ struct ScheduleItem {
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
                     int group_lanes, int max_waves, double step_cost, std::vector<WorkUnit> *units,
                     std::vector<int32_t> *wave_begin);
+
+// Free a geometry's device arrays and the geometry (null: nothing).
+void free_geometry(tsqbx_geometry *g);
 
 // The device address of device's scratch array (tsqbx_noalloc.hip).
 hipError_t noalloc_scratch_init(int device, void **out);

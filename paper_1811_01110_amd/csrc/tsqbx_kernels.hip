@@ -80,14 +80,27 @@ k_stage(int64_t n, const double4 *__restrict__ pos_w, const double4 *__restrict_
   }
 }
 
-// The same staging for many items (blockIdx.y selects the item).  A density
-// in device memory is gathered while walking the sources in device order; a
+// The same staging for many items in one launch.  The items' elements lie
+// end to end, each item starting at a multiple of kStageBlock (begin), and
+// block b takes elements [b kStageBlock, (b + 1) kStageBlock) of the one
+// item they fall in (one per thread), found by a binary search on the block
+// index (uniform across the block, so its loads are scalar).  A density in
+// device memory is gathered while walking the sources in device order; a
 // density in pinned host memory is read contiguously, walking the sources in
 // the caller's order, since every read then crosses PCIe.
-__global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict__ items) {
+__global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict__ items,
+                                                     int n_items) {
   typedef TSQBX_GLOBAL double *GD;
   typedef const TSQBX_GLOBAL double *GR;
-  const TSQBX_GLOBAL StageItem *gi = (const TSQBX_GLOBAL StageItem *)items + blockIdx.y;
+  const TSQBX_GLOBAL StageItem *all = (const TSQBX_GLOBAL StageItem *)items;
+  const int64_t base = (int64_t)blockIdx.x * kStageBlock;
+  int lo = 0, hi = n_items - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (all[mid].begin <= base) lo = mid;
+    else hi = mid - 1;
+  }
+  const TSQBX_GLOBAL StageItem *gi = all + lo;
   const int64_t n = gi->n;
   const int want_dlp = gi->want_dlp;
   const int host_sigma = gi->host_sigma;
@@ -97,23 +110,22 @@ __global__ void __launch_bounds__(256) k_stage_multi(const StageItem *__restrict
   const TSQBX_GLOBAL int64_t *perm = (const TSQBX_GLOBAL int64_t *)gi->order;
   const double *sigma = gi->sigma;  // device or pinned host memory
   const GD xy = (GD)gi->xy, zq = (GD)gi->zq, nxy = (GD)gi->nxy, nz = (GD)gi->nz;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i == n) {
-      stage_pad(n, xy, zq, nxy, nz, want_dlp);
-      continue;
-    }
-    int64_t j;  // device index
-    double sg;
-    if (host_sigma) {
-      j = rank ? (int64_t)rank[i] : i;
-      sg = sigma[i];
-    } else {
-      j = i;
-      sg = sigma[perm ? perm[i] : i];
-    }
-    stage_one(j, pw, nv, sg, xy, zq, nxy, nz, want_dlp);
+  const int64_t i = base - gi->begin + threadIdx.x;  // one source per thread
+  if (i > n) return;
+  if (i == n) {
+    stage_pad(n, xy, zq, nxy, nz, want_dlp);
+    return;
   }
+  int64_t j;  // device index
+  double sg;
+  if (host_sigma) {
+    j = rank ? (int64_t)rank[i] : i;
+    sg = sigma[i];
+  } else {
+    j = i;
+    sg = sigma[perm ? perm[i] : i];
+  }
+  stage_one(j, pw, nv, sg, xy, zq, nxy, nz, want_dlp);
 }
 
 // Contiguous copies, blockIdx.y selects the item.
@@ -220,13 +232,21 @@ StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned
   return it;
 }
 
-hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t max_n,
+int64_t assign_stage_blocks(StageItem *items, int n_items) {
+  int64_t at = 0;
+  for (int i = 0; i < n_items; ++i) {
+    items[i].begin = at;
+    at += (items[i].n + 1 + kStageBlock - 1) / kStageBlock * kStageBlock;
+  }
+  return at;
+}
+
+hipError_t launch_stage_multi(const StageItem *d_items, int n_items, int64_t total,
                               hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  if (n_items > 65535) return hipErrorInvalidValue;
-  const int64_t bx = std::min<int64_t>((max_n + 1 + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_stage_multi, dim3((unsigned)std::max<int64_t>(bx, 1), (unsigned)n_items),
-                     dim3(256), 0, s, d_items);
+  if (n_items <= 0 || total <= 0) return hipSuccess;
+  if (n_items > 65535 || total / kStageBlock > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stage_multi, dim3((unsigned)(total / kStageBlock)), dim3(kStageBlock), 0, s,
+                     d_items, n_items);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct tsqbx_plan {
   int32_t n_waves = 0;
   StageItem *d_stage = nullptr;  // staging of every item, one launch
   int64_t max_sources = 0;
+  int64_t stage_total = 0;   // staging launch's index space (assign_stage_blocks)
   int64_t n_units = 0;
   int64_t pairs = 0, pair_terms = 0;
   int grid = 0;
@@ -259,7 +260,7 @@ hipError_t plan_launch(tsqbx_plan *pl, hipStream_t s, hipEvent_t *ev) {
     e = launch_helm_prepare_multi(pl->d_hprep, (int)pl->hitems.size(), pl->max_sources,
                                   pl->max_targets, s);
   else
-    e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->max_sources, s);
+    e = launch_stage_multi(pl->d_stage, (int)pl->items.size(), pl->stage_total, s);
   if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
   if (e == hipSuccess && pl->n_units > 0) {
     if (pl->helm) {
@@ -435,6 +436,7 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_items, n_items * sizeof(WorkItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_items, witems.data(), n_items * sizeof(WorkItem), hipMemcpyHostToDevice);
+  pl->stage_total = assign_stage_blocks(sitems.data(), (int)n_items);
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_stage, n_items * sizeof(StageItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_stage, sitems.data(), n_items * sizeof(StageItem), hipMemcpyHostToDevice);

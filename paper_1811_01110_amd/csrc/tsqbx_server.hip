@@ -222,7 +222,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
   // DMA copies: densities of pageable-staged and of Helmholtz requests up,
   // outputs of pageable-staged requests down: (destination, source, doubles)
   std::vector<std::tuple<double *, const double *, size_t>> dma_up, pageable_down;
-  int64_t max_n = 0, max_t = 0, hmax_n = 0, hmax_t = 0;
+  int64_t max_t = 0, hmax_n = 0, hmax_t = 0;
   LayerClass lc;
   int p_all = -1;
   unsigned h_first = 0;
@@ -312,7 +312,6 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
         sig = d_sigma;
       }
       stage.push_back(make_stage_item(g, sig, r->layers, stg, host_pinned));
-      max_n = std::max<int64_t>(max_n, g->n_sources);
       WorkItem w{};
       w.tgt = g->tgt;
       w.idx = g->idx;
@@ -383,6 +382,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     if (n) std::memcpy(ss.h_meta + o, src, n);
   };
   put(o_items, items.data(), KL * sizeof(WorkItem));
+  const int64_t stage_total = assign_stage_blocks(stage.data(), (int)KL);
   put(o_stage, stage.data(), KL * sizeof(StageItem));
   put(o_copy, copies.data(), copies.size() * sizeof(CopyItem));
   put(o_units, units.data(), units.size() * sizeof(WorkUnit));
@@ -396,7 +396,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
     e = hipMemcpyAsync(std::get<0>(dma_up[i]), std::get<1>(dma_up[i]),
                        std::get<2>(dma_up[i]) * sizeof(double), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return fail_e(e, "step upload");
-  e = launch_stage_multi((const StageItem *)(ss.d_meta + o_stage), (int)KL, max_n, s);
+  e = launch_stage_multi((const StageItem *)(ss.d_meta + o_stage), (int)KL, stage_total, s);
   if (e == hipSuccess && KH)
     e = launch_helm_prepare_multi((const HelmPrepItem *)(ss.d_meta + o_hprep), (int)KH, hmax_n,
                                   hmax_t, s);
