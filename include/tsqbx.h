@@ -158,6 +158,28 @@ int tsqbx_geometry_layout(const tsqbx_geometry_desc *desc, unsigned flags, int64
                           int64_t row_offsets_cap, int32_t *rows, int64_t rows_cap,
                           tsqbx_layout_info *info);
 
+/* Create a geometry from arrays in device memory: every pointer of desc is
+ * a device pointer (the offsets and lists may come straight from
+ * tsqbx_ball_lists or tsqbx_knn_lists), with the meaning and layout of
+ * tsqbx_geometry_create.  The Morton orders, rows, remap, padding and sort
+ * run on the device, on hip_stream; the call returns when the geometry is
+ * complete, and the result equals tsqbx_geometry_create's on the same
+ * arrays bit for bit (tsqbx_geometry_read_layout shows it).  Only the counts
+ * (8 bytes for the list total, 4 bytes for the row count) and the list
+ * length of each target (8 T bytes, for plans) come back to the host.  The
+ * checks of tsqbx_validate_geometry run on the device (TSQBX_E_INVALID,
+ * TSQBX_E_RANGE); TSQBX_NO_REORDER is not supported (TSQBX_E_INVALID).
+ * The caller's arrays may be freed once the call returns. */
+int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *desc,
+                                 unsigned flags, void *hip_stream, tsqbx_geometry **out);
+/* Read a geometry's device layout back into host buffers, in the form of
+ * tsqbx_geometry_layout (same outputs, each nullable, same errors for small
+ * buffers).  Synchronous. */
+int tsqbx_geometry_read_layout(const tsqbx_geometry *geom, int64_t *source_order,
+                               int64_t *target_order, int64_t *target_row, int64_t *row_offsets,
+                               int64_t row_offsets_cap, int32_t *rows, int64_t rows_cap,
+                               tsqbx_layout_info *info);
+
 /* Check (p, layers) against a geometry's capabilities without a launch:
  * p in [0, TSQBX_P_MAX], layers a nonempty subset of SLP|DLP|SPRIME, DLP
  * needs source normals and SPRIME target normals.  geom may be NULL (then the

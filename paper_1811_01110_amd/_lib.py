@@ -142,6 +142,10 @@ _SIGNATURES = {
                                          c_void_p, c_void_p, c_uint, c_void_p]),
     "tsqbx_geometry_layout": (c_int, [P(GeometryDesc), c_uint, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_int64, c_void_p, c_int64, P(LayoutInfo)]),
+    "tsqbx_geometry_create_device": (c_int, [c_void_p, P(GeometryDesc), c_uint, c_void_p,
+                                             P(c_void_p)]),
+    "tsqbx_geometry_read_layout": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                           c_int64, c_void_p, c_int64, P(LayoutInfo)]),
     "tsqbx_plan_get_tuning": (c_int, [c_void_p, P(PlanTuning)]),
     "tsqbx_plan_set_tuning": (c_int, [c_void_p, P(PlanTuning)]),
     "tsqbx_plan_profile": (c_int, [c_void_p, c_int, c_void_p, P(PlanTiming)]),

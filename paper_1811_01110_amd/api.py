@@ -180,6 +180,39 @@ class Context:
             pass
 
     # -- geometry ---------------------------------------------------------
+    def geometry_device(self, *, sources, weights, centers, list_offsets, list_sources, targets,
+                        normals=None, target_center=None, target_normals=None, flags: int = 0,
+                        stream=None) -> "Geometry":
+        """Build a geometry from CUDA tensors (float64 [n][3] points, float64
+        weights, int64 offsets, int32 lists and target centers) on the device:
+        the same geometry as geometry() on the same arrays."""
+        def ptr(t, n, cols, dtype, name):
+            if t is None:
+                return None
+            import torch
+
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and
+                    t.is_contiguous() and t.numel() == n * cols):
+                raise ValueError(f"{name} must be a contiguous CUDA tensor of {n * cols} {dtype}")
+            return ctypes.c_void_p(t.data_ptr())
+        import torch
+
+        N, M, T = int(weights.numel()), int(centers.numel() // 3), int(targets.numel() // 3)
+        nnz = int(list_sources.numel())
+        d = L.GeometryDesc(
+            N, ptr(sources, N, 3, torch.float64, "sources"), ptr(weights, N, 1, torch.float64, "weights"),
+            ptr(normals, N, 3, torch.float64, "normals"), M,
+            ptr(centers, M, 3, torch.float64, "centers"),
+            ptr(list_offsets, M + 1, 1, torch.int64, "list_offsets"),
+            ptr(list_sources, nnz, 1, torch.int32, "list_sources") if nnz else None, T,
+            ptr(targets, T, 3, torch.float64, "targets"),
+            ptr(target_center, T, 1, torch.int32, "target_center"),
+            ptr(target_normals, T, 3, torch.float64, "target_normals"))
+        h = ctypes.c_void_p()
+        _check(_lib().tsqbx_geometry_create_device(self.handle, ctypes.byref(d), int(flags),
+                                                   _stream_handle(stream), ctypes.byref(h)))
+        return Geometry(self, handle=h)
+
     def geometry(self, g=None, *, flags: int = 0, **arrays) -> "Geometry":
         """Upload a workload Geometry (or keyword arrays) to the device."""
         if g is not None:
@@ -412,10 +445,14 @@ class Context:
 class Geometry:
     """A device-resident geometry (sources, weights, normals, centers, lists, targets)."""
 
-    def __init__(self, ctx: Context, *, flags: int = 0, **arrays):
-        d, keep = make_desc(**arrays)
-        h = ctypes.c_void_p()
-        _check(_lib().tsqbx_geometry_create(ctx.handle, ctypes.byref(d), int(flags), ctypes.byref(h)))
+    def __init__(self, ctx: Context, *, flags: int = 0, handle=None, **arrays):
+        if handle is None:
+            d, keep = make_desc(**arrays)
+            h = ctypes.c_void_p()
+            _check(_lib().tsqbx_geometry_create(ctx.handle, ctypes.byref(d), int(flags),
+                                                ctypes.byref(h)))
+        else:
+            h = handle
         self.handle = h
         self.ctx = ctx
         info = L.GeometryInfo()
@@ -441,6 +478,25 @@ class Geometry:
                 self.close()
         except Exception:
             pass
+
+    def read_layout(self) -> dict:
+        """The geometry's device layout read back to the host, in the form of
+        geometry_layout()."""
+        info = L.LayoutInfo()
+        lib = _lib()
+        _check(lib.tsqbx_geometry_read_layout(self.handle, None, None, None, None, 0, None, 0,
+                                              ctypes.byref(info)))
+        out = {"source_order": np.zeros(self.n_sources, dtype=np.int64),
+               "target_order": np.zeros(self.n_targets, dtype=np.int64),
+               "target_row": np.zeros(self.n_targets, dtype=np.int64),
+               "row_offsets": np.zeros(info.n_rows + 1, dtype=np.int64),
+               "rows": np.zeros(info.nnz, dtype=np.int32)}
+        _check(lib.tsqbx_geometry_read_layout(self.handle, _ptr(out["source_order"]),
+                                              _ptr(out["target_order"]), _ptr(out["target_row"]),
+                                              _ptr(out["row_offsets"]), info.n_rows + 1,
+                                              _ptr(out["rows"]), info.nnz, ctypes.byref(info)))
+        out.update({k: getattr(info, k) for k, _ in info._fields_})
+        return out
 
     def pair_terms(self, p: int, layers: int) -> int:
         return self.pairs * (p + 1) * bin(layers & 7).count("1")

@@ -211,7 +211,9 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
   return g->n_targets > 0 ? (g->pairs + g->n_targets - 1) / g->n_targets : 0;
 }
 
-static void free_geometry(tsqbx_geometry *g) {
+}  // namespace tsqbx
+
+void tsqbx::free_geometry(tsqbx_geometry *g) {
   if (!g) return;
   void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
                   g->ctr, g->row_tgts, g->stage.xy, g->stage.nxy, g->helm.rec, g->helm.tab,
@@ -220,6 +222,8 @@ static void free_geometry(tsqbx_geometry *g) {
     if (p) (void)hipFree(p);
   delete g;
 }
+
+namespace tsqbx {
 
 template <class T>
 static hipError_t dev_upload(T **dst, const T *src, size_t n, size_t *bytes) {

@@ -1,0 +1,213 @@
+"""A geometry built on the device from device arrays (tsqbx_geometry_create_device)
+equals the one the host builds from the same arrays, bit for bit: the same
+orders, rows and padding (integer layout, compared exactly) and therefore the
+same potentials (compared exactly), with device-built near-field lists fed in
+directly."""
+import numpy as np
+import pytest
+
+from conftest import cached_workload
+from paper_1811_01110_amd import _lib as L
+from paper_1811_01110_amd import api
+from paper_1811_01110_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+LAYOUT_KEYS = ("source_order", "target_order", "target_row", "row_offsets", "rows")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _arrays(g, normals=True, target_normals=True, target_center=True):
+    return dict(sources=g.sources, weights=g.weights, normals=g.normals if normals else None,
+                centers=g.centers, list_offsets=g.list_offsets, list_sources=g.list_sources,
+                targets=g.targets,
+                target_center=g.target_center if target_center else None,
+                target_normals=getattr(g, "target_normals", None) if target_normals else None)
+
+
+def _to_device(arrays):
+    import torch
+
+    out = {}
+    for k, v in arrays.items():
+        if v is None:
+            out[k] = None
+            continue
+        v = np.ascontiguousarray(v)
+        if k in ("list_sources", "target_center"):
+            v = v.astype(np.int32)
+        elif k == "list_offsets":
+            v = v.astype(np.int64)
+        else:
+            v = v.astype(np.float64)
+        out[k] = torch.from_numpy(v).to("cuda:0")
+    return out
+
+
+def _same_layout(a, b):
+    for k in LAYOUT_KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("n_rows", "nnz", "pairs", "max_list"):
+        assert a[k] == b[k], k
+
+
+def _check(ctx, arrays, p=8, layers=None):
+    print(f"device geometry: N={len(arrays['weights'])} M={len(arrays['centers'])} "
+          f"T={len(arrays['targets'])}", flush=True)
+    preview = api.geometry_layout(**arrays)
+    gh = api.Geometry(ctx, **arrays)
+    gd = ctx.geometry_device(**_to_device(arrays))
+    _same_layout(gh.read_layout(), preview)
+    _same_layout(gd.read_layout(), preview)
+    for k in ("n_sources", "n_targets", "n_centers", "nnz", "pairs", "max_list",
+              "has_normals", "has_target_normals"):
+        assert getattr(gd, k) == getattr(gh, k), k
+    if layers is None:
+        layers = 1 | (2 if arrays["normals"] is not None else 0) | \
+            (4 if arrays["target_normals"] is not None else 0)
+    rng = np.random.default_rng(len(arrays["weights"]))
+    sigma = rng.standard_normal(len(arrays["weights"]))
+    a = ctx.eval(gh, sigma, p, layers)
+    b = ctx.eval(gd, sigma, p, layers)
+    for x, y in zip(a, b):
+        assert (x is None) == (y is None)
+        if x is not None:
+            assert np.array_equal(x, y)
+    return gh, gd, sigma
+
+
+@pytest.mark.parametrize("tpc", [1, 3])
+def test_fuzz_geometry_equals_host_build(ctx, tpc):
+    g = W.fuzz_geometry(300 + tpc, n=3000, m=400, max_list=300, p=8, layers=7,
+                        targets_per_center=tpc)
+    arrays = _arrays(g)
+    _check(ctx, arrays)
+    # the read-back of a host geometry kept in the caller's order
+    gn = api.Geometry(ctx, flags=L.NO_REORDER, **arrays)
+    _same_layout(gn.read_layout(), api.geometry_layout(L.NO_REORDER, **arrays))
+
+
+def test_without_normals_or_target_map(ctx):
+    g = W.fuzz_geometry(311, n=2000, m=300, max_list=120, p=6, layers=1)
+    # target t belongs to center t (no map): reorder the targets to match
+    a = _arrays(g, normals=False, target_normals=False)
+    order = np.argsort(g.target_center, kind="stable")
+    a["targets"] = g.targets[order]
+    a["target_center"] = None
+    _check(ctx, a, p=6, layers=1)
+
+
+def test_unused_centers_empty_rows_and_coincident_points(ctx):
+    """Centers no target uses, empty lists, lists of one entry, and sources
+    and centers sharing coordinates (equal Morton keys: ties by index)."""
+    g = W.fuzz_geometry(312, n=1500, m=200, max_list=40, p=4, layers=3,
+                        targets_per_center=2)
+    a = _arrays(g, target_normals=False)
+    src = a["sources"].copy()
+    src[1::7] = src[0::7][:len(src[1::7])]  # coincident sources
+    a["sources"] = src
+    ctr = a["centers"].copy()
+    ctr[5:40] = ctr[4]  # coincident centers
+    a["centers"] = ctr
+    keep = (a["target_center"] % 5) != 3  # centers 3, 8, .. lose their targets
+    a["targets"] = g.targets[keep] - g.centers[g.target_center[keep]] + ctr[g.target_center[keep]]
+    a["target_center"] = g.target_center[keep]
+    off = g.list_offsets.copy()
+    lens = np.diff(off)
+    lens[::9] = 0
+    lens[1::11] = np.minimum(lens[1::11], 1)
+    new_off = np.zeros_like(off)
+    np.cumsum(lens, out=new_off[1:])
+    a["list_offsets"] = new_off
+    a["list_sources"] = np.concatenate(
+        [g.list_sources[off[i]:off[i] + lens[i]] for i in range(len(lens))]).astype(np.int32)
+    _check(ctx, a, p=4, layers=3)
+
+
+def test_config_a_full_size(ctx):
+    g = cached_workload("config_a")
+    gh, gd, sigma = _check(ctx, _arrays(g, target_normals=False), p=16, layers=3)
+
+
+def test_helmholtz_and_plan_on_a_device_geometry(ctx):
+    import torch
+
+    g = W.fuzz_geometry(313, n=2500, m=300, max_list=200, p=10, layers=3)
+    arrays = _arrays(g, target_normals=False)
+    gh = api.Geometry(ctx, **arrays)
+    gd = ctx.geometry_device(**_to_device(arrays))
+    x = ctx.eval_helmholtz(gh, g.sigma, 10, 3, 2.5)
+    y = ctx.eval_helmholtz(gd, g.sigma, 10, 3, 2.5)
+    for u, v in zip(x, y):
+        if u is not None:
+            assert np.array_equal(u, v)
+    T = g.n_targets
+    sig = torch.from_numpy(g.sigma).to("cuda:0")
+    outs = {k: [torch.zeros(T, dtype=torch.float64, device="cuda:0") for _ in range(2)]
+            for k in ("slp", "dlp")}
+    items = [dict(geom=gm, p=10, layers=3, sigma=sig, out_slp=outs["slp"][i],
+                  out_dlp=outs["dlp"][i]) for i, gm in enumerate((gh, gd))]
+    plan = ctx.plan(items)
+    plan.execute()
+    torch.cuda.synchronize()
+    for k in ("slp", "dlp"):
+        assert torch.equal(outs[k][0], outs[k][1])
+    plan.close()
+
+
+def test_device_ball_lists_feed_a_device_geometry(ctx):
+    """Lists from the device's near-field search go straight into a device
+    geometry; the result equals the host build from the same lists."""
+    g = cached_workload("config_b", 16)
+    off, idx = ctx.ball_lists(g.sources, g.centers, 0.6)
+    host = _arrays(g, target_normals=False)
+    host["list_offsets"] = off.cpu().numpy()
+    host["list_sources"] = idx.cpu().numpy()
+    dev = _to_device(host)
+    dev["list_offsets"], dev["list_sources"] = off, idx.contiguous()
+    preview = api.geometry_layout(**host)
+    gd = ctx.geometry_device(**dev)
+    _same_layout(gd.read_layout(), preview)
+    gh = api.Geometry(ctx, **host)
+    a = ctx.eval(gh, g.sigma, 16, 3)
+    b = ctx.eval(gd, g.sigma, 16, 3)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_bad_inputs_are_rejected(ctx):
+    g = W.fuzz_geometry(314, n=500, m=60, max_list=30, p=4, layers=1)
+    base = _arrays(g, target_normals=False)
+
+    def rc_of(**changes):
+        a = dict(base)
+        a.update(changes)
+        with pytest.raises(api.TsqbxError) as e:
+            ctx.geometry_device(**_to_device(a))
+        return e.value.code
+
+    bad = g.list_sources.copy()
+    bad[len(bad) // 2] = g.n_sources
+    assert rc_of(list_sources=bad) == L.E_RANGE
+    bad = g.list_sources.copy()
+    bad[0] = -1
+    assert rc_of(list_sources=bad) == L.E_RANGE
+    tc = g.target_center.copy()
+    tc[-1] = g.n_centers
+    assert rc_of(target_center=tc) == L.E_RANGE
+    off = g.list_offsets.copy()
+    i = int(np.argmax(np.diff(off) > 0)) + 1
+    off[i] = off[i + 1] + 1  # decreasing
+    off[-1] = max(off[-1], off[i])
+    assert rc_of(list_offsets=off,
+                 list_sources=np.zeros(int(off[-1]), dtype=np.int32)) == L.E_INVALID
+    with pytest.raises(api.TsqbxError) as e:
+        ctx.geometry_device(flags=L.NO_REORDER, **_to_device(base))
+    assert e.value.code == L.E_INVALID
+    # the context still works after the failures
+    _check(ctx, base, p=4, layers=1)
