@@ -1,7 +1,7 @@
 """Benchmark: TSQBX pair-terms/s in FP64 on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-serve]
-                    [--with-d] [--no-cpu] [--requests R] [--min-warm S]
+                    [--no-high-order] [--no-cpu] [--requests R] [--min-warm S]
                     [--no-sprime] [--no-helmholtz] [--no-lists] [--no-conventional]
                     [--only headline|batched|high_order|serve|sprime|helmholtz|lists|conventional]
                     [--calibration-copy]
@@ -49,8 +49,9 @@ def separate_recurrence_flops_per_pair(p: int, layers: int) -> int:
     own: 6p + 20 for the single layer and 11p + 36 for the double layer
     (the per-pair estimate of the work the method does, fma = 2).  The kernel
     shares one recurrence among the layers (flops_per_pair), so this figure
-    exceeds what it executes; it is reported beside the executed rate, never
-    as the roofline's `achieved`."""
+    exceeds what it executes.  It is reported as a count only: divided by the
+    kernel's time it would exceed the chip's peak, which makes it no rate of
+    the ALUs."""
     return (6 * p + 20 if layers & 1 else 0) + (11 * p + 36 if layers & 2 else 0)
 
 
@@ -85,8 +86,9 @@ HELM_SINCOS_FLOPS = 60
 
 
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_eval_p16_slp_dlp_sphere262144_traffic.json")
+COUNTER_RECORD = os.path.join(ROOT, "profiles", "k_eval_p16_slp_dlp_sphere262144_counters.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_01110_amd", "csrc", f)
-                  for f in ("tsqbx_device.h", "tsqbx_kernels.hip")]
+                  for f in ("tsqbx_device.h", "tsqbx_eval.hip")]
 
 
 def kernel_source_sha256() -> str:
@@ -111,6 +113,32 @@ def measured_traffic():
     if rec.get("kernel_source_sha256") != cur:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def measured_counters():
+    """Per-pair instruction counts and unit utilisations of the evaluation
+    kernel from the committed rocprofv3 counter record (same kernel sources),
+    with the bound derived from them: the unit whose utilisation is highest
+    among the FP64 vector ALU issue slots ("alu") and HBM bandwidth ("hbm"),
+    and the busiest unit of all those measured named as the limiter (the
+    vector memory pipeline's units count there too).  None when the kernel
+    source has changed since the counters were taken."""
+    try:
+        rec = json.load(open(COUNTER_RECORD))
+        cur = kernel_source_sha256()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != cur:
+        return None
+    util = rec["utilisation"]
+    bound = "alu" if util["valu_issue"] >= util["hbm"] else "hbm"
+    names = {"valu_issue": "FP64 vector ALU issue", "ta_busy": "vector memory address unit (TA)",
+             "td_busy": "vector memory data path (TD)", "hbm": "HBM bandwidth"}
+    busiest = max(names, key=lambda k: util[k])
+    return {"bound": bound, "limiter": f"{names[busiest]}, {util[busiest]:.0%} busy",
+            "utilisation": util, "per_pair": rec["per_pair"],
+            "clock_ghz": rec["clock_ghz"], "valu_full_issue_frac": rec["ceiling"]["valu_full_issue"],
+            "source": os.path.relpath(COUNTER_RECORD, ROOT)}
 
 
 def per_launch_ms(fn, n, torch):
@@ -155,14 +183,27 @@ def timed_steps(fn, steps, warmup, torch, min_warm_s=None):
 
 
 def cpu_model():
+    """The host CPU's model name, with its family, model and stepping numbers
+    when the name alone is only a brand (such as "AMD EPYC")."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = (x.strip() for x in line.split(":", 1))
+                    if k in ("model name", "cpu family", "model", "stepping") and k not in fields:
+                        fields[k] = v
+                if not line.strip() and fields:
+                    break
     except OSError:
-        pass
-    return None
+        return None
+    name = fields.get("model name")
+    if name is None:
+        return None
+    if len(name.split()) <= 2 and "cpu family" in fields:
+        name += (f" (family {fields['cpu family']}, model {fields.get('model', '?')}, "
+                 f"stepping {fields.get('stepping', '?')})")
+    return name
 
 
 def cpu_baseline(g, p, layers):
@@ -194,6 +235,50 @@ def cpu_baseline(g, p, layers):
                          f"every 32nd target ({len(sel)}), one thread"}}
 
 
+def roofline_obj(flops, kernel_ms, kernel, **extra):
+    """The roofline object of one kernel: executed FP64 operations per launch
+    divided by the kernel's average launch duration (HIP events on its
+    stream), against the FP64 vector peak."""
+    achieved = flops / (kernel_ms / 1e3) / 1e12
+    d = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+         "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+         "kernel": kernel, "kernel_ms_per_launch": kernel_ms, "flops_per_launch": flops}
+    d.update(extra)
+    return d
+
+
+def plan_flops(items, helm=False):
+    """Executed FP64 operations of one run of a plan's persistent kernel."""
+    if helm:
+        return sum(it["geom"].pairs * helm_flops_per_pair(it["p"], it["layers"]) for it in items)
+    return sum(it["geom"].pairs * flops_per_pair(it["p"], it["layers"]) for it in items)
+
+
+def tune_and_profile(plan, steps, label):
+    """Per-kernel times of the plan with its default tuning, then the plan
+    autotuner's choice and the per-kernel times with it."""
+    reps = max(steps // 2, 5)
+    default = plan.get_tuning()
+    log(f"{label}: profiling the default tuning {default}")
+    prof0 = plan.profile(reps)
+    log(f"{label}: autotuning the plan")
+    t0 = time.perf_counter()
+    tuned, _ = plan.autotune()
+    tune_s = time.perf_counter() - t0
+    log(f"{label}: tuned {tuned}; profiling it")
+    prof1 = plan.profile(reps)
+    return {"default": default, "default_stage_ms": prof0["stage_ms"],
+            "default_eval_ms": prof0["eval_ms"], "tuned": tuned,
+            "tuned_stage_ms": prof1["stage_ms"], "tuned_eval_ms": prof1["eval_ms"],
+            "autotune_s": tune_s, "profile_reps": reps}
+
+
+def max_rel_diff(a_list, b_list):
+    num = max((float((a - b).abs().max()) for a, b in zip(a_list, b_list)), default=0.0)
+    den = max((float(a.abs().max()) for a in a_list), default=0.0)
+    return num / den if den > 0 else num
+
+
 def bench_batched(ctx, api, torch, W, steps, warmup, geoms=None):
     if geoms is None:
         log("generating 64 batched geometries (mixed p, single layer)")
@@ -213,12 +298,12 @@ def bench_batched(ctx, api, torch, W, steps, warmup, geoms=None):
             torch.cuda.synchronize()
 
     log("timing plain per-geometry launches")
-    wall_plain, _ = timed_steps(plain, max(steps // 4, 3), 2, torch)
+    n_plain = max(steps // 4, 3)
+    wall_plain, _ = timed_steps(plain, n_plain, 2, torch)
     plan = ctx.plan(items)
+    tuning = tune_and_profile(plan, steps, "batched")
     log("timing the batched plan (graph replay)")
     wall_plan, ev_plan = timed_steps(lambda: plan.execute(), steps, warmup, torch)
-    n_plain = max(steps // 4, 3)
-    diff = max(float((a["out_slp"] - b).abs().max()) for a, b in zip(items, plain_out))
     res = {
         "workload": "64 geometries (ellipsoids / perturbed spheres), N log-uniform 2048..65536, "
                     "T=N/4, p in {4,8,12,16}, single layer, ball lists r=8h",
@@ -227,8 +312,12 @@ def bench_batched(ctx, api, torch, W, steps, warmup, geoms=None):
         "batched_pair_terms_per_s": pair_terms * steps / wall_plan,
         "plain_ms": wall_plain / n_plain * 1e3,
         "batched_ms": wall_plan / steps * 1e3,
-        "max_abs_diff_batched_vs_plain": diff,
+        "max_rel_diff_batched_vs_plain": max_rel_diff([it["out_slp"] for it in items], plain_out),
         "plan": plan.info(),
+        "tuning": tuning,
+        "roofline": roofline_obj(plan_flops(items), tuning["tuned_eval_ms"],
+                                 "k_persistent<1, -1, G, U> (the plan's evaluation kernel alone)",
+                                 stage_kernel_ms=tuning["tuned_stage_ms"]),
     }
     res["speedup"] = res["batched_pair_terms_per_s"] / res["plain_pair_terms_per_s"]
     plan.close()
@@ -266,10 +355,11 @@ def bench_helm_batched(ctx, api, torch, W, steps, warmup, geoms=None, k=10.0):
     log("timing plain per-geometry Helmholtz launches")
     wall_plain, _ = timed_steps(plain, n_plain, 2, torch)
     plan = ctx.plan_helmholtz(items)
+    tuning = tune_and_profile(plan, steps, "Helmholtz batched")
     log("timing the batched Helmholtz plan (graph replay)")
     wall_plan, _ = timed_steps(lambda: plan.execute(), steps, warmup, torch)
-    diff = max(max(float((it["out_slp"] - a).abs().max()), float((it["out_dlp"] - b).abs().max()))
-               for it, (a, b) in zip(items, plain_out))
+    got = [it[key] for it in items for key in ("out_slp", "out_dlp")]
+    ref = [x for ab in plain_out for x in ab]
     res = {
         "workload": f"the 64 batched geometries, Helmholtz k={k:g} single + double layer, "
                     "p in {4,8,12,16}, complex density",
@@ -278,8 +368,12 @@ def bench_helm_batched(ctx, api, torch, W, steps, warmup, geoms=None, k=10.0):
         "batched_pair_terms_per_s": pair_terms * steps / wall_plan,
         "plain_ms": wall_plain / n_plain * 1e3,
         "batched_ms": wall_plan / steps * 1e3,
-        "max_abs_diff_batched_vs_plain": diff,
+        "max_rel_diff_batched_vs_plain": max_rel_diff(got, ref),
         "plan": plan.info(),
+        "tuning": tuning,
+        "roofline": roofline_obj(plan_flops(items, helm=True), tuning["tuned_eval_ms"],
+                                 "k_helm_persistent<3, G, U> (the plan's evaluation kernel alone)",
+                                 stage_kernel_ms=tuning["tuned_stage_ms"]),
     }
     res["speedup"] = res["batched_pair_terms_per_s"] / res["plain_pair_terms_per_s"]
     plan.close()
@@ -298,23 +392,43 @@ def bench_d(ctx, api, torch, W, steps, warmup):
                           sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64),
                           out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)))
     pair_terms = sum(it["geom"].pair_terms(24, 2) for it in items)
-    pairs = sum(it["geom"].pairs for it in items)
+    plain_out = [torch.zeros_like(it["out_dlp"]) for it in items]
 
     def plain():
-        for it in items:
-            ctx.eval_async(it["geom"], it["sigma"], 24, 2, None, it["out_dlp"])
+        for it, o in zip(items, plain_out):
+            ctx.eval_async(it["geom"], it["sigma"], 24, 2, None, o)
             torch.cuda.synchronize()
 
+    log("timing plain per-geometry launches (high order)")
     wall_plain, _ = timed_steps(plain, 3, 1, torch)
+    # the plain kernel alone, for its roofline fraction
+    ms_plain_kernel = 0.0
+    for it, o in zip(items, plain_out):
+        ctx.stage_async(it["geom"], it["sigma"], 2)
+        ms = per_launch_ms(lambda: ctx.eval_staged_async(it["geom"], 24, 2, None, o), 3, torch)
+        ms_plain_kernel += float(np.mean(ms))
     plan = ctx.plan(items)
-    wall_plan, _ = timed_steps(lambda: plan.execute(), max(steps // 2, 3), 1, torch)
+    tuning = tune_and_profile(plan, steps, "high order")
+    n = max(steps // 2, 3)
+    log("timing the high-order plan (graph replay)")
+    wall_plan, _ = timed_steps(lambda: plan.execute(), n, 1, torch)
+    flops = plan_flops(items)
     res = {
         "workload": "16 perturbed spheres, N=131072, T=32768, p=24, double layer, k-NN lists "
                     "log-uniform 100..8000",
         "pair_terms": pair_terms,
         "plain_pair_terms_per_s": pair_terms * 3 / wall_plain,
-        "batched_pair_terms_per_s": pair_terms * max(steps // 2, 3) / wall_plan,
-        "batched_tflops": pairs * flops_per_pair(24, 2) * max(steps // 2, 3) / wall_plan / 1e12,
+        "batched_pair_terms_per_s": pair_terms * n / wall_plan,
+        "plain_ms": wall_plain / 3 * 1e3,
+        "batched_ms": wall_plan / n * 1e3,
+        "plain_kernels_ms": ms_plain_kernel,
+        "plain_kernels_frac": flops / (ms_plain_kernel / 1e3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+        "max_rel_diff_batched_vs_plain": max_rel_diff([it["out_dlp"] for it in items], plain_out),
+        "plan": plan.info(),
+        "tuning": tuning,
+        "roofline": roofline_obj(flops, tuning["tuned_eval_ms"],
+                                 "k_persistent<2, 24, G, U> (the plan's evaluation kernel alone)",
+                                 stage_kernel_ms=tuning["tuned_stage_ms"]),
     }
     res["speedup"] = res["batched_pair_terms_per_s"] / res["plain_pair_terms_per_s"]
     plan.close()
@@ -522,14 +636,12 @@ def bench_sprime(ctx, api, torch, g, geom, steps, warmup):
         ctx.stage_async(geom, sig, layers)
         kern = lambda: ctx.eval_staged_async(geom, p, layers, *outs)
         _, ev_k = timed_steps(kern, steps, warmup, torch)
-        achieved = geom.pairs * fpp / (ev_k / steps) / 1e12
         res[name] = {
             "layers": layers, "pair_terms_per_s": geom.pair_terms(p, layers) / (wall / steps),
             "ms_per_step": wall / steps * 1e3, "event_ms_per_step": ev / steps * 1e3,
-            "flops_per_pair": fpp, "achieved_tflops": achieved,
-            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "kernel": f"k_eval<16, {layers}, G, U>", "kernel_ms_per_launch": ev_k / steps * 1e3,
             "tuning": ctx.get_tuning(p, layers, geom.pairs // g.n_targets),
+            "roofline": roofline_obj(geom.pairs * fpp, ev_k / steps * 1e3,
+                                     f"k_eval<16, {layers}, G, U>", flops_per_pair=fpp),
         }
     return res
 
@@ -686,6 +798,41 @@ def bench_lists(ctx, api, torch, g, steps, with_host=True):
            "entries": cap, "ms_per_build": dt * 1e3, "entries_per_s": cap / dt,
            "same_as_host_generator": bool(np.array_equal(off.cpu().numpy(), g.list_offsets)
                                           and np.array_equal(idx.cpu().numpy(), g.list_sources))}
+    # the device lists straight into a geometry, built on the device, against
+    # the host build (layout on the host, then the upload) from the same lists
+    def dev_arr(a, dtype):
+        return None if a is None else torch.tensor(np.ascontiguousarray(a), device="cuda",
+                                                   dtype=dtype)
+    dev = dict(sources=src, weights=dev_arr(g.weights, torch.float64),
+               normals=dev_arr(g.normals, torch.float64), centers=ctr, list_offsets=off,
+               list_sources=idx.contiguous(), targets=dev_arr(g.targets, torch.float64),
+               target_center=dev_arr(g.target_center, torch.int32))
+    ctx.geometry_device(**dev).close()  # warm-up
+    torch.cuda.synchronize()
+    log(f"timing device geometry builds from the device lists, {n} builds")
+    t0 = time.perf_counter()
+    for _ in range(n):
+        gd = ctx.geometry_device(**dev)
+        gd.close()
+    torch.cuda.synchronize()
+    dg = (time.perf_counter() - t0) / n
+    gd = ctx.geometry_device(**dev)
+    host_arrays = dict(sources=g.sources, weights=g.weights, normals=g.normals, centers=g.centers,
+                       list_offsets=off.cpu().numpy(), list_sources=idx.cpu().numpy(),
+                       targets=g.targets, target_center=g.target_center)
+    log("timing the host geometry build from the same lists once")
+    t0 = time.perf_counter()
+    gh = api.Geometry(ctx, **host_arrays)
+    dh = time.perf_counter() - t0
+    a, b = gd.read_layout(), gh.read_layout()
+    res["geometry_from_device_lists"] = {
+        "device_ms_per_build": dg * 1e3, "host_ms_per_build": dh * 1e3,
+        "host_over_device": dh / dg,
+        "same_layout_as_host_build": bool(all(np.array_equal(a[k], b[k]) for k in
+                                              ("source_order", "target_order", "target_row",
+                                               "row_offsets", "rows")))}
+    gd.close()
+    gh.close()
     from paper_1811_01110_amd import workloads as W
 
     if with_host:
@@ -742,7 +889,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--with-d", action="store_true")
+    ap.add_argument("--no-high-order", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--min-warm", type=float, default=0.3,
@@ -846,13 +993,18 @@ def main():
             "kernel_ms_median": float(np.median(per_launch)), "kernel_ms_min": min(per_launch),
             "event_ms_per_step": ev / args.steps * 1e3,
             "flops_per_pair": flops_per_pair(p, layers),
-            "separate_recurrences": {
-                "flops_per_pair": separate_recurrence_flops_per_pair(p, layers),
-                "tflops": geom.pairs * separate_recurrence_flops_per_pair(p, layers)
-                / (ev / args.steps) / 1e12,
-            },
+            "separate_recurrences_flops_per_pair": separate_recurrence_flops_per_pair(p, layers),
         },
     }
+    counters = measured_counters()
+    if counters is not None:
+        # the ceiling of this design: the vector-memory data path at full
+        # occupancy (frac / td_busy) or every VALU issue slot used
+        frac = out["roofline"]["frac"]
+        counters["ceiling_frac"] = min(frac / counters["utilisation"]["td_busy"],
+                                       counters["valu_full_issue_frac"])
+        out["roofline"]["counters"] = counters
+        out["roofline"]["bound"] = counters["bound"]
     if args.only == "headline":
         geom.close()
         ctx.close()
@@ -881,7 +1033,7 @@ def main():
             out["helmholtz_batched"] = bench_helm_batched(ctx, api, torch, W, args.steps,
                                                           args.warmup, geoms_c)
         del geoms_c
-    if args.with_d:
+    if not args.no_high_order:
         out["batched_high_order"] = bench_d(ctx, api, torch, W, args.steps, args.warmup)
     if not args.no_serve:
         out["serving"] = bench_serve(ctx, api, torch, W, args.requests)

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtsqbx.so")
 ARCH = "gfx950"
 
-SOURCES = ["tsqbx_api.hip", "tsqbx_kernels.hip", "tsqbx_persistent.hip", "tsqbx_helmholtz.hip",
+SOURCES = ["tsqbx_api.hip", "tsqbx_eval.hip", "tsqbx_stage.hip", "tsqbx_persistent.hip", "tsqbx_helmholtz.hip",
            "tsqbx_lists.hip", "tsqbx_plan.hip", "tsqbx_server.hip", "tsqbx_conventional.hip",
            "tsqbx_noalloc.hip", "tsqbx_geometry_device.hip"]
 

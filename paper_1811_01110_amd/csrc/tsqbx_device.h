@@ -1,6 +1,6 @@
-// Device routines shared by the kernels of libtsqbx.so (tsqbx_kernels.hip,
-// tsqbx_persistent.hip): target-specific QBX near-field sums for gfx950
-// (CDNA4), FP64 on the vector ALUs.  Everything here has internal linkage,
+// Device routines shared by the kernels of libtsqbx.so (tsqbx_eval.hip,
+// tsqbx_stage.hip, tsqbx_persistent.hip): target-specific QBX near-field sums
+// for gfx950 (CDNA4), FP64 on the vector ALUs.  Everything here has internal linkage,
 // so each kernel file compiles its own copy.
 //
 // Per pair (target t, center c, listed source y) the kernels evaluate the

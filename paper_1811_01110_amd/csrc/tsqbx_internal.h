@@ -173,7 +173,7 @@ int fail_hip(hipError_t e, const char *what);
     if (e__ != hipSuccess) return ::tsqbx::fail_hip(e__, #call); \
   } while (0)
 
-// kernel launchers (tsqbx_kernels.hip)
+// kernel launchers (tsqbx_eval.hip, tsqbx_stage.hip)
 hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
                         const SourceStage &st, hipStream_t s);
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
