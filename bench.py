@@ -476,7 +476,15 @@ def bench_serve(ctx, api, torch, W, n_requests):
         ctx.eval(gs[r.geometry], s_.numpy(), r.p, r.layers, out_slp=a, out_dlp=b)
     dt = time.perf_counter() - t0
     plain_rate, plain_rps = sum(per_req[:k0]) / dt, k0 / dt
-    # saturation: everything submitted at once
+    # saturation: everything submitted at once, after one untimed pass (the
+    # first launches of the step kernels load their code)
+    log("serving: untimed warm-up pass")
+    srv = ctx.server(budget, SERVE_SLOTS)
+    for r, s_, o in zip(reqs, sig, outs):
+        a, b = out_args(r, o)
+        srv.submit_pinned(gs[r.geometry], s_, r.p, r.layers, out_slp=a, out_dlp=b)
+    srv.drain(600)
+    srv.close()
     srv = ctx.server(budget, SERVE_SLOTS)
     log("serving: saturation run (pinned submissions)")
     t0 = time.perf_counter()
@@ -581,6 +589,9 @@ def bench_serve_helmholtz(ctx, torch, gs, reqs, k=10.0):
         ctx.eval_helmholtz(gs[r.geometry], s_.numpy(), r.p, 3, k, o[0].numpy(), o[1].numpy())
     plain_s = time.perf_counter() - t0
     srv = ctx.server(2 << 30, SERVE_SLOTS)
+    for r, s_, o in list(zip(reqs, sig, outs))[:64]:  # untimed: first launches load code
+        srv.submit_helmholtz_pinned(gs[r.geometry], s_, r.p, 3, k, out_slp=o[0], out_dlp=o[1])
+    srv.drain(600)
     log("serving Helmholtz: saturation run")
     t0 = time.perf_counter()
     for r, s_, o in zip(reqs, sig, outs):

@@ -63,7 +63,8 @@ typedef enum {
   TSQBX_E_DEVICE = -4,  /* a HIP runtime call failed (message names it) */
   TSQBX_E_BUDGET = -5,  /* a request can never fit the server's device-memory budget */
   TSQBX_E_STATE = -6,   /* call not valid in the object's current state */
-  TSQBX_E_TIMEOUT = -7  /* a wait ran out of time; the work is still pending */
+  TSQBX_E_TIMEOUT = -7, /* a wait ran out of time; the work is still pending */
+  TSQBX_E_CANCELED = -8 /* a served request was withdrawn before it ran */
 } tsqbx_status;
 
 /* Layer bitmask: which potentials to evaluate. */
@@ -598,6 +599,11 @@ int tsqbx_server_poll(tsqbx_server *srv, uint64_t ticket, int *done);
 int tsqbx_server_wait(tsqbx_server *srv, uint64_t ticket, double timeout_s);
 /* Block until every submitted request has completed. */
 int tsqbx_server_drain(tsqbx_server *srv, double timeout_s);
+/* Withdraw a request that is still queued (not yet admitted to a step): it
+ * completes with TSQBX_E_CANCELED, its outputs untouched, and counts as
+ * failed.  TSQBX_E_STATE once it has been admitted or has ended,
+ * TSQBX_E_INVALID for an unknown ticket.  Thread-safe. */
+int tsqbx_server_cancel(tsqbx_server *srv, uint64_t ticket);
 /* Counters since creation; latency and queueing percentiles over the last
  * 65536 completed requests. */
 int tsqbx_server_get_stats(tsqbx_server *srv, tsqbx_server_stats *out);

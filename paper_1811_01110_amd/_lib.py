@@ -18,6 +18,7 @@ c_int, c_uint, c_int64, c_uint64, c_size_t, c_double, c_void_p, c_char_p = (
     ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p)
 
 OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_BUDGET, E_STATE, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+E_CANCELED = -8
 SLP, DLP, SPRIME = 1, 2, 4
 HELMHOLTZ = 64
 ACCUMULATE, NO_REORDER = 1, 2
@@ -168,6 +169,7 @@ _SIGNATURES = {
     "tsqbx_server_poll": (c_int, [c_void_p, c_uint64, P(c_int)]),
     "tsqbx_server_wait": (c_int, [c_void_p, c_uint64, c_double]),
     "tsqbx_server_drain": (c_int, [c_void_p, c_double]),
+    "tsqbx_server_cancel": (c_int, [c_void_p, c_uint64]),
     "tsqbx_server_get_stats": (c_int, [c_void_p, P(ServerStats)]),
     "tsqbx_server_destroy": (c_int, [c_void_p]),
 }

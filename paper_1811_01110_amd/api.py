@@ -692,6 +692,11 @@ class Server:
         _check(_lib().tsqbx_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s)))
         return self._live.pop(ticket, (None, None, None))[:3]
 
+    def cancel(self, ticket: int):
+        """Withdraw a request that is still queued; it then ends with
+        TSQBX_E_CANCELED (wait raises it)."""
+        _check(_lib().tsqbx_server_cancel(self.handle, ctypes.c_uint64(ticket)))
+
     def drain(self, timeout_s: float = 600.0):
         _check(_lib().tsqbx_server_drain(self.handle, float(timeout_s)))
         self._live.clear()

@@ -2,31 +2,29 @@
 // under a device-memory budget and batched continuously.
 //
 // submit() copies the density into a pinned host arena (pageable memory if
-// that arena is full).  A scheduler thread admits queued requests in FIFO
-// order while their buffers fit in the budget (one device arena of exactly
-// that size) and a request slot is free, and launches everything it admitted
-// as one step: density uploads, one staging kernel and one persistent kernel
-// over the step's work units, then output downloads into pinned memory.  Up to kStreams steps are in flight on
-// separate streams, so requests that arrive while a step runs are launched in
-// the next step and overlap with it on the device.  A completion thread polls
-// the steps' events, copies outputs to the callers' buffers, releases the
-// memory and wakes the scheduler.  Every request is summed by the same device
+// that arena is full).  The scheduler (tsqbx_sched.h) admits queued requests
+// in FIFO order while their buffers fit in the budget (one device arena of
+// exactly that size) and a request slot is free; this file is its device
+// executor, which launches everything admitted together as one step: density
+// uploads, one staging kernel and one persistent kernel over the step's work
+// units, then output downloads into pinned memory.  Up to kStreams steps are
+// in flight on separate streams, so requests that arrive while a step runs
+// are launched in the next step and overlap with it on the device.  When a
+// step's event has fired, the executor copies the outputs to the callers'
+// buffers and the scheduler releases the memory.  Every request is summed by the same device
 // routine with the same group width whatever it is batched with, so its
 // result does not depend on the mix.  Helmholtz requests (complex density and
 // outputs) share the steps: their densities are uploaded by DMA and they get
 // their own staging, table and persistent launches in the step.
 #include <algorithm>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <list>
-#include <thread>
+#include <memory>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
-#include "tsqbx_arena.h"
 #include "tsqbx_internal.h"
+#include "tsqbx_sched.h"
 
 using namespace tsqbx;
 
@@ -45,15 +43,9 @@ constexpr size_t kKeepDone = 4096;
 // Latency percentiles cover the most recent completions, at most this many.
 constexpr size_t kLatWindow = 65536;
 
-double now_s() {
-  using namespace std::chrono;
-  return duration<double>(steady_clock::now().time_since_epoch()).count();
-}
-
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-struct Request {
-  uint64_t ticket = 0;
+struct Request : Job {
   const tsqbx_geometry *geom = nullptr;
   int p = 0;
   unsigned layers = 0;
@@ -68,18 +60,6 @@ struct Request {
   size_t pin_off = 0, pin_bytes = 0;
   std::vector<double> pageable;  // fallback staging
   double *out[3] = {nullptr, nullptr, nullptr};  // caller's outputs per layer
-  size_t bytes = 0, arena_off = 0;
-  double t_submit = 0, t_launch = 0, t_done = 0;
-  int status = TSQBX_OK;
-  bool done = false;
-  int waiters = 0;                  // threads blocked in tsqbx_server_wait on it
-};
-
-struct Step {
-  int stream = -1;
-  std::vector<Request *> reqs;
-  hipEvent_t done_ev = nullptr;
-  double t_launch = 0;
 };
 
 struct StreamSlot {
@@ -92,73 +72,49 @@ struct StreamSlot {
   size_t cap_meta = 0;
 };
 
-double percentile(std::vector<double> v, double q) {
-  if (v.empty()) return 0.0;
-  std::sort(v.begin(), v.end());
-  const double pos = q * (v.size() - 1);
-  const size_t i = (size_t)pos;
-  const double f = pos - i;
-  return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
-}
-
 }  // namespace
 
-struct tsqbx_server {
+// The server is the scheduler's device executor.
+struct tsqbx_server final : public Executor {
   tsqbx_ctx *ctx = nullptr;
   int device = 0;
   size_t budget = 0;
-  int max_slots = 0;
   Tuning tn;
   char *arena_base = nullptr;
-  Arena arena;
   char *pinned_base = nullptr;  // pinned host arena for densities and outputs
   size_t pinned_cap = 0;
   Arena pinned;
   std::mutex pinned_mu;
-  StreamSlot streams[kStreams];
+  StreamSlot strm[kStreams];
+  std::unique_ptr<Scheduler> sched;
 
-  std::mutex mu;
-  std::condition_variable cv_sched, cv_done, cv_comp;
-  std::deque<Request *> queue;
-  std::map<uint64_t, Request *> all;
-  std::vector<Step> inflight;
-  uint64_t next_ticket = 1;
-  bool stopping = false;
-  size_t bytes_in_flight = 0, peak_bytes = 0;
-  int reqs_in_flight = 0;
-  tsqbx_server_stats st{};
-  std::vector<double> lat_ms, queue_ms;  // rings of the last kLatWindow completions
-  size_t lat_next = 0;
-  std::deque<uint64_t> retired;          // completed tickets, oldest first
-  double busy_since = -1, busy_acc = 0;
-  double host_launch_s = 0;  // scheduler time spent issuing steps
-  std::thread sched, comp;
-
-  int launch_step(Step &step, std::string &err);
-  // Record a completion (caller holds mu): latency rings, and forget the
-  // oldest completed requests beyond kKeepDone (not one a waiter still holds).
-  void retire(Request *r) {
-    const double lat = (r->t_done - r->t_submit) * 1e3, qu = (r->t_launch - r->t_submit) * 1e3;
-    if (lat_ms.size() < kLatWindow) {
-      lat_ms.push_back(lat);
-      queue_ms.push_back(qu);
-    } else {
-      lat_ms[lat_next] = lat;
-      queue_ms[lat_next] = qu;
-    }
-    lat_next = (lat_next + 1) % kLatWindow;
-    retired.push_back(r->ticket);
-    while (retired.size() > kKeepDone) {
-      auto it = all.find(retired.front());
-      if (it != all.end()) {
-        if (it->second->waiters > 0) break;
-        delete it->second;
-        all.erase(it);
-      }
-      retired.pop_front();
-    }
+  int streams() const override { return kStreams; }
+  void thread_start() override { (void)hipSetDevice(device); }
+  int launch(int stream, const std::vector<Job *> &jobs, std::string &err) override;
+  int query(int stream) override {
+    const hipError_t q = hipEventQuery(strm[stream].ev);
+    if (q == hipSuccess) return 1;
+    return q == hipErrorNotReady ? 0 : TSQBX_E_DEVICE;
   }
-  void release_host_stage(Request *r) {
+  void sync(int stream) override { (void)hipStreamSynchronize(strm[stream].s); }
+  // Outputs staged in the request's host buffer go to the caller's buffers.
+  int finish(Job *job, int step_status) override {
+    if (step_status != TSQBX_OK) return TSQBX_E_DEVICE;
+    Request *r = static_cast<Request *>(job);
+    const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
+    const size_t cw = r->cw();
+    if (!r->borrowed && T) {
+      const double *h = r->h_stage + cw * N;
+      for (int l = 0; l < 3; ++l)
+        if (r->layers & (1u << l)) {
+          std::memcpy(r->out[l], h, cw * T * sizeof(double));
+          h += cw * T;
+        }
+    }
+    return TSQBX_OK;
+  }
+  void release(Job *job) override {
+    Request *r = static_cast<Request *>(job);
     if (r->pinned) {
       std::lock_guard<std::mutex> g(pinned_mu);
       pinned.release(r->pin_off, r->pin_bytes);
@@ -167,8 +123,6 @@ struct tsqbx_server {
     r->h_stage = nullptr;
     std::vector<double>().swap(r->pageable);
   }
-  void scheduler();
-  void completer();
 };
 
 static int n_layers(unsigned layers) {
@@ -199,19 +153,19 @@ static size_t request_bytes_helm(const tsqbx_geometry *g, int p, unsigned layers
   return std::max<size_t>(b, kAlign);
 }
 
-// Launch one step (called by the scheduler with the lock released).
+// Launch one step (called by the scheduler with its lock released).
 // Densities in pinned host memory are read by the staging kernel directly
 // and outputs are written back by one copy kernel; only requests whose host
 // staging had to fall back to pageable memory use DMA copies.
-int tsqbx_server::launch_step(Step &step, std::string &err) {
-  StreamSlot &ss = streams[step.stream];
+int tsqbx_server::launch(int stream, const std::vector<Job *> &jobs, std::string &err) {
+  StreamSlot &ss = strm[stream];
   hipStream_t s = ss.s;
   hipError_t e = hipSuccess;
   auto fail_e = [&](hipError_t x, const char *what) {
     err = std::string(what) + ": " + hipGetErrorString(x);
     return TSQBX_E_DEVICE;
   };
-  const size_t K = step.reqs.size();
+  const size_t K = jobs.size();
   std::vector<WorkItem> items;         // Laplace requests
   std::vector<StageItem> stage;
   std::vector<HelmWorkItem> hitems;    // Helmholtz requests
@@ -229,7 +183,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
   bool h_same = true;
   const int64_t per_unit = (int64_t)kUnitSteps * (64 / tn.group_lanes);
   for (size_t i = 0; i < K; ++i) {
-    Request *r = step.reqs[i];
+    Request *r = static_cast<Request *>(jobs[i]);
     const tsqbx_geometry *g = r->geom;
     const size_t N = (size_t)g->n_sources, T = (size_t)g->n_targets;
     const size_t cw = r->cw();
@@ -419,172 +373,7 @@ int tsqbx_server::launch_step(Step &step, std::string &err) {
                        std::get<2>(pageable_down[i]) * sizeof(double), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(ss.ev, s);
   if (e != hipSuccess) return fail_e(e, "step launch");
-  step.done_ev = ss.ev;
   return TSQBX_OK;
-}
-
-void tsqbx_server::scheduler() {
-  (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
-  for (;;) {
-    cv_sched.wait(lk, [&] {
-      if (stopping && queue.empty()) return true;
-      if (queue.empty()) return false;
-      bool free_stream = false;
-      for (auto &ss : streams) free_stream |= !ss.busy;
-      return free_stream && reqs_in_flight < max_slots &&
-             bytes_in_flight + queue.front()->bytes <= budget;
-    });
-    if (stopping && queue.empty()) break;
-    // admit in FIFO order while memory and slots allow
-    Step step;
-    for (int k = 0; k < kStreams; ++k)
-      if (!streams[k].busy) {
-        step.stream = k;
-        break;
-      }
-    while (!queue.empty() && reqs_in_flight < max_slots &&
-           step.reqs.size() < (size_t)kMaxStepRequests) {
-      Request *r = queue.front();
-      size_t off = 0;
-      if (bytes_in_flight + r->bytes > budget || !arena.alloc(r->bytes, &off)) break;
-      queue.pop_front();
-      r->arena_off = off;
-      bytes_in_flight += r->bytes;
-      peak_bytes = std::max(peak_bytes, bytes_in_flight);
-      ++reqs_in_flight;
-      ++st.admitted;
-      step.reqs.push_back(r);
-    }
-    if (step.reqs.empty()) {
-      // the head fits the budget but not the fragmented arena: wait for a release
-      cv_sched.wait_for(lk, std::chrono::milliseconds(1));
-      continue;
-    }
-    streams[step.stream].busy = true;
-    const double t0 = now_s();
-    for (Request *r : step.reqs) r->t_launch = t0;
-    step.t_launch = t0;
-    if (busy_since < 0) busy_since = t0;
-    lk.unlock();
-    std::string err;
-    const double th0 = now_s();
-    int rc;
-    {
-      TraceRange trace_("tsqbx server step launch");
-      rc = launch_step(step, err);
-    }
-    const double th1 = now_s();
-    lk.lock();
-    host_launch_s += th1 - th0;
-    if (rc != TSQBX_OK) {
-      // the stream may hold partial work: wait for it, then fail the step's requests
-      lk.unlock();
-      (void)hipStreamSynchronize(streams[step.stream].s);
-      lk.lock();
-      for (Request *r : step.reqs) {
-        r->status = rc;
-        r->done = true;
-        r->t_done = now_s();
-        arena.release(r->arena_off, r->bytes);
-        bytes_in_flight -= r->bytes;
-        --reqs_in_flight;
-        ++st.failed;
-        release_host_stage(r);
-        retire(r);
-      }
-      streams[step.stream].busy = false;
-      fprintf(stderr, "tsqbx server: step failed: %s\n", err.c_str());
-      if (inflight.empty() && busy_since >= 0) {
-        busy_acc += now_s() - busy_since;
-        busy_since = -1;
-      }
-      cv_done.notify_all();
-      continue;
-    }
-    ++st.steps;
-    inflight.push_back(std::move(step));
-    cv_comp.notify_all();
-  }
-}
-
-void tsqbx_server::completer() {
-  (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
-  for (;;) {
-    cv_comp.wait(lk, [&] { return !inflight.empty() || (stopping && queue.empty() && reqs_in_flight == 0); });
-    if (inflight.empty()) break;
-    // find a finished step (poll without the lock)
-    std::vector<hipEvent_t> evs;
-    for (auto &s : inflight) evs.push_back(s.done_ev);
-    lk.unlock();
-    int found = -1;
-    hipError_t qerr = hipSuccess;
-    for (int spin = 0; found < 0; ++spin) {
-      for (size_t i = 0; i < evs.size(); ++i) {
-        hipError_t q = hipEventQuery(evs[i]);
-        if (q == hipSuccess) {
-          found = (int)i;
-          break;
-        }
-        if (q != hipErrorNotReady) {
-          found = (int)i;
-          qerr = q;
-          break;
-        }
-      }
-      if (found < 0) {
-        if (spin < 200)
-          std::this_thread::yield();
-        else
-          std::this_thread::sleep_for(std::chrono::microseconds(20));
-      }
-      if (spin > 0 && spin % 64 == 0) {
-        // new steps may have been launched meanwhile
-        std::lock_guard<std::mutex> g(mu);
-        if (inflight.size() != evs.size()) break;
-      }
-    }
-    lk.lock();
-    if (found < 0) continue;
-    Step step = std::move(inflight[found]);
-    inflight.erase(inflight.begin() + found);
-    StreamSlot &ss = streams[step.stream];
-    const double t1 = now_s();
-    for (Request *r : step.reqs) {
-      const size_t N = (size_t)r->geom->n_sources, T = (size_t)r->geom->n_targets;
-      const size_t cw = r->cw();
-      if (qerr == hipSuccess) {
-        if (!r->borrowed && T) {
-          const double *h = r->h_stage + cw * N;
-          for (int l = 0; l < 3; ++l)
-            if (r->layers & (1u << l)) {
-              std::memcpy(r->out[l], h, cw * T * sizeof(double));
-              h += cw * T;
-            }
-        }
-        ++st.completed;
-        st.pair_terms_completed += r->geom->pairs * (int64_t)(r->p + 1) * n_layers(r->layers);
-      } else {
-        r->status = TSQBX_E_DEVICE;
-        ++st.failed;
-      }
-      r->t_done = t1;
-      r->done = true;
-      arena.release(r->arena_off, r->bytes);
-      bytes_in_flight -= r->bytes;
-      --reqs_in_flight;
-      release_host_stage(r);
-      retire(r);
-    }
-    ss.busy = false;
-    if (inflight.empty() && busy_since >= 0) {
-      busy_acc += t1 - busy_since;
-      busy_since = -1;
-    }
-    cv_done.notify_all();
-    cv_sched.notify_all();
-  }
 }
 
 extern "C" {
@@ -618,11 +407,9 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   sv->ctx = ctx;
   sv->device = ctx->device;
   sv->budget = hbm_budget / kAlign * kAlign;
-  sv->max_slots = max_slots;
   // one launch shape for the server's lifetime (near-field lists of a few
   // hundred sources); a request's result then does not depend on its step
   sv->tn = default_tuning(16, 3u, 256);
-  sv->st.budget_bytes = sv->budget;
   hipError_t e = hipMalloc((void **)&sv->arena_base, sv->budget);
   // pinned host arena: densities and outputs of queued and running requests
   sv->pinned_cap = std::min<size_t>(sv->budget, size_t(1) << 30);
@@ -632,11 +419,11 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   }
   if (sv->pinned_cap) sv->pinned.init(sv->pinned_cap);
   for (int k = 0; k < kStreams && e == hipSuccess; ++k) {
-    e = hipStreamCreateWithFlags(&sv->streams[k].s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->streams[k].ev, hipEventDisableTiming);
+    e = hipStreamCreateWithFlags(&sv->strm[k].s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->strm[k].ev, hipEventDisableTiming);
   }
   if (e != hipSuccess) {
-    for (auto &ss : sv->streams) {
+    for (auto &ss : sv->strm) {
       if (ss.ev) (void)hipEventDestroy(ss.ev);
       if (ss.s) (void)hipStreamDestroy(ss.s);
     }
@@ -646,9 +433,14 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
     if (prev >= 0) (void)hipSetDevice(prev);
     return fail_hip(e, "server setup");
   }
-  sv->arena.init(sv->budget);
-  sv->sched = std::thread([sv] { sv->scheduler(); });
-  sv->comp = std::thread([sv] { sv->completer(); });
+  SchedLimits lim;
+  lim.budget = sv->budget;
+  lim.max_slots = max_slots;
+  lim.max_step_jobs = kMaxStepRequests;
+  lim.keep_done = kKeepDone;
+  lim.lat_window = kLatWindow;
+  sv->sched = std::make_unique<Scheduler>(sv, lim);
+  sv->sched->start();
   if (prev >= 0) (void)hipSetDevice(prev);
   *out = sv;
   return TSQBX_OK;
@@ -714,26 +506,12 @@ static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsi
   }
   for (int l = 0; l < 3; ++l) r->out[l] = (layers & (1u << l)) ? out_host[l] : nullptr;
   r->bytes = bytes;
-  std::lock_guard<std::mutex> lk(sv->mu);
-  ++sv->st.submitted;
-  if (sv->stopping) {
-    sv->release_host_stage(r);
-    delete r;
-    return fail(TSQBX_E_STATE, "server is shutting down");
-  }
-  if (bytes > sv->budget) {
-    ++sv->st.rejected;
-    sv->release_host_stage(r);
-    delete r;
-    return fail(TSQBX_E_BUDGET, "request needs %zu bytes but the budget is %zu", bytes, sv->budget);
-  }
-  r->ticket = sv->next_ticket++;
-  r->t_submit = now_s();
-  sv->all[r->ticket] = r;
-  sv->queue.push_back(r);
-  *ticket = r->ticket;
-  sv->cv_sched.notify_all();
-  return TSQBX_OK;
+  r->pair_terms = geom->pairs * (int64_t)(p + 1) * n_layers(layers);
+  rc = sv->sched->submit(r, ticket);  // r belongs to the scheduler from here on
+  if (rc == TSQBX_E_STATE) return fail(rc, "server is shutting down");
+  if (rc == TSQBX_E_BUDGET)
+    return fail(rc, "request needs %zu bytes but the budget is %zu", bytes, sv->budget);
+  return rc;
 }
 
 int tsqbx_server_submit(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
@@ -774,79 +552,57 @@ int tsqbx_server_submit_helmholtz_pinned(tsqbx_server *sv, const tsqbx_geometry 
 
 int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {
   if (!sv || !done) return fail(TSQBX_E_INVALID, "server or done is NULL");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  auto it = sv->all.find(ticket);
-  if (it == sv->all.end()) return fail(TSQBX_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-  *done = it->second->done ? 1 : 0;
-  if (it->second->done && it->second->status != TSQBX_OK)
-    return fail(it->second->status, "request %llu failed", (unsigned long long)ticket);
+  int status = TSQBX_OK;
+  if (sv->sched->poll(ticket, done, &status) != TSQBX_OK)
+    return fail(TSQBX_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  if (status != TSQBX_OK) return fail(status, "request %llu failed", (unsigned long long)ticket);
   return TSQBX_OK;
 }
 
 int tsqbx_server_wait(tsqbx_server *sv, uint64_t ticket, double timeout_s) {
   TraceRange trace_("tsqbx_server_wait");
   if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
-  std::unique_lock<std::mutex> lk(sv->mu);
-  auto it = sv->all.find(ticket);
-  if (it == sv->all.end()) return fail(TSQBX_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-  Request *r = it->second;
-  ++r->waiters;  // keeps r from being forgotten while this thread waits
-  const bool ok =
-      sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; });
-  --r->waiters;
-  if (!ok)
-    return fail(TSQBX_E_TIMEOUT, "request %llu not done after %.3f s", (unsigned long long)ticket, timeout_s);
-  if (r->status != TSQBX_OK) return fail(r->status, "request %llu failed", (unsigned long long)ticket);
+  int status = TSQBX_OK;
+  const int rc = sv->sched->wait(ticket, timeout_s, &status);
+  if (rc == TSQBX_E_INVALID)
+    return fail(rc, "unknown ticket %llu", (unsigned long long)ticket);
+  if (rc == TSQBX_E_TIMEOUT)
+    return fail(rc, "request %llu not done after %.3f s", (unsigned long long)ticket, timeout_s);
+  if (status != TSQBX_OK) return fail(status, "request %llu failed", (unsigned long long)ticket);
   return TSQBX_OK;
+}
+
+int tsqbx_server_cancel(tsqbx_server *sv, uint64_t ticket) {
+  if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
+  const int rc = sv->sched->cancel(ticket);
+  if (rc == TSQBX_E_INVALID)
+    return fail(rc, "unknown ticket %llu", (unsigned long long)ticket);
+  if (rc == TSQBX_E_STATE)
+    return fail(rc, "request %llu is no longer queued", (unsigned long long)ticket);
+  return rc;
 }
 
 int tsqbx_server_drain(tsqbx_server *sv, double timeout_s) {
   TraceRange trace_("tsqbx_server_drain");
   if (!sv) return fail(TSQBX_E_INVALID, "server is NULL");
-  std::unique_lock<std::mutex> lk(sv->mu);
-  if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                            [&] { return sv->queue.empty() && sv->reqs_in_flight == 0; }))
+  if (sv->sched->drain(timeout_s) != TSQBX_OK)
     return fail(TSQBX_E_TIMEOUT, "requests still pending after %.3f s", timeout_s);
   return TSQBX_OK;
 }
 
 int tsqbx_server_get_stats(tsqbx_server *sv, tsqbx_server_stats *out) {
   if (!sv || !out) return fail(TSQBX_E_INVALID, "server or out is NULL");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  *out = sv->st;
-  out->bytes_in_flight = sv->bytes_in_flight;
-  out->peak_bytes_in_flight = sv->peak_bytes;
-  out->latency_p50_ms = percentile(sv->lat_ms, 0.50);
-  out->latency_p90_ms = percentile(sv->lat_ms, 0.90);
-  out->latency_p99_ms = percentile(sv->lat_ms, 0.99);
-  out->latency_max_ms = sv->lat_ms.empty() ? 0.0 : *std::max_element(sv->lat_ms.begin(), sv->lat_ms.end());
-  out->queue_p50_ms = percentile(sv->queue_ms, 0.50);
-  out->queue_p99_ms = percentile(sv->queue_ms, 0.99);
-  out->busy_s = sv->busy_acc + (sv->busy_since >= 0 ? now_s() - sv->busy_since : 0.0);
-  out->host_launch_s = sv->host_launch_s;
+  sv->sched->stats(out);
   return TSQBX_OK;
 }
 
 int tsqbx_server_destroy(tsqbx_server *sv) {
   if (!sv) return TSQBX_OK;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sv->stopping = true;
-  }
-  sv->cv_sched.notify_all();
-  sv->cv_comp.notify_all();
-  if (sv->sched.joinable()) sv->sched.join();
-  {
-    // wake the completer once the last step is done
-    std::unique_lock<std::mutex> lk(sv->mu);
-    sv->cv_done.wait(lk, [&] { return sv->reqs_in_flight == 0; });
-  }
-  sv->cv_comp.notify_all();
-  if (sv->comp.joinable()) sv->comp.join();
+  sv->sched->stop();  // refuses new requests, finishes the queued and running ones
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(sv->device);
-  for (auto &ss : sv->streams) {
+  for (auto &ss : sv->strm) {
     if (ss.s) (void)hipStreamSynchronize(ss.s);
     if (ss.d_meta) (void)hipFree(ss.d_meta);
     if (ss.h_meta) (void)hipHostFree(ss.h_meta);
@@ -854,7 +610,7 @@ int tsqbx_server_destroy(tsqbx_server *sv) {
     if (ss.s) (void)hipStreamDestroy(ss.s);
   }
   if (sv->arena_base) (void)hipFree(sv->arena_base);
-  for (auto &kv : sv->all) delete kv.second;
+  sv->sched.reset();  // forgets the remaining requests
   if (sv->pinned_base) (void)hipHostFree(sv->pinned_base);
   if (prev >= 0) (void)hipSetDevice(prev);
   delete sv;

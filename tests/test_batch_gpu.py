@@ -146,6 +146,43 @@ def test_server_rejects_oversized_and_respects_budget(ctx):
     srv.close()
 
 
+def test_server_cancels_a_queued_request(ctx):
+    """A request still queued can be withdrawn: it ends with
+    TSQBX_E_CANCELED and its outputs stay untouched; one already admitted or
+    ended cannot (the scheduler's full failure matrix runs on the CPU in
+    test_server_fake.py)."""
+    g = W.fuzz_geometry(401, n=3000, m=500, max_list=100, p=8, layers=3)
+    geom = ctx.geometry(g)
+    need = api.Server.request_bytes(geom, 3)
+    srv = ctx.server(need + need // 2, 4)  # one request at a time
+    ts = [srv.submit(geom, g.sigma, 8, 3) for _ in range(8)]
+    try:
+        srv.cancel(ts[-1][0])
+        cancelled = True
+    except api.TsqbxError as e:  # already admitted: the queue drained first
+        assert e.code == -6
+        cancelled = False
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.cancel(10 ** 12)
+    assert ei.value.code == -1
+    srv.drain(60)
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.cancel(ts[0][0])  # ended
+    assert ei.value.code == -6
+    st = srv.stats()
+    if cancelled:
+        with pytest.raises(api.TsqbxError) as ei:
+            srv.wait(ts[-1][0])
+        assert ei.value.code == -8
+        assert not ts[-1][1].any() and st["completed"] == 7 and st["failed"] == 1
+    else:
+        assert st["completed"] == 8
+    for _, a, _b, _t in ts[:-1]:
+        assert np.array_equal(a, ts[0][1])
+    srv.close()
+    geom.close()
+
+
 def test_server_pinned_submissions_match_copying_ones(ctx):
     import torch
 
