@@ -805,8 +805,13 @@ def bench_lists(ctx, api, torch, g, steps, with_host=True):
         off, idx = ctx.ball_lists(src, ctr, 0.15, capacity=cap)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n
+    # compulsory HBM bytes of a build: points read once, offsets and entries written
+    ball_bytes = 24 * (g.n_sources + g.n_centers) + 8 * (g.n_centers + 1) + 4 * cap
     res = {"workload": "ball lists r=0.15 of the perturbed sphere: 262144 sources, 65536 centers",
            "entries": cap, "ms_per_build": dt * 1e3, "entries_per_s": cap / dt,
+           "roofline": {"bound": "hbm", "achieved": ball_bytes / dt / 1e9, "peak": 8000.0,
+                        "unit": "GB/s", "frac": ball_bytes / dt / 8e12, "traffic": None,
+                        "algorithmic_bytes": ball_bytes},
            "same_as_host_generator": bool(np.array_equal(off.cpu().numpy(), g.list_offsets)
                                           and np.array_equal(idx.cpu().numpy(), g.list_sources))}
     # the device lists straight into a geometry, built on the device, against
@@ -867,8 +872,13 @@ def bench_lists(ctx, api, torch, g, steps, with_host=True):
         off, idx = ctx.knn_lists(src, ctr, cnt)
     torch.cuda.synchronize()
     dk = (time.perf_counter() - t0) / n
+    knn_bytes = 24 * (d.n_sources + d.n_centers) + 4 * d.n_centers + 8 * (d.n_centers + 1) + \
+        4 * int(counts.sum())
     knn = {"workload": "k nearest of one config D geometry: 131072 sources on a perturbed "
                        "sphere, 32768 centers, k log-uniform 100..8000",
+           "roofline": {"bound": "hbm", "achieved": knn_bytes / dk / 1e9, "peak": 8000.0,
+                        "unit": "GB/s", "frac": knn_bytes / dk / 8e12, "traffic": None,
+                        "algorithmic_bytes": knn_bytes},
            "entries": int(counts.sum()), "ms_per_build": dk * 1e3,
            "entries_per_s": float(counts.sum()) / dk,
            "same_as_host_kdtree": bool(np.array_equal(off.cpu().numpy(), d.list_offsets)

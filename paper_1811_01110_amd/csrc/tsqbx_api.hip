@@ -215,7 +215,7 @@ static int64_t mean_list_of(const tsqbx_geometry *g) {
 
 void tsqbx::free_geometry(tsqbx_geometry *g) {
   if (!g) return;
-  void *ptrs[] = {g->src_pos, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
+  void *ptrs[] = {g->src_pos, g->src_w, g->src_nrm, g->src_perm, g->src_rank, g->tgt, g->tgt_nrm, g->idx,
                   g->ctr, g->row_tgts, g->stage.xy, g->stage.nxy, g->helm.rec, g->helm.tab,
                   g->helm.tabs};
   for (void *p : ptrs)
@@ -457,11 +457,13 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   }
 
   std::vector<double4> pos(N), nrm(d->normals ? N : 0);
+  std::vector<double> wdev(N);
   std::vector<int64_t> perm(reorder ? N : 0);
   for (int64_t i = 0; i < N; ++i) {
     const int64_t s = src_ord[i];
     pos[i] = make_double4(d->sources[3 * s], d->sources[3 * s + 1], d->sources[3 * s + 2],
                           d->weights[s]);
+    wdev[i] = d->weights[s];
     if (d->normals)
       nrm[i] = make_double4(d->normals[3 * s], d->normals[3 * s + 1], d->normals[3 * s + 2], 0.0);
     if (reorder) perm[i] = s;
@@ -483,6 +485,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   g->host_row_len = std::move(host_row_len);
   size_t bytes = 0;
   hipError_t e = dev_upload(&g->src_pos, pos.data(), N, &bytes);
+  if (e == hipSuccess) e = dev_upload(&g->src_w, wdev.data(), N, &bytes);
   if (e == hipSuccess && d->normals) e = dev_upload(&g->src_nrm, nrm.data(), N, &bytes);
   if (e == hipSuccess && reorder) e = dev_upload(&g->src_perm, perm.data(), N, &bytes);
   if (e == hipSuccess && reorder) e = dev_upload(&g->src_rank, src_rank.data(), N, &bytes);
@@ -497,6 +500,9 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   if (e == hipSuccess) e = dev_upload<char>(&spos, nullptr, stage_pos_bytes(N), &bytes);
   if (e == hipSuccess && d->normals) e = dev_upload<char>(&snrm, nullptr, stage_nrm_bytes(N), &bytes);
   g->stage = stage_views(spos, snrm, N);
+  // the positions and the padding entry, once: evaluations stage strengths only
+  if (e == hipSuccess) e = launch_stage_positions(g, g->stage, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) {
     free_geometry(g);
     return fail_hip(e, "geometry upload");
@@ -556,7 +562,7 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned la
   o.s = d_out_slp;
   o.d = d_out_dlp;
   o.t = d_out_sprime;
-  TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, s));
+  TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, true, s));
   g->staged_layers.store(layers);
   TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn, s));
   return TSQBX_OK;
@@ -572,7 +578,7 @@ int tsqbx_stage_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, unsigned layers,
   if (g->n_sources > 0 && !d_sigma) return fail(TSQBX_E_INVALID, "sigma is NULL");
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
-  TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, (hipStream_t)hip_stream));
+  TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, true, (hipStream_t)hip_stream));
   g->staged_layers.store(layers);
   return TSQBX_OK;
 }
@@ -619,7 +625,7 @@ int tsqbx_qbxl_form_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, const 
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)hip_stream;
-  TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
+  TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, true, s));
   g->staged_layers.store(TSQBX_SLP);
   TSQBX_HIP(launch_qbxl(g, p, 1, g->stage, nullptr, d_coeffs, nullptr,
                         (flags & TSQBX_ACCUMULATE) != 0, s));
@@ -651,7 +657,7 @@ int tsqbx_eval_conventional_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
   hipStream_t s = (hipStream_t)hip_stream;
-  TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, s));
+  TSQBX_HIP(launch_stage(g, d_sigma, TSQBX_SLP, g->stage, true, s));
   g->staged_layers.store(TSQBX_SLP);
   TSQBX_HIP(launch_qbxl(g, p, 3, g->stage, nullptr, nullptr, d_out,
                         (flags & TSQBX_ACCUMULATE) != 0, s));
@@ -694,7 +700,7 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
   o.d = ctx->d_out + T;
   o.t = ctx->d_out + 2 * T;
   const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
-  TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, s));
+  TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, true, s));
   g->staged_layers.store(layers);
   TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, false, tn, s));
   // without ACCUMULATE the outputs go straight into the caller's arrays
@@ -885,7 +891,7 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   hipStream_t s = ctx->stream;
-  if (e == hipSuccess) e = launch_stage(g, sig, layers, g->stage, s);
+  if (e == hipSuccess) e = launch_stage(g, sig, layers, g->stage, true, s);
   // the staging buffer now holds a density of ones: a later
   // tsqbx_eval_staged_async must stage again
   g->staged_layers.store(0);

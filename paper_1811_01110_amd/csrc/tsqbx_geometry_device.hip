@@ -57,7 +57,8 @@ k_validate(const int64_t *__restrict__ off, int64_t M, const int32_t *__restrict
 __global__ void __launch_bounds__(kBlock)
 k_bbox_partial(const double *__restrict__ xyz, int64_t n, double *__restrict__ part) {
   __shared__ double sh[6][kBlock];
-  double lo[3] = {1e308, 1e308, 1e308}, hi[3] = {-1e308, -1e308, -1e308};
+  const double big = __builtin_inf();
+  double lo[3] = {big, big, big}, hi[3] = {-big, -big, -big};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     for (int a = 0; a < 3; ++a) {
@@ -82,15 +83,35 @@ k_bbox_partial(const double *__restrict__ xyz, int64_t n, double *__restrict__ p
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(64) k_bbox_final(const double *__restrict__ part, int nb,
-                                                   double *__restrict__ box) {
-  if (threadIdx.x != 0) return;
-  double lo[3] = {part[0], part[1], part[2]}, hi[3] = {part[3], part[4], part[5]};
-  for (int b = 1; b < nb; ++b)
+__global__ void __launch_bounds__(kBlock) k_bbox_final(const double *__restrict__ part, int nb,
+                                                       double *__restrict__ box) {
+  __shared__ double sh[6][kBlock];
+  const double big = __builtin_inf();
+  double lo[3] = {big, big, big}, hi[3] = {-big, -big, -big};
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
     for (int a = 0; a < 3; ++a) {
       lo[a] = part[6 * b + a] < lo[a] ? part[6 * b + a] : lo[a];
       hi[a] = part[6 * b + 3 + a] > hi[a] ? part[6 * b + 3 + a] : hi[a];
     }
+  for (int a = 0; a < 3; ++a) {
+    sh[a][threadIdx.x] = lo[a];
+    sh[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int a = 0; a < 3; ++a) {
+        const double l = sh[a][threadIdx.x + w], h = sh[3 + a][threadIdx.x + w];
+        sh[a][threadIdx.x] = l < sh[a][threadIdx.x] ? l : sh[a][threadIdx.x];
+        sh[3 + a][threadIdx.x] = h > sh[3 + a][threadIdx.x] ? h : sh[3 + a][threadIdx.x];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = sh[a][0];
+    hi[a] = sh[3 + a][0];
+  }
   double span = 1e-300;
   for (int a = 0; a < 3; ++a) span = hi[a] - lo[a] > span ? hi[a] - lo[a] : span;
   for (int a = 0; a < 3; ++a) box[a] = lo[a];
@@ -131,11 +152,13 @@ k_morton(const double *__restrict__ xyz, int64_t n, const double *__restrict__ b
 __global__ void __launch_bounds__(kBlock)
 k_sources(const int32_t *__restrict__ ord, int64_t n, const double *__restrict__ xyz,
           const double *__restrict__ w, const double *__restrict__ nrm, double4 *__restrict__ pos,
-          double4 *__restrict__ nrm_out, int64_t *__restrict__ perm, int32_t *__restrict__ rank) {
+          double *__restrict__ w_out, double4 *__restrict__ nrm_out, int64_t *__restrict__ perm,
+          int32_t *__restrict__ rank) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int64_t s = ord[k];
   pos[k] = make_double4(xyz[3 * s], xyz[3 * s + 1], xyz[3 * s + 2], w[s]);
+  w_out[k] = w[s];
   if (nrm) nrm_out[k] = make_double4(nrm[3 * s], nrm[3 * s + 1], nrm[3 * s + 2], 0.0);
   perm[k] = s;
   rank[s] = (int32_t)k;
@@ -392,18 +415,20 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
     TQ(sc.get(&v0, N));
     TQ(sc.get(&src_ord, N));
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, s, d->sources, N, part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, nbb, box);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s, part, nbb, box);
     hipLaunchKernelGGL(k_morton, dim3(grid_of(N)), dim3(kBlock), 0, s, d->sources, N, box, k0, v0);
     TQ(hipGetLastError());
     TQ(rocprim::radix_sort_pairs(nullptr, need, k0, k1, v0, src_ord, (size_t)N, 0, 63, s));
     TQ(tmp_for(need));
     TQ(rocprim::radix_sort_pairs(tmp, need, k0, k1, v0, src_ord, (size_t)N, 0, 63, s));
     TQ(keep(&g->src_pos, N));
+    TQ(keep(&g->src_w, N));
     if (d->normals) TQ(keep(&g->src_nrm, N));
     TQ(keep(&g->src_perm, N));
     TQ(keep(&g->src_rank, N));
     hipLaunchKernelGGL(k_sources, dim3(grid_of(N)), dim3(kBlock), 0, s, src_ord, N, d->sources,
-                       d->weights, d->normals, g->src_pos, g->src_nrm, g->src_perm, g->src_rank);
+                       d->weights, d->normals, g->src_pos, g->src_w, g->src_nrm, g->src_perm,
+                       g->src_rank);
     TQ(hipGetLastError());
   }
 
@@ -426,7 +451,7 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
     TQ(sc.get(&flag, T));
     TQ(sc.get(&row_id, T));
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, s, d->centers, M, part);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, nbb, box);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kBlock), 0, s, part, nbb, box);
     hipLaunchKernelGGL(k_morton, dim3(grid_of(M)), dim3(kBlock), 0, s, d->centers, M, box, ckey,
                        (int32_t *)nullptr);
     hipLaunchKernelGGL(k_target_centers, dim3(grid_of(T)), dim3(kBlock), 0, s, d->target_center, T,
@@ -462,8 +487,10 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
   TQ(sc.get(&padlen, R));
   TQ(sc.get(&row_off, R + 1));
   TQ(hipMemsetAsync(row_off, 0, sizeof(int64_t), s));
-  int64_t nnz_dev = 0;
+  int64_t nnz_dev = 0, longest = 0;
   if (R > 0) {
+    int64_t *d_longest = nullptr;
+    TQ(sc.get(&d_longest, 1));
     hipLaunchKernelGGL(k_row_setup, dim3(grid_of(T)), dim3(kBlock), 0, s, tgt_ord, T,
                        d->target_center, flag, row_id, d->list_offsets,
                        row_center, row_first, padlen);
@@ -473,7 +500,13 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
     TQ(tmp_for(need));
     TQ(rocprim::inclusive_scan(tmp, need, padlen, row_off + 1, (size_t)R, rocprim::plus<int64_t>(),
                                s));
+    TQ(rocprim::reduce(nullptr, need, padlen, d_longest, int64_t(0), (size_t)R,
+                       rocprim::maximum<int64_t>(), s));
+    TQ(tmp_for(need));
+    TQ(rocprim::reduce(tmp, need, padlen, d_longest, int64_t(0), (size_t)R,
+                       rocprim::maximum<int64_t>(), s));
     TQ(hipMemcpyAsync(&nnz_dev, row_off + R, sizeof nnz_dev, hipMemcpyDeviceToHost, s));
+    TQ(hipMemcpyAsync(&longest, d_longest, sizeof longest, hipMemcpyDeviceToHost, s));
     TQ(hipStreamSynchronize(s));
   }
   g->nnz = nnz_dev;
@@ -481,19 +514,28 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
   TQ(keep(&g->idx, nnz_dev));
   if (nnz_dev > 0) {
     int32_t *buf = nullptr;
-    TQ(sc.get(&buf, nnz_dev));
-    hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)std::min<int64_t>(R, 1 << 20)), dim3(kBlock), 0,
-                       s, R, row_center, row_off, d->list_offsets, d->list_sources, g->src_rank,
-                       (int32_t)N, buf);
-    TQ(hipGetLastError());
-    // entries lie in [0, N]: sort them as unsigned keys on their low bits
-    const int ib = bits_for(N);
-    uint32_t *ub = (uint32_t *)buf, *uo = (uint32_t *)g->idx;
-    TQ(rocprim::segmented_radix_sort_keys(nullptr, need, ub, uo, (size_t)nnz_dev, (unsigned)R,
-                                          row_off, row_off + 1, 0, ib, s));
-    TQ(tmp_for(need));
-    TQ(rocprim::segmented_radix_sort_keys(tmp, need, ub, uo, (size_t)nnz_dev, (unsigned)R,
-                                          row_off, row_off + 1, 0, ib, s));
+    if (!(longest <= kRowSortMax && R <= INT32_MAX)) TQ(sc.get(&buf, nnz_dev));
+    if (longest <= kRowSortMax && R <= INT32_MAX) {
+      // rows short enough for one workgroup each: filled in place, sorted in LDS
+      hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)std::min<int64_t>(R, 1 << 20)),
+                         dim3(kBlock), 0, s, R, row_center, row_off, d->list_offsets,
+                         d->list_sources, g->src_rank, (int32_t)N, g->idx);
+      TQ(hipGetLastError());
+      TQ(sort_rows(row_off, g->idx, R, longest, N, s));
+    } else {
+      hipLaunchKernelGGL(k_fill_rows, dim3((unsigned)std::min<int64_t>(R, 1 << 20)),
+                         dim3(kBlock), 0, s, R, row_center, row_off, d->list_offsets,
+                         d->list_sources, g->src_rank, (int32_t)N, buf);
+      TQ(hipGetLastError());
+      // entries lie in [0, N]: sort them as unsigned keys on their low bits
+      const int ib = bits_for(N);
+      uint32_t *ub = (uint32_t *)buf, *uo = (uint32_t *)g->idx;
+      TQ(rocprim::segmented_radix_sort_keys(nullptr, need, ub, uo, (size_t)nnz_dev, (unsigned)R,
+                                            row_off, row_off + 1, 0, ib, s));
+      TQ(tmp_for(need));
+      TQ(rocprim::segmented_radix_sort_keys(tmp, need, ub, uo, (size_t)nnz_dev, (unsigned)R,
+                                            row_off, row_off + 1, 0, ib, s));
+    }
   }
 
   // per-target and per-row records
@@ -520,6 +562,8 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
   TQ(keep(&spos, stage_pos_bytes(N)));
   if (d->normals) TQ(keep(&snrm, stage_nrm_bytes(N)));
   g->stage = stage_views(spos, snrm, N);
+  // the positions and the padding entry, once: evaluations stage strengths only
+  TQ(launch_stage_positions(g, g->stage, s));
   TQ(hipStreamSynchronize(s));  // the scratch buffers are freed on return
   for (int64_t v : g->host_row_len) {
     g->pairs += v;

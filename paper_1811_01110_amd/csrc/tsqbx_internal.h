@@ -137,6 +137,7 @@ struct tsqbx_geometry {
   bool has_normals = false;
   bool has_target_normals = false;
   double4 *src_pos = nullptr;    // [N] (x, y, z, w) in device order
+  double *src_w = nullptr;       // [N] w in device order
   double4 *src_nrm = nullptr;    // [N] (nx, ny, nz, 0) or null
   int64_t *src_perm = nullptr;   // [N] device order -> caller index, null if identity
   int32_t *src_rank = nullptr;   // [N] caller index -> device order, null if identity
@@ -146,7 +147,7 @@ struct tsqbx_geometry {
   int64_t n_rows = 0;            // rows = distinct centers with targets
   tsqbx::CenterRec *ctr = nullptr;  // [n_rows]
   int32_t *row_tgts = nullptr;   // [T] device-order targets grouped by row
-  tsqbx::SourceStage stage;      // staging used by the plain path
+  tsqbx::SourceStage stage;      // staging used by the plain path (positions written at creation)
   // layers the last tsqbx_stage_async call staged for (0: none yet)
   mutable std::atomic<unsigned> staged_layers{0};
   tsqbx::HelmStage helm;         // Helmholtz staging, allocated on first use
@@ -174,8 +175,11 @@ int fail_hip(hipError_t e, const char *what);
   } while (0)
 
 // kernel launchers (tsqbx_eval.hip, tsqbx_stage.hip)
+// positions_ready: st already holds the positions and the padding entry
+// (launch_stage_positions), so only the strengths are written.
 hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned layers,
-                        const SourceStage &st, hipStream_t s);
+                        const SourceStage &st, bool positions_ready, hipStream_t s);
+hipError_t launch_stage_positions(const tsqbx_geometry *g, const SourceStage &st, hipStream_t s);
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
                        const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
 bool tuning_supported(const Tuning &tn);
@@ -195,8 +199,9 @@ hipError_t launch_helmholtz(const tsqbx_geometry *g, int p, unsigned layers, dou
                             bool accumulate, const Tuning &tn, hipStream_t s);
 
 // Staging of many items in one launch (batched and served paths).
-struct StageItem {         // 80 bytes
+struct StageItem {
   const double4 *pos_w;
+  const double *w;           // weights in device order
   const double4 *nrm;
   const void *order;         // host_sigma: rank (int32, caller -> device); else perm (int64)
   const double *sigma;       // caller order; device or pinned host memory
@@ -208,10 +213,12 @@ struct StageItem {         // 80 bytes
   int32_t want_dlp;
   int32_t host_sigma;        // 1: walk sources in caller order (contiguous reads of sigma)
   int64_t begin;             // first element of the item in the launch's index space
+  int32_t strengths_only;    // 1: positions and padding entry already in place
+  int32_t unused;
 };
-static_assert(sizeof(StageItem) == 88, "StageItem layout");
+static_assert(sizeof(StageItem) == 104, "StageItem layout");
 StageItem make_stage_item(const tsqbx_geometry *g, const double *sigma, unsigned layers,
-                          const SourceStage &st, bool sigma_on_host);
+                          const SourceStage &st, bool sigma_on_host, bool positions_ready);
 // Lay the items' n + 1 elements end to end, each item starting at a multiple
 // of kStageBlock, in begin; returns the total (a multiple of kStageBlock).
 constexpr int64_t kStageBlock = 256;
@@ -362,6 +369,13 @@ struct ScheduleItem {
 void build_schedule(const std::vector<ScheduleItem> &items, const std::vector<int32_t> &order,
                     int group_lanes, int max_waves, double step_cost, std::vector<WorkUnit> *units,
                     std::vector<int32_t> *wave_begin);
+
+// Sort every row of a CSR in place (tsqbx_lists.hip): M rows, the longest of
+// at most 8192 entries, every entry in [0, max_value].  hipErrorInvalidValue
+// for longer rows or larger values.
+hipError_t sort_rows(const int64_t *d_offsets, int32_t *d_indices, int64_t M, int64_t longest,
+                     int64_t max_value, hipStream_t s);
+constexpr int64_t kRowSortMax = 8192;
 
 // Free a geometry's device arrays and the geometry (null: nothing).
 void free_geometry(tsqbx_geometry *g);

@@ -26,7 +26,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
+
+#include <rocprim/block/block_radix_sort.hpp>
 
 #include "tsqbx_internal.h"
 
@@ -592,38 +595,33 @@ k_knn(const double *__restrict__ ctr, const int32_t *__restrict__ counts,
 }
 
 // ---- row sort --------------------------------------------------------------------
-constexpr int kSortMax = 8192;
-
-// CAP: the LDS capacity, at least the longest row (smaller capacities let
-// more workgroups share a CU).
-template <int CAP>
+// One workgroup per row whose length lies in (min_len, ITEMS x 256]: a
+// block-wide LSD radix sort of the row's entries in registers and LDS
+// (rocPRIM's block radix sort, 4 bits per pass), on the end_bit low bits
+// that hold every entry; padding keys (2^end_bit - 1, above every entry) sort
+// last and are not written back.  Rows of other lengths are left to the
+// launches of the other length classes.
+template <int ITEMS>
 __global__ void __launch_bounds__(256)
-k_row_sort(const int64_t *__restrict__ offsets, int32_t *__restrict__ idx) {
-  __shared__ int32_t s[CAP];
+k_row_sort(const int64_t *__restrict__ offsets, int32_t *__restrict__ idx, int end_bit,
+           int min_len) {
+  using Sort = rocprim::block_radix_sort<uint32_t, 256, ITEMS>;
+  __shared__ typename Sort::storage_type storage;
   const int64_t b = offsets[blockIdx.x];
-  const int len = (int)(offsets[blockIdx.x + 1] - b);
-  if (len <= 1) return;
-  int P = 1;
-  while (P < len) P <<= 1;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < len ? idx[b + i] : INT32_MAX;
-  __syncthreads();
-  // bitonic network over the P/2 compare-exchange pairs of each stage
-  const int half = P >> 1;
-  for (int k = 2; k <= P; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int q = threadIdx.x; q < half; q += blockDim.x) {
-        const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // lower index of pair q
-        const int l = i | j;
-        const int32_t x = s[i], y = s[l];
-        const bool up = (i & k) == 0;
-        if ((x > y) == up) {
-          s[i] = y;
-          s[l] = x;
-        }
-      }
-      __syncthreads();
-    }
-  for (int i = threadIdx.x; i < len; i += blockDim.x) idx[b + i] = s[i];
+  const int64_t len64 = offsets[blockIdx.x + 1] - b;
+  if (len64 <= min_len || len64 <= 1 || len64 > 256 * ITEMS) return;
+  const int len = (int)len64;
+  const uint32_t pad = (1u << end_bit) - 1u;
+  uint32_t k[ITEMS];
+  for (int j = 0; j < ITEMS; ++j) {  // blocked: thread t holds entries t ITEMS ..
+    const int i = (int)threadIdx.x * ITEMS + j;
+    k[j] = i < len ? (uint32_t)idx[b + i] : pad;
+  }
+  Sort().sort(k, storage, 0, (unsigned)end_bit);
+  for (int j = 0; j < ITEMS; ++j) {
+    const int i = (int)threadIdx.x * ITEMS + j;
+    if (i < len) idx[b + i] = (int32_t)k[j];
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -711,19 +709,6 @@ hipError_t build_grid(Grid &g, int64_t N, const double *d_sources, int64_t M,
   return hipGetLastError();
 }
 
-// Sorts every row of the CSR (rows of at most `longest` <= kSortMax entries).
-hipError_t sort_rows(const int64_t *d_offsets, int32_t *d_indices, int64_t M,
-                     unsigned long long longest, hipStream_t s) {
-  if (longest <= 512)
-    hipLaunchKernelGGL(k_row_sort<512>, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices);
-  else if (longest <= 2048)
-    hipLaunchKernelGGL(k_row_sort<2048>, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices);
-  else
-    hipLaunchKernelGGL(k_row_sort<kSortMax>, dim3((unsigned)M), dim3(256), 0, s, d_offsets,
-                       d_indices);
-  return hipGetLastError();
-}
-
 __global__ void __launch_bounds__(256)
 k_count_range(const int32_t *__restrict__ counts, int64_t m, int *__restrict__ out) {
   int mn = INT32_MAX, mx = INT32_MIN;
@@ -744,6 +729,25 @@ struct RestoreDevice {
 };
 
 }  // namespace
+
+hipError_t sort_rows(const int64_t *d_offsets, int32_t *d_indices, int64_t M,
+                     int64_t longest, int64_t max_value, hipStream_t s) {
+  if (M <= 0 || longest <= 1) return hipSuccess;
+  if (longest > kRowSortMax || M > INT32_MAX || max_value >= INT32_MAX) return hipErrorInvalidValue;
+  int end_bit = 1;  // 2^end_bit - 1 > max_value: the padding key sorts after every entry
+  while ((int64_t(1) << end_bit) - 1 <= max_value) ++end_bit;
+  // one launch per length class up to the longest row
+  hipLaunchKernelGGL(k_row_sort<2>, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices,
+                     end_bit, 0);
+  if (longest > 512)
+    hipLaunchKernelGGL(k_row_sort<8>, dim3((unsigned)M), dim3(256), 0, s, d_offsets, d_indices,
+                       end_bit, 512);
+  if (longest > 2048)
+    hipLaunchKernelGGL(k_row_sort<(int)(kRowSortMax / 256)>, dim3((unsigned)M), dim3(256), 0, s, d_offsets,
+                       d_indices, end_bit, 2048);
+  return hipGetLastError();
+}
+
 }  // namespace tsqbx
 
 using namespace tsqbx;
@@ -798,9 +802,9 @@ extern "C" int tsqbx_ball_lists(tsqbx_ctx *ctx, int64_t n_sources, const double 
   TSQBX_HIP(hipMemcpyAsync(&longest, maxrow.p, sizeof(longest), hipMemcpyDeviceToHost, s));
   TSQBX_HIP(hipStreamSynchronize(s));
   *nnz = total;
-  if ((int64_t)longest > kSortMax)
+  if ((int64_t)longest > kRowSortMax)
     return fail(TSQBX_E_RANGE, "a ball holds %llu sources; at most %d per center", longest,
-                kSortMax);
+                (int)kRowSortMax);
   if (total > capacity)
     return fail(TSQBX_E_RANGE, "the lists need %lld entries; capacity is %lld", (long long)total,
                 (long long)capacity);
@@ -809,7 +813,7 @@ extern "C" int tsqbx_ball_lists(tsqbx_ctx *ctx, int64_t n_sources, const double 
                        g.keys.p, g.mask, g.cell_start.p, g.counts.p, g.cell_pts.p, nullptr,
                        d_offsets, d_indices);
     TSQBX_HIP(hipGetLastError());
-    TSQBX_HIP(sort_rows(d_offsets, d_indices, M, longest, s));
+    TSQBX_HIP(sort_rows(d_offsets, d_indices, M, (int64_t)longest, N - 1, s));
   }
   TSQBX_HIP(hipStreamSynchronize(s));
   return TSQBX_OK;
@@ -841,7 +845,7 @@ extern "C" int tsqbx_knn_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *
     TSQBX_HIP(hipStreamSynchronize(s));
     return TSQBX_OK;
   }
-  // the counts: 0 <= k <= min(N, kSortMax)
+  // the counts: 0 <= k <= min(N, kRowSortMax)
   DevBuf<int> range;
   TSQBX_HIP(range.alloc(3));
   const int init[3] = {INT32_MAX, INT32_MIN, 0};
@@ -855,8 +859,8 @@ extern "C" int tsqbx_knn_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *
   if (got[0] < 0) return fail(TSQBX_E_RANGE, "a count is negative (%d)", got[0]);
   if ((int64_t)got[1] > N)
     return fail(TSQBX_E_RANGE, "a count (%d) exceeds n_sources = %lld", got[1], (long long)N);
-  if (got[1] > kSortMax)
-    return fail(TSQBX_E_RANGE, "a count (%d) exceeds %d per center", got[1], kSortMax);
+  if (got[1] > kRowSortMax)
+    return fail(TSQBX_E_RANGE, "a count (%d) exceeds %d per center", got[1], (int)kRowSortMax);
   Grid g;
   if (got[1] > 0) TSQBX_HIP(build_grid(g, N, d_sources, M, d_centers, 0.0, M, s));
   else TSQBX_HIP(g.scan_tmp.alloc((size_t)(M / kScanBlock + 2)));
@@ -873,7 +877,7 @@ extern "C" int tsqbx_knn_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *
                        g.gp.p, g.keys.p, g.mask, g.cell_start.p, g.counts.p, g.cell_pts.p,
                        d_indices, range.p + 2);
     TSQBX_HIP(hipGetLastError());
-    TSQBX_HIP(sort_rows(d_offsets, d_indices, M, (unsigned long long)got[1], s));
+    TSQBX_HIP(sort_rows(d_offsets, d_indices, M, (int64_t)got[1], N - 1, s));
     int bad = 0;
     TSQBX_HIP(hipMemcpyAsync(&bad, range.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     TSQBX_HIP(hipStreamSynchronize(s));

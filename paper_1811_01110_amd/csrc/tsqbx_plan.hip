@@ -415,7 +415,9 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
       pl->device_bytes += stage_nrm_bytes(N);
     }
     pl->stages[i] = stage_views(spos, snrm, N);
-    sitems[i] = make_stage_item(it.geom, it.d_sigma, it.layers, pl->stages[i], false);
+    // positions once; every execution stages the strengths only
+    if (e == hipSuccess) e = launch_stage_positions(it.geom, pl->stages[i], nullptr);
+    sitems[i] = make_stage_item(it.geom, it.d_sigma, it.layers, pl->stages[i], false, true);
     pl->max_sources = std::max<int64_t>(pl->max_sources, it.geom->n_sources);
     WorkItem &w = witems[i];
     w = WorkItem{};
@@ -433,6 +435,7 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
     w.layers = (int32_t)it.layers;
     w.accumulate = (flags & TSQBX_ACCUMULATE) ? 1 : 0;
   }
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);  // positions in place before any execution
   if (e == hipSuccess && n_items) e = hipMalloc((void **)&pl->d_items, n_items * sizeof(WorkItem));
   if (e == hipSuccess && n_items)
     e = hipMemcpy(pl->d_items, witems.data(), n_items * sizeof(WorkItem), hipMemcpyHostToDevice);

@@ -265,7 +265,7 @@ int tsqbx_server::launch(int stream, const std::vector<Job *> &jobs, std::string
         if (N) dma_up.emplace_back(d_sigma, r->sigma_src, N);
         sig = d_sigma;
       }
-      stage.push_back(make_stage_item(g, sig, r->layers, stg, host_pinned));
+      stage.push_back(make_stage_item(g, sig, r->layers, stg, host_pinned, false));
       WorkItem w{};
       w.tgt = g->tgt;
       w.idx = g->idx;

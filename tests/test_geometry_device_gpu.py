@@ -130,6 +130,14 @@ def test_unused_centers_empty_rows_and_coincident_points(ctx):
     _check(ctx, a, p=4, layers=3)
 
 
+def test_rows_longer_than_one_workgroup_sorts(ctx):
+    """Lists past 8192 entries (with repeated sources) take the segmented
+    sort instead of the per-row LDS sort; both give the host's rows."""
+    g = W.fuzz_geometry(315, n=20000, m=6, max_list=14000, p=4, layers=1, allow_empty=False)
+    assert np.diff(g.list_offsets).max() > 8192
+    _check(ctx, _arrays(g, target_normals=False), p=4, layers=3)
+
+
 def test_config_a_full_size(ctx):
     g = cached_workload("config_a")
     gh, gd, sigma = _check(ctx, _arrays(g, target_normals=False), p=16, layers=3)
