@@ -254,16 +254,27 @@ def plan_flops(items, helm=False):
     return sum(it["geom"].pairs * flops_per_pair(it["p"], it["layers"]) for it in items)
 
 
+# --plan-tuning: one fixed plan tuning instead of the autotuner (for counter
+# runs, whose passes must all time the same launch shape)
+FIXED_PLAN_TUNING = None
+
+
 def tune_and_profile(plan, steps, label):
     """Per-kernel times of the plan with its default tuning, then the plan
-    autotuner's choice and the per-kernel times with it."""
+    autotuner's choice (or the fixed --plan-tuning) and the per-kernel times
+    with it."""
     reps = max(steps // 2, 5)
     default = plan.get_tuning()
     log(f"{label}: profiling the default tuning {default}")
     prof0 = plan.profile(reps)
-    log(f"{label}: autotuning the plan")
     t0 = time.perf_counter()
-    tuned, _ = plan.autotune()
+    if FIXED_PLAN_TUNING is not None:
+        log(f"{label}: fixed tuning {FIXED_PLAN_TUNING}")
+        plan.set_tuning(**FIXED_PLAN_TUNING)
+        tuned = plan.get_tuning()
+    else:
+        log(f"{label}: autotuning the plan")
+        tuned, _ = plan.autotune()
     tune_s = time.perf_counter() - t0
     log(f"{label}: tuned {tuned}; profiling it")
     prof1 = plan.profile(reps)
@@ -903,7 +914,7 @@ def calibration_copy(torch):
 
 
 def main():
-    global MIN_WARM_S
+    global MIN_WARM_S, FIXED_PLAN_TUNING
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -919,6 +930,9 @@ def main():
     ap.add_argument("--no-helmholtz", action="store_true")
     ap.add_argument("--no-lists", action="store_true")
     ap.add_argument("--no-conventional", action="store_true")
+    ap.add_argument("--plan-tuning", default=None,
+                    help="fixed plan tuning instead of the autotuner, e.g. group_lanes=16,unroll=2,"
+                         "waves_per_block=2,oversubscription=16,step_cost=1000")
     ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime",
                                        "helmholtz", "helm_batched", "lists", "conventional"],
                     help="run one section (for profiling); the JSON line then carries only it")
@@ -926,6 +940,9 @@ def main():
                     help="run a 256 MiB device copy first (for counter calibration)")
     args = ap.parse_args()
     MIN_WARM_S = args.min_warm
+    if args.plan_tuning:
+        FIXED_PLAN_TUNING = {k: int(v) for k, v in
+                             (kv.split("=") for kv in args.plan_tuning.split(","))}
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the evaluation shards by "
               "targets across GPUs, and this benchmark measures one GPU", file=sys.stderr)
