@@ -158,6 +158,7 @@ static size_t request_bytes_helm(const tsqbx_geometry *g, int p, unsigned layers
 // and outputs are written back by one copy kernel; only requests whose host
 // staging had to fall back to pageable memory use DMA copies.
 int tsqbx_server::launch(int stream, const std::vector<Job *> &jobs, std::string &err) {
+  TraceRange trace_("tsqbx server step launch");
   StreamSlot &ss = strm[stream];
   hipStream_t s = ss.s;
   hipError_t e = hipSuccess;
