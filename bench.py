@@ -489,14 +489,38 @@ def bench_serve(ctx, api, torch, W, n_requests):
     plain_rate, plain_rps = sum(per_req[:k0]) / dt, k0 / dt
     # saturation: everything submitted at once, after one untimed pass (the
     # first launches of the step kernels load their code)
+    def saturation_pass(tuning=None):
+        srv = ctx.server(budget, SERVE_SLOTS)
+        if tuning:
+            srv.set_tuning(**tuning)
+        t0 = time.perf_counter()
+        for r, s_, o in zip(reqs, sig, outs):
+            a, b = out_args(r, o)
+            srv.submit_pinned(gs[r.geometry], s_, r.p, r.layers, out_slp=a, out_dlp=b)
+        srv.drain(600)
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return dt, st
+
     log("serving: untimed warm-up pass")
+    saturation_pass()
+    log("serving: saturation pass at the default tuning")
+    default_s, _ = saturation_pass()
+    # the server autotuner on bursts of the same request mix
     srv = ctx.server(budget, SERVE_SLOTS)
-    for r, s_, o in zip(reqs, sig, outs):
-        a, b = out_args(r, o)
-        srv.submit_pinned(gs[r.geometry], s_, r.p, r.layers, out_slp=a, out_dlp=b)
-    srv.drain(600)
+    default_tuning = srv.get_tuning()
+    log("serving: autotuning the server")
+    t0 = time.perf_counter()
+    tuned, burst_ms = srv.autotune([(gs[r.geometry], r.p, r.layers) for r in reqs],
+                                   n_requests=len(reqs))
+    tune_s = time.perf_counter() - t0
     srv.close()
+    log(f"serving: tuned {tuned}")
+    serve_tuning = {"default": default_tuning, "default_saturation_rps": len(reqs) / default_s,
+                    "tuned": tuned, "autotune_s": tune_s, "tuned_burst_ms": burst_ms}
     srv = ctx.server(budget, SERVE_SLOTS)
+    srv.set_tuning(**tuned)
     log("serving: saturation run (pinned submissions)")
     t0 = time.perf_counter()
     for r, s_, o in zip(reqs, sig, outs):
@@ -509,6 +533,7 @@ def bench_serve(ctx, api, torch, W, n_requests):
     srv.close()
     # the copying submission path at saturation, for reference
     srv = ctx.server(budget, SERVE_SLOTS)
+    srv.set_tuning(**tuned)
     k1 = min(len(reqs), 600)
     t0 = time.perf_counter()
     for r, s_ in zip(reqs[:k1], sig[:k1]):
@@ -521,6 +546,7 @@ def bench_serve(ctx, api, torch, W, n_requests):
         rate = factor * sat_rps
         arrivals = np.array([r.arrival_s for r in reqs]) / rate  # unit-rate schedule scaled
         srv = ctx.server(budget, SERVE_SLOTS)
+        srv.set_tuning(**tuned)
         log(f"serving: Poisson stream at {rate:.0f} requests/s ({factor}x saturation)")
         t0 = time.perf_counter()
         for r, s_, o, ta in zip(reqs, sig, outs, arrivals):
@@ -549,6 +575,7 @@ def bench_serve(ctx, api, torch, W, n_requests):
     sat_stats = st_sat
     return {
         "helmholtz": helm,
+        "tuning": serve_tuning,
         "workload": f"{n_requests} requests, Poisson arrivals at 0.7x saturation, 32 resident "
                     "geometries N log-uniform 4096..262144, p in {8,16}, single or double layer, "
                     "densities and outputs in pinned host memory",

@@ -78,6 +78,14 @@ class PlanTuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerTuning(ctypes.Structure):
+    _fields_ = [("group_lanes", c_int), ("unroll", c_int), ("waves_per_block", c_int),
+                ("unit_steps", c_int), ("step_requests", c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanTiming(ctypes.Structure):
     _fields_ = [("stage_ms", c_double), ("eval_ms", c_double), ("reps", c_int)]
 
@@ -170,6 +178,10 @@ _SIGNATURES = {
     "tsqbx_server_wait": (c_int, [c_void_p, c_uint64, c_double]),
     "tsqbx_server_drain": (c_int, [c_void_p, c_double]),
     "tsqbx_server_cancel": (c_int, [c_void_p, c_uint64]),
+    "tsqbx_server_get_tuning": (c_int, [c_void_p, P(ServerTuning)]),
+    "tsqbx_server_set_tuning": (c_int, [c_void_p, P(ServerTuning)]),
+    "tsqbx_server_autotune": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int,
+                                      P(ServerTuning), P(c_double)]),
     "tsqbx_server_get_stats": (c_int, [c_void_p, P(ServerStats)]),
     "tsqbx_server_destroy": (c_int, [c_void_p]),
 }

@@ -692,6 +692,32 @@ class Server:
         _check(_lib().tsqbx_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s)))
         return self._live.pop(ticket, (None, None, None))[:3]
 
+    def get_tuning(self) -> dict:
+        t = L.ServerTuning()
+        _check(_lib().tsqbx_server_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **tuning) -> None:
+        """Only before the first submission (TSQBX_E_STATE after it)."""
+        cur = self.get_tuning()
+        cur.update(tuning)
+        t = L.ServerTuning(**cur)
+        _check(_lib().tsqbx_server_set_tuning(self.handle, ctypes.byref(t)))
+
+    def autotune(self, requests, n_requests: int = 256):
+        """requests: sequence of (geometry, p, layers) cycled over by the
+        synthetic bursts.  Returns (tuning dict, best burst ms)."""
+        n = len(requests)
+        geoms = (ctypes.c_void_p * n)(*[g.handle for g, _, _ in requests])
+        ps = np.array([p for _, p, _ in requests], dtype=np.int32)
+        ls = np.array([l for _, _, l in requests], dtype=np.uint32)
+        t = L.ServerTuning()
+        ms = ctypes.c_double()
+        _check(_lib().tsqbx_server_autotune(self.handle, n, ctypes.cast(geoms, ctypes.c_void_p),
+                                            _ptr(ps), _ptr(ls),
+                                            int(n_requests), ctypes.byref(t), ctypes.byref(ms)))
+        return t.as_dict(), ms.value
+
     def cancel(self, ticket: int):
         """Withdraw a request that is still queued; it then ends with
         TSQBX_E_CANCELED (wait raises it)."""

@@ -31,11 +31,11 @@ using namespace tsqbx;
 namespace {
 
 constexpr int kStreams = 4;
-constexpr int kUnitSteps = 8;  // wave-steps (group_lanes-wide passes) per unit
+constexpr int kUnitSteps = 8;  // default wave-steps (group_lanes-wide passes) per unit
 // Requests per step: small enough that the next step's density reads (PCIe)
 // overlap this step's evaluation on another stream, large enough to amortise
 // the step's launches.
-constexpr int kMaxStepRequests = 32;
+constexpr int kMaxStepRequests = 32;  // the default
 constexpr size_t kAlign = 256;
 // Completed requests whose status stays queryable (poll, wait); older ones
 // are forgotten, so that a long-running server holds bounded host memory.
@@ -79,7 +79,13 @@ struct tsqbx_server final : public Executor {
   tsqbx_ctx *ctx = nullptr;
   int device = 0;
   size_t budget = 0;
+  int max_slots = 1;
+  // launch shape and step shape, fixed once a caller's request has been
+  // submitted (a request's bits depend on the group width only)
   Tuning tn;
+  int unit_steps = kUnitSteps;
+  int step_requests = kMaxStepRequests;
+  std::atomic<bool> used{false};
   char *arena_base = nullptr;
   char *pinned_base = nullptr;  // pinned host arena for densities and outputs
   size_t pinned_cap = 0;
@@ -112,6 +118,21 @@ struct tsqbx_server final : public Executor {
         }
     }
     return TSQBX_OK;
+  }
+  SchedLimits limits() const {
+    SchedLimits lim;
+    lim.budget = budget;
+    lim.max_slots = max_slots;
+    lim.max_step_jobs = step_requests;
+    lim.keep_done = kKeepDone;
+    lim.lat_window = kLatWindow;
+    return lim;
+  }
+  // A fresh scheduler with the current limits (the old one idle).
+  void restart_scheduler() {
+    if (sched) sched->stop();
+    sched = std::make_unique<Scheduler>(this, limits());
+    sched->start();
   }
   void release(Job *job) override {
     Request *r = static_cast<Request *>(job);
@@ -182,7 +203,7 @@ int tsqbx_server::launch(int stream, const std::vector<Job *> &jobs, std::string
   int p_all = -1;
   unsigned h_first = 0;
   bool h_same = true;
-  const int64_t per_unit = (int64_t)kUnitSteps * (64 / tn.group_lanes);
+  const int64_t per_unit = (int64_t)unit_steps * (64 / tn.group_lanes);
   for (size_t i = 0; i < K; ++i) {
     Request *r = static_cast<Request *>(jobs[i]);
     const tsqbx_geometry *g = r->geom;
@@ -408,8 +429,10 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   sv->ctx = ctx;
   sv->device = ctx->device;
   sv->budget = hbm_budget / kAlign * kAlign;
-  // one launch shape for the server's lifetime (near-field lists of a few
-  // hundred sources); a request's result then does not depend on its step
+  sv->max_slots = max_slots;
+  // one launch shape for the server's lifetime (by default that of near-field
+  // lists of a few hundred sources); a request's result then does not
+  // depend on its step
   sv->tn = default_tuning(16, 3u, 256);
   hipError_t e = hipMalloc((void **)&sv->arena_base, sv->budget);
   // pinned host arena: densities and outputs of queued and running requests
@@ -434,14 +457,7 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
     if (prev >= 0) (void)hipSetDevice(prev);
     return fail_hip(e, "server setup");
   }
-  SchedLimits lim;
-  lim.budget = sv->budget;
-  lim.max_slots = max_slots;
-  lim.max_step_jobs = kMaxStepRequests;
-  lim.keep_done = kKeepDone;
-  lim.lat_window = kLatWindow;
-  sv->sched = std::make_unique<Scheduler>(sv, lim);
-  sv->sched->start();
+  sv->restart_scheduler();
   if (prev >= 0) (void)hipSetDevice(prev);
   *out = sv;
   return TSQBX_OK;
@@ -458,10 +474,12 @@ static bool is_pinned_host(const void *p) {
 }
 
 // k > 0: a Helmholtz request (complex density and outputs, interleaved).
+// internal: a request of the autotuner (does not fix the tuning).
 static int submit_impl(tsqbx_server *sv, const tsqbx_geometry *geom, int p, unsigned layers,
                        double k, const double *sigma_host, double *const out_host[3],
-                       uint64_t *ticket, bool borrow) {
+                       uint64_t *ticket, bool borrow, bool internal = false) {
   if (!sv || !geom || !ticket) return fail(TSQBX_E_INVALID, "server, geometry or ticket is NULL");
+  if (!internal) sv->used = true;
   if (geom->ctx != sv->ctx) return fail(TSQBX_E_INVALID, "geometry belongs to another context");
   const bool helm = k != 0.0;
   int rc = helm ? check_helmholtz_request(geom, p, layers, k) : tsqbx_check_request(geom, p, layers);
@@ -549,6 +567,161 @@ int tsqbx_server_submit_helmholtz_pinned(tsqbx_server *sv, const tsqbx_geometry 
   if (!(k > 0.0)) return fail(TSQBX_E_RANGE, "the wavenumber k = %g must be positive and finite", k);
   double *const outs[3] = {out_slp_host, out_dlp_host, out_sprime_host};
   return submit_impl(sv, geom, p, layers, k, sigma_host, outs, ticket, true);
+}
+
+int tsqbx_server_get_tuning(tsqbx_server *sv, tsqbx_server_tuning *out) {
+  if (!sv || !out) return fail(TSQBX_E_INVALID, "server or out is NULL");
+  out->group_lanes = sv->tn.group_lanes;
+  out->unroll = sv->tn.unroll;
+  out->waves_per_block = sv->tn.waves_per_block;
+  out->unit_steps = sv->unit_steps;
+  out->step_requests = sv->step_requests;
+  return TSQBX_OK;
+}
+
+static int check_server_tuning(const tsqbx_server_tuning *t) {
+  Tuning tn;
+  tn.group_lanes = t->group_lanes;
+  tn.unroll = t->unroll;
+  tn.waves_per_block = t->waves_per_block;
+  tn.xcd_remap = 1;
+  if (!tuning_supported(tn))
+    return fail(TSQBX_E_RANGE, "unsupported launch shape (group_lanes %d, unroll %d, waves %d)",
+                t->group_lanes, t->unroll, t->waves_per_block);
+  if (t->unit_steps < 1 || t->unit_steps > 64 || t->step_requests < 1 || t->step_requests > 256)
+    return fail(TSQBX_E_RANGE, "unit_steps must lie in [1, 64] and step_requests in [1, 256]");
+  return TSQBX_OK;
+}
+
+// Install a tuning on an idle server (caller holds no request in it).
+static void apply_server_tuning(tsqbx_server *sv, const tsqbx_server_tuning &t) {
+  sv->tn.group_lanes = t.group_lanes;
+  sv->tn.unroll = t.unroll;
+  sv->tn.waves_per_block = t.waves_per_block;
+  sv->tn.xcd_remap = 1;
+  sv->unit_steps = t.unit_steps;
+  sv->step_requests = t.step_requests;
+  sv->restart_scheduler();
+}
+
+int tsqbx_server_set_tuning(tsqbx_server *sv, const tsqbx_server_tuning *t) {
+  if (!sv || !t) return fail(TSQBX_E_INVALID, "server or tuning is NULL");
+  if (sv->used) return fail(TSQBX_E_STATE, "the server has taken requests; its tuning is fixed");
+  int rc = check_server_tuning(t);
+  if (rc != TSQBX_OK) return rc;
+  apply_server_tuning(sv, *t);
+  return TSQBX_OK;
+}
+
+int tsqbx_server_autotune(tsqbx_server *sv, int64_t n, const tsqbx_geometry *const *geoms,
+                          const int *p, const unsigned *layers, int n_requests,
+                          tsqbx_server_tuning *out, double *best_ms) {
+  TraceRange trace_("tsqbx_server_autotune");
+  if (!sv || n <= 0 || !geoms || !p || !layers || n_requests <= 0)
+    return fail(TSQBX_E_INVALID, "server, geometries, orders or layers missing, or no requests");
+  if (sv->used) return fail(TSQBX_E_STATE, "the server has taken requests; its tuning is fixed");
+  int64_t max_n = 1, max_t = 1;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!geoms[i] || geoms[i]->ctx != sv->ctx)
+      return fail(TSQBX_E_INVALID, "geometry %lld is NULL or of another context", (long long)i);
+    int rc = tsqbx_check_request(geoms[i], p[i], layers[i]);
+    if (rc != TSQBX_OK) return rc;
+    size_t b = 0;
+    tsqbx_server_request_bytes(geoms[i], layers[i], &b);
+    if (b > sv->budget) return fail(TSQBX_E_BUDGET, "request %lld can never fit the budget", (long long)i);
+    max_n = std::max<int64_t>(max_n, geoms[i]->n_sources);
+    max_t = std::max<int64_t>(max_t, geoms[i]->n_targets);
+  }
+  // densities of ones and throw-away outputs in pinned host memory (the
+  // requests' results are not kept, so they may share them)
+  double *h_sigma = nullptr, *h_out = nullptr;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  TSQBX_HIP(hipSetDevice(sv->device));
+  struct Free {
+    double **a, **b;
+    int prev;
+    ~Free() {
+      if (*a) (void)hipHostFree(*a);
+      if (*b) (void)hipHostFree(*b);
+      if (prev >= 0) (void)hipSetDevice(prev);
+    }
+  } fr{&h_sigma, &h_out, prev};
+  TSQBX_HIP(hipHostMalloc((void **)&h_sigma, (size_t)max_n * sizeof(double), 0));
+  TSQBX_HIP(hipHostMalloc((void **)&h_out, 3 * (size_t)max_t * sizeof(double), 0));
+  for (int64_t i = 0; i < max_n; ++i) h_sigma[i] = 1.0;
+  auto burst = [&](int count, double *ms) -> int {
+    const double t0 = sched_now_s();
+    for (int r = 0; r < count; ++r) {
+      const int64_t i = r % n;
+      double *const outs[3] = {h_out, h_out + max_t, h_out + 2 * max_t};
+      uint64_t tk = 0;
+      int rc = submit_impl(sv, geoms[i], p[i], layers[i], 0.0, h_sigma, outs, &tk, true, true);
+      if (rc != TSQBX_OK) return rc;
+    }
+    if (sv->sched->drain(600.0) != TSQBX_OK)
+      return fail(TSQBX_E_TIMEOUT, "autotune burst did not finish");
+    *ms = (sched_now_s() - t0) * 1e3;
+    return TSQBX_OK;
+  };
+  tsqbx_server_tuning cur{};
+  tsqbx_server_get_tuning(sv, &cur);
+  // best of two bursts per candidate, after a warm-up burst
+  auto time_of = [&](const tsqbx_server_tuning &t, double *ms) -> int {
+    apply_server_tuning(sv, t);
+    double a = 0, b = 0, w = 0;
+    int rc = burst(std::min(n_requests, 64), &w);
+    if (rc == TSQBX_OK) rc = burst(n_requests, &a);
+    if (rc == TSQBX_OK) rc = burst(n_requests, &b);
+    *ms = std::min(a, b);
+    return rc;
+  };
+  // a candidate replaces the best only when clearly faster: burst times vary
+  // by a few per cent from run to run
+  constexpr double kTuneMargin = 0.97;
+  double best = 0;
+  int rc = time_of(cur, &best);
+  tsqbx_server_tuning best_t = cur;
+  // one field at a time, each from the best so far
+  const int gu[3][2] = {{16, 2}, {32, 2}, {64, 2}};
+  for (int k = 0; k < 3 && rc == TSQBX_OK; ++k) {
+    tsqbx_server_tuning t = best_t;
+    t.group_lanes = gu[k][0];
+    t.unroll = gu[k][1];
+    if (t.group_lanes == best_t.group_lanes && t.unroll == best_t.unroll) continue;
+    double ms = 0;
+    rc = time_of(t, &ms);
+    if (rc == TSQBX_OK && ms < kTuneMargin * best) best = ms, best_t = t;
+  }
+  for (int w : {1, 2, 4}) {
+    if (rc != TSQBX_OK || w == best_t.waves_per_block) continue;
+    tsqbx_server_tuning t = best_t;
+    t.waves_per_block = w;
+    double ms = 0;
+    rc = time_of(t, &ms);
+    if (rc == TSQBX_OK && ms < kTuneMargin * best) best = ms, best_t = t;
+  }
+  for (int u : {4, 8, 16}) {
+    if (rc != TSQBX_OK || u == best_t.unit_steps) continue;
+    tsqbx_server_tuning t = best_t;
+    t.unit_steps = u;
+    double ms = 0;
+    rc = time_of(t, &ms);
+    if (rc == TSQBX_OK && ms < kTuneMargin * best) best = ms, best_t = t;
+  }
+  for (int q : {16, 32, 64}) {
+    if (rc != TSQBX_OK || q == best_t.step_requests) continue;
+    tsqbx_server_tuning t = best_t;
+    t.step_requests = q;
+    double ms = 0;
+    rc = time_of(t, &ms);
+    if (rc == TSQBX_OK && ms < kTuneMargin * best) best = ms, best_t = t;
+  }
+  apply_server_tuning(sv, rc == TSQBX_OK ? best_t : cur);  // fresh statistics too
+  if (rc != TSQBX_OK) return rc;
+  if (out) *out = best_t;
+  if (best_ms) *best_ms = best;
+  return TSQBX_OK;
 }
 
 int tsqbx_server_poll(tsqbx_server *sv, uint64_t ticket, int *done) {

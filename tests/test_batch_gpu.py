@@ -183,6 +183,58 @@ def test_server_cancels_a_queued_request(ctx):
     geom.close()
 
 
+def test_server_autotune_and_tuning_rules():
+    """The server autotuner installs a tuning; results then equal plain
+    launches at the same group width bit for bit and match the oracle; the
+    tuning is fixed once a request has been submitted.  (A context of its
+    own: the plain-path tunings it sets stay out of the other tests.)"""
+    ctx = api.Context(0)
+    g1 = W.fuzz_geometry(402, n=3000, m=400, max_list=120, p=8, layers=3)
+    g2 = W.fuzz_geometry(403, n=1500, m=200, max_list=60, p=4, layers=1)
+    gg1, gg2 = ctx.geometry(g1), ctx.geometry(g2)
+    budget = 16 * max(api.Server.request_bytes(gg1, 3), api.Server.request_bytes(gg2, 1))
+    srv = ctx.server(budget, 16)
+    assert srv.get_tuning() == {"group_lanes": 16, "unroll": 2, "waves_per_block": 4,
+                                "unit_steps": 8, "step_requests": 32}
+    tuning, ms = srv.autotune([(gg1, 8, 3), (gg2, 4, 1)], n_requests=48)
+    assert ms > 0 and tuning == srv.get_tuning()
+    assert srv.stats()["submitted"] == 0  # the bursts leave no trace
+    t, a, b, _ = srv.submit(gg1, g1.sigma, 8, 3)
+    srv.wait(t)
+    ref = oracle.evaluate_geometry(g1, p=8, layers=3)
+    assert_parity(a, ref["slp"], ref["abs_slp"], what="tuned server slp")
+    assert_parity(b, ref["dlp"], ref["abs_dlp"], what="tuned server dlp")
+    mean_list = max(1, -(-gg1.pairs // gg1.n_targets))
+    ctx.set_tuning(8, 3, mean_list, group_lanes=tuning["group_lanes"],
+                   unroll=tuning["unroll"], waves_per_block=4, xcd_remap=1)
+    pa, pb, _ = ctx.eval(gg1, g1.sigma, 8, 3)
+    assert np.array_equal(a, pa) and np.array_equal(b, pb)
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.set_tuning(group_lanes=64)
+    assert ei.value.code == -6
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.autotune([(gg1, 8, 3)], n_requests=8)
+    assert ei.value.code == -6
+    srv.close()
+    # a chosen tuning on a fresh server; a bad one is refused
+    srv = ctx.server(budget, 16)
+    with pytest.raises(api.TsqbxError) as ei:
+        srv.set_tuning(group_lanes=8)
+    assert ei.value.code == -2
+    srv.set_tuning(group_lanes=64, unroll=2, waves_per_block=2, unit_steps=4, step_requests=16)
+    ts = [srv.submit(gg2, g2.sigma, 4, 1) for _ in range(5)]
+    srv.drain(60)
+    ctx.set_tuning(4, 1, max(1, -(-gg2.pairs // gg2.n_targets)), group_lanes=64, unroll=2,
+                   waves_per_block=4, xcd_remap=1)
+    pa, _, _ = ctx.eval(gg2, g2.sigma, 4, 1)
+    for _, o, _b, _t in ts:
+        assert np.array_equal(o, pa)
+    srv.close()
+    gg1.close()
+    gg2.close()
+    ctx.close()
+
+
 def test_server_pinned_submissions_match_copying_ones(ctx):
     import torch
 
