@@ -503,34 +503,24 @@ def bench_serve(ctx, api, torch, W, n_requests):
         srv.close()
         return dt, st
 
-    log("serving: untimed warm-up pass")
-    saturation_pass()
-    log("serving: saturation pass at the default tuning")
-    default_s, _ = saturation_pass()
-    # the server autotuner on bursts of the same request mix
+    # the server autotuner on bursts of the same request mix and densities
     srv = ctx.server(budget, SERVE_SLOTS)
     default_tuning = srv.get_tuning()
     log("serving: autotuning the server")
     t0 = time.perf_counter()
     tuned, burst_ms = srv.autotune([(gs[r.geometry], r.p, r.layers) for r in reqs],
-                                   n_requests=len(reqs))
+                                   n_requests=len(reqs), sigmas=sig)
     tune_s = time.perf_counter() - t0
     srv.close()
     log(f"serving: tuned {tuned}")
-    serve_tuning = {"default": default_tuning, "default_saturation_rps": len(reqs) / default_s,
-                    "tuned": tuned, "autotune_s": tune_s, "tuned_burst_ms": burst_ms}
-    srv = ctx.server(budget, SERVE_SLOTS)
-    srv.set_tuning(**tuned)
-    log("serving: saturation run (pinned submissions)")
-    t0 = time.perf_counter()
-    for r, s_, o in zip(reqs, sig, outs):
-        a, b = out_args(r, o)
-        srv.submit_pinned(gs[r.geometry], s_, r.p, r.layers, out_slp=a, out_dlp=b)
-    srv.drain(600)
-    sat_s = time.perf_counter() - t0
+    serve_tuning = {"default": default_tuning, "tuned": tuned, "autotune_s": tune_s,
+                    "tuned_burst_ms": burst_ms}
+    log("serving: untimed warm-up pass")
+    saturation_pass(tuned)
+    log("serving: three timed saturation passes (pinned submissions)")
+    passes = [saturation_pass(tuned) for _ in range(3)]
+    sat_s, st_sat = sorted(passes, key=lambda x: x[0])[1]  # the median pass
     sat_rps = len(reqs) / sat_s
-    st_sat = srv.stats()
-    srv.close()
     # the copying submission path at saturation, for reference
     srv = ctx.server(budget, SERVE_SLOTS)
     srv.set_tuning(**tuned)
@@ -581,6 +571,7 @@ def bench_serve(ctx, api, torch, W, n_requests):
                     "densities and outputs in pinned host memory",
         "offered_rps": rate,
         "saturation_rps": sat_rps,
+        "saturation_rps_passes": [len(reqs) / p_[0] for p_ in passes],
         "served_pair_terms_per_s": st["pair_terms_completed"] / wall,
         "saturation_pair_terms_per_s": sum(per_req) / sat_s,
         "plain_sequential_pair_terms_per_s": plain_rate,

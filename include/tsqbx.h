@@ -601,31 +601,36 @@ int tsqbx_server_wait(tsqbx_server *srv, uint64_t ticket, double timeout_s);
 int tsqbx_server_drain(tsqbx_server *srv, double timeout_s);
 /* The server's launch and step shape: the persistent kernel's group width
  * and pairs in flight per lane (16/2, 32/2, 64/1 or 64/2) and waves per
- * block (1, 2 or 4), the wave-steps per work unit (1..64) and the requests
- * per step (1..256).  A request's result depends on group_lanes only.  The
- * defaults: 16, 2, 4, 8, 32. */
+ * block (1, 2 or 4), the wave-steps per work unit (1..64), the requests per
+ * step (1..256), and dma_min_sources: densities in pinned memory of
+ * geometries with at least this many sources are uploaded by DMA instead of
+ * being read by the staging kernel over PCIe (0: never).  A request's result
+ * depends on group_lanes only.  The defaults: 16, 2, 4, 8, 32, 0. */
 typedef struct {
   int group_lanes, unroll, waves_per_block;
   int unit_steps, step_requests;
+  int64_t dma_min_sources;
 } tsqbx_server_tuning;
 int tsqbx_server_get_tuning(tsqbx_server *srv, tsqbx_server_tuning *out);
 /* Install a tuning; only before the first submission (TSQBX_E_STATE after
  * it, so that every request of a server is summed with one group width);
  * TSQBX_E_RANGE for an unsupported shape. */
 int tsqbx_server_set_tuning(tsqbx_server *srv, const tsqbx_server_tuning *tuning);
-/* Time candidate tunings on synthetic bursts of n_requests requests cycling
- * over the n (geometry, order, layer mask) triples, with densities of ones
- * (the same request path as tsqbx_server_submit_pinned; results discarded):
- * one field at a time from the best so far (group width and pairs in flight,
- * then waves per block {1, 2, 4}, unit steps {4, 8, 16}, requests per step
- * {16, 32, 64}), best of two bursts each after a warm-up burst, a candidate
- * replacing the best only when 3 % faster.  Installs the result, returns it
- * in *out and its burst time in *best_ms (both
+/* Time candidate tunings on bursts of n_requests requests cycling over the
+ * n (geometry, order, layer mask, density) tuples (the path of
+ * tsqbx_server_submit_pinned; results discarded): one field at a time from
+ * the best so far (group width and pairs in flight, then waves per block
+ * {1, 2, 4}, unit steps {4, 8, 16}, requests per step {16, 32, 64}), best of
+ * two bursts each after a warm-up burst, a candidate replacing the best only
+ * when 3 % faster.  sigmas: n densities in pinned host memory (the caller's
+ * own, so that reads over PCIe cost what they will), or NULL for densities
+ * of ones in one shared buffer.  dma_min_sources is left as it is.  Installs
+ * the result, returns it in *out and its burst time in *best_ms (both
  * nullable), and resets the statistics.  Only before the first submission
  * (TSQBX_E_STATE), and not concurrently with submissions on this server. */
 int tsqbx_server_autotune(tsqbx_server *srv, int64_t n, const tsqbx_geometry *const *geoms,
-                          const int *p, const unsigned *layers, int n_requests,
-                          tsqbx_server_tuning *out, double *best_ms);
+                          const int *p, const unsigned *layers, const double *const *sigmas,
+                          int n_requests, tsqbx_server_tuning *out, double *best_ms);
 /* Withdraw a request that is still queued (not yet admitted to a step): it
  * completes with TSQBX_E_CANCELED, its outputs untouched, and counts as
  * failed.  TSQBX_E_STATE once it has been admitted or has ended,

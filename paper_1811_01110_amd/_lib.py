@@ -80,7 +80,7 @@ class PlanTuning(ctypes.Structure):
 
 class ServerTuning(ctypes.Structure):
     _fields_ = [("group_lanes", c_int), ("unroll", c_int), ("waves_per_block", c_int),
-                ("unit_steps", c_int), ("step_requests", c_int)]
+                ("unit_steps", c_int), ("step_requests", c_int), ("dma_min_sources", c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -180,8 +180,8 @@ _SIGNATURES = {
     "tsqbx_server_cancel": (c_int, [c_void_p, c_uint64]),
     "tsqbx_server_get_tuning": (c_int, [c_void_p, P(ServerTuning)]),
     "tsqbx_server_set_tuning": (c_int, [c_void_p, P(ServerTuning)]),
-    "tsqbx_server_autotune": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int,
-                                      P(ServerTuning), P(c_double)]),
+    "tsqbx_server_autotune": (c_int, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_int, P(ServerTuning), P(c_double)]),
     "tsqbx_server_get_stats": (c_int, [c_void_p, P(ServerStats)]),
     "tsqbx_server_destroy": (c_int, [c_void_p]),
 }

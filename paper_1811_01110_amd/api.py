@@ -704,17 +704,24 @@ class Server:
         t = L.ServerTuning(**cur)
         _check(_lib().tsqbx_server_set_tuning(self.handle, ctypes.byref(t)))
 
-    def autotune(self, requests, n_requests: int = 256):
+    def autotune(self, requests, n_requests: int = 256, sigmas=None):
         """requests: sequence of (geometry, p, layers) cycled over by the
-        synthetic bursts.  Returns (tuning dict, best burst ms)."""
+        bursts; sigmas: matching pinned host tensors (float64) of densities,
+        or None for densities of ones.  Returns (tuning dict, best burst ms)."""
         n = len(requests)
         geoms = (ctypes.c_void_p * n)(*[g.handle for g, _, _ in requests])
         ps = np.array([p for _, p, _ in requests], dtype=np.int32)
         ls = np.array([l for _, _, l in requests], dtype=np.uint32)
+        sig = None
+        if sigmas is not None:
+            if len(sigmas) != n:
+                raise ValueError("one density per request")
+            sig = (ctypes.c_void_p * n)(*[s.data_ptr() for s in sigmas])
         t = L.ServerTuning()
         ms = ctypes.c_double()
         _check(_lib().tsqbx_server_autotune(self.handle, n, ctypes.cast(geoms, ctypes.c_void_p),
                                             _ptr(ps), _ptr(ls),
+                                            None if sig is None else ctypes.cast(sig, ctypes.c_void_p),
                                             int(n_requests), ctypes.byref(t), ctypes.byref(ms)))
         return t.as_dict(), ms.value
 

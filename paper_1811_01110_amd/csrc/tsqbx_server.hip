@@ -36,6 +36,15 @@ constexpr int kUnitSteps = 8;  // default wave-steps (group_lanes-wide passes) p
 // overlap this step's evaluation on another stream, large enough to amortise
 // the step's launches.
 constexpr int kMaxStepRequests = 32;  // the default
+constexpr int64_t kNoDma = int64_t(1) << 40;  // no density is uploaded by DMA
+// By default no density goes up by DMA: the staging kernel reads pinned
+// densities over PCIe.  DMA for the larger geometries raises the saturation
+// rate of the serving mix (about 58k-61k against 52k requests/s with a
+// threshold of 32768 sources) but makes it vary from run to run (45k-60k at
+// 131072) and raises the p99 latency under Poisson load (3-5 ms against
+// about 1 ms at 0.7x saturation): the copies of one step queue on the copy
+// engines ahead of the next step's.  It stays a tuning the caller chooses.
+constexpr int64_t kDmaMinSources = kNoDma;
 constexpr size_t kAlign = 256;
 // Completed requests whose status stays queryable (poll, wait); older ones
 // are forgotten, so that a long-running server holds bounded host memory.
@@ -85,6 +94,7 @@ struct tsqbx_server final : public Executor {
   Tuning tn;
   int unit_steps = kUnitSteps;
   int step_requests = kMaxStepRequests;
+  int64_t dma_min_sources = kDmaMinSources;
   std::atomic<bool> used{false};
   char *arena_base = nullptr;
   char *pinned_base = nullptr;  // pinned host arena for densities and outputs
@@ -282,12 +292,15 @@ int tsqbx_server::launch(int stream, const std::vector<Job *> &jobs, std::string
           d_out[l] = (double *)(base + off);
           off += align_up(T * sizeof(double));
         }
+      // a density in pinned memory is read by the staging kernel over PCIe,
+      // unless the geometry is large enough for a DMA upload (dma_min_sources)
+      const bool zero_copy = host_pinned && g->n_sources < dma_min_sources;
       const double *sig = r->sigma_src;
-      if (!host_pinned) {
+      if (!zero_copy) {
         if (N) dma_up.emplace_back(d_sigma, r->sigma_src, N);
         sig = d_sigma;
       }
-      stage.push_back(make_stage_item(g, sig, r->layers, stg, host_pinned, false));
+      stage.push_back(make_stage_item(g, sig, r->layers, stg, zero_copy, false));
       WorkItem w{};
       w.tgt = g->tgt;
       w.idx = g->idx;
@@ -576,6 +589,7 @@ int tsqbx_server_get_tuning(tsqbx_server *sv, tsqbx_server_tuning *out) {
   out->waves_per_block = sv->tn.waves_per_block;
   out->unit_steps = sv->unit_steps;
   out->step_requests = sv->step_requests;
+  out->dma_min_sources = sv->dma_min_sources >= kNoDma ? 0 : sv->dma_min_sources;
   return TSQBX_OK;
 }
 
@@ -590,6 +604,7 @@ static int check_server_tuning(const tsqbx_server_tuning *t) {
                 t->group_lanes, t->unroll, t->waves_per_block);
   if (t->unit_steps < 1 || t->unit_steps > 64 || t->step_requests < 1 || t->step_requests > 256)
     return fail(TSQBX_E_RANGE, "unit_steps must lie in [1, 64] and step_requests in [1, 256]");
+  if (t->dma_min_sources < 0) return fail(TSQBX_E_RANGE, "dma_min_sources must not be negative");
   return TSQBX_OK;
 }
 
@@ -601,6 +616,7 @@ static void apply_server_tuning(tsqbx_server *sv, const tsqbx_server_tuning &t) 
   sv->tn.xcd_remap = 1;
   sv->unit_steps = t.unit_steps;
   sv->step_requests = t.step_requests;
+  sv->dma_min_sources = t.dma_min_sources > 0 ? t.dma_min_sources : kNoDma;
   sv->restart_scheduler();
 }
 
@@ -614,8 +630,8 @@ int tsqbx_server_set_tuning(tsqbx_server *sv, const tsqbx_server_tuning *t) {
 }
 
 int tsqbx_server_autotune(tsqbx_server *sv, int64_t n, const tsqbx_geometry *const *geoms,
-                          const int *p, const unsigned *layers, int n_requests,
-                          tsqbx_server_tuning *out, double *best_ms) {
+                          const int *p, const unsigned *layers, const double *const *sigmas,
+                          int n_requests, tsqbx_server_tuning *out, double *best_ms) {
   TraceRange trace_("tsqbx_server_autotune");
   if (!sv || n <= 0 || !geoms || !p || !layers || n_requests <= 0)
     return fail(TSQBX_E_INVALID, "server, geometries, orders or layers missing, or no requests");
@@ -631,6 +647,8 @@ int tsqbx_server_autotune(tsqbx_server *sv, int64_t n, const tsqbx_geometry *con
     if (b > sv->budget) return fail(TSQBX_E_BUDGET, "request %lld can never fit the budget", (long long)i);
     max_n = std::max<int64_t>(max_n, geoms[i]->n_sources);
     max_t = std::max<int64_t>(max_t, geoms[i]->n_targets);
+    if (sigmas && geoms[i]->n_sources > 0 && !is_pinned_host(sigmas[i]))
+      return fail(TSQBX_E_INVALID, "density %lld is not pinned host memory", (long long)i);
   }
   // densities of ones and throw-away outputs in pinned host memory (the
   // requests' results are not kept, so they may share them)
@@ -656,7 +674,8 @@ int tsqbx_server_autotune(tsqbx_server *sv, int64_t n, const tsqbx_geometry *con
       const int64_t i = r % n;
       double *const outs[3] = {h_out, h_out + max_t, h_out + 2 * max_t};
       uint64_t tk = 0;
-      int rc = submit_impl(sv, geoms[i], p[i], layers[i], 0.0, h_sigma, outs, &tk, true, true);
+      const double *sg = sigmas ? sigmas[i] : h_sigma;
+      int rc = submit_impl(sv, geoms[i], p[i], layers[i], 0.0, sg, outs, &tk, true, true);
       if (rc != TSQBX_OK) return rc;
     }
     if (sv->sched->drain(600.0) != TSQBX_OK)

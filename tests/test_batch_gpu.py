@@ -195,8 +195,11 @@ def test_server_autotune_and_tuning_rules():
     budget = 16 * max(api.Server.request_bytes(gg1, 3), api.Server.request_bytes(gg2, 1))
     srv = ctx.server(budget, 16)
     assert srv.get_tuning() == {"group_lanes": 16, "unroll": 2, "waves_per_block": 4,
-                                "unit_steps": 8, "step_requests": 32}
-    tuning, ms = srv.autotune([(gg1, 8, 3), (gg2, 4, 1)], n_requests=48)
+                                "unit_steps": 8, "step_requests": 32, "dma_min_sources": 0}
+    import torch
+
+    pinned = [torch.from_numpy(g.sigma).pin_memory() for g in (g1, g2)]
+    tuning, ms = srv.autotune([(gg1, 8, 3), (gg2, 4, 1)], n_requests=48, sigmas=pinned)
     assert ms > 0 and tuning == srv.get_tuning()
     assert srv.stats()["submitted"] == 0  # the bursts leave no trace
     t, a, b, _ = srv.submit(gg1, g1.sigma, 8, 3)
@@ -221,7 +224,8 @@ def test_server_autotune_and_tuning_rules():
     with pytest.raises(api.TsqbxError) as ei:
         srv.set_tuning(group_lanes=8)
     assert ei.value.code == -2
-    srv.set_tuning(group_lanes=64, unroll=2, waves_per_block=2, unit_steps=4, step_requests=16)
+    srv.set_tuning(group_lanes=64, unroll=2, waves_per_block=2, unit_steps=4, step_requests=16,
+                   dma_min_sources=1000)  # g2's densities go up by DMA
     ts = [srv.submit(gg2, g2.sigma, 4, 1) for _ in range(5)]
     srv.drain(60)
     ctx.set_tuning(4, 1, max(1, -(-gg2.pairs // gg2.n_targets)), group_lanes=64, unroll=2,
