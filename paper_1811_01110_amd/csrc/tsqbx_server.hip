@@ -676,7 +676,10 @@ int tsqbx_server_autotune(tsqbx_server *sv, int64_t n, const tsqbx_geometry *con
       uint64_t tk = 0;
       const double *sg = sigmas ? sigmas[i] : h_sigma;
       int rc = submit_impl(sv, geoms[i], p[i], layers[i], 0.0, sg, outs, &tk, true, true);
-      if (rc != TSQBX_OK) return rc;
+      if (rc != TSQBX_OK) {
+        (void)sv->sched->drain(600.0);  // the buffers stay in use until then
+        return rc;
+      }
     }
     if (sv->sched->drain(600.0) != TSQBX_OK)
       return fail(TSQBX_E_TIMEOUT, "autotune burst did not finish");
