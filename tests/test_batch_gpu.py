@@ -376,6 +376,66 @@ def test_plan_edge_cases(ctx):
     plan.close()
 
 
+def test_plan_stress_many_tiny_items():
+    """Hundreds of tiny items of every order and layer mask in one plan,
+    with ACCUMULATE into outputs zeroed before each of 100 graph replays
+    (eager fills and synchronisations between them): a target summed twice
+    would double, a skipped one stay 0.  Every replay equals the plain
+    launches at the same group width bit for bit; a sample matches the
+    oracle.  (A context of its own, with the default plain tunings.)"""
+    import torch
+
+    ctx = api.Context(0)
+    rng = np.random.default_rng(4242)
+    geoms = []
+    for i in range(360):
+        p = int(rng.integers(0, 33))
+        layers = int(rng.integers(1, 8))
+        geoms.append(W.fuzz_geometry(5000 + i, n=int(rng.integers(8, 200)),
+                                     m=int(rng.integers(1, 30)), max_list=int(rng.integers(1, 60)),
+                                     p=p, layers=layers,
+                                     targets_per_center=int(rng.integers(1, 4))))
+    items = []
+    for g in geoms:
+        geom = ctx.geometry(g)
+        it = dict(geom=geom, p=g.p, layers=g.layers, g=g,
+                  sigma=torch.tensor(g.sigma, device="cuda", dtype=torch.float64))
+        for bit, name in ((1, "out_slp"), (2, "out_dlp"), (4, "out_sprime")):
+            if g.layers & bit:
+                it[name] = torch.zeros(g.n_targets, device="cuda", dtype=torch.float64)
+        items.append(it)
+    plan = ctx.plan(items, flags=api.ACCUMULATE)
+    plan.set_tuning(group_lanes=16, unroll=2)
+    plain = []
+    for it in items:  # every mean list is below 384 entries: the plain path runs 16 lanes
+        plain.append(ctx.eval(it["geom"], it["g"].sigma, it["p"], it["layers"]))
+    outs = [(it.get("out_slp"), it.get("out_dlp"), it.get("out_sprime")) for it in items]
+    for rep in range(100):
+        for o in outs:
+            for t in o:
+                if t is not None:
+                    t.zero_()
+        torch.cuda.synchronize()
+        plan.execute()
+        torch.cuda.synchronize()
+        if rep in (0, 1, 17, 99):
+            for k, (o, ref) in enumerate(zip(outs, plain)):
+                for t, r in zip(o, ref):
+                    if t is not None:
+                        assert np.array_equal(t.cpu().numpy(), r), (rep, k)
+    for k in range(0, len(items), 37):
+        g = items[k]["g"]
+        ref = oracle.evaluate_geometry(g)
+        for t, name in zip(outs[k], ("slp", "dlp", "sprime")):
+            if t is not None:
+                assert_parity(t.cpu().numpy(), ref[name], ref["abs_" + name],
+                              what=f"stress item {k} {name}")
+    plan.close()
+    for it in items:
+        it["geom"].close()
+    ctx.close()
+
+
 def test_server_mixes_helmholtz_and_laplace_requests(ctx):
     """Helmholtz requests (complex density and outputs) share steps with
     Laplace ones: each result is the same served alone or in the mix, equals
