@@ -109,7 +109,7 @@ typedef struct {
   const int32_t *list_sources; /* [offsets[M]] source indices in [0, N); repeats count twice */
   int64_t n_targets;           /* T >= 0 */
   const double *targets;       /* [T][3] target points t */
-  const int32_t *target_center;/* [T] center of each target in [0, M); NULL: T == M, target i uses center i */
+  const int32_t *target_center;/* [T] center of each target in [0, M); NULL: T == M (or T == 0), target i uses center i */
   const double *target_normals;/* [T][3] unit normals at the targets, or NULL (then no TSQBX_SPRIME) */
 } tsqbx_geometry_desc;
 

@@ -127,7 +127,7 @@ static int validate(const tsqbx_geometry_desc *d) {
   if (d->n_centers > 0 && !d->centers) return fail(TSQBX_E_INVALID, "centers is NULL");
   if (!d->list_offsets) return fail(TSQBX_E_INVALID, "list_offsets is NULL");
   if (d->n_targets > 0 && !d->targets) return fail(TSQBX_E_INVALID, "targets is NULL");
-  if (!d->target_center && d->n_targets != d->n_centers)
+  if (!d->target_center && d->n_targets > 0 && d->n_targets != d->n_centers)
     return fail(TSQBX_E_INVALID, "target_center is NULL but n_targets (%lld) != n_centers (%lld)",
                 (long long)d->n_targets, (long long)d->n_centers);
   const int64_t *off = d->list_offsets;

@@ -333,7 +333,7 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
   if ((N > 0 && (!d->sources || !d->weights)) || (M > 0 && !d->centers) || !d->list_offsets ||
       (T > 0 && !d->targets))
     return fail(TSQBX_E_INVALID, "a required array is NULL");
-  if (!d->target_center && T != M)
+  if (!d->target_center && T > 0 && T != M)
     return fail(TSQBX_E_INVALID, "target_center is NULL but n_targets (%lld) != n_centers (%lld)",
                 (long long)T, (long long)M);
   Guard dg(ctx->device);

@@ -138,6 +138,36 @@ def test_rows_longer_than_one_workgroup_sorts(ctx):
     _check(ctx, _arrays(g, target_normals=False), p=4, layers=3)
 
 
+@pytest.mark.parametrize("case", ["one_of_each", "unused_center", "all_lists_empty",
+                                  "no_targets"])
+def test_degenerate_sizes(ctx, case):
+    rng = np.random.default_rng(7)
+
+    def pts(n, scale=1.0):
+        return rng.standard_normal((n, 3)) * scale
+
+    if case == "one_of_each":
+        N, M, off, lst, tc = 1, 1, [0, 1], [0], None
+    elif case == "unused_center":
+        N, M, off, lst, tc = 5, 3, [0, 0, 2, 3], [1, 2, 4], [2, 0]
+    elif case == "all_lists_empty":
+        N, M, off, lst, tc = 10, 4, [0, 0, 0, 0, 0], [], None
+    else:
+        N, M, off, lst, tc = 6, 2, [0, 3, 5], [0, 1, 2, 3, 5], []
+    src = pts(N) * 0.2 + np.array([3.0, 0.0, 0.0])
+    ctr = pts(M) * 0.01
+    T = M if tc is None else len(tc)
+    tgt = (ctr if tc is None else ctr[np.asarray(tc, dtype=np.int64)]) + pts(T, 0.001) \
+        if T else np.zeros((0, 3))
+    arrays = dict(sources=src, weights=rng.uniform(0.5, 1.0, N), normals=pts(N),
+                  centers=ctr, list_offsets=np.asarray(off, dtype=np.int64),
+                  list_sources=np.asarray(lst, dtype=np.int32), targets=tgt,
+                  target_center=None if tc is None else np.asarray(tc, dtype=np.int32),
+                  target_normals=None)
+    arrays["normals"] /= np.linalg.norm(arrays["normals"], axis=1, keepdims=True)
+    _check(ctx, arrays, p=6, layers=3)
+
+
 def test_config_a_full_size(ctx):
     g = cached_workload("config_a")
     gh, gd, sigma = _check(ctx, _arrays(g, target_normals=False), p=16, layers=3)
