@@ -444,7 +444,7 @@ k_helm_eval(HelmWorkItem v, int64_t n_targets, int remap) {
 // Laplace persistent kernel does.  LC: the layer mask shared by every item
 // (1..7), or kLayersAny (a switch over the masks).
 template <int LC, int G, int U>
-__global__ void __launch_bounds__(256) k_helm_persistent(HelmPersistentArgs a) {
+__global__ void __launch_bounds__(256, 3) k_helm_persistent(HelmPersistentArgs a) {
   constexpr int TPW = 64 / G;
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
