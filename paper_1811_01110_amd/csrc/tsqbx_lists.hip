@@ -756,6 +756,7 @@ extern "C" int tsqbx_ball_lists(tsqbx_ctx *ctx, int64_t n_sources, const double 
                                 int64_t n_centers, const double *d_centers, double radius,
                                 int64_t *d_offsets, int32_t *d_indices, int64_t capacity,
                                 int64_t *nnz, void *hip_stream) {
+  TraceRange trace_("tsqbx_ball_lists");
   if (!ctx || !nnz || !d_offsets) return fail(TSQBX_E_INVALID, "ctx, offsets or nnz is NULL");
   if (n_sources < 0 || n_centers < 0 || capacity < 0)
     return fail(TSQBX_E_INVALID, "negative count");
@@ -823,6 +824,7 @@ extern "C" int tsqbx_knn_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *
                                int64_t n_centers, const double *d_centers, const int32_t *d_counts,
                                int64_t *d_offsets, int32_t *d_indices, int64_t capacity,
                                int64_t *nnz, void *hip_stream) {
+  TraceRange trace_("tsqbx_knn_lists");
   if (!ctx || !nnz || !d_offsets) return fail(TSQBX_E_INVALID, "ctx, offsets or nnz is NULL");
   if (n_sources < 0 || n_centers < 0 || capacity < 0)
     return fail(TSQBX_E_INVALID, "negative count");
