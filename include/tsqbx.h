@@ -194,7 +194,11 @@ int tsqbx_ctx_destroy(tsqbx_ctx *ctx);
 /* Copy a geometry into device memory.  The library reorders sources and
  * targets along a Morton curve for locality (unless TSQBX_NO_REORDER) and
  * sorts each list ascending; outputs are still in the caller's order.  The
- * caller may free its arrays when the call returns. */
+ * caller may free its arrays when the call returns.  The arrays are checked
+ * on the host; a reordered geometry of 2^20 list entries or more is then
+ * uploaded as given and laid out on the device (the layout of
+ * tsqbx_geometry_create_device, identical to the host's), using temporary
+ * device memory of about the input's size during the call. */
 int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *desc, unsigned flags,
                           tsqbx_geometry **out);
 int tsqbx_geometry_destroy(tsqbx_geometry *geom);

@@ -316,14 +316,9 @@ struct Scratch {
 
 using namespace tsqbx;
 
-extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d,
-                                            unsigned flags, void *hip_stream,
-                                            tsqbx_geometry **out) {
-  TraceRange trace_("tsqbx_geometry_create_device");
-  if (!ctx || !out || !d) return fail(TSQBX_E_INVALID, "ctx, desc or out is NULL");
+int tsqbx::build_geometry_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, hipStream_t s,
+                                 tsqbx_geometry **out) {
   *out = nullptr;
-  if (flags & TSQBX_NO_REORDER)
-    return fail(TSQBX_E_INVALID, "geometry_create_device builds the reordered layout only");
   const int64_t N = d->n_sources, M = d->n_centers, T = d->n_targets;
   if (N < 0 || M < 0 || T < 0) return fail(TSQBX_E_INVALID, "negative count");
   if (N >= TSQBX_MAX_SOURCES)
@@ -338,7 +333,6 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
                 (long long)T, (long long)M);
   Guard dg(ctx->device);
   if (dg.err != hipSuccess) return fail_hip(dg.err, "hipSetDevice");
-  hipStream_t s = (hipStream_t)hip_stream;
   Scratch sc;
   hipError_t e = hipSuccess;
 #define TQ(call)                                  \
@@ -574,6 +568,17 @@ extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry
   own.g = nullptr;
   *out = g;
   return TSQBX_OK;
+}
+
+extern "C" int tsqbx_geometry_create_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d,
+                                            unsigned flags, void *hip_stream,
+                                            tsqbx_geometry **out) {
+  TraceRange trace_("tsqbx_geometry_create_device");
+  if (!ctx || !out || !d) return fail(TSQBX_E_INVALID, "ctx, desc or out is NULL");
+  *out = nullptr;
+  if (flags & TSQBX_NO_REORDER)
+    return fail(TSQBX_E_INVALID, "geometry_create_device builds the reordered layout only");
+  return build_geometry_device(ctx, d, (hipStream_t)hip_stream, out);
 }
 
 extern "C" int tsqbx_geometry_read_layout(const tsqbx_geometry *g, int64_t *source_order,

@@ -377,6 +377,12 @@ hipError_t sort_rows(const int64_t *d_offsets, int32_t *d_indices, int64_t M, in
                      int64_t max_value, hipStream_t s);
 constexpr int64_t kRowSortMax = 8192;
 
+// The reordered geometry built on the device from a description whose arrays
+// are device pointers (tsqbx_geometry_device.hip); the same layout, bit for
+// bit, as the host build.  Synchronises s before returning.
+int build_geometry_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, hipStream_t s,
+                          tsqbx_geometry **out);
+
 // Free a geometry's device arrays and the geometry (null: nothing).
 void free_geometry(tsqbx_geometry *g);
 

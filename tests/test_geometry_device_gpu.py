@@ -173,6 +173,17 @@ def test_config_a_full_size(ctx):
     gh, gd, sigma = _check(ctx, _arrays(g, target_normals=False), p=16, layers=3)
 
 
+def test_host_arrays_either_side_of_the_device_build_threshold(ctx):
+    """tsqbx_geometry_create lays out reordered geometries of 2^20 list
+    entries and more on the device; below that on the host.  Both give the
+    host layout exactly, and the potentials agree bit for bit with a geometry
+    built from device arrays."""
+    for m, want_device in ((1700, False), (4000, True)):
+        g = W.fuzz_geometry(320, n=60000, m=m, max_list=600, p=8, layers=3)
+        assert (g.nnz >= 1 << 20) == want_device, g.nnz
+        _check(ctx, _arrays(g, target_normals=False), p=8, layers=3)
+
+
 def test_helmholtz_and_plan_on_a_device_geometry(ctx):
     import torch
 
