@@ -379,7 +379,10 @@ int tsqbx_knn_lists(tsqbx_ctx *ctx, int64_t n_sources, const double *d_sources,
  * batched and served paths at equal group_lanes.
  * ------------------------------------------------------------------------- */
 typedef struct {
-  int waves_per_block;   /* 1, 2 or 4 */
+  int waves_per_block;   /* 1, 2, 4, or 8 for the plain Laplace kernel only (its
+                            default with one target per wave); plans and
+                            servers run blocks of at most 4, and a Helmholtz
+                            key refuses 8 */
   int group_lanes;       /* lanes that share one target: 64, 32 or 16 */
   int unroll;            /* independent pairs in flight per lane: 1, 2 or 4 */
   int xcd_remap;         /* 1: give each XCD a contiguous range of targets */

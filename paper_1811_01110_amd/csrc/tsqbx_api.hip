@@ -206,13 +206,14 @@ uint64_t tuning_key(int p, unsigned layers, int64_t mean_list) {
 
 Tuning default_tuning(int p, unsigned layers, int64_t mean_list) {
   (void)p;
-  (void)layers;
   Tuning t;
-  t.waves_per_block = 4;
   t.xcd_remap = 1;
   // short lists: several targets per wave; long lists: one target per wave
   t.group_lanes = mean_list < 384 ? 16 : 64;
   t.unroll = 2;
+  // the plain Laplace kernel with one target per wave: blocks of 8 adjacent
+  // targets (their lists overlap, and the block's waves share the L1)
+  t.waves_per_block = (t.group_lanes == 64 && !(layers & TSQBX_HELMHOLTZ)) ? 8 : 4;
   return t;
 }
 
@@ -806,7 +807,7 @@ int tsqbx_set_tuning(tsqbx_ctx *ctx, int p, unsigned layers, int64_t mean_list,
   t.group_lanes = tuning->group_lanes;
   t.unroll = tuning->unroll;
   t.xcd_remap = tuning->xcd_remap;
-  if (!tuning_supported(t))
+  if (!((layers & TSQBX_HELMHOLTZ) ? tuning_supported(t) : eval_tuning_supported(t)))
     return fail(TSQBX_E_INVALID, "unsupported tuning (waves %d, group %d, unroll %d, remap %d)",
                 t.waves_per_block, t.group_lanes, t.unroll, t.xcd_remap);
   std::lock_guard<std::mutex> lk(ctx->tuning_mu);
@@ -897,7 +898,7 @@ int tsqbx_tuning_load(tsqbx_ctx *ctx, const char *path, int *n_loaded) {
                        "\"group_lanes\": %d, \"unroll\": %d, \"waves_per_block\": %d, "
                        "\"xcd_remap\": %d}",
                        &t.group_lanes, &t.unroll, &t.waves_per_block, &t.xcd_remap) == 4 &&
-           tuning_supported(t);
+           ((key >> 8 & TSQBX_HELMHOLTZ) ? tuning_supported(t) : eval_tuning_supported(t));
       if (ok && arch == a && rt == r) plain[key] = t;
     } else if (!std::strcmp(kind, "plan")) {
       PlanTuning t;
@@ -965,7 +966,7 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
   Tuning best;
   double best_t = 1e300;
   const int GU[][2] = {{64, 1}, {64, 2}, {64, 4}, {32, 2}, {16, 2}};
-  const int W[] = {1, 2, 4};
+  const int W[] = {1, 2, 4, 8};
   for (auto &gu : GU)
     for (int w : W)
       for (int remap = 0; remap <= 1; ++remap) {

@@ -9,7 +9,7 @@ namespace tsqbx {
 namespace {
 
 template <int P, int L, int G, int U>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_eval(const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm, int64_t n_targets,
        const int32_t *__restrict__ idx, SrcView src, double *__restrict__ out_s,
        double *__restrict__ out_d, double *__restrict__ out_t, int accumulate, int p_rt,
@@ -74,17 +74,25 @@ hipError_t launch_l(const tsqbx_geometry *g, int p, unsigned layers, const Sourc
 
 }  // namespace
 
-bool tuning_supported(const Tuning &tn) {
-  const int w = tn.waves_per_block;
-  if (!(w == 1 || w == 2 || w == 4)) return false;
+static bool group_supported(const Tuning &tn) {
   if (!(tn.xcd_remap == 0 || tn.xcd_remap == 1)) return false;
   const int G = tn.group_lanes, U = tn.unroll;
   return (G == 64 && (U == 1 || U == 2 || U == 4)) || (G == 32 && U == 2) || (G == 16 && U == 2);
 }
 
+bool tuning_supported(const Tuning &tn) {
+  const int w = tn.waves_per_block;
+  return (w == 1 || w == 2 || w == 4) && group_supported(tn);
+}
+
+bool eval_tuning_supported(const Tuning &tn) {
+  const int w = tn.waves_per_block;
+  return (w == 1 || w == 2 || w == 4 || w == 8) && group_supported(tn);
+}
+
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
                        const Outputs &o, bool accumulate, const Tuning &tn, hipStream_t s) {
-  if (!tuning_supported(tn)) return hipErrorInvalidValue;
+  if (!eval_tuning_supported(tn)) return hipErrorInvalidValue;
   const int G = tn.group_lanes, U = tn.unroll;
   if (G == 64 && U == 1) return launch_l<64, 1>(g, p, layers, st, o, accumulate, tn, s);
   if (G == 64 && U == 2) return launch_l<64, 2>(g, p, layers, st, o, accumulate, tn, s);

@@ -182,7 +182,18 @@ hipError_t launch_stage(const tsqbx_geometry *g, const double *d_sigma, unsigned
 hipError_t launch_stage_positions(const tsqbx_geometry *g, const SourceStage &st, hipStream_t s);
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
                        const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
+// Tunings every kernel takes (blocks of up to 4 waves) ...
 bool tuning_supported(const Tuning &tn);
+// ... and those of the plain Laplace kernel, which also takes blocks of 8
+// waves (8 Morton-adjacent targets per block share more of their sources in
+// the compute unit's L1).
+bool eval_tuning_supported(const Tuning &tn);
+// A tuning for the persistent (batched, served) and Helmholtz kernels: blocks
+// of at most 4 waves.
+inline Tuning clamp_to_common(Tuning t) {
+  if (t.waves_per_block > 4) t.waves_per_block = 4;
+  return t;
+}
 // Conventional QBX (tsqbx_conventional.hip): mode 1 forms the local
 // coefficients of every row's center from the staged sources into
 // coeffs_out, mode 2 evaluates coeffs_in at the targets into out, mode 3

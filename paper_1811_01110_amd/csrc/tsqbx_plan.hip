@@ -384,10 +384,10 @@ int tsqbx_plan_create(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_item *items, 
   }
   pl->layer_class = lc.get();
   const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
-  pl->tn = lookup_tuning(ctx, pmax, lay_all ? lay_all : 1u, mean_list);
+  pl->tn = clamp_to_common(lookup_tuning(ctx, pmax, lay_all ? lay_all : 1u, mean_list));
   if (pl->tn.unroll > 2) pl->tn.unroll = 2;  // the persistent kernels keep two pairs in flight
   if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
-  if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, 3u, mean_list);
+  if (!tuning_supported(pl->tn)) pl->tn = clamp_to_common(default_tuning(pmax, 3u, mean_list));
   uint64_t pmask = 0;
   for (auto &it : pl->items) pmask |= uint64_t(1) << it.p;
   pl->tune_key = plan_tuning_key(false, pmask, lay_all, mean_list, tot_targets);
@@ -499,10 +499,11 @@ int tsqbx_plan_create_helmholtz(tsqbx_ctx *ctx, int64_t n_items, const tsqbx_hel
   }
   pl->layer_class = same && first >= 1 && first <= 7 ? first : kLayersAny;
   const int64_t mean_list = tot_targets ? (tot_pairs + tot_targets - 1) / tot_targets : 0;
-  pl->tn = lookup_tuning(ctx, pmax, (lay_all ? lay_all : 1u) | TSQBX_HELMHOLTZ, mean_list);
+  pl->tn = clamp_to_common(
+      lookup_tuning(ctx, pmax, (lay_all ? lay_all : 1u) | TSQBX_HELMHOLTZ, mean_list));
   pl->tn.unroll = std::min(std::max(pl->tn.unroll, 1), 2);
   if (pl->tn.group_lanes < 64) pl->tn.unroll = 2;
-  if (!tuning_supported(pl->tn)) pl->tn = default_tuning(pmax, lay_all, mean_list);
+  if (!tuning_supported(pl->tn)) pl->tn = clamp_to_common(default_tuning(pmax, lay_all, mean_list));
   uint64_t pmask = 0;
   for (auto &it : pl->hitems) pmask |= uint64_t(1) << it.p;
   pl->tune_key = plan_tuning_key(true, pmask, lay_all, mean_list, tot_targets);

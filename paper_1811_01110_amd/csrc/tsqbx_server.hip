@@ -446,7 +446,7 @@ int tsqbx_server_create(tsqbx_ctx *ctx, size_t hbm_budget, int max_slots, tsqbx_
   // one launch shape for the server's lifetime (by default that of near-field
   // lists of a few hundred sources); a request's result then does not
   // depend on its step
-  sv->tn = default_tuning(16, 3u, 256);
+  sv->tn = clamp_to_common(default_tuning(16, 3u, 256));
   hipError_t e = hipMalloc((void **)&sv->arena_base, sv->budget);
   // pinned host arena: densities and outputs of queued and running requests
   sv->pinned_cap = std::min<size_t>(sv->budget, size_t(1) << 30);

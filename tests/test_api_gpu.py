@@ -22,7 +22,7 @@ def test_autotune_installs_a_supported_tuning(ctx):
     geom = ctx.geometry(g)
     tuning, ms = ctx.autotune(geom, 16, 3)
     assert ms > 0
-    assert tuning["group_lanes"] in (16, 32, 64) and tuning["waves_per_block"] in (1, 2, 4)
+    assert tuning["group_lanes"] in (16, 32, 64) and tuning["waves_per_block"] in (1, 2, 4, 8)
     mean = max(geom.pairs // geom.n_targets, 1)
     assert ctx.get_tuning(16, 3, mean) == tuning
     s, d, _ = ctx.eval(geom, g.sigma, 16, 3)
@@ -31,6 +31,48 @@ def test_autotune_installs_a_supported_tuning(ctx):
     assert_parity(d, ref["dlp"], ref["abs_dlp"], what="autotuned dlp")
     with pytest.raises(api.TsqbxError):
         ctx.set_tuning(16, 3, mean, group_lanes=48)
+    geom.close()
+
+
+def test_blocks_of_eight_waves_stay_in_the_plain_kernel(ctx):
+    """The plain Laplace kernel takes blocks of 8 waves (its default with one
+    target per wave); the Helmholtz kernels refuse them, and a plan built
+    while the plain tuning has them runs blocks of 4, with the plain path's
+    bits."""
+    import torch
+
+    g = W.fuzz_geometry(502, n=3000, m=400, max_list=1200, p=16, layers=3, allow_empty=False)
+    geom = ctx.geometry(g)
+    mean = max(geom.pairs // geom.n_targets, 1)
+    assert mean >= 384 and ctx.get_tuning(16, 3, mean)["waves_per_block"] == 8
+    assert ctx.get_tuning(16, 3 | api.HELMHOLTZ, mean)["waves_per_block"] == 4
+    with pytest.raises(api.TsqbxError):
+        ctx.set_tuning(16, 3 | api.HELMHOLTZ, mean, waves_per_block=8)
+    for bad in (3, 16):
+        with pytest.raises(api.TsqbxError):
+            ctx.set_tuning(16, 3, mean, waves_per_block=bad)
+    ref = oracle.evaluate_geometry(g)
+    outs = []
+    for w in (8, 4, 1):
+        ctx.set_tuning(16, 3, mean, group_lanes=64, unroll=2, waves_per_block=w, xcd_remap=1)
+        s, d, _ = ctx.eval(geom, g.sigma, 16, 3)
+        assert_parity(s, ref["slp"], ref["abs_slp"], what=f"w{w} slp")
+        assert_parity(d, ref["dlp"], ref["abs_dlp"], what=f"w{w} dlp")
+        outs.append((s, d))
+    assert all(np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1]) for o in outs)
+    ctx.set_tuning(16, 3, mean, group_lanes=64, unroll=2, waves_per_block=8, xcd_remap=1)
+    sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
+    item = dict(geom=geom, p=16, layers=3, sigma=sig,
+                out_slp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64),
+                out_dlp=torch.zeros(g.n_targets, device="cuda", dtype=torch.float64))
+    plan = ctx.plan([item])
+    t = plan.get_tuning()
+    assert t["group_lanes"] == 64 and t["waves_per_block"] == 4
+    plan.execute()
+    torch.cuda.synchronize()
+    assert np.array_equal(item["out_slp"].cpu().numpy(), outs[0][0])
+    assert np.array_equal(item["out_dlp"].cpu().numpy(), outs[0][1])
+    plan.close()
     geom.close()
 
 

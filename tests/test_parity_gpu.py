@@ -135,7 +135,7 @@ def test_tuning_variants(ctx):
     mean = max(geom.pairs // max(geom.n_targets, 1), 1)
     base = None
     for G, U in ((64, 1), (64, 2), (64, 4), (32, 2), (16, 2)):
-        for w in (1, 2, 4):
+        for w in (1, 2, 4, 8):
             for remap in (0, 1):
                 ctx.set_tuning(16, 3, mean, waves_per_block=w, group_lanes=G, unroll=U,
                                xcd_remap=remap)
