@@ -270,3 +270,21 @@ def test_sprime_needs_target_normals(ctx):
         ctx.eval(geom, g.sigma, 4, 8)
     assert ei.value.code == -1
     geom.close()
+
+
+@pytest.mark.parametrize("G", [64, 32, 16])
+def test_several_targets_per_center(ctx, G):
+    """Several targets share one center (and so one row of the layout): every
+    target against the oracle, all three layers, at each group width and
+    block size the plain kernel takes."""
+    g = W.fuzz_geometry(1200 + G, n=4000, m=300, max_list=900, p=12, layers=7,
+                        targets_per_center=4)
+    geom = ctx.geometry(g)
+    mean = max(geom.pairs // geom.n_targets, 1)
+    ref = oracle.evaluate_geometry(g, p=12, layers=7)
+    for w in (2, 8):
+        ctx.set_tuning(12, 7, mean, group_lanes=G, unroll=2, waves_per_block=w, xcd_remap=1)
+        s, d, t = ctx.eval(geom, g.sigma, 12, 7)
+        for out, key in ((s, "slp"), (d, "dlp"), (t, "sprime")):
+            assert_parity(out, ref[key], ref["abs_" + key], what=f"tpc4 G{G} w{w} {key}")
+    geom.close()
