@@ -21,7 +21,7 @@ OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_BUDGET, E_STATE, E_TIMEOUT = 0, -1,
 E_CANCELED = -8
 SLP, DLP, SPRIME = 1, 2, 4
 HELMHOLTZ = 64
-ACCUMULATE, NO_REORDER = 1, 2
+ACCUMULATE, NO_REORDER, PER_TARGET = 1, 2, 4
 P_MAX = 32
 
 

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib as L
 
 SLP, DLP, SPRIME, HELMHOLTZ = L.SLP, L.DLP, L.SPRIME, L.HELMHOLTZ
-ACCUMULATE, NO_REORDER, P_MAX = L.ACCUMULATE, L.NO_REORDER, L.P_MAX
+ACCUMULATE, NO_REORDER, PER_TARGET, P_MAX = L.ACCUMULATE, L.NO_REORDER, L.PER_TARGET, L.P_MAX
 LAYER_BITS = (SLP, DLP, SPRIME)  # the order of every (slp, dlp, sprime) tuple
 
 

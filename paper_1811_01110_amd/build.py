@@ -23,7 +23,7 @@ ARCH = "gfx950"
 
 SOURCES = ["tsqbx_api.hip", "tsqbx_eval.hip", "tsqbx_stage.hip", "tsqbx_persistent.hip", "tsqbx_helmholtz.hip",
            "tsqbx_lists.hip", "tsqbx_plan.hip", "tsqbx_server.hip", "tsqbx_conventional.hip",
-           "tsqbx_noalloc.hip", "tsqbx_geometry_device.hip"]
+           "tsqbx_noalloc.hip", "tsqbx_geometry_device.hip", "tsqbx_eval_rows.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -624,7 +624,8 @@ int tsqbx_eval_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned la
   o.t = d_out_sprime;
   TSQBX_HIP(launch_stage(g, d_sigma, layers, g->stage, true, s));
   g->staged_layers.store(layers);
-  TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn, s));
+  TSQBX_HIP(launch_eval_plain(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn,
+                              (flags & TSQBX_PER_TARGET) != 0, s));
   return TSQBX_OK;
 }
 
@@ -663,8 +664,8 @@ int tsqbx_eval_staged_async(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsi
   o.s = d_out_slp;
   o.d = d_out_dlp;
   o.t = d_out_sprime;
-  TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn,
-                        (hipStream_t)hip_stream));
+  TSQBX_HIP(launch_eval_plain(g, p, layers, g->stage, o, (flags & TSQBX_ACCUMULATE) != 0, tn,
+                              (flags & TSQBX_PER_TARGET) != 0, (hipStream_t)hip_stream));
   return TSQBX_OK;
 }
 
@@ -762,7 +763,8 @@ int tsqbx_eval(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned layers,
   const Tuning tn = lookup_tuning(ctx, p, layers, mean_list_of(g));
   TSQBX_HIP(launch_stage(g, ctx->d_sigma, layers, g->stage, true, s));
   g->staged_layers.store(layers);
-  TSQBX_HIP(launch_eval(g, p, layers, g->stage, o, false, tn, s));
+  TSQBX_HIP(launch_eval_plain(g, p, layers, g->stage, o, false, tn,
+                              (flags & TSQBX_PER_TARGET) != 0, s));
   // without ACCUMULATE the outputs go straight into the caller's arrays
   const bool acc = (flags & TSQBX_ACCUMULATE) != 0;
   double *const dev[3] = {o.s, o.d, o.t};
@@ -975,11 +977,11 @@ int tsqbx_autotune(tsqbx_ctx *ctx, const tsqbx_geometry *g, int p, unsigned laye
         t.unroll = gu[1];
         t.waves_per_block = w;
         t.xcd_remap = remap;
-        e = launch_eval(g, p, layers, g->stage, outs, false, t, s);  // warm-up
+        e = launch_eval_plain(g, p, layers, g->stage, outs, false, t, false, s);  // warm-up
         float best_rep = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
           e = hipEventRecord(e0, s);
-          if (e == hipSuccess) e = launch_eval(g, p, layers, g->stage, outs, false, t, s);
+          if (e == hipSuccess) e = launch_eval_plain(g, p, layers, g->stage, outs, false, t, false, s);
           if (e == hipSuccess) e = hipEventRecord(e1, s);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0;

@@ -100,6 +100,7 @@ extern "C" int tsqbx_eval_async_noalloc(tsqbx_ctx *ctx, const tsqbx_geometry *g,
   o.t = d_out_sprime;
   hipStream_t s = (hipStream_t)hip_stream;
   TSQBX_HIP(launch_stage(g, d_sigma, layers, st, false, s));
-  TSQBX_HIP(launch_eval(g, p, layers, st, o, (flags & TSQBX_ACCUMULATE) != 0, tn, s));
+  TSQBX_HIP(launch_eval_plain(g, p, layers, st, o, (flags & TSQBX_ACCUMULATE) != 0, tn,
+                              (flags & TSQBX_PER_TARGET) != 0, s));
   return TSQBX_OK;
 }
