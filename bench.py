@@ -2,8 +2,9 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-serve]
                     [--no-high-order] [--no-cpu] [--requests R] [--min-warm S]
-                    [--no-sprime] [--no-helmholtz] [--no-lists] [--no-conventional]
-                    [--only headline|batched|high_order|serve|sprime|helmholtz|lists|conventional]
+                    [--no-sprime] [--no-helmholtz] [--no-lists] [--no-conventional] [--no-shared]
+                    [--only headline|batched|high_order|serve|sprime|helmholtz|lists|conventional|
+                            shared|helm_batched]
                     [--calibration-copy]
 
 The headline `value` is the plain single- plus double-layer evaluation at
@@ -18,7 +19,8 @@ S' (the target normal derivative of the single layer) and the Helmholtz
 single + double layer (k = 20) on the headline workload, the device build of
 the headline workload's near-field lists, conventional QBX (coefficients
 formed per center, then evaluated) against the target-specific single layer,
-and the served Poisson stream (p50/p99 latency).  The oracle timed on the
+the row kernel against one wave per target where four targets share each
+center, and the served Poisson stream (p50/p99 latency).  The oracle timed on the
 host cores is reported as `cpu_baseline`.  Progress goes to stderr; one JSON
 line goes to stdout.
 """
@@ -77,6 +79,19 @@ def flops_per_pair(p: int, layers: int) -> int:
     f += 17 if layers & 2 else 0
     f += (12 if layers & 2 else 13) if layers & 4 else 0
     return f
+
+
+def rows_flops_per_pair(p: int, layers: int) -> float:
+    """FP64 operations per pair of the row kernel, which walks a list once for
+    two targets: the source's offset from the center, |d|^2, 1/|d| and
+    1/|d|^2 (18), and the products that depend on the source and center
+    only (nu.d and 1/|d|^3 with the double layer, 6; q/|d| with the single
+    layer, 1; q/|d|^3 with S', 1, and 1/|d|^3 when S' comes without the
+    double layer, 1) are formed once per source for both targets."""
+    shared = 18 + (6 if layers & 2 else 0) + (1 if layers & 1 else 0)
+    if layers & 4:
+        shared += 1 + (0 if layers & 2 else 1)
+    return flops_per_pair(p, layers) - shared / 2.0
 
 
 MIN_WARM_S = 0.3
@@ -817,6 +832,45 @@ def bench_helmholtz(ctx, api, torch, g, geom, steps, warmup, k=20.0, p=16):
     return res
 
 
+def bench_shared(ctx, api, torch, W, steps, warmup):
+    """Geometry B's sources with four near-surface targets per center (16384
+    centers, 65536 targets, the same pairs per target): the row kernel (one
+    list walk for two targets of a center, the plain path's default here)
+    against one wave per target (TSQBX_PER_TARGET), single + double layer,
+    p = 16, kernels alone on strengths staged once."""
+    log("generating geometry B with four targets per center")
+    g = W.config_b_shared(4)
+    geom = ctx.geometry(g)
+    p, layers = 16, 3
+    sig = torch.tensor(g.sigma, device="cuda", dtype=torch.float64)
+    outs = {k: [torch.zeros(g.n_targets, device="cuda", dtype=torch.float64) for _ in range(2)]
+            for k in ("rows", "per_target")}
+    ctx.stage_async(geom, sig, layers)
+    flops = {"rows": geom.pairs * rows_flops_per_pair(p, layers),
+             "per_target": geom.pairs * flops_per_pair(p, layers)}
+    res = {"workload": "perturbed sphere r=1+0.1f, 262144 sources; 16384 centers 0.02 inside, "
+                       "4 targets each on the segment to the surface (65536 targets); ball lists "
+                       "r=0.15; p=16, single+double layer",
+           "pairs": geom.pairs, "pair_terms": geom.pair_terms(p, layers)}
+    for name, flags in (("rows", 0), ("per_target", api.PER_TARGET)):
+        o = outs[name]
+        kern = lambda: ctx.eval_staged_async(geom, p, layers, o[0], o[1], flags=flags)
+        log(f"timing the {name} kernel, {steps} launches")
+        _, ev = timed_steps(kern, steps, warmup, torch)
+        ms = ev / steps * 1e3
+        res[name] = {"kernel_ms_per_launch": ms,
+                     "pair_terms_per_s": res["pair_terms"] / (ms / 1e3),
+                     "roofline": roofline_obj(flops[name], ms, "k_eval_rows<16, 3>"
+                                              if name == "rows" else "k_eval<16, 3, 64, 2>")}
+    torch.cuda.synchronize()
+    res["speedup_rows_vs_per_target"] = (res["per_target"]["kernel_ms_per_launch"] /
+                                         res["rows"]["kernel_ms_per_launch"])
+    res["identical_results"] = bool(all(torch.equal(a, b) for a, b in zip(outs["rows"],
+                                                                          outs["per_target"])))
+    geom.close()
+    return res
+
+
 def bench_lists(ctx, api, torch, g, steps, with_host=True):
     """Near-field ball lists of the headline workload (262144 sources, 65536
     centers, r = 0.15) built on the device, against the host grid generator
@@ -955,8 +1009,10 @@ def main():
     ap.add_argument("--plan-tuning", default=None,
                     help="fixed plan tuning instead of the autotuner, e.g. group_lanes=16,unroll=2,"
                          "waves_per_block=2,oversubscription=16,step_cost=1000")
+    ap.add_argument("--no-shared", action="store_true")
     ap.add_argument("--only", choices=["headline", "batched", "high_order", "serve", "sprime",
-                                       "helmholtz", "helm_batched", "lists", "conventional"],
+                                       "helmholtz", "helm_batched", "lists", "conventional",
+                                       "shared"],
                     help="run one section (for profiling); the JSON line then carries only it")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run a 256 MiB device copy first (for counter calibration)")
@@ -981,7 +1037,7 @@ def main():
                                        "conventional"):
         ctx = api.Context(0)
         fn = {"batched": bench_batched, "high_order": bench_d,
-              "helm_batched": bench_helm_batched}.get(args.only)
+              "helm_batched": bench_helm_batched, "shared": bench_shared}.get(args.only)
         if fn is not None:
             res = fn(ctx, api, torch, W, args.steps, args.warmup)
         else:
@@ -1085,6 +1141,8 @@ def main():
                                                  args.warmup)
     geom.close()
     del sig, os_, od_
+    if not args.no_shared:
+        out["shared_centers"] = bench_shared(ctx, api, torch, W, args.steps, args.warmup)
     if not args.no_batched:
         log("generating 64 batched geometries (mixed p)")
         geoms_c = W.config_c()

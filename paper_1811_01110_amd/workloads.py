@@ -362,6 +362,33 @@ def config_b(scale: int = 1, radius: float = 0.15) -> Geometry:
                     target_normals=tnrm)
 
 
+def config_b_shared(targets_per_center: int = 4, scale: int = 1,
+                    radius: float = 0.15) -> Geometry:
+    """Geometry B's sources and density with several targets per center.
+
+    A quarter as many centers as B has targets (16384), each 0.02 inside the
+    perturbed sphere along the normal, with `targets_per_center` targets on
+    the segment from the center to the surface, at 1, 3/4, 1/2, ... of the
+    way (the first on the surface): near-surface targets sharing one QBX
+    expansion.  Lists hold every source within `radius` of the center, so
+    the pairs per target are those of B.
+    """
+    rng = rng_for("B")
+    surf = PerturbedSphere(rng)
+    n, k = 262144 // scale, 65536 // scale // targets_per_center
+    src, nrm, w, (th, ph), tgt0, ctr, tnrm0 = _on_surface_targets(
+        surf, n, k, rng, 0.02, phase_tgt=0.5 * GOLDEN_ANGLE)
+    sigma = _ys32_real(th, ph) + 0.1 * rng.standard_normal(n)
+    r = radius * math.sqrt(scale)
+    offsets, idx = csr_ball(ctr, src, r)
+    frac = 1.0 - np.arange(targets_per_center) / (targets_per_center)
+    tgt = (ctr[:, None, :] + 0.02 * frac[None, :, None] * tnrm0[:, None, :]).reshape(-1, 3)
+    tc = np.repeat(np.arange(k, dtype=np.int32), targets_per_center)
+    tnrm = np.repeat(tnrm0, targets_per_center, axis=0)
+    return Geometry(src, w, nrm, ctr, offsets, idx, tgt, tc, sigma, 16, 3,
+                    f"B shared x{targets_per_center}", target_normals=tnrm)
+
+
 def _random_surface(rng):
     if rng.random() < 0.5:
         axes = rng.uniform(0.5, 2.0, size=3)
