@@ -81,17 +81,17 @@ def flops_per_pair(p: int, layers: int) -> int:
     return f
 
 
-def rows_flops_per_pair(p: int, layers: int) -> float:
+def rows_flops_per_pair(p: int, layers: int, per_walk: int = 4) -> float:
     """FP64 operations per pair of the row kernel, which walks a list once for
-    two targets: the source's offset from the center, |d|^2, 1/|d| and
+    per_walk targets: the source's offset from the center, |d|^2, 1/|d| and
     1/|d|^2 (18), and the products that depend on the source and center
     only (nu.d and 1/|d|^3 with the double layer, 6; q/|d| with the single
     layer, 1; q/|d|^3 with S', 1, and 1/|d|^3 when S' comes without the
-    double layer, 1) are formed once per source for both targets."""
+    double layer, 1) are formed once per source for all of them."""
     shared = 18 + (6 if layers & 2 else 0) + (1 if layers & 1 else 0)
     if layers & 4:
         shared += 1 + (0 if layers & 2 else 1)
-    return flops_per_pair(p, layers) - shared / 2.0
+    return flops_per_pair(p, layers) - shared * (1.0 - 1.0 / per_walk)
 
 
 MIN_WARM_S = 0.3
@@ -835,7 +835,7 @@ def bench_helmholtz(ctx, api, torch, g, geom, steps, warmup, k=20.0, p=16):
 def bench_shared(ctx, api, torch, W, steps, warmup):
     """Geometry B's sources with four near-surface targets per center (16384
     centers, 65536 targets, the same pairs per target): the row kernel (one
-    list walk for two targets of a center, the plain path's default here)
+    list walk for four targets of a center, the plain path's default here)
     against one wave per target (TSQBX_PER_TARGET), single + double layer,
     p = 16, kernels alone on strengths staged once."""
     log("generating geometry B with four targets per center")

@@ -80,7 +80,7 @@ enum {
   TSQBX_NO_REORDER = 2u, /* geometry_create: keep the caller's source/target order on device */
   TSQBX_PER_TARGET = 4u  /* plain Laplace eval: one wave per target even where targets share a
                             center's list (by default, with one target per wave and 1.5 or
-                            more targets per list, one wave walks a list once for two of its
+                            more targets per list, one wave walks a list once for up to four of its
                             targets; the results are the same bits either way) */
 };
 

@@ -1,8 +1,8 @@
 // The plain path for geometries whose targets share centers: one wave per
-// row (a center and its list) walks the list once for two of the row's
-// targets at a time, so each source record is gathered once per two
-// targets and the source's offset from the center, its distance and 1/R are
-// formed once.  Each target's terms are the same operations in the same
+// row (a center and its list) walks the list once for four (then two) of
+// the row's targets at a time, so each source record is gathered once per
+// four targets and the source's offset from the center, its distance and
+// 1/R are formed once.  Each target's terms are the same operations in the same
 // order as in the one-target-per-wave kernel (lane l adds the entries l,
 // l + 64, ... of the list, then the same butterfly), so the results equal
 // that kernel's bit for bit.
@@ -117,32 +117,36 @@ __device__ __forceinline__ TargetGeom geom_of(const TargetRec &tr, const double4
   return tg;
 }
 
-// Two targets of one row (tr0.row_begin == tr1.row_begin): lane gl adds the
+// K targets of one row (all with the row's row_begin): lane gl adds the
 // entries gl, gl + 64, ... (the next entry's index loaded a step ahead),
 // then the 64 lanes' sums are folded by the butterfly of target_sum.
-template <int P, int L>
-__device__ __forceinline__ void row_sum2(int p_rt, int gl, const TargetRec &tr0,
-                                         const TargetRec &tr1, const double4 *tn0,
-                                         const double4 *tn1, const int32_t *__restrict__ idx,
-                                         const SrcView &src, double (&out)[2][3]) {
+template <int P, int L, int K>
+__device__ __forceinline__ void row_sumK(int p_rt, int gl, const TargetRec (&tr)[K],
+                                         const double4 *tnrm, const int (&t)[K],
+                                         const int32_t *__restrict__ idx, const SrcView &src,
+                                         double (&out)[K][3]) {
   constexpr int G = 64;
-  const TargetGeom tg[2] = {geom_of<L>(tr0, tn0), geom_of<L>(tr1, tn1)};
-  const int32_t *__restrict__ row = idx + tr0.row_begin;
-  const int len = tr0.row_len;
-  double acc_s[2] = {0.0, 0.0}, acc_d[2] = {0.0, 0.0}, acc_t[2] = {0.0, 0.0};
+  TargetGeom tg[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) tg[k] = geom_of<L>(tr[k], tnrm + t[k]);
+  const int32_t *__restrict__ row = idx + tr[0].row_begin;
+  const int len = tr[0].row_len;
+  double acc_s[K], acc_d[K], acc_t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc_s[k] = acc_d[k] = acc_t[k] = 0.0;
   const int full = len - len % G;
   int c0 = 0;
   uint32_t s = 0;
   if (full > 0) s = load_idx(row, (uint32_t)gl);
   for (; c0 < full; c0 += G) {
     const uint32_t sn = load_idx(row, (uint32_t)min(c0 + G + gl, len - 1));
-    source_terms<P, L, 2>(p_rt, s, src, tg, acc_s, acc_d, acc_t);
+    source_terms<P, L, K>(p_rt, s, src, tg, acc_s, acc_d, acc_t);
     s = sn;
   }
-  if (c0 + gl < len) source_terms<P, L, 2>(p_rt, load_idx(row, (uint32_t)(c0 + gl)), src, tg,
+  if (c0 + gl < len) source_terms<P, L, K>(p_rt, load_idx(row, (uint32_t)(c0 + gl)), src, tg,
                                            acc_s, acc_d, acc_t);
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < K; ++k) {
 #pragma unroll
     for (int off = G / 2; off >= 1; off >>= 1) {
       if constexpr (L & 1) acc_s[k] += __shfl_xor(acc_s[k], off, 64);
@@ -155,8 +159,31 @@ __device__ __forceinline__ void row_sum2(int p_rt, int gl, const TargetRec &tr0,
   }
 }
 
-// One wave per row; its targets two at a time, an odd last one through the
-// one-target routine.
+// The row's targets first + k .. first + k + K - 1: sums and stores.
+template <int P, int L, int K>
+__device__ __forceinline__ void do_group(int p_rt, int lane, int first, int k,
+                                         const int32_t *__restrict__ row_tgts,
+                                         const TargetRec *__restrict__ tgt,
+                                         const double4 *__restrict__ tnrm,
+                                         const int32_t *__restrict__ idx, const SrcView &src,
+                                         double *out_s, double *out_d, double *out_t,
+                                         int accumulate) {
+  int t[K];
+  TargetRec tr[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    t[j] = __builtin_amdgcn_readfirstlane(row_tgts[first + k + j]);
+    tr[j] = tgt[t[j]];
+  }
+  double v[K][3];
+  row_sumK<P, L, K>(p_rt, lane, tr, tnrm, t, idx, src, v);
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < K; ++j) store_out<L>(tr[j], v[j], out_s, out_d, out_t, accumulate);
+}
+
+// One wave per row; its targets four at a time, then two, and a last odd
+// one through the one-target routine.
 template <int P, int L>
 __global__ void __launch_bounds__(512)
 k_eval_rows(const CenterRec *__restrict__ ctr, int64_t n_rows, const int32_t *__restrict__ row_tgts,
@@ -173,17 +200,12 @@ k_eval_rows(const CenterRec *__restrict__ ctr, int64_t n_rows, const int32_t *__
   const int first = __builtin_amdgcn_readfirstlane(ctr[r].tgt_begin);
   const int count = __builtin_amdgcn_readfirstlane(ctr[r].tgt_count);
   int k = 0;
-  for (; k + 1 < count; k += 2) {
-    const int t0 = __builtin_amdgcn_readfirstlane(row_tgts[first + k]);
-    const int t1 = __builtin_amdgcn_readfirstlane(row_tgts[first + k + 1]);
-    const TargetRec tr0 = tgt[t0], tr1 = tgt[t1];
-    double v[2][3];
-    row_sum2<P, L>(p_rt, lane, tr0, tr1, tnrm + t0, tnrm + t1, idx, src, v);
-    if (lane == 0) {
-      store_out<L>(tr0, v[0], out_s, out_d, out_t, accumulate);
-      store_out<L>(tr1, v[1], out_s, out_d, out_t, accumulate);
-    }
-  }
+  for (; k + 3 < count; k += 4)
+    do_group<P, L, 4>(p_rt, lane, first, k, row_tgts, tgt, tnrm, idx, src, out_s, out_d, out_t,
+                      accumulate);
+  for (; k + 1 < count; k += 2)
+    do_group<P, L, 2>(p_rt, lane, first, k, row_tgts, tgt, tnrm, idx, src, out_s, out_d, out_t,
+                      accumulate);
   if (k < count) {
     const int t0 = __builtin_amdgcn_readfirstlane(row_tgts[first + k]);
     const TargetRec tr = tgt[t0];

@@ -184,8 +184,8 @@ hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const So
                        const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
 // The plain Laplace path (tsqbx_eval_rows.hip): where targets share rows
 // (on average 1.5 or more per row) and one wave takes a target, one wave
-// per row walks each list once for two targets (k_eval_rows), with the bits
-// of launch_eval; per_target (TSQBX_PER_TARGET) keeps launch_eval.
+// per row walks each list once for up to four targets (k_eval_rows), with
+// the bits of launch_eval; per_target (TSQBX_PER_TARGET) keeps launch_eval.
 bool rows_kernel_pays(const tsqbx_geometry *g, const Tuning &tn);
 hipError_t launch_eval_plain(const tsqbx_geometry *g, int p, unsigned layers,
                              const SourceStage &st, const Outputs &out, bool accumulate,

@@ -1,7 +1,8 @@
-"""The row kernel of the plain path (one wave per center's list, two of its
-targets per walk) against the one-target-per-wave kernel (TSQBX_PER_TARGET),
-bit for bit, and against the oracle, for every layer mask, compiled and
-run-time orders, even and odd target counts per row, accumulation, the
+"""The row kernel of the plain path (one wave per center's list, four, then
+two of its targets per walk, then one) against the one-target-per-wave
+kernel (TSQBX_PER_TARGET), bit for bit, and against the oracle, for every
+layer mask, compiled and run-time orders, target counts per row from 1 to 6
+(every mix of the three walks), accumulation, the
 device-resident entry points, and plans and servers (which run the
 per-target kernels) on the same geometry."""
 import numpy as np
