@@ -118,3 +118,33 @@ def test_device_entry_points_accumulate_and_batched_paths(ctx):
     assert np.array_equal(out[0], host[0]) and np.array_equal(out[1], host[1])
     srv.close()
     geom.close()
+
+
+@pytest.mark.parametrize("p,layers", [(32, 7), (1, 3)])
+def test_rows_with_empty_and_short_lists(ctx, p, layers):
+    """Empty lists (outputs 0), lists shorter than a wave, the highest and a
+    low order, several targets per center."""
+    g0 = W.fuzz_geometry(1400 + p, n=3000, m=250, max_list=900, p=p, layers=layers,
+                         targets_per_center=4)
+    off = g0.list_offsets
+    lens = np.diff(off)
+    lens[::10] = 0  # every tenth center's list emptied
+    new_off = np.zeros_like(off)
+    np.cumsum(lens, out=new_off[1:])
+    lst = np.concatenate([g0.list_sources[off[i]:off[i] + lens[i]] for i in range(len(lens))])
+    g = W.Geometry(g0.sources, g0.weights, g0.normals, g0.centers, new_off, lst.astype(np.int32),
+                   g0.targets, g0.target_center, g0.sigma, p, layers, "rows short",
+                   target_normals=g0.target_normals)
+    assert (lens == 0).any() and ((lens > 0) & (lens < 64)).any()
+    geom = ctx.geometry(g)
+    mean = max(geom.pairs // geom.n_targets, 1)
+    ctx.set_tuning(p, layers, mean, group_lanes=64, unroll=2, waves_per_block=4, xcd_remap=1)
+    rows, per = _both(ctx, geom, g, p, layers)
+    ref = oracle.evaluate_geometry(g, p=p, layers=layers)
+    empty = np.isin(g.target_center, np.flatnonzero(lens == 0))
+    for bit, key, a, b in zip((1, 2, 4), KEYS, rows, per):
+        if layers & bit:
+            assert np.array_equal(a, b), key
+            assert np.all(a[empty] == 0.0)
+            assert_parity(a, ref[key], ref["abs_" + key], what=f"rows short p{p} {key}")
+    geom.close()
