@@ -1,6 +1,6 @@
 // The plain path for geometries whose targets share centers: one wave per
 // row (a center and its list) walks the list once for four (then two) of
-// the row's targets at a time, so each source record is gathered once per
+// the row's targets at a time (two where rows hold fewer than 3.5), so each source record is gathered once per
 // four targets and the source's offset from the center, its distance and
 // 1/R are formed once.  Each target's terms are the same operations in the same
 // order as in the one-target-per-wave kernel (lane l adds the entries l,
@@ -182,9 +182,11 @@ __device__ __forceinline__ void do_group(int p_rt, int lane, int first, int k,
     for (int j = 0; j < K; ++j) store_out<L>(tr[j], v[j], out_s, out_d, out_t, accumulate);
 }
 
-// One wave per row; its targets four at a time, then two, and a last odd
-// one through the one-target routine.
-template <int P, int L>
+// One wave per row; its targets four at a time (KMAX = 4), then two, and a
+// last odd one through the one-target routine.  The four-target walk takes
+// more VGPRs (half the waves per SIMD), so rows of two or three targets run
+// the KMAX = 2 kernel.
+template <int P, int L, int KMAX>
 __global__ void __launch_bounds__(512)
 k_eval_rows(const CenterRec *__restrict__ ctr, int64_t n_rows, const int32_t *__restrict__ row_tgts,
             const TargetRec *__restrict__ tgt, const double4 *__restrict__ tnrm,
@@ -200,9 +202,10 @@ k_eval_rows(const CenterRec *__restrict__ ctr, int64_t n_rows, const int32_t *__
   const int first = __builtin_amdgcn_readfirstlane(ctr[r].tgt_begin);
   const int count = __builtin_amdgcn_readfirstlane(ctr[r].tgt_count);
   int k = 0;
-  for (; k + 3 < count; k += 4)
-    do_group<P, L, 4>(p_rt, lane, first, k, row_tgts, tgt, tnrm, idx, src, out_s, out_d, out_t,
-                      accumulate);
+  if constexpr (KMAX >= 4)
+    for (; k + 3 < count; k += 4)
+      do_group<P, L, 4>(p_rt, lane, first, k, row_tgts, tgt, tnrm, idx, src, out_s, out_d, out_t,
+                        accumulate);
   for (; k + 1 < count; k += 2)
     do_group<P, L, 2>(p_rt, lane, first, k, row_tgts, tgt, tnrm, idx, src, out_s, out_d, out_t,
                       accumulate);
@@ -222,9 +225,15 @@ hipError_t launch_rows_one(const tsqbx_geometry *g, int p, const SourceStage &st
   if (blocks <= 0) return hipSuccess;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
   const SrcView src{st.xy, st.zq, st.nxy, st.nz};
-  hipLaunchKernelGGL((k_eval_rows<P, L>), dim3((unsigned)blocks), dim3(64 * tn.waves_per_block),
-                     0, s, g->ctr, g->n_rows, g->row_tgts, g->tgt, g->tgt_nrm, g->idx, src, o.s,
-                     o.d, o.t, acc ? 1 : 0, p, tn.xcd_remap);
+  // four targets per walk where rows hold 3.5 or more on average
+  if (2 * g->n_targets >= 7 * g->n_rows)
+    hipLaunchKernelGGL((k_eval_rows<P, L, 4>), dim3((unsigned)blocks),
+                       dim3(64 * tn.waves_per_block), 0, s, g->ctr, g->n_rows, g->row_tgts, g->tgt,
+                       g->tgt_nrm, g->idx, src, o.s, o.d, o.t, acc ? 1 : 0, p, tn.xcd_remap);
+  else
+    hipLaunchKernelGGL((k_eval_rows<P, L, 2>), dim3((unsigned)blocks),
+                       dim3(64 * tn.waves_per_block), 0, s, g->ctr, g->n_rows, g->row_tgts, g->tgt,
+                       g->tgt_nrm, g->idx, src, o.s, o.d, o.t, acc ? 1 : 0, p, tn.xcd_remap);
   return hipGetLastError();
 }
 
