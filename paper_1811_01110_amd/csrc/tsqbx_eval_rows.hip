@@ -1,8 +1,9 @@
 // The plain path for geometries whose targets share centers: one wave per
-// row (a center and its list) walks the list once for four (then two) of
-// the row's targets at a time (two where rows hold fewer than 3.5), so each source record is gathered once per
-// four targets and the source's offset from the center, its distance and
-// 1/R are formed once.  Each target's terms are the same operations in the same
+// row (a center and its list) walks the list once for several of the row's
+// targets (four at a time, then two; two at a time where rows hold fewer
+// than 3.5 targets on average), so each source record is gathered once per
+// walk and the source's offset from the center, its distance and 1/R are
+// formed once.  Each target's terms are the same operations in the same
 // order as in the one-target-per-wave kernel (lane l adds the entries l,
 // l + 64, ... of the list, then the same butterfly), so the results equal
 // that kernel's bit for bit.
