@@ -79,9 +79,10 @@ enum {
   TSQBX_ACCUMULATE = 1u, /* eval: add into the outputs instead of overwriting */
   TSQBX_NO_REORDER = 2u, /* geometry_create: keep the caller's source/target order on device */
   TSQBX_PER_TARGET = 4u  /* plain Laplace eval: one wave per target even where targets share a
-                            center's list (by default, with one target per wave and 1.5 or
-                            more targets per list, one wave walks a list once for up to four of its
-                            targets; the results are the same bits either way) */
+                            center's list (by default, with one target per wave, 1.5 or more
+                            targets per list on average and at most 16 on any, one wave walks a
+                            list once for up to four of its targets; the results are the same
+                            bits either way) */
 };
 
 /* Highest supported expansion order. */

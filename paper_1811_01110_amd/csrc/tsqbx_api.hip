@@ -494,6 +494,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
     host_row_len[k] = len;
   }
 
+  int64_t g_max_row_targets = 0;
   // rows for the conventional path: center, unpadded list, targets by row
   std::vector<CenterRec> crec(R);
   std::vector<int32_t> row_tgts(T);
@@ -511,6 +512,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
       x.tgt_begin = (int32_t)cnt[r];
       x.tgt_count = (int32_t)(cnt[r + 1] - cnt[r]);
       x.pad = 0;
+      g_max_row_targets = std::max<int64_t>(g_max_row_targets, x.tgt_count);
     }
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
     for (int64_t k = 0; k < T; ++k) row_tgts[fill[row_of_center[tc[tgt_ord[k]]]]++] = (int32_t)k;
@@ -553,6 +555,7 @@ int tsqbx_geometry_create(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, unsigned
   if (e == hipSuccess && d->target_normals) e = dev_upload(&g->tgt_nrm, tnrm.data(), T, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->idx, idx.data(), nnz_dev, &bytes);
   g->n_rows = R;
+  g->max_row_targets = g_max_row_targets;
   if (e == hipSuccess) e = dev_upload(&g->ctr, crec.data(), R, &bytes);
   if (e == hipSuccess) e = dev_upload(&g->row_tgts, row_tgts.data(), T, &bytes);
   // staging blocks of the plain path (see SourceStage)

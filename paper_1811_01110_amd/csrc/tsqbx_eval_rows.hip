@@ -254,8 +254,11 @@ hipError_t launch_rows_p(const tsqbx_geometry *g, int p, const SourceStage &st, 
 }  // namespace
 
 bool rows_kernel_pays(const tsqbx_geometry *g, const Tuning &tn) {
-  // one wave per target group, and on average 1.5 targets or more per row
-  return tn.group_lanes == 64 && g->n_rows > 0 && 2 * g->n_targets >= 3 * g->n_rows;
+  // one wave per target group, on average 1.5 targets or more per row, and
+  // at most 16 in any row: a wave takes a whole row, so a row with many more
+  // targets than the others would hold one wave while the GPU idles
+  return tn.group_lanes == 64 && g->n_rows > 0 && 2 * g->n_targets >= 3 * g->n_rows &&
+         g->max_row_targets <= 16;
 }
 
 hipError_t launch_eval_plain(const tsqbx_geometry *g, int p, unsigned layers,

@@ -259,7 +259,8 @@ __global__ void __launch_bounds__(kBlock)
 k_centers(int64_t R, int64_t T, const int64_t *__restrict__ row_center,
           const int64_t *__restrict__ row_first, const int64_t *__restrict__ row_off,
           const int64_t *__restrict__ off, const double *__restrict__ centers,
-          CenterRec *__restrict__ crec, int32_t *__restrict__ row_tgts) {
+          CenterRec *__restrict__ crec, int32_t *__restrict__ row_tgts,
+          unsigned *__restrict__ max_count) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r < T) row_tgts[r] = (int32_t)r;
   if (r >= R) return;
@@ -273,6 +274,7 @@ k_centers(int64_t R, int64_t T, const int64_t *__restrict__ row_center,
   x.tgt_count = (int32_t)((r + 1 < R ? row_first[r + 1] : T) - row_first[r]);
   x.pad = 0;
   crec[r] = x;
+  atomicMax(max_count, (unsigned)x.tgt_count);
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
@@ -539,14 +541,18 @@ int tsqbx::build_geometry_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, h
   if (d->target_normals) TQ(keep(&g->tgt_nrm, T));
   TQ(keep(&g->ctr, R));
   TQ(keep(&g->row_tgts, T));
+  unsigned *d_maxc = nullptr, h_maxc = 0;  // most targets in a row
+  TQ(sc.get(&d_maxc, 1));
+  TQ(hipMemsetAsync(d_maxc, 0, sizeof(unsigned), s));
   if (T > 0) {
     hipLaunchKernelGGL(k_targets, dim3(grid_of(T)), dim3(kBlock), 0, s, tgt_ord, T,
                        d->target_center, row_id, row_off, d->list_offsets, d->centers, d->targets,
                        d->target_normals, g->tgt, g->tgt_nrm, row_len);
     hipLaunchKernelGGL(k_centers, dim3(grid_of(std::max(R, T))), dim3(kBlock), 0, s, R, T,
                        row_center, row_first, row_off, d->list_offsets, d->centers, g->ctr,
-                       g->row_tgts);
+                       g->row_tgts, d_maxc);
     TQ(hipGetLastError());
+    TQ(hipMemcpyAsync(&h_maxc, d_maxc, sizeof h_maxc, hipMemcpyDeviceToHost, s));
   }
   g->host_row_len.resize(T);
   if (T > 0)
@@ -559,6 +565,7 @@ int tsqbx::build_geometry_device(tsqbx_ctx *ctx, const tsqbx_geometry_desc *d, h
   // the positions and the padding entry, once: evaluations stage strengths only
   TQ(launch_stage_positions(g, g->stage, s));
   TQ(hipStreamSynchronize(s));  // the scratch buffers are freed on return
+  g->max_row_targets = h_maxc;
   for (int64_t v : g->host_row_len) {
     g->pairs += v;
     g->max_list = std::max(g->max_list, v);

@@ -145,6 +145,7 @@ struct tsqbx_geometry {
   double4 *tgt_nrm = nullptr;    // [T] (nx, ny, nz, 0) at the targets, device order, or null
   int32_t *idx = nullptr;        // [nnz'] lists in device numbering, one row per target group
   int64_t n_rows = 0;            // rows = distinct centers with targets
+  int64_t max_row_targets = 0;   // most targets any row has
   tsqbx::CenterRec *ctr = nullptr;  // [n_rows]
   int32_t *row_tgts = nullptr;   // [T] device-order targets grouped by row
   tsqbx::SourceStage stage;      // staging used by the plain path (positions written at creation)
@@ -183,9 +184,10 @@ hipError_t launch_stage_positions(const tsqbx_geometry *g, const SourceStage &st
 hipError_t launch_eval(const tsqbx_geometry *g, int p, unsigned layers, const SourceStage &st,
                        const Outputs &out, bool accumulate, const Tuning &tn, hipStream_t s);
 // The plain Laplace path (tsqbx_eval_rows.hip): where targets share rows
-// (on average 1.5 or more per row) and one wave takes a target, one wave
-// per row walks each list once for up to four targets (k_eval_rows), with
-// the bits of launch_eval; per_target (TSQBX_PER_TARGET) keeps launch_eval.
+// (on average 1.5 or more per row, at most 16 in any) and one wave takes a
+// target, one wave per row walks each list once for up to four targets
+// (k_eval_rows), with the bits of launch_eval; per_target
+// (TSQBX_PER_TARGET) keeps launch_eval.
 bool rows_kernel_pays(const tsqbx_geometry *g, const Tuning &tn);
 hipError_t launch_eval_plain(const tsqbx_geometry *g, int p, unsigned layers,
                              const SourceStage &st, const Outputs &out, bool accumulate,

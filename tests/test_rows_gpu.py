@@ -154,3 +154,34 @@ def test_rows_with_empty_and_short_lists(ctx, p, layers):
             assert np.all(a[empty] == 0.0)
             assert_parity(a, ref[key], ref["abs_" + key], what=f"rows short p{p} {key}")
     geom.close()
+
+
+def test_crowded_row_runs_one_wave_per_target(ctx):
+    """A center with far more targets than the others (here 40 beside rows
+    of two): the plain path keeps one wave per target (a row kernel would
+    hold that row's whole walk on one wave); same bits and the oracle's
+    values either way, for host- and device-built geometries."""
+    import torch
+
+    rng = np.random.default_rng(1410)
+    g = _geom(1410, 2, 16, 3, m=200)
+    tc = g.target_center.copy()
+    tc[:40] = 0  # center 0 takes 40 targets
+    r = np.linalg.norm(g.targets[0] - g.centers[g.target_center[0]])
+    dirs = rng.standard_normal((len(tc), 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    tgt = g.centers[tc] + dirs * (0.5 * r)
+    g2 = W.Geometry(g.sources, g.weights, g.normals, g.centers, g.list_offsets, g.list_sources,
+                    tgt, tc.astype(np.int32), g.sigma, 16, 3, "crowded row")
+    ref = oracle.evaluate_geometry(g2)
+    dev = {k: (torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0") if v is not None else None)
+           for k, v in dict(sources=g2.sources, weights=g2.weights, normals=g2.normals,
+                            centers=g2.centers, list_offsets=g2.list_offsets,
+                            list_sources=g2.list_sources, targets=g2.targets,
+                            target_center=g2.target_center).items()}
+    for geom in (ctx.geometry(g2), ctx.geometry_device(**dev)):
+        rows, per = _both(ctx, geom, g2, 16, 3)
+        for k in (0, 1):
+            assert np.array_equal(rows[k], per[k])
+            assert_parity(rows[k], ref[KEYS[k]], ref["abs_" + KEYS[k]], what="crowded row")
+        geom.close()
